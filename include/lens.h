@@ -1,0 +1,175 @@
+/*
+ * lens.h -- C ABI of the MI355X (gfx950) image-plane chi^2 library.
+ *
+ * The library evaluates the strong-lensing goodness of fit of Rexroth,
+ * Schaefer, Fourestey & Kneib (2019), "High Performance Computing for
+ * gravitational lens modeling: single vs double precision on GPUs and CPUs":
+ *   - the deflection gradient grad Psi of a sum of pseudo-elliptical
+ *     potentials at every node of a regular image-plane grid (Algorithm 1;
+ *     the singular isothermal radial profile generalised to the cored/cut
+ *     isothermal profile named in Sec. 5),
+ *   - the lens equation in the form of Sec. 2.2.2,
+ *     beta = theta - (D_LS/D_OS) grad Psi(theta),
+ *   - the re-lensing chi^2 of Sec. 2.2.1-2.2.2 and Fig. 1: observed images to
+ *     the source plane, barycentre per system, two triangles per grid cell
+ *     mapped to the source plane, containment of the barycentre, predicted
+ *     images, chi^2 = sum_i sum_j |x_obs,ij - x_ij|^2 / sigma_ij^2.
+ *
+ * Conventions shared by every entry point
+ *   Units: angles in arcsec, position angle phi in radians counter-clockwise
+ *   from the theta_1 axis, velocity dispersion in km/s.
+ *   Memory: every array argument is a DEVICE pointer (memory of the device
+ *   the context was created on) unless stated otherwise; the caller owns all
+ *   of them.  The context owns only its internal scratch.
+ *   Streams: all work is enqueued on the given stream and is asynchronous;
+ *   outputs are valid once the stream has been synchronised.  The context
+ *   keeps per-call scratch, so calls that share one context must be issued on
+ *   one stream (or be otherwise serialised); one context per host thread.
+ *   Errors: every function returns LENS_OK or a LENS_ERR_* code for problems
+ *   visible on the host (null pointers, sizes, grid shape, device errors).
+ *   Problems in device-resident values (parameter domains, capacity) are
+ *   reported in the device status word (stats[LENS_STAT_STATUS] or the
+ *   status argument), and the numeric outputs are then NaN.  No C++
+ *   exception crosses this interface.
+ */
+#ifndef LENS_H
+#define LENS_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LENS_OK 0
+#define LENS_ERR_INVALID 1   /* bad argument or parameter domain             */
+#define LENS_ERR_DEVICE 2    /* a HIP call failed                             */
+#define LENS_ERR_CAPACITY 3  /* more predicted images than the output holds  */
+
+/* Slots of the int64 statistics array written by lens_image_chi2. */
+#define LENS_STAT_HITS 0        /* predicted images (triangle hits) found          */
+#define LENS_STAT_FLAGGED 1     /* FP32 tests sent to the FP64 fallback            */
+#define LENS_STAT_TILE_PASS 2   /* (tile, system) pairs surviving the tile cull    */
+#define LENS_STAT_BBOX_PASS 3   /* triangle tests surviving the bounding-box test  */
+#define LENS_STAT_STATUS 4      /* LENS_OK or LENS_ERR_INVALID / _CAPACITY         */
+#define LENS_STAT_FB_HITS 5     /* hits decided by the FP64 fallback               */
+#define LENS_STAT_TESTS 6       /* triangle x system tests in the full problem     */
+#define LENS_STAT_N 8
+
+typedef struct lens_ctx lens_ctx;
+
+typedef enum {
+    LENS_FP64 = 0,  /* every step in FP64                                        */
+    LENS_FP32 = 1,  /* deflection only: FP32 field (lens_deflect)                 */
+    LENS_MIXED = 2  /* FP32 field and containment tests, FP64 where the FP32 test
+                       cannot decide, FP64 source positions, images and chi^2     */
+} lens_precision;
+
+/* Potentials as a structure of arrays (Sec. 2.3), n entries each, device
+ * memory, float64.  Domain: 0 <= eps < 1; r_core >= 0; r_cut > r_core
+ * (r_cut = +INFINITY: no cut); sigma_v >= 0; all values finite except r_cut.
+ * r_core = 0 and r_cut = +INFINITY is the singular isothermal ellipsoid of
+ * Algorithm 1.  n may be 0 (no deflection). */
+typedef struct {
+    int32_t n;
+    const double *x, *y;          /* centre, arcsec                              */
+    const double *eps;            /* pseudo-ellipticity of the potential         */
+    const double *phi;            /* position angle, radians                     */
+    const double *r_core, *r_cut; /* core and cut radius, arcsec                 */
+    const double *sigma_v;        /* velocity dispersion, km/s                   */
+} lens_potentials;
+
+/* Regular grid of nodes: node (i, j) = (x0 + i h, y0 + j h), 0 <= i < nx,
+ * 0 <= j < ny; node arrays are row-major [ny][nx].  nx, ny >= 2, h > 0.
+ * Cell (i, j) is split along its anti-diagonal into triangle 0 with vertices
+ * (i,j), (i+1,j), (i,j+1) and triangle 1 with vertices (i+1,j+1), (i,j+1),
+ * (i+1,j); triangle id = 2 (j (nx-1) + i) + k (Fig. 1 of the paper). */
+typedef struct {
+    double x0, y0, h;
+    int32_t nx, ny;
+} lens_grid;
+
+/* Observed multiple-image systems (Sec. 2.2.1) in CSR form.  Host-side
+ * counts; device arrays. */
+typedef struct {
+    int32_t n_sys;               /* number of systems (sources), >= 1            */
+    int32_t n_img;               /* number of observed images, == sys_off[n_sys] */
+    const int32_t *sys_off;      /* [n_sys + 1], non-decreasing, sys_off[0] = 0  */
+    const double *x, *y;         /* [n_img] observed positions, arcsec           */
+    const double *sigma;         /* [n_img] positional error sigma_ij, arcsec    */
+    const double *dls_dos;       /* [n_sys] D_LS/D_OS of each source (Sec. 2.2.2,
+                                    computed once per source, e.g. lens_dls_dos) */
+} lens_obs;
+
+typedef struct {
+    lens_precision prec;  /* LENS_FP64 or LENS_MIXED                                 */
+    int32_t fb_mode;      /* MIXED only.  0: a test is sent to FP64 when its FP32 sign
+                             is not certified by the FP32 error bound (hit sets equal
+                             to the FP64 path).  1: literal threshold, a test is sent
+                             to FP64 when min_k |c_k| < fb_tau * h^2                 */
+    double fb_tau;        /* literal-mode factor (e.g. 1e-6); ignored in mode 0    */
+    int32_t hit_capacity; /* rows of out->hits / out->img_xy, >= 1                */
+} lens_chi2_opts;
+
+typedef struct {
+    double *chi2;        /* [1]       total chi^2 (+inf if any system has no image) */
+    double *chi2_sys;    /* [n_sys]   per-system chi^2                              */
+    int32_t *n_pred;     /* [n_sys]   predicted images per system                   */
+    int32_t *hits;       /* [2 * hit_capacity] (system, triangle id) pairs, sorted    */
+    double *img_xy;      /* [2 * hit_capacity] predicted image positions (x, y)       */
+    int32_t *match;      /* [n_img]   index into hits of each observed image's match,
+                                      -1 if its system has no predicted image; may
+                                      be NULL                                        */
+    int64_t *stats;      /* [LENS_STAT_N] statistics and device status               */
+} lens_chi2_out;
+
+/* Create a context on HIP device `device`.  Returns LENS_ERR_INVALID for a
+ * null ctx pointer or a bad device, LENS_ERR_DEVICE if HIP fails. */
+int lens_create(lens_ctx **ctx, int device);
+
+/* Release the context and its scratch.  Synchronises the device first.
+ * NULL is ignored. */
+void lens_destroy(lens_ctx *ctx);
+
+/* D_LS/D_OS for n source redshifts zs[n] behind a lens at zl in a flat
+ * universe (Omega_m + Omega_Lambda = 1; the paper uses 0.3, 0.7), by
+ * composite Simpson quadrature of the comoving distance on the device.
+ * zs, out: device float64 [n].  A source at zs <= zl gets 0. */
+int lens_dls_dos(lens_ctx *ctx, double zl, const double *zs, int32_t n, double omega_m,
+                 double omega_l, double *out, hipStream_t stream);
+
+/* Deflection gradient grad Psi at every node of the grid (Algorithm 1 summed
+ * over all potentials; Sec. 2.2.2 superposition).  prec = LENS_FP64: ax, ay
+ * are double [ny*nx]; LENS_FP32 or LENS_MIXED: float [ny*nx].  Output layout
+ * row-major, node (i,j) at index j*nx + i.  status: device int32 [1] or NULL,
+ * receives LENS_OK or LENS_ERR_INVALID (parameter domain; outputs NaN). */
+int lens_deflect(lens_ctx *ctx, const lens_potentials *pot, const lens_grid *grid,
+                 lens_precision prec, void *ax, void *ay, int32_t *status, hipStream_t stream);
+
+/* Source positions of the observed images and barycentres of the systems
+ * (Sec. 2.2.2): beta_ij = theta_ij - (D_LS/D_OS)_i grad Psi(theta_ij) in FP64,
+ * barycentre = unweighted mean of the system's beta_ij.  beta_x, beta_y:
+ * double [n_img]; bar_x, bar_y: double [n_sys]. */
+int lens_source_positions(lens_ctx *ctx, const lens_potentials *pot, const lens_obs *obs,
+                          double *beta_x, double *beta_y, double *bar_x, double *bar_y,
+                          int32_t *status, hipStream_t stream);
+
+/* Full image-plane chi^2 (Sec. 2.2.1, 2.2.2, Fig. 1).  Each observed image is
+ * paired with the nearest predicted image of its system (ties to the lower
+ * triangle id); a system without predicted images has chi2_sys = +inf.  If
+ * more hits exist than opts->hit_capacity, stats[LENS_STAT_STATUS] =
+ * LENS_ERR_CAPACITY, stats[LENS_STAT_HITS] holds the required capacity and
+ * chi2 outputs are NaN. */
+int lens_image_chi2(lens_ctx *ctx, const lens_potentials *pot, const lens_grid *grid,
+                    const lens_obs *obs, const lens_chi2_opts *opts, lens_chi2_out *out,
+                    hipStream_t stream);
+
+/* Human-readable name of a return code (static string). */
+const char *lens_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LENS_H */

@@ -1,0 +1,208 @@
+"""MI355X (gfx950) image-plane chi^2 for strong-lens models.
+
+Python face of the C ABI in include/lens.h (Rexroth et al. 2019: Algorithm 1
+deflection generalised to cored/cut isothermal potentials, the lens equation of
+Sec. 2.2.2, and the triangle re-lensing chi^2 of Sec. 2.2.1-2.2.2).  The
+functions below only marshal torch tensors into the library calls; all
+arithmetic runs in the HIP kernels of liblens.so.
+
+Potentials are a float64 CUDA tensor of shape [7, P] (rows x, y, eps, phi,
+r_core, r_cut, sigma_v; structure of arrays).  Observations are an ``Obs``
+(CSR over systems).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+
+import torch
+
+from . import _lib as L
+from ._lib import LENS_FP32, LENS_FP64, LENS_MIXED, STAT_N  # noqa: F401
+
+_PREC = {"fp64": LENS_FP64, "fp32": LENS_FP32, "mixed": LENS_MIXED}
+
+
+@dataclasses.dataclass
+class Obs:
+    """Observed multiple-image systems: sys_off [S+1] int32, x, y, sigma [n_img]
+    float64, dls [S] float64 (D_LS/D_OS), all on the same CUDA device."""
+    sys_off: torch.Tensor
+    x: torch.Tensor
+    y: torch.Tensor
+    sigma: torch.Tensor
+    dls: torch.Tensor
+
+    @property
+    def n_sys(self) -> int:
+        return self.sys_off.numel() - 1
+
+    @property
+    def n_img(self) -> int:
+        return self.x.numel()
+
+    @staticmethod
+    def from_numpy(d, device="cuda"):
+        f = lambda a, dt: torch.as_tensor(a, dtype=dt, device=device).contiguous()
+        return Obs(f(d["sys_off"], torch.int32), f(d["x"], torch.float64), f(d["y"], torch.float64),
+                   f(d["sigma"], torch.float64), f(d["dls"], torch.float64))
+
+
+def _require_cuda(t: torch.Tensor, dtype, name: str):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _pots(params: torch.Tensor) -> L.LensPotentials:
+    _require_cuda(params, torch.float64, "params")
+    if params.dim() != 2 or params.shape[0] != 7:
+        raise ValueError("params must have shape [7, P]")
+    n = params.shape[1]
+    rows = [params[k].data_ptr() if n > 0 else None for k in range(7)]
+    return L.LensPotentials(n, *rows)
+
+
+def _grid(grid) -> L.LensGrid:
+    return L.LensGrid(float(grid.x0), float(grid.y0), float(grid.h), int(grid.nx), int(grid.ny))
+
+
+def _obs(obs: Obs) -> L.LensObs:
+    _require_cuda(obs.sys_off, torch.int32, "sys_off")
+    for name in ("x", "y", "sigma", "dls"):
+        _require_cuda(getattr(obs, name), torch.float64, name)
+    return L.LensObs(obs.n_sys, obs.n_img, obs.sys_off.data_ptr(), obs.x.data_ptr(), obs.y.data_ptr(),
+                     obs.sigma.data_ptr(), obs.dls.data_ptr())
+
+
+class Context:
+    """Owns a lens_ctx (device scratch) on one device."""
+
+    def __init__(self, device=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device available: the lens library has no CPU path")
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        torch.cuda.init()
+        self._lib = L.load()
+        h = C.c_void_p()
+        L.check(self._lib.lens_create(C.byref(h), self.device.index), "lens_create")
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.lens_destroy(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def stream(self):
+        return L.stream_handle(self.device)
+
+
+_contexts: dict[int, Context] = {}
+
+
+def context(device=None) -> Context:
+    idx = torch.cuda.current_device() if device is None else torch.device("cuda", device).index
+    if idx not in _contexts:
+        _contexts[idx] = Context(idx)
+    return _contexts[idx]
+
+
+def lens_dls_dos(z_lens: float, z_src: torch.Tensor, omega_m: float = 0.3, omega_l: float = 0.7,
+                 ctx: Context | None = None) -> torch.Tensor:
+    """D_LS/D_OS for every source redshift (flat universe, GPU quadrature)."""
+    ctx = ctx or context(z_src.device.index)
+    _require_cuda(z_src, torch.float64, "z_src")
+    out = torch.empty_like(z_src)
+    L.check(ctx._lib.lens_dls_dos(ctx.handle, float(z_lens), L.ptr(z_src), z_src.numel(), omega_m, omega_l,
+                                  L.ptr(out), ctx.stream()), "lens_dls_dos")
+    return out
+
+
+def lens_deflect(params: torch.Tensor, grid, prec: str = "fp64", ctx: Context | None = None,
+                 check: bool = True):
+    """grad Psi at every grid node; returns (ax, ay) of shape [ny, nx] (float64 for
+    'fp64', float32 for 'fp32'/'mixed')."""
+    ctx = ctx or context(params.device.index)
+    p = _pots(params)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    ax = torch.empty((grid.ny, grid.nx), dtype=dt, device=params.device)
+    ay = torch.empty_like(ax)
+    status = torch.zeros(1, dtype=torch.int32, device=params.device)
+    L.check(ctx._lib.lens_deflect(ctx.handle, C.byref(p), C.byref(_grid(grid)), _PREC[prec], L.ptr(ax), L.ptr(ay),
+                                  L.ptr(status), ctx.stream()), "lens_deflect")
+    if check and int(status.item()) != L.LENS_OK:
+        raise RuntimeError(f"lens_deflect: invalid potential parameters (status {int(status.item())})")
+    return ax, ay
+
+
+def lens_source_positions(params: torch.Tensor, obs: Obs, ctx: Context | None = None, check: bool = True):
+    """Source positions of the observed images [n_img, 2] and barycentres [n_sys, 2]."""
+    ctx = ctx or context(params.device.index)
+    p, o = _pots(params), _obs(obs)
+    dev = params.device
+    bx = torch.empty(obs.n_img, dtype=torch.float64, device=dev)
+    by = torch.empty_like(bx)
+    cx = torch.empty(obs.n_sys, dtype=torch.float64, device=dev)
+    cy = torch.empty_like(cx)
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    L.check(ctx._lib.lens_source_positions(ctx.handle, C.byref(p), C.byref(o), L.ptr(bx), L.ptr(by), L.ptr(cx),
+                                           L.ptr(cy), L.ptr(status), ctx.stream()), "lens_source_positions")
+    if check and int(status.item()) != L.LENS_OK:
+        raise RuntimeError(f"lens_source_positions: invalid input (status {int(status.item())})")
+    return torch.stack([bx, by], 1), torch.stack([cx, cy], 1)
+
+
+@dataclasses.dataclass
+class Chi2Result:
+    chi2: torch.Tensor      # [1] float64
+    chi2_sys: torch.Tensor  # [S] float64
+    n_pred: torch.Tensor    # [S] int32
+    hits: torch.Tensor      # [cap, 2] int32 (system, triangle id); first stats[0] rows valid
+    img_xy: torch.Tensor    # [cap, 2] float64
+    match: torch.Tensor     # [n_img] int32
+    stats: torch.Tensor     # [8] int64
+
+    def host(self) -> dict:
+        """Copy to host and trim the hit list (synchronises)."""
+        st = self.stats.cpu().numpy()
+        n = int(st[L.STAT_HITS]) if st[L.STAT_STATUS] == L.LENS_OK else 0
+        return dict(chi2=float(self.chi2.cpu()[0]), chi2_sys=self.chi2_sys.cpu().numpy(),
+                    n_pred=self.n_pred.cpu().numpy(), hit_sys=self.hits[:n, 0].cpu().numpy(),
+                    hit_tid=self.hits[:n, 1].cpu().numpy(), hit_x=self.img_xy[:n, 0].cpu().numpy(),
+                    hit_y=self.img_xy[:n, 1].cpu().numpy(), match=self.match.cpu().numpy(), stats=st,
+                    status=int(st[L.STAT_STATUS]))
+
+
+def chi2_buffers(obs: Obs, hit_capacity: int, device) -> Chi2Result:
+    z = lambda *s, dt=torch.float64: torch.zeros(*s, dtype=dt, device=device)
+    return Chi2Result(z(1), z(obs.n_sys), z(obs.n_sys, dt=torch.int32), z(hit_capacity, 2, dt=torch.int32),
+                      z(hit_capacity, 2), z(max(obs.n_img, 1), dt=torch.int32), z(STAT_N, dt=torch.int64))
+
+
+def lens_image_chi2(params: torch.Tensor, grid, obs: Obs, prec: str = "mixed", fb_mode: int = 0,
+                    fb_tau: float = 1e-6, hit_capacity: int = 4096, out: Chi2Result | None = None,
+                    ctx: Context | None = None) -> Chi2Result:
+    """Image-plane chi^2 (asynchronous; outputs valid after stream sync)."""
+    ctx = ctx or context(params.device.index)
+    if prec not in ("fp64", "mixed"):
+        raise ValueError("prec must be 'fp64' or 'mixed'")
+    p, o = _pots(params), _obs(obs)
+    out = out or chi2_buffers(obs, hit_capacity, params.device)
+    opts = L.LensChi2Opts(_PREC[prec], int(fb_mode), float(fb_tau), int(out.hits.shape[0]))
+    co = L.LensChi2Out(out.chi2.data_ptr(), out.chi2_sys.data_ptr(), out.n_pred.data_ptr(), out.hits.data_ptr(),
+                       out.img_xy.data_ptr(), out.match.data_ptr(), out.stats.data_ptr())
+    L.check(ctx._lib.lens_image_chi2(ctx.handle, C.byref(p), C.byref(_grid(grid)), C.byref(o), C.byref(opts),
+                                     C.byref(co), ctx.stream()), "lens_image_chi2")
+    return out
+
+
+__all__ = ["Obs", "Context", "context", "lens_dls_dos", "lens_deflect", "lens_source_positions",
+           "lens_image_chi2", "Chi2Result", "chi2_buffers"]

@@ -1,0 +1,92 @@
+"""ctypes binding of liblens.so (include/lens.h).
+
+Argument marshalling only: torch tensors are passed as device pointers, the
+stream is torch's current stream.  Every computation runs in the HIP library;
+there is no fallback -- a missing library or GPU raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "liblens.so")
+
+LENS_OK, LENS_ERR_INVALID, LENS_ERR_DEVICE, LENS_ERR_CAPACITY = 0, 1, 2, 3
+LENS_FP64, LENS_FP32, LENS_MIXED = 0, 1, 2
+STAT_HITS, STAT_FLAGGED, STAT_TILE_PASS, STAT_BBOX_PASS, STAT_STATUS, STAT_FB_HITS, STAT_TESTS = range(7)
+STAT_N = 8
+
+EXPORTS = ("lens_create", "lens_destroy", "lens_dls_dos", "lens_deflect", "lens_source_positions",
+           "lens_image_chi2", "lens_strerror")
+
+
+class LensPotentials(C.Structure):
+    _fields_ = [("n", C.c_int32), ("x", C.c_void_p), ("y", C.c_void_p), ("eps", C.c_void_p),
+                ("phi", C.c_void_p), ("r_core", C.c_void_p), ("r_cut", C.c_void_p), ("sigma_v", C.c_void_p)]
+
+
+class LensGrid(C.Structure):
+    _fields_ = [("x0", C.c_double), ("y0", C.c_double), ("h", C.c_double), ("nx", C.c_int32), ("ny", C.c_int32)]
+
+
+class LensObs(C.Structure):
+    _fields_ = [("n_sys", C.c_int32), ("n_img", C.c_int32), ("sys_off", C.c_void_p), ("x", C.c_void_p),
+                ("y", C.c_void_p), ("sigma", C.c_void_p), ("dls_dos", C.c_void_p)]
+
+
+class LensChi2Opts(C.Structure):
+    _fields_ = [("prec", C.c_int), ("fb_mode", C.c_int32), ("fb_tau", C.c_double), ("hit_capacity", C.c_int32)]
+
+
+class LensChi2Out(C.Structure):
+    _fields_ = [("chi2", C.c_void_p), ("chi2_sys", C.c_void_p), ("n_pred", C.c_void_p), ("hits", C.c_void_p),
+                ("img_xy", C.c_void_p), ("match", C.c_void_p), ("stats", C.c_void_p)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load liblens.so (after torch has initialised its HIP runtime, so that both
+    share one runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run `python -m paper_1902_03252_amd.build`")
+    lib = C.CDLL(path)
+    vp, i32, d = C.c_void_p, C.c_int32, C.c_double
+    lib.lens_create.argtypes = [C.POINTER(vp), C.c_int]
+    lib.lens_create.restype = C.c_int
+    lib.lens_destroy.argtypes = [vp]
+    lib.lens_destroy.restype = None
+    lib.lens_dls_dos.argtypes = [vp, d, vp, i32, d, d, vp, vp]
+    lib.lens_dls_dos.restype = C.c_int
+    lib.lens_deflect.argtypes = [vp, C.POINTER(LensPotentials), C.POINTER(LensGrid), C.c_int, vp, vp, vp, vp]
+    lib.lens_deflect.restype = C.c_int
+    lib.lens_source_positions.argtypes = [vp, C.POINTER(LensPotentials), C.POINTER(LensObs), vp, vp, vp, vp, vp, vp]
+    lib.lens_source_positions.restype = C.c_int
+    lib.lens_image_chi2.argtypes = [vp, C.POINTER(LensPotentials), C.POINTER(LensGrid), C.POINTER(LensObs),
+                                    C.POINTER(LensChi2Opts), C.POINTER(LensChi2Out), vp]
+    lib.lens_image_chi2.restype = C.c_int
+    lib.lens_strerror.argtypes = [C.c_int]
+    lib.lens_strerror.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def check(rc: int, what: str):
+    if rc != LENS_OK:
+        msg = load().lens_strerror(rc).decode()
+        raise RuntimeError(f"{what} failed: {msg} (code {rc})")
+
+
+def ptr(t: torch.Tensor | None):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def stream_handle(device: torch.device) -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)

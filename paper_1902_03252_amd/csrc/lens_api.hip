@@ -1,0 +1,327 @@
+// C ABI of the gfx950 chi^2 library (declared in include/lens.h): argument
+// checks on the host, context scratch, and the launch sequence of each entry
+// point.  No C++ exception crosses this file's extern "C" functions.
+#include "lens.h"
+#include "lens_device.hpp"
+#include "lens_internal.hpp"
+
+#include <cmath>
+#include <stdlib.h>
+#include <string.h>
+
+using namespace lens;
+
+namespace {
+
+enum Buf { B_TAB64, B_TAB32, B_BTERM, B_FIELD, B_BX, B_BY, B_SYS, B_STATE, B_HITS, B_FLAGS, B_CONTRIB, B_NBUF };
+
+}  // namespace
+
+struct lens_ctx {
+    int device;
+    void* buf[B_NBUF];
+    size_t cap[B_NBUF];
+};
+
+namespace {
+
+// Restores the caller's current device on scope exit.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) return;
+        ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+// Grows scratch buffer `which` to at least `bytes`.  Growing frees the old
+// block after a device synchronisation, so earlier asynchronous calls that
+// still read it have finished.
+int ensure(lens_ctx* c, int which, size_t bytes)
+{
+    if (bytes == 0) bytes = 256;
+    if (c->cap[which] >= bytes) return LENS_OK;
+    size_t nb = c->cap[which] + c->cap[which] / 2;
+    if (nb < bytes) nb = bytes;
+    nb = (nb + 255) & ~(size_t)255;
+    if (c->buf[which]) {
+        if (hipDeviceSynchronize() != hipSuccess) return LENS_ERR_DEVICE;
+        (void)hipFree(c->buf[which]);
+        c->buf[which] = nullptr;
+        c->cap[which] = 0;
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, nb) != hipSuccess) return LENS_ERR_DEVICE;
+    c->buf[which] = p;
+    c->cap[which] = nb;
+    return LENS_OK;
+}
+
+bool is_fin(double v) { return std::isfinite(v); }
+
+int check_pot(const lens_potentials* pot)
+{
+    if (!pot || pot->n < 0) return LENS_ERR_INVALID;
+    if (pot->n > 0 && (!pot->x || !pot->y || !pot->eps || !pot->phi || !pot->r_core || !pot->r_cut || !pot->sigma_v))
+        return LENS_ERR_INVALID;
+    return LENS_OK;
+}
+
+int check_grid(const lens_grid* g)
+{
+    if (!g || g->nx < 2 || g->ny < 2 || g->ny > 65535 || !(g->h > 0.0) || !is_fin(g->h) || !is_fin(g->x0) ||
+        !is_fin(g->y0))
+        return LENS_ERR_INVALID;
+    if ((long long)(g->nx - 1) * (long long)(g->ny - 1) >= (1ll << 30)) return LENS_ERR_INVALID;  // int32 ids
+    return LENS_OK;
+}
+
+int check_obs(const lens_obs* o)
+{
+    if (!o || o->n_sys < 1 || o->n_img < 0 || !o->sys_off || !o->dls_dos) return LENS_ERR_INVALID;
+    if (o->n_img > 0 && (!o->x || !o->y || !o->sigma)) return LENS_ERR_INVALID;
+    return LENS_OK;
+}
+
+PotPtrs pot_ptrs(const lens_potentials* p)
+{
+    PotPtrs q;
+    q.n = p->n;
+    q.x = p->x;
+    q.y = p->y;
+    q.eps = p->eps;
+    q.phi = p->phi;
+    q.r_core = p->r_core;
+    q.r_cut = p->r_cut;
+    q.sigma_v = p->sigma_v;
+    return q;
+}
+
+GridDesc grid_desc(const lens_grid* g)
+{
+    GridDesc d;
+    d.x0 = g->x0;
+    d.y0 = g->y0;
+    d.h = g->h;
+    d.nx = g->nx;
+    d.ny = g->ny;
+    return d;
+}
+
+ObsPtrs obs_ptrs(const lens_obs* o)
+{
+    ObsPtrs q;
+    q.n_sys = o->n_sys;
+    q.n_img = o->n_img;
+    q.sys_off = o->sys_off;
+    q.x = o->x;
+    q.y = o->y;
+    q.sigma = o->sigma;
+    q.dls = o->dls_dos;
+    return q;
+}
+
+ObsPtrs no_obs()
+{
+    ObsPtrs q;
+    memset(&q, 0, sizeof q);
+    return q;
+}
+
+// Nodes per thread of the FP32 field kernel: enough waves to fill 256 CUs,
+// as many nodes per thread as that allows (amortises the per-row work and
+// overlaps the transcendental latency).  LENS_FIELD_NPL overrides.
+int field_npl(const GridDesc& g)
+{
+    const char* env = getenv("LENS_FIELD_NPL");
+    if (env) {
+        const int v = atoi(env);
+        if (v == 1 || v == 2 || v == 4 || v == 8) return v;
+    }
+    const long long nodes = (long long)g.nx * g.ny;
+    if (nodes >= (8ll << 20)) return 4;
+    if (nodes >= (1ll << 20)) return 2;
+    return 1;
+}
+
+// Runs prep (+ source positions) + bound: the common head of every entry point.
+int head(lens_ctx* c, const lens_potentials* pot, const GridDesc& g, const ObsPtrs& obs, double* bx, double* by,
+         hipStream_t s)
+{
+    const int np = pot->n;
+    int rc;
+    if ((rc = ensure(c, B_TAB64, (size_t)np * T64_STRIDE * 8)) ||
+        (rc = ensure(c, B_TAB32, (size_t)np * T32_STRIDE * 4)) || (rc = ensure(c, B_BTERM, (size_t)np * 3 * 8)) ||
+        (rc = ensure(c, B_SYS, (size_t)(obs.n_sys > 0 ? obs.n_sys : 1) * SYS_STRIDE * 8)) ||
+        (rc = ensure(c, B_STATE, sizeof(EvalState))))
+        return rc;
+    double* tab64 = (double*)c->buf[B_TAB64];
+    if (launch_prep(pot_ptrs(pot), g, tab64, (float*)c->buf[B_TAB32], (double*)c->buf[B_BTERM], s) != hipSuccess)
+        return LENS_ERR_DEVICE;
+    if (obs.n_img > 0 && launch_src(tab64, np, obs, bx, by, s) != hipSuccess) return LENS_ERR_DEVICE;
+    if (launch_bound((double*)c->buf[B_BTERM], np, g, obs, bx, by, (double*)c->buf[B_SYS],
+                     (EvalState*)c->buf[B_STATE], s) != hipSuccess)
+        return LENS_ERR_DEVICE;
+    return LENS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lens_create(lens_ctx** ctx, int device)
+{
+    if (!ctx) return LENS_ERR_INVALID;
+    *ctx = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess) return LENS_ERR_DEVICE;
+    if (device < 0 || device >= n) return LENS_ERR_INVALID;
+    lens_ctx* c = (lens_ctx*)calloc(1, sizeof(lens_ctx));
+    if (!c) return LENS_ERR_DEVICE;
+    c->device = device;
+    *ctx = c;
+    return LENS_OK;
+}
+
+void lens_destroy(lens_ctx* ctx)
+{
+    if (!ctx) return;
+    {
+        DeviceGuard dg(ctx->device);
+        (void)hipDeviceSynchronize();
+        for (int k = 0; k < B_NBUF; k++)
+            if (ctx->buf[k]) (void)hipFree(ctx->buf[k]);
+    }
+    free(ctx);
+}
+
+const char* lens_strerror(int code)
+{
+    switch (code) {
+    case LENS_OK: return "ok";
+    case LENS_ERR_INVALID: return "invalid argument or parameter domain";
+    case LENS_ERR_DEVICE: return "HIP device error";
+    case LENS_ERR_CAPACITY: return "hit capacity exceeded";
+    default: return "unknown error";
+    }
+}
+
+int lens_dls_dos(lens_ctx* ctx, double zl, const double* zs, int32_t n, double omega_m, double omega_l, double* out,
+                 hipStream_t stream)
+{
+    if (!ctx || n < 0 || (n > 0 && (!zs || !out)) || !is_fin(zl) || zl < 0.0 || !is_fin(omega_m) ||
+        !is_fin(omega_l) || fabs(omega_m + omega_l - 1.0) > 1e-12 || omega_m < 0.0)
+        return LENS_ERR_INVALID;
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return LENS_ERR_DEVICE;
+    return launch_dls(zl, zs, n, omega_m, omega_l, out, stream) == hipSuccess ? LENS_OK : LENS_ERR_DEVICE;
+}
+
+int lens_deflect(lens_ctx* ctx, const lens_potentials* pot, const lens_grid* grid, lens_precision prec, void* ax,
+                 void* ay, int32_t* status, hipStream_t stream)
+{
+    if (!ctx || check_pot(pot) || check_grid(grid) || !ax || !ay) return LENS_ERR_INVALID;
+    if (prec != LENS_FP64 && prec != LENS_FP32 && prec != LENS_MIXED) return LENS_ERR_INVALID;
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return LENS_ERR_DEVICE;
+    const GridDesc g = grid_desc(grid);
+    int rc = head(ctx, pot, g, no_obs(), nullptr, nullptr, stream);
+    if (rc) return rc;
+    const EvalState* st = (const EvalState*)ctx->buf[B_STATE];
+    hipError_t e;
+    if (prec == LENS_FP64)
+        e = launch_field64((const double*)ctx->buf[B_TAB64], pot->n, g, (double*)ax, (double*)ay, st, stream);
+    else
+        e = launch_field32((const float*)ctx->buf[B_TAB32], pot->n, g, (float*)ax, (float*)ay, st, field_npl(g),
+                           stream);
+    if (e != hipSuccess) return LENS_ERR_DEVICE;
+    if (status && launch_export(nullptr, 0, st, nullptr, nullptr, status, stream) != hipSuccess)
+        return LENS_ERR_DEVICE;
+    return LENS_OK;
+}
+
+int lens_source_positions(lens_ctx* ctx, const lens_potentials* pot, const lens_obs* obs, double* beta_x,
+                          double* beta_y, double* bar_x, double* bar_y, int32_t* status, hipStream_t stream)
+{
+    if (!ctx || check_pot(pot) || check_obs(obs) || !bar_x || !bar_y) return LENS_ERR_INVALID;
+    if (obs->n_img > 0 && (!beta_x || !beta_y)) return LENS_ERR_INVALID;
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return LENS_ERR_DEVICE;
+    GridDesc g;  // the split of the barycentres needs some grid; a unit grid at the origin
+    g.x0 = 0.0;
+    g.y0 = 0.0;
+    g.h = 1.0;
+    g.nx = 2;
+    g.ny = 2;
+    int rc = head(ctx, pot, g, obs_ptrs(obs), beta_x, beta_y, stream);
+    if (rc) return rc;
+    if (launch_export((const double*)ctx->buf[B_SYS], obs->n_sys, (const EvalState*)ctx->buf[B_STATE], bar_x,
+                      bar_y, status, stream) != hipSuccess)
+        return LENS_ERR_DEVICE;
+    return LENS_OK;
+}
+
+int lens_image_chi2(lens_ctx* ctx, const lens_potentials* pot, const lens_grid* grid, const lens_obs* obs,
+                    const lens_chi2_opts* opts, lens_chi2_out* out, hipStream_t stream)
+{
+    if (!ctx || check_pot(pot) || check_grid(grid) || check_obs(obs) || !opts || !out) return LENS_ERR_INVALID;
+    if (opts->prec != LENS_FP64 && opts->prec != LENS_MIXED) return LENS_ERR_INVALID;
+    if (opts->hit_capacity < 1 || opts->hit_capacity > kHitScratch) return LENS_ERR_INVALID;
+    if (opts->prec == LENS_MIXED && (opts->fb_mode < 0 || opts->fb_mode > 1)) return LENS_ERR_INVALID;
+    if (opts->prec == LENS_MIXED && opts->fb_mode == 1 && !(opts->fb_tau >= 0.0 && is_fin(opts->fb_tau)))
+        return LENS_ERR_INVALID;
+    if (!out->chi2 || !out->chi2_sys || !out->n_pred || !out->hits || !out->img_xy || !out->stats)
+        return LENS_ERR_INVALID;
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return LENS_ERR_DEVICE;
+    const GridDesc g = grid_desc(grid);
+    const ObsPtrs o = obs_ptrs(obs);
+    const int np = pot->n;
+    const bool mixed = opts->prec == LENS_MIXED;
+    const size_t nn = (size_t)g.nx * g.ny;
+    int rc;
+    if ((rc = ensure(ctx, B_FIELD, nn * 2 * (mixed ? 4 : 8))) || (rc = ensure(ctx, B_BX, (size_t)o.n_img * 8)) ||
+        (rc = ensure(ctx, B_BY, (size_t)o.n_img * 8)) || (rc = ensure(ctx, B_HITS, (size_t)kHitScratch * 8)) ||
+        (rc = ensure(ctx, B_FLAGS, (size_t)(mixed ? kFlagScratch : 1) * 8)) ||
+        (rc = ensure(ctx, B_CONTRIB, (size_t)o.n_img * 8)))
+        return rc;
+    if ((rc = head(ctx, pot, g, o, (double*)ctx->buf[B_BX], (double*)ctx->buf[B_BY], stream))) return rc;
+
+    const double* tab64 = (const double*)ctx->buf[B_TAB64];
+    const double* sysrow = (const double*)ctx->buf[B_SYS];
+    EvalState* st = (EvalState*)ctx->buf[B_STATE];
+    unsigned long long* hits = (unsigned long long*)ctx->buf[B_HITS];
+    unsigned long long* flags = (unsigned long long*)ctx->buf[B_FLAGS];
+    const long long flag_cap = mixed ? kFlagScratch : 0;
+    hipError_t e;
+    if (mixed) {
+        float* ax = (float*)ctx->buf[B_FIELD];
+        float* ay = ax + nn;
+        e = launch_field32((const float*)ctx->buf[B_TAB32], np, g, ax, ay, nullptr, field_npl(g), stream);
+        if (e == hipSuccess)
+            e = launch_tri32(ax, ay, g, o.n_sys, sysrow, st, opts->fb_mode, (float)(opts->fb_tau * g.h * g.h), hits,
+                             kHitScratch, flags, flag_cap, stream);
+        if (e == hipSuccess) e = launch_fb(tab64, np, g, sysrow, st, flags, flag_cap, hits, kHitScratch, stream);
+    } else {
+        double* ax = (double*)ctx->buf[B_FIELD];
+        double* ay = ax + nn;
+        e = launch_field64(tab64, np, g, ax, ay, nullptr, stream);
+        if (e == hipSuccess) e = launch_tri64(ax, ay, g, o.n_sys, sysrow, st, hits, kHitScratch, stream);
+    }
+    if (e == hipSuccess)
+        e = launch_sort(hits, st, flag_cap, opts->hit_capacity, o.n_sys, out->hits, out->n_pred, stream);
+    if (e == hipSuccess) e = launch_pos(tab64, np, g, sysrow, st, opts->hit_capacity, hits, out->img_xy, stream);
+    const long long n_tests = 2ll * (g.nx - 1) * (g.ny - 1) * o.n_sys;
+    if (e == hipSuccess)
+        e = launch_chi2(o, st, opts->hit_capacity, hits, out->img_xy, (double*)ctx->buf[B_CONTRIB], out->chi2,
+                        out->chi2_sys, out->match, (long long*)out->stats, n_tests, stream);
+    return e == hipSuccess ? LENS_OK : LENS_ERR_DEVICE;
+}
+
+}  // extern "C"

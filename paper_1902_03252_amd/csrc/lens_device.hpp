@@ -1,0 +1,232 @@
+// Device-side building blocks of the gfx950 chi^2 path.
+//
+// Deflection of one pseudo-elliptical cored/cut isothermal potential
+// (Algorithm 1 of Rexroth et al. 2019, radial profile generalised as the paper
+// suggests in Sec. 5).  Algorithm 1 translates, rotates by -Phi, scales the
+// two axes by (1 -/+ eps), forms R and rotates back by +Phi.  The two
+// rotations and the axis scaling collapse into one symmetric matrix
+//     M = Rot(Phi) diag(1-eps, 1+eps) Rot(-Phi) = [[A, B], [B, C]],
+//     A = (1-eps) cos^2 + (1+eps) sin^2,  B = -2 eps cos sin,
+//     C = (1-eps) sin^2 + (1+eps) cos^2,
+// so that with d = theta - theta_c:
+//     R^2 = d . M d,   grad Psi = K f(R) M d,
+//     f(R) = 1/(sqrt(a^2+R^2) + a) - 1/(sqrt(s^2+R^2) + s),
+// K = b0 s/(s - a), b0 = 4 pi (sigma_v/c)^2 (Sec. 2.2.2).  For a = 0 and
+// s = inf, K f M d = b0 M d / R: the SIE gradient of Sec. 2.2.2.  The matrix
+// form needs 4 multiply-adds for the quadratic form and the gradient
+// direction instead of 8 for the two explicit rotations; per-potential
+// constants are precomputed once (FP64) by the prep kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lens {
+
+// ---------------------------------------------------------------- tables
+
+// FP64 table, arcsec units, one 128-byte row per potential.
+enum : int {
+    T64_XC = 0, T64_YC, T64_A, T64_B, T64_C, T64_A2, T64_S2, T64_RA, T64_RS, T64_K, T64_SINF,
+    T64_STRIDE = 16
+};
+
+// FP32 table, grid-node units, one 64-byte row per potential.  The centre is
+// stored as (index of the nearest node) + (fraction): with node index i an
+// exact float, (i - c_hi) is exact and (i - c_hi) - c_lo carries only a
+// relative rounding error, so the FP32 offset from a potential's centre is
+// accurate to a few ulps of the offset itself, wherever the potential sits.
+// This removes the paper's error growth near potential centres far from the
+// origin (the |theta_center| / |Delta theta| term of its Appendix A).
+enum : int {
+    T32_CXH = 0, T32_CXL, T32_CYH, T32_CYL,  // centre in node units (hi + lo)
+    T32_A, T32_B, T32_C,                     // M h^2
+    T32_A2,                                  // a^2 (arcsec^2)
+    T32_S2A2,                                // s^2 - a^2
+    T32_RA, T32_RS,                          // a, s (arcsec)
+    T32_K,                                   // K / h
+    T32_KIND,                                // 0: a>0,s<inf  1: a>0,s=inf  2: a=0,s<inf  3: a=0,s=inf
+    T32_STRIDE = 16
+};
+
+// Per-system row (FP64): barycentre, its node-unit split, D_LS/D_OS and the
+// FP32 error bound of the source-plane vertex positions.
+enum : int {
+    SYS_BX = 0, SYS_BY, SYS_BXH, SYS_BXL, SYS_BYH, SYS_BYL, SYS_R, SYS_EB, SYS_STRIDE = 8
+};
+
+// Device-side state of one evaluation (zeroed by the bound kernel).
+struct EvalState {
+    unsigned long long n_hits;       // hits appended (FP32-certain + fallback)
+    unsigned long long n_flags;      // tests sent to the fallback
+    unsigned long long n_tile_pass;  // (tile, system) pairs surviving the cull
+    unsigned long long n_bbox_pass;  // triangle tests surviving bbox rejection
+    unsigned long long n_fb_hits;    // hits found by the fallback
+    int status;                      // LENS_OK / LENS_ERR_INVALID / LENS_ERR_CAPACITY
+    int pad;
+    double e_alpha;                  // bound on |alpha_fp32 - alpha| per component
+    double w_sum;                    // sum of per-potential deflection bounds
+};
+
+constexpr int kStatusOk = 0;
+constexpr int kStatusInvalid = 1;
+constexpr int kStatusCapacity = 3;
+
+// ---------------------------------------------------------------- wave helpers
+
+__device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+    // butterfly: every lane ends with the same, order-fixed result
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+__device__ __forceinline__ float wave_max(float v)
+{
+    for (int m = 32; m >= 1; m >>= 1) v = fmaxf(v, __shfl_xor(v, m, 64));
+    return v;
+}
+
+__device__ __forceinline__ float wave_min(float v)
+{
+    for (int m = 32; m >= 1; m >>= 1) v = fminf(v, __shfl_xor(v, m, 64));
+    return v;
+}
+
+// ---------------------------------------------------------------- FP64 deflection
+
+// Adds the deflection of the potential in row `t` (FP64 table) at the point
+// (t1, t2) to (s1, s2).
+__device__ __forceinline__ void add_alpha64(const double* __restrict__ t, double t1, double t2,
+                                            double& s1, double& s2)
+{
+    const double d1 = t1 - t[T64_XC];
+    const double d2 = t2 - t[T64_YC];
+    const double m1 = t[T64_A] * d1 + t[T64_B] * d2;
+    const double m2 = t[T64_B] * d1 + t[T64_C] * d2;
+    const double R2 = d1 * m1 + d2 * m2;
+    const double ra = t[T64_RA];
+    const double qa = sqrt(t[T64_A2] + R2) + ra;
+    double f;
+    if (t[T64_SINF] != 0.0) {
+        f = 1.0 / qa;
+    } else {
+        const double qs = sqrt(t[T64_S2] + R2) + t[T64_RS];
+        f = (qs - qa) / (qa * qs);
+    }
+    if (ra == 0.0 && R2 == 0.0) f = 0.0;  // centre of a singular profile contributes 0
+    const double kf = t[T64_K] * f;
+    s1 += kf * m1;
+    s2 += kf * m2;
+}
+
+// grad Psi at one point with the potentials split over the 64 lanes of a
+// wave and a fixed butterfly reduction (deterministic).  All lanes return the
+// same value.
+__device__ __forceinline__ void alpha64_wave(const double* __restrict__ tab, int np, double t1, double t2,
+                                             double& a1, double& a2)
+{
+    double s1 = 0.0, s2 = 0.0;
+    for (int p = lane_id(); p < np; p += 64) add_alpha64(tab + (size_t)p * T64_STRIDE, t1, t2, s1, s2);
+    a1 = wave_sum(s1);
+    a2 = wave_sum(s2);
+}
+
+// ---------------------------------------------------------------- exact orientation
+
+// Error-free transformations (Knuth's TwoSum; TwoProduct through the fused
+// multiply-add).  Exact barring overflow/underflow.
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e)
+{
+    s = a + b;
+    const double bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+__device__ __forceinline__ void two_prod(double a, double b, double& p, double& e)
+{
+    p = a * b;
+    e = fma(a, b, -p);
+}
+
+// Sign of the exact sum of n doubles by growing a non-overlapping expansion
+// (Shewchuk 1997, "Adaptive precision floating-point arithmetic"): the sign of
+// an expansion is the sign of its largest non-zero component.
+__device__ __noinline__ int exact_sum_sign(const double* terms, int n)
+{
+    double h[16];
+    int m = 0;
+    for (int k = 0; k < n; k++) {
+        double q = terms[k];
+        for (int i = 0; i < m; i++) {
+            double s, e;
+            two_sum(q, h[i], s, e);
+            h[i] = e;
+            q = s;
+        }
+        h[m++] = q;
+    }
+    for (int i = m - 1; i >= 0; i--)
+        if (h[i] != 0.0) return h[i] > 0.0 ? 1 : -1;
+    return 0;
+}
+
+// Exact sign of (a - p) x (b - p) for FP64 inputs.  A forward error bound
+// decides almost every case in plain FP64; otherwise the determinant is
+// expanded exactly: each difference is a two-term sum (TwoSum), each product
+// of two-term sums four TwoProducts, 16 terms in all.
+__device__ __forceinline__ int orient_exact(double ax, double ay, double bx, double by, double px, double py)
+{
+    const double l = (ax - px) * (by - py);
+    const double r = (ay - py) * (bx - px);
+    const double det = l - r;
+    // |fl(det) - det| <= (3u + O(u^2)) (|l| + |r|) + u |det|, u = 2^-53; use 8u
+    const double bound = 8.881784197001252e-16 * (fabs(l) + fabs(r));
+    if (det > bound) return 1;
+    if (-det > bound) return -1;
+    double x1, x1e, y2, y2e, y1, y1e, x2, x2e;
+    two_sum(ax, -px, x1, x1e);
+    two_sum(by, -py, y2, y2e);
+    two_sum(ay, -py, y1, y1e);
+    two_sum(bx, -px, x2, x2e);
+    double t[16];
+    two_prod(x1, y2, t[0], t[1]);
+    two_prod(x1, y2e, t[2], t[3]);
+    two_prod(x1e, y2, t[4], t[5]);
+    two_prod(x1e, y2e, t[6], t[7]);
+    two_prod(-y1, x2, t[8], t[9]);
+    two_prod(-y1, x2e, t[10], t[11]);
+    two_prod(-y1e, x2, t[12], t[13]);
+    two_prod(-y1e, x2e, t[14], t[15]);
+    return exact_sum_sign(t, 16);
+}
+
+// Containment of p in the triangle (v0, v1, v2) decided exactly on the FP64
+// vertex values: exact bounding-box rejection, then the three exact edge
+// signs; strict inequalities (a point on an edge is a miss).
+__device__ __forceinline__ bool contains_exact(const double* vx, const double* vy, double px, double py)
+{
+    const double xmin = fmin(vx[0], fmin(vx[1], vx[2])), xmax = fmax(vx[0], fmax(vx[1], vx[2]));
+    const double ymin = fmin(vy[0], fmin(vy[1], vy[2])), ymax = fmax(vy[0], fmax(vy[1], vy[2]));
+    if (px < xmin || px > xmax || py < ymin || py > ymax) return false;
+    const int s0 = orient_exact(vx[0], vy[0], vx[1], vy[1], px, py);
+    const int s1 = orient_exact(vx[1], vy[1], vx[2], vy[2], px, py);
+    const int s2 = orient_exact(vx[2], vy[2], vx[0], vy[0], px, py);
+    return (s0 > 0 && s1 > 0 && s2 > 0) || (s0 < 0 && s1 < 0 && s2 < 0);
+}
+
+// Grid-node indices of the three vertices of triangle `tid` (Fig. 1 split).
+__device__ __forceinline__ void triangle_nodes(int nx, int tid, int* ni, int* nj)
+{
+    const int cell = tid >> 1, k = tid & 1;
+    const int i = cell % (nx - 1), j = cell / (nx - 1);
+    if (k == 0) {
+        ni[0] = i; nj[0] = j; ni[1] = i + 1; nj[1] = j; ni[2] = i; nj[2] = j + 1;
+    } else {
+        ni[0] = i + 1; nj[0] = j + 1; ni[1] = i; nj[1] = j + 1; ni[2] = i + 1; nj[2] = j;
+    }
+}
+
+}  // namespace lens

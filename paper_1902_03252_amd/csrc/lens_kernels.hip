@@ -1,0 +1,988 @@
+// HIP kernels of the image-plane chi^2 path for gfx950 (MI355X).
+//
+// One chi^2 evaluation (Rexroth et al. 2019, Sec. 2.2.1-2.2.2, Fig. 1) runs as
+//   k_prep   per-potential constants (FP64) + domain checks
+//   k_src    observed images -> source plane (FP64, one wave per image)
+//   k_bound  barycentres, FP32 error bound, counters (one workgroup)
+//   k_field  deflection at every grid node (FP32 or FP64)        <- the time
+//   k_tri    tiles of cells: cull (tile, system) pairs, triangle containment,
+//            ballot/prefix-sum compaction of hits and undecided tests
+//   k_fb     FP64 re-test of the undecided FP32 tests (mixed path only)
+//   k_sort   bitonic sort of the hit keys (system, triangle id) in LDS
+//   k_pos    predicted image positions from FP64 vertex deflections
+//   k_chi2   nearest-image matching and the FP64 chi^2 sum, fixed order
+#include "lens_device.hpp"
+#include "lens_internal.hpp"
+
+#include <math.h>
+
+namespace lens {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kCkms = 299792.458;                 // km/s
+constexpr double kArcsecPerRad = 206264.80624709636;  // 180 * 3600 / pi
+constexpr double kU32 = 5.9604644775390625e-08;       // 2^-24, unit roundoff of FP32
+constexpr double kNodeSplitErr = 2.9802322387695312e-08;  // 2^-25 node units
+
+// ============================================================== prep
+
+// One thread per potential: domain check, FP64 and FP32 constant rows, and the
+// two per-potential terms of the FP32 error bound:
+//   w_p  >= |grad Psi_p| anywhere:  K (1+eps) / sqrt(1-eps)
+//   j_p  >= |Jacobian of grad Psi_p| x (absolute error of the FP32 offset):
+//          2 K (1+eps) / ((1-eps) (sqrt(a^2+rho^2)+a)) * err,  rho = elliptical
+//          distance from the centre to the nearest lattice node.
+__global__ void k_prep(PotPtrs pot, GridDesc g, double* __restrict__ tab64, float* __restrict__ tab32,
+                       double* __restrict__ bterm)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= pot.n) return;
+    const double xc = pot.x[p], yc = pot.y[p], eps = pot.eps[p], phi = pot.phi[p];
+    const double a = pot.r_core[p], s = pot.r_cut[p], sig = pot.sigma_v[p];
+    bool ok = isfinite(xc) && isfinite(yc) && isfinite(eps) && isfinite(phi) && isfinite(a) &&
+              isfinite(sig) && eps >= 0.0 && eps < 1.0 && a >= 0.0 && sig >= 0.0 && s > a;
+    const bool sinf = isinf(s);
+    const double c = cos(phi), sn = sin(phi);
+    const double a1 = 1.0 - eps, a2 = 1.0 + eps;
+    const double A = a1 * c * c + a2 * sn * sn;
+    const double B = -2.0 * eps * c * sn;
+    const double C = a1 * sn * sn + a2 * c * c;
+    const double ratio = sig / kCkms;
+    const double b0 = 4.0 * kPi * ratio * ratio * kArcsecPerRad;
+    const double K = sinf ? b0 : b0 * s / (s - a);
+
+    double* t = tab64 + (size_t)p * T64_STRIDE;
+    t[T64_XC] = xc;
+    t[T64_YC] = yc;
+    t[T64_A] = A;
+    t[T64_B] = B;
+    t[T64_C] = C;
+    t[T64_A2] = a * a;
+    t[T64_S2] = sinf ? 0.0 : s * s;
+    t[T64_RA] = a;
+    t[T64_RS] = sinf ? 0.0 : s;
+    t[T64_K] = K;
+    t[T64_SINF] = sinf ? 1.0 : 0.0;
+    for (int k = T64_SINF + 1; k < T64_STRIDE; k++) t[k] = 0.0;
+
+    const double cxn = (xc - g.x0) / g.h, cyn = (yc - g.y0) / g.h;
+    ok = ok && fabs(cxn) < 4194304.0 && fabs(cyn) < 4194304.0;  // |centre| < 2^22 nodes
+    const double cxh = rint(cxn), cyh = rint(cyn);
+    const double cxl = cxn - cxh, cyl = cyn - cyh;
+    const double h2 = g.h * g.h;
+    float* u = tab32 + (size_t)p * T32_STRIDE;
+    u[T32_CXH] = (float)cxh;
+    u[T32_CXL] = (float)cxl;
+    u[T32_CYH] = (float)cyh;
+    u[T32_CYL] = (float)cyl;
+    u[T32_A] = (float)(A * h2);
+    u[T32_B] = (float)(B * h2);
+    u[T32_C] = (float)(C * h2);
+    u[T32_A2] = (float)(a * a);
+    u[T32_S2A2] = sinf ? 0.0f : (float)(s * s - a * a);
+    u[T32_RA] = (float)a;
+    u[T32_RS] = sinf ? 0.0f : (float)s;
+    u[T32_K] = (float)(K / g.h);
+    u[T32_KIND] = (float)((a == 0.0 ? 2 : 0) + (sinf ? 1 : 0));
+    for (int k = T32_KIND + 1; k < T32_STRIDE; k++) u[k] = 0.0f;
+
+    // error-bound terms
+    const double w = K * a2 / sqrt(a1);
+    const double rho = sqrt(a1) * g.h * sqrt(cxl * cxl + cyl * cyl);
+    const double den = a1 * (sqrt(a * a + rho * rho) + a);
+    const double J = den > 0.0 ? 2.0 * K * a2 / den : INFINITY;
+    // absolute offset error: FP32 rounding of the centre fraction, plus the FP64
+    // reference's own rounding of theta - theta_c
+    const double span = fabs(g.x0) + fabs(g.y0) + (double)(g.nx + g.ny) * g.h + fabs(xc) + fabs(yc);
+    const double derr = g.h * kNodeSplitErr + 4.5e-16 * span;
+    bterm[3 * p + 0] = ok ? w : 0.0;
+    bterm[3 * p + 1] = ok ? J * derr : 0.0;
+    bterm[3 * p + 2] = ok ? 0.0 : 1.0;
+}
+
+// ============================================================== source positions
+
+// Index of the system that owns observed image j: sys_off is non-decreasing
+// for valid input; the search is clamped so that invalid input stays in range
+// (it is then reported by k_bound).
+__device__ __forceinline__ int system_of(const int* __restrict__ sys_off, int nsys, int j)
+{
+    int lo = 0, hi = nsys - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (sys_off[mid] <= j) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// One wave per observed image: beta_ij = theta_ij - r_i grad Psi(theta_ij), FP64
+// (Sec. 2.2.2), grad Psi evaluated at the observed position itself.
+__global__ __launch_bounds__(256) void k_src(const double* __restrict__ tab64, int np, ObsPtrs obs,
+                                             double* __restrict__ beta_x, double* __restrict__ beta_y)
+{
+    const int j = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (j >= obs.n_img) return;
+    const double t1 = obs.x[j], t2 = obs.y[j];
+    double a1, a2;
+    alpha64_wave(tab64, np, t1, t2, a1, a2);
+    const int s = system_of(obs.sys_off, obs.n_sys, j);
+    const double r = obs.dls[s];
+    if (lane_id() == 0) {
+        beta_x[j] = t1 - r * a1;
+        beta_y[j] = t2 - r * a2;
+    }
+}
+
+// ============================================================== bound / barycentres
+
+// One workgroup of 1024 threads.  Zeroes the evaluation state, reduces the
+// per-potential bound terms in a fixed order, and writes one row per system:
+// barycentre (unweighted mean of its beta_ij, Sec. 2.2.2), its node-unit split,
+// D_LS/D_OS and the FP32 error bound E_B of source-plane offsets:
+//   E_alpha = u (64 + P) sum_p w_p + sum_p j_p + 1e-9
+//   E_B     = r E_alpha + 4u Theta + 2u r (W + E_alpha) + 2^-25 h + 1e-9
+// with u = 2^-24, W = sum_p w_p and Theta = max |theta - barycentre| over the
+// grid.  64 u w_p bounds the rounding of one potential's FP32 evaluation
+// (about 30 u w_p by operation count, doubled), (P-1) u W the sequential FP32
+// sum over potentials, sum_p j_p the Jacobian-amplified absolute offset error.
+__global__ __launch_bounds__(1024) void k_bound(const double* __restrict__ bterm, int np, GridDesc g,
+                                                ObsPtrs obs, const double* __restrict__ beta_x,
+                                                const double* __restrict__ beta_y, double* __restrict__ sysrow,
+                                                EvalState* __restrict__ st)
+{
+    __shared__ double sw[1024], sj[1024], sb[1024];
+    const int t = threadIdx.x;
+    double w = 0.0, jt = 0.0, bad = 0.0;
+    for (int p = t; p < np; p += 1024) {
+        w += bterm[3 * p + 0];
+        jt += bterm[3 * p + 1];
+        bad += bterm[3 * p + 2];
+    }
+    sw[t] = w;
+    sj[t] = jt;
+    sb[t] = bad;
+    __syncthreads();
+    for (int m = 512; m >= 1; m >>= 1) {
+        if (t < m) {
+            sw[t] += sw[t + m];
+            sj[t] += sj[t + m];
+            sb[t] += sb[t + m];
+        }
+        __syncthreads();
+    }
+    const double W = sw[0];
+    const double e_alpha = kU32 * (64.0 + np) * W + sj[0] + 1e-9;
+    __shared__ int sys_bad;
+    if (t == 0) {
+        sys_bad = 0;
+        st->n_hits = 0;
+        st->n_flags = 0;
+        st->n_tile_pass = 0;
+        st->n_bbox_pass = 0;
+        st->n_fb_hits = 0;
+        st->e_alpha = e_alpha;
+        st->w_sum = W;
+        if (obs.n_sys > 0 && (obs.sys_off[0] != 0 || obs.sys_off[obs.n_sys] != obs.n_img)) sys_bad = 1;
+    }
+    __syncthreads();
+    const double xlo = g.x0, xhi = g.x0 + (g.nx - 1) * g.h, ylo = g.y0, yhi = g.y0 + (g.ny - 1) * g.h;
+    for (int s = t; s < obs.n_sys; s += 1024) {
+        const int j0 = obs.sys_off[s], j1 = obs.sys_off[s + 1];
+        bool ok = j0 <= j1 && j0 >= 0 && j1 <= obs.n_img;
+        double bx = 0.0, by = 0.0;
+        if (ok) {
+            for (int j = j0; j < j1; j++) {
+                bx += beta_x[j];
+                by += beta_y[j];
+                ok = ok && obs.sigma[j] > 0.0 && isfinite(obs.sigma[j]) && isfinite(obs.x[j]) && isfinite(obs.y[j]);
+            }
+            if (j1 > j0) {
+                bx /= (j1 - j0);
+                by /= (j1 - j0);
+            }
+        }
+        const double r = obs.dls[s];
+        ok = ok && isfinite(r) && r >= 0.0;
+        const double bxn = (bx - g.x0) / g.h, byn = (by - g.y0) / g.h;
+        ok = ok && fabs(bxn) < 4194304.0 && fabs(byn) < 4194304.0;
+        const double theta = fmax(fmax(fabs(xlo - bx), fabs(xhi - bx)), fmax(fabs(ylo - by), fabs(yhi - by)));
+        const double eb = r * e_alpha + 4.0 * kU32 * theta + 2.0 * kU32 * r * (W + e_alpha) +
+                          g.h * kNodeSplitErr + 1e-9;
+        double* row = sysrow + (size_t)s * SYS_STRIDE;
+        row[SYS_BX] = bx;
+        row[SYS_BY] = by;
+        row[SYS_BXH] = rint(bxn);
+        row[SYS_BXL] = bxn - rint(bxn);
+        row[SYS_BYH] = rint(byn);
+        row[SYS_BYL] = byn - rint(byn);
+        row[SYS_R] = r;
+        row[SYS_EB] = eb * (1.0 + 1e-6);
+        if (!ok) atomicOr(&sys_bad, 1);
+    }
+    __syncthreads();
+    if (t == 0) st->status = (sb[0] != 0.0 || sys_bad) ? kStatusInvalid : kStatusOk;
+}
+
+// ============================================================== deflection field
+
+// FP32 contribution of one potential row `c` (node units) for NPL nodes of a
+// row.  KIND selects the radial profile at compile time: bit 0 = no cut
+// radius, bit 1 = no core.  f = (B_ - A_) / (A_ B_) with A_ = sqrt(a^2+R^2)+a,
+// B_ = sqrt(s^2+R^2)+s; without a cut f = 1/A_; for the singular uncut case
+// f = 1/R = rsq(R^2).  Offsets from the centre use the exact hi/lo split
+// (see the FP32 table); hardware sqrt/rcp/rsq (1 ulp) are accounted for in
+// the error bound.
+template <int KIND, int NPL>
+__device__ __forceinline__ void field32_pot(const float* __restrict__ c, float fj, const float* fi, float* sx,
+                                            float* sy)
+{
+    const float cxh = c[T32_CXH], cxl = c[T32_CXL], cyh = c[T32_CYH], cyl = c[T32_CYL];
+    const float A = c[T32_A], B = c[T32_B], C = c[T32_C];
+    const float a2 = c[T32_A2], s2a2 = c[T32_S2A2], ra = c[T32_RA], rs = c[T32_RS], K = c[T32_K];
+    const float nyv = (fj - cyh) - cyl;
+    const float bny = B * nyv, cny = C * nyv;
+#pragma unroll
+    for (int k = 0; k < NPL; k++) {
+        const float nxv = (fi[k] - cxh) - cxl;
+        const float m1 = fmaf(A, nxv, bny);
+        const float m2 = fmaf(B, nxv, cny);
+        const float qa2 = fmaf(nxv, m1, fmaf(nyv, m2, a2));  // a^2 + R^2 (node units^2 * h^2)
+        float f;
+        if constexpr (KIND == 0) {          // cored, cut
+            const float qa = __builtin_amdgcn_sqrtf(qa2) + ra;
+            const float qs = __builtin_amdgcn_sqrtf(qa2 + s2a2) + rs;
+            f = (qs - qa) * __builtin_amdgcn_rcpf(qa * qs);
+        } else if constexpr (KIND == 1) {   // cored, uncut
+            f = __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(qa2) + ra);
+        } else if constexpr (KIND == 2) {   // singular, cut
+            const float R2 = fmaxf(qa2, 0.0f);
+            const float qa = __builtin_amdgcn_sqrtf(R2);
+            const float qs = __builtin_amdgcn_sqrtf(R2 + s2a2) + rs;
+            f = R2 > 0.0f ? (qs - qa) * __builtin_amdgcn_rcpf(qa * qs) : 0.0f;
+        } else {                            // singular isothermal ellipsoid
+            const float R2 = fmaxf(qa2, 0.0f);
+            f = R2 > 0.0f ? __builtin_amdgcn_rsqf(R2) : 0.0f;
+        }
+        const float kf = K * f;
+        sx[k] = fmaf(kf, m1, sx[k]);
+        sy[k] = fmaf(kf, m2, sy[k]);
+    }
+}
+
+// Each thread owns NPL consecutive nodes of one grid row; a workgroup of 256
+// threads covers 256*NPL nodes of that row, so the row offset is uniform and
+// every per-potential constant is a wave-uniform (scalar) operand.
+template <int NPL>
+__global__ __launch_bounds__(256) void k_field32(const float* __restrict__ tab32, int np, int nx, int ny,
+                                                 float* __restrict__ ax, float* __restrict__ ay,
+                                                 const EvalState* __restrict__ st)
+{
+    const int j = blockIdx.y;
+    const int i0 = (blockIdx.x * 256 + threadIdx.x) * NPL;
+    if (i0 >= nx) return;
+    const float fj = (float)j;
+    float fi[NPL], sx[NPL], sy[NPL];
+#pragma unroll
+    for (int k = 0; k < NPL; k++) {
+        fi[k] = (float)(i0 + k);
+        sx[k] = 0.0f;
+        sy[k] = 0.0f;
+    }
+    for (int p = 0; p < np; p++) {
+        const float* c = tab32 + (size_t)p * T32_STRIDE;
+        const int kind = (int)c[T32_KIND];
+        if (kind == 0) field32_pot<0, NPL>(c, fj, fi, sx, sy);
+        else if (kind == 1) field32_pot<1, NPL>(c, fj, fi, sx, sy);
+        else if (kind == 2) field32_pot<2, NPL>(c, fj, fi, sx, sy);
+        else field32_pot<3, NPL>(c, fj, fi, sx, sy);
+    }
+    const bool bad = st != nullptr && st->status != kStatusOk;
+    const size_t row = (size_t)j * nx;
+#pragma unroll
+    for (int k = 0; k < NPL; k++) {
+        if (i0 + k < nx) {
+            ax[row + i0 + k] = bad ? __builtin_nanf("") : sx[k];
+            ay[row + i0 + k] = bad ? __builtin_nanf("") : sy[k];
+        }
+    }
+}
+
+// FP64 field: one node per thread, the same matrix form in arcsec.
+__global__ __launch_bounds__(256) void k_field64(const double* __restrict__ tab64, int np, GridDesc g,
+                                                 double* __restrict__ ax, double* __restrict__ ay,
+                                                 const EvalState* __restrict__ st)
+{
+    const int j = blockIdx.y;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= g.nx) return;
+    const double t1 = g.x0 + i * g.h, t2 = g.y0 + j * g.h;
+    double s1 = 0.0, s2 = 0.0;
+    for (int p = 0; p < np; p++) add_alpha64(tab64 + (size_t)p * T64_STRIDE, t1, t2, s1, s2);
+    const bool bad = st != nullptr && st->status != kStatusOk;
+    const size_t n = (size_t)j * g.nx + i;
+    ax[n] = bad ? __builtin_nan("") : s1;
+    ay[n] = bad ? __builtin_nan("") : s2;
+}
+
+// ============================================================== triangle stage
+
+constexpr int TX = kTileX, TY = kTileY;  // cells per tile
+constexpr int TNX = TX + 1, TNY = TY + 1; // nodes per tile (one-node halo)
+
+enum : int { kMiss = 0, kHit = 1, kFlag = 2 };
+
+// Appends `key` for every lane with `pred` set: one atomic per wave, slots
+// from the ballot prefix count.  Must be called by all 64 lanes together.
+__device__ __forceinline__ void wave_append(bool pred, unsigned long long key, unsigned long long* counter,
+                                            unsigned long long* list, long long cap)
+{
+    const unsigned long long m = __ballot(pred);
+    if (m == 0) return;
+    const int leader = __ffsll((long long)m) - 1;
+    const int cnt = __popcll(m);
+    long long base = 0;
+    if (lane_id() == leader) base = (long long)atomicAdd(counter, (unsigned long long)cnt);
+    base = __shfl(base, leader, 64);
+    const int off = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+    if (pred && base + off < cap) list[base + off] = key;
+}
+
+__device__ __forceinline__ unsigned long long hit_key(int s, int tid)
+{
+    return ((unsigned long long)(unsigned)s << 32) | (unsigned)tid;
+}
+
+// FP32 containment decision with a certified sign (mixed path).  d* are the
+// vertex offsets B_k - barycentre; each component is within E of the exact
+// FP64 value.  Returns kMiss / kHit when certain, kFlag otherwise.
+__device__ __forceinline__ int decide32(const float* dx, const float* dy, float E, int mode, float tau,
+                                        unsigned& nbbox)
+{
+    const float xmin = fminf(dx[0], fminf(dx[1], dx[2])), xmax = fmaxf(dx[0], fmaxf(dx[1], dx[2]));
+    const float ymin = fminf(dy[0], fminf(dy[1], dy[2])), ymax = fmaxf(dy[0], fmaxf(dy[1], dy[2]));
+    if (mode == 1) {  // literal threshold
+        if (xmin > 0.0f || xmax < 0.0f || ymin > 0.0f || ymax < 0.0f) return kMiss;
+        nbbox++;
+        int pos = 0, neg = 0;
+        bool small = false;
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            const int k1 = k == 2 ? 0 : k + 1;
+            const float c = fmaf(dx[k], dy[k1], -(dy[k] * dx[k1]));
+            small = small || fabsf(c) < tau;
+            pos += c > 0.0f;
+            neg += c < 0.0f;
+        }
+        if (small) return kFlag;
+        return (pos == 3 || neg == 3) ? kHit : kMiss;
+    }
+    if (xmin > E || xmax < -E || ymin > E || ymax < -E) return kMiss;
+    nbbox++;
+    int pos = 0, neg = 0;
+    const float e2 = 2.0f * E * E;
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        const int k1 = k == 2 ? 0 : k + 1;
+        const float p = dy[k] * dx[k1];
+        const float q = dx[k] * dy[k1];
+        const float c = fmaf(dx[k], dy[k1], -p);
+        const float s1 = fabsf(dx[k]) + fabsf(dy[k]) + fabsf(dx[k1]) + fabsf(dy[k1]);
+        // |c_exact - c| <= E s1 + 2E^2 + 2u (|q| + |p|), evaluated with margin
+        const float T = (E * s1 + e2 + 1.2e-7f * (fabsf(q) + fabsf(p))) * 1.001f;
+        pos += c > T;
+        neg += c < -T;
+    }
+    if (pos > 0 && neg > 0) return kMiss;
+    if (pos == 3 || neg == 3) return kHit;
+    return kFlag;
+}
+
+// Block-wide min/max of a tile's deflection, result broadcast through LDS.
+__device__ __forceinline__ void tile_range(float& vmin, float& vmax, float* red /* [2*4] */)
+{
+    vmin = wave_min(vmin);
+    vmax = wave_max(vmax);
+    const int w = threadIdx.x >> 6;
+    if (lane_id() == 0) {
+        red[2 * w] = vmin;
+        red[2 * w + 1] = vmax;
+    }
+    __syncthreads();
+    vmin = fminf(fminf(red[0], red[2]), fminf(red[4], red[6]));
+    vmax = fmaxf(fmaxf(red[1], red[3]), fmaxf(red[5], red[7]));
+    __syncthreads();
+}
+
+__device__ __forceinline__ void tile_range64(double& vmin, double& vmax, double* red)
+{
+    for (int m = 32; m >= 1; m >>= 1) {
+        vmin = fmin(vmin, __shfl_xor(vmin, m, 64));
+        vmax = fmax(vmax, __shfl_xor(vmax, m, 64));
+    }
+    const int w = threadIdx.x >> 6;
+    if (lane_id() == 0) {
+        red[2 * w] = vmin;
+        red[2 * w + 1] = vmax;
+    }
+    __syncthreads();
+    vmin = fmin(fmin(red[0], red[2]), fmin(red[4], red[6]));
+    vmax = fmax(fmax(red[1], red[3]), fmax(red[5], red[7]));
+    __syncthreads();
+}
+
+// Mixed path, one workgroup (4 waves) per tile of TX x TY cells.  The tile's
+// FP32 deflections (with a one-node halo) are staged in LDS; the box
+//   [theta_min - r alpha_max, theta_max - r alpha_min] (per axis, widened by E_B)
+// contains every source-plane vertex of the tile, so a system whose barycentre
+// lies outside it is skipped for the whole tile.  Systems are tested 64 at a
+// time, one per lane, and the survivors enumerated from the ballot mask.
+__global__ __launch_bounds__(256) void k_tri32(const float* __restrict__ ax, const float* __restrict__ ay,
+                                               GridDesc g, int nsys, const double* __restrict__ sysrow,
+                                               EvalState* __restrict__ st, int mode, float tau,
+                                               unsigned long long* __restrict__ hit_keys, long long hit_cap,
+                                               unsigned long long* __restrict__ flag_keys, long long flag_cap)
+{
+    __shared__ float sx[TNY][TNX], sy[TNY][TNX];
+    __shared__ float red[8];
+    const int ci0 = blockIdx.x * TX, cj0 = blockIdx.y * TY;
+    const int ncx = min(TX, g.nx - 1 - ci0), ncy = min(TY, g.ny - 1 - cj0);
+    float xmn = INFINITY, xmx = -INFINITY, ymn = INFINITY, ymx = -INFINITY;
+    for (int q = threadIdx.x; q < TNX * TNY; q += 256) {
+        const int li = q % TNX, lj = q / TNX;
+        float vx = 0.0f, vy = 0.0f;
+        if (li <= ncx && lj <= ncy) {
+            const size_t n = (size_t)(cj0 + lj) * g.nx + (ci0 + li);
+            vx = ax[n];
+            vy = ay[n];
+            xmn = fminf(xmn, vx);
+            xmx = fmaxf(xmx, vx);
+            ymn = fminf(ymn, vy);
+            ymx = fmaxf(ymx, vy);
+        }
+        sx[lj][li] = vx;
+        sy[lj][li] = vy;
+    }
+    __syncthreads();
+    tile_range(xmn, xmx, red);
+    tile_range(ymn, ymx, red);
+    const double tx0 = g.x0 + ci0 * g.h, tx1 = g.x0 + (ci0 + ncx) * g.h;
+    const double ty0 = g.y0 + cj0 * g.h, ty1 = g.y0 + (cj0 + ncy) * g.h;
+    const float h32 = (float)g.h;
+    const int lane = lane_id();
+    unsigned nbbox = 0;
+    for (int sbase = 0; sbase < nsys; sbase += 64) {
+        const int s = sbase + lane;
+        bool pass = false;
+        if (s < nsys) {
+            const double* row = sysrow + (size_t)s * SYS_STRIDE;
+            const double r = row[SYS_R], eb = row[SYS_EB], bx = row[SYS_BX], by = row[SYS_BY];
+            pass = bx >= tx0 - r * xmx - eb && bx <= tx1 - r * xmn + eb && by >= ty0 - r * ymx - eb &&
+                   by <= ty1 - r * ymn + eb;
+        }
+        unsigned long long m = __ballot(pass);
+        if (threadIdx.x == 0 && m) atomicAdd(&st->n_tile_pass, (unsigned long long)__popcll(m));
+        while (m) {
+            const int sb = __ffsll((long long)m) - 1;
+            m &= m - 1;
+            const int sys = sbase + sb;
+            const double* row = sysrow + (size_t)sys * SYS_STRIDE;
+            const float r = (float)row[SYS_R];
+            const float E = (float)row[SYS_EB];
+            const float bxh = (float)row[SYS_BXH], bxl = (float)row[SYS_BXL];
+            const float byh = (float)row[SYS_BYH], byl = (float)row[SYS_BYL];
+#pragma unroll
+            for (int it = 0; it < (TX * TY) / 256; it++) {
+                const int cidx = threadIdx.x + 256 * it;
+                const int li = cidx % TX, lj = cidx / TX;
+                const bool valid = li < ncx && lj < ncy;
+                const int gi = ci0 + li, gj = cj0 + lj;
+                // offsets theta - barycentre in node units (exact hi part), then arcsec
+                const float ex0 = (((float)gi - bxh) - bxl) * h32, ex1 = (((float)(gi + 1) - bxh) - bxl) * h32;
+                const float ey0 = (((float)gj - byh) - byl) * h32, ey1 = (((float)(gj + 1) - byh) - byl) * h32;
+                const float d00x = fmaf(-r, sx[lj][li], ex0), d00y = fmaf(-r, sy[lj][li], ey0);
+                const float d10x = fmaf(-r, sx[lj][li + 1], ex1), d10y = fmaf(-r, sy[lj][li + 1], ey0);
+                const float d01x = fmaf(-r, sx[lj + 1][li], ex0), d01y = fmaf(-r, sy[lj + 1][li], ey1);
+                const float d11x = fmaf(-r, sx[lj + 1][li + 1], ex1), d11y = fmaf(-r, sy[lj + 1][li + 1], ey1);
+                int res0 = kMiss, res1 = kMiss;
+                if (valid) {
+                    const float tx[3] = {d00x, d10x, d01x}, ty[3] = {d00y, d10y, d01y};
+                    const float ux[3] = {d11x, d01x, d10x}, uy[3] = {d11y, d01y, d10y};
+                    res0 = decide32(tx, ty, E, mode, tau, nbbox);
+                    res1 = decide32(ux, uy, E, mode, tau, nbbox);
+                }
+                const int tid0 = 2 * (gj * (g.nx - 1) + gi);
+                wave_append(res0 == kHit, hit_key(sys, tid0), &st->n_hits, hit_keys, hit_cap);
+                wave_append(res1 == kHit, hit_key(sys, tid0 + 1), &st->n_hits, hit_keys, hit_cap);
+                wave_append(res0 == kFlag, hit_key(sys, tid0), &st->n_flags, flag_keys, flag_cap);
+                wave_append(res1 == kFlag, hit_key(sys, tid0 + 1), &st->n_flags, flag_keys, flag_cap);
+            }
+        }
+    }
+    unsigned long long nb = nbbox;
+    for (int m = 32; m >= 1; m >>= 1) nb += __shfl_xor(nb, m, 64);
+    if (lane == 0 && nb) atomicAdd(&st->n_bbox_pass, nb);
+}
+
+// FP64 path: same tiling, FP64 deflections in LDS, every surviving triangle
+// decided exactly (exact bounding box, then exact orientation signs).
+__global__ __launch_bounds__(256) void k_tri64(const double* __restrict__ ax, const double* __restrict__ ay,
+                                               GridDesc g, int nsys, const double* __restrict__ sysrow,
+                                               EvalState* __restrict__ st,
+                                               unsigned long long* __restrict__ hit_keys, long long hit_cap)
+{
+    __shared__ double sx[TNY][TNX], sy[TNY][TNX];
+    __shared__ double red[8];
+    const int ci0 = blockIdx.x * TX, cj0 = blockIdx.y * TY;
+    const int ncx = min(TX, g.nx - 1 - ci0), ncy = min(TY, g.ny - 1 - cj0);
+    double xmn = INFINITY, xmx = -INFINITY, ymn = INFINITY, ymx = -INFINITY;
+    for (int q = threadIdx.x; q < TNX * TNY; q += 256) {
+        const int li = q % TNX, lj = q / TNX;
+        double vx = 0.0, vy = 0.0;
+        if (li <= ncx && lj <= ncy) {
+            const size_t n = (size_t)(cj0 + lj) * g.nx + (ci0 + li);
+            vx = ax[n];
+            vy = ay[n];
+            xmn = fmin(xmn, vx);
+            xmx = fmax(xmx, vx);
+            ymn = fmin(ymn, vy);
+            ymx = fmax(ymx, vy);
+        }
+        sx[lj][li] = vx;
+        sy[lj][li] = vy;
+    }
+    __syncthreads();
+    tile_range64(xmn, xmx, red);
+    tile_range64(ymn, ymx, red);
+    const double tx0 = g.x0 + ci0 * g.h, tx1 = g.x0 + (ci0 + ncx) * g.h;
+    const double ty0 = g.y0 + cj0 * g.h, ty1 = g.y0 + (cj0 + ncy) * g.h;
+    const int lane = lane_id();
+    unsigned nbbox = 0;
+    for (int sbase = 0; sbase < nsys; sbase += 64) {
+        const int s = sbase + lane;
+        bool pass = false;
+        if (s < nsys) {
+            const double* row = sysrow + (size_t)s * SYS_STRIDE;
+            const double r = row[SYS_R], bx = row[SYS_BX], by = row[SYS_BY];
+            const double eb = 1e-9;  // FP64 rounding of the box, far below this margin
+            pass = bx >= tx0 - r * xmx - eb && bx <= tx1 - r * xmn + eb && by >= ty0 - r * ymx - eb &&
+                   by <= ty1 - r * ymn + eb;
+        }
+        unsigned long long m = __ballot(pass);
+        if (threadIdx.x == 0 && m) atomicAdd(&st->n_tile_pass, (unsigned long long)__popcll(m));
+        while (m) {
+            const int sb = __ffsll((long long)m) - 1;
+            m &= m - 1;
+            const int sys = sbase + sb;
+            const double* row = sysrow + (size_t)sys * SYS_STRIDE;
+            const double r = row[SYS_R], bx = row[SYS_BX], by = row[SYS_BY];
+#pragma unroll 1
+            for (int it = 0; it < (TX * TY) / 256; it++) {
+                const int cidx = threadIdx.x + 256 * it;
+                const int li = cidx % TX, lj = cidx / TX;
+                const bool valid = li < ncx && lj < ncy;
+                const int gi = ci0 + li, gj = cj0 + lj;
+                bool h0 = false, h1 = false;
+                if (valid) {
+                    const double t0x = g.x0 + gi * g.h, t1x = g.x0 + (gi + 1) * g.h;
+                    const double t0y = g.y0 + gj * g.h, t1y = g.y0 + (gj + 1) * g.h;
+                    const double b00x = t0x - r * sx[lj][li], b00y = t0y - r * sy[lj][li];
+                    const double b10x = t1x - r * sx[lj][li + 1], b10y = t0y - r * sy[lj][li + 1];
+                    const double b01x = t0x - r * sx[lj + 1][li], b01y = t1y - r * sy[lj + 1][li];
+                    const double b11x = t1x - r * sx[lj + 1][li + 1], b11y = t1y - r * sy[lj + 1][li + 1];
+                    const double vx0[3] = {b00x, b10x, b01x}, vy0[3] = {b00y, b10y, b01y};
+                    const double vx1[3] = {b11x, b01x, b10x}, vy1[3] = {b11y, b01y, b10y};
+                    const double lo0 = fmin(vx0[0], fmin(vx0[1], vx0[2])), hi0 = fmax(vx0[0], fmax(vx0[1], vx0[2]));
+                    const double lo1 = fmin(vy0[0], fmin(vy0[1], vy0[2])), hi1 = fmax(vy0[0], fmax(vy0[1], vy0[2]));
+                    if (!(bx < lo0 || bx > hi0 || by < lo1 || by > hi1)) {
+                        nbbox++;
+                        h0 = contains_exact(vx0, vy0, bx, by);
+                    }
+                    const double lo2 = fmin(vx1[0], fmin(vx1[1], vx1[2])), hi2 = fmax(vx1[0], fmax(vx1[1], vx1[2]));
+                    const double lo3 = fmin(vy1[0], fmin(vy1[1], vy1[2])), hi3 = fmax(vy1[0], fmax(vy1[1], vy1[2]));
+                    if (!(bx < lo2 || bx > hi2 || by < lo3 || by > hi3)) {
+                        nbbox++;
+                        h1 = contains_exact(vx1, vy1, bx, by);
+                    }
+                }
+                const int tid0 = 2 * (gj * (g.nx - 1) + gi);
+                wave_append(h0, hit_key(sys, tid0), &st->n_hits, hit_keys, hit_cap);
+                wave_append(h1, hit_key(sys, tid0 + 1), &st->n_hits, hit_keys, hit_cap);
+            }
+        }
+    }
+    unsigned long long nb = nbbox;
+    for (int m = 32; m >= 1; m >>= 1) nb += __shfl_xor(nb, m, 64);
+    if (lane == 0 && nb) atomicAdd(&st->n_bbox_pass, nb);
+}
+
+// ============================================================== FP64 fallback
+
+// FP64 vertex offsets B_k - barycentre of triangle `tid` for system row `row`:
+// grad Psi at the three vertices with the potentials spread over the wave.
+__device__ __forceinline__ void vertices64(const double* __restrict__ tab64, int np, GridDesc g, int tid,
+                                           double r, double* vx, double* vy, double* tx, double* ty)
+{
+    int ni[3], nj[3];
+    triangle_nodes(g.nx, tid, ni, nj);
+    double s[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int v = 0; v < 3; v++) {
+        tx[v] = g.x0 + ni[v] * g.h;
+        ty[v] = g.y0 + nj[v] * g.h;
+    }
+    for (int p = lane_id(); p < np; p += 64) {
+        const double* t = tab64 + (size_t)p * T64_STRIDE;
+#pragma unroll
+        for (int v = 0; v < 3; v++) add_alpha64(t, tx[v], ty[v], s[2 * v], s[2 * v + 1]);
+    }
+#pragma unroll
+    for (int v = 0; v < 3; v++) {
+        vx[v] = tx[v] - r * wave_sum(s[2 * v]);
+        vy[v] = ty[v] - r * wave_sum(s[2 * v + 1]);
+    }
+}
+
+// Persistent waves over the undecided tests of the mixed path.
+__global__ __launch_bounds__(256) void k_fb(const double* __restrict__ tab64, int np, GridDesc g,
+                                            const double* __restrict__ sysrow, EvalState* __restrict__ st,
+                                            const unsigned long long* __restrict__ flag_keys, long long flag_cap,
+                                            unsigned long long* __restrict__ hit_keys, long long hit_cap)
+{
+    const long long nwaves = (long long)gridDim.x * (blockDim.x >> 6);
+    const long long w0 = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const long long nf = (long long)min((unsigned long long)flag_cap, st->n_flags);
+    for (long long q = w0; q < nf; q += nwaves) {
+        const unsigned long long key = flag_keys[q];
+        const int sys = (int)(key >> 32), tid = (int)(key & 0xffffffffu);
+        const double* row = sysrow + (size_t)sys * SYS_STRIDE;
+        double vx[3], vy[3], tx[3], ty[3];
+        vertices64(tab64, np, g, tid, row[SYS_R], vx, vy, tx, ty);
+        if (lane_id() == 0 && contains_exact(vx, vy, row[SYS_BX], row[SYS_BY])) {
+            const unsigned long long slot = atomicAdd(&st->n_hits, 1ull);
+            if ((long long)slot < hit_cap) hit_keys[slot] = key;
+            atomicAdd(&st->n_fb_hits, 1ull);
+        }
+    }
+}
+
+// ============================================================== sort
+
+constexpr int kSortCap = (int)kHitScratch;
+
+// One workgroup of 1024 threads: bitonic sort of the hit keys (system in the
+// high word, triangle id in the low word) in LDS, then the sorted pairs and
+// the per-system counts.  Sets the capacity status if the hits (or the
+// undecided tests of the mixed path) overflowed their buffers.
+__global__ __launch_bounds__(1024) void k_sort(unsigned long long* __restrict__ hit_keys,
+                                               EvalState* __restrict__ st, long long flag_cap,
+                                               int hit_capacity, int nsys, int* __restrict__ out_hits,
+                                               int* __restrict__ n_pred)
+{
+    __shared__ unsigned long long key[kSortCap];
+    const int t = threadIdx.x;
+    const unsigned long long nh = st->n_hits;
+    const bool over = nh > (unsigned long long)hit_capacity || nh > (unsigned long long)kSortCap ||
+                      st->n_flags > (unsigned long long)flag_cap;
+    for (int s = t; s < nsys; s += 1024) n_pred[s] = 0;
+    if (over || st->status != kStatusOk) {
+        if (t == 0 && over && st->status == kStatusOk) st->status = kStatusCapacity;
+        return;
+    }
+    const int n = (int)nh;
+    int npad = 1;
+    while (npad < n) npad <<= 1;
+    for (int q = t; q < npad; q += 1024) key[q] = q < n ? hit_keys[q] : ~0ull;
+    __syncthreads();
+    for (int size = 2; size <= npad; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int q = t; q < npad / 2; q += 1024) {
+                const int lo = 2 * q - (q & (stride - 1));
+                const int hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const unsigned long long a = key[lo], b = key[hi];
+                if ((a > b) == up) {
+                    key[lo] = b;
+                    key[hi] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int q = t; q < n; q += 1024) {
+        const unsigned long long k = key[q];
+        hit_keys[q] = k;
+        out_hits[2 * q + 0] = (int)(k >> 32);
+        out_hits[2 * q + 1] = (int)(k & 0xffffffffu);
+    }
+    __syncthreads();
+    for (int q = t; q < n; q += 1024) atomicAdd(&n_pred[(int)(key[q] >> 32)], 1);
+}
+
+// ============================================================== positions
+
+// Persistent waves over the sorted hits: barycentric interpolation of the
+// image-plane vertices with weights from the FP64 source-plane triangle,
+// lambda_k = c_{k+1} / (c_0 + c_1 + c_2), c_k = (B_k - p) x (B_{k+1} - p).
+__global__ __launch_bounds__(256) void k_pos(const double* __restrict__ tab64, int np, GridDesc g,
+                                             const double* __restrict__ sysrow, const EvalState* __restrict__ st,
+                                             int hit_capacity, const unsigned long long* __restrict__ hit_keys,
+                                             double* __restrict__ img_xy)
+{
+    if (st->status != kStatusOk) return;
+    const long long nwaves = (long long)gridDim.x * (blockDim.x >> 6);
+    const long long w0 = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const long long nh = (long long)min(st->n_hits, (unsigned long long)hit_capacity);
+    for (long long q = w0; q < nh; q += nwaves) {
+        const unsigned long long key = hit_keys[q];
+        const int sys = (int)(key >> 32), tid = (int)(key & 0xffffffffu);
+        const double* row = sysrow + (size_t)sys * SYS_STRIDE;
+        double vx[3], vy[3], tx[3], ty[3];
+        vertices64(tab64, np, g, tid, row[SYS_R], vx, vy, tx, ty);
+        if (lane_id() == 0) {
+            const double px = row[SYS_BX], py = row[SYS_BY];
+            double c[3];
+            for (int v = 0; v < 3; v++) {
+                const int w = v == 2 ? 0 : v + 1;
+                c[v] = (vx[v] - px) * (vy[w] - py) - (vy[v] - py) * (vx[w] - px);
+            }
+            const double sum = c[0] + c[1] + c[2];
+            const double l0 = c[1] / sum, l1 = c[2] / sum, l2 = c[0] / sum;
+            img_xy[2 * q + 0] = l0 * tx[0] + l1 * tx[1] + l2 * tx[2];
+            img_xy[2 * q + 1] = l0 * ty[0] + l1 * ty[1] + l2 * ty[2];
+        }
+    }
+}
+
+// ============================================================== chi^2
+
+__device__ __forceinline__ int lower_bound_key(const unsigned long long* k, int n, unsigned long long v)
+{
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (k[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// One workgroup of 1024 threads.  Each observed image is paired with the
+// nearest predicted image of its system (ties to the lower triangle id); then
+// chi2_i = sum_j |x_obs - x|^2 / sigma^2 in image order, +inf without any
+// predicted image, and chi^2 = sum_i chi2_i in system order (Sec. 2.2.1).
+__global__ __launch_bounds__(1024) void k_chi2(ObsPtrs obs, const EvalState* __restrict__ st, int hit_capacity,
+                                               const unsigned long long* __restrict__ hit_keys,
+                                               const double* __restrict__ img_xy, double* __restrict__ contrib,
+                                               double* __restrict__ chi2, double* __restrict__ chi2_sys,
+                                               int* __restrict__ match, long long* __restrict__ stats,
+                                               long long n_tests)
+{
+    const int t = threadIdx.x;
+    const bool ok = st->status == kStatusOk;
+    const int nh = ok ? (int)st->n_hits : 0;
+    if (t == 0) {
+        stats[0] = (long long)st->n_hits;
+        stats[1] = (long long)st->n_flags;
+        stats[2] = (long long)st->n_tile_pass;
+        stats[3] = (long long)st->n_bbox_pass;
+        stats[4] = st->status;
+        stats[5] = (long long)st->n_fb_hits;
+        stats[6] = n_tests;
+        stats[7] = 0;
+    }
+    if (!ok) {
+        for (int s = t; s < obs.n_sys; s += 1024) chi2_sys[s] = __builtin_nan("");
+        for (int j = t; j < obs.n_img; j += 1024)
+            if (match) match[j] = -1;
+        if (t == 0) chi2[0] = __builtin_nan("");
+        return;
+    }
+    for (int j = t; j < obs.n_img; j += 1024) {
+        const int s = system_of(obs.sys_off, obs.n_sys, j);
+        const int q0 = lower_bound_key(hit_keys, nh, (unsigned long long)(unsigned)s << 32);
+        const int q1 = lower_bound_key(hit_keys, nh, (unsigned long long)(unsigned)(s + 1) << 32);
+        int best = -1;
+        double bd = 0.0;
+        for (int q = q0; q < q1; q++) {
+            const double dx = obs.x[j] - img_xy[2 * q], dy = obs.y[j] - img_xy[2 * q + 1];
+            const double d2 = dx * dx + dy * dy;
+            if (best < 0 || d2 < bd) {
+                best = q;
+                bd = d2;
+            }
+        }
+        if (match) match[j] = best;
+        contrib[j] = best >= 0 ? bd / (obs.sigma[j] * obs.sigma[j]) : 0.0;
+    }
+    __syncthreads();
+    for (int s = t; s < obs.n_sys; s += 1024) {
+        const int q0 = lower_bound_key(hit_keys, nh, (unsigned long long)(unsigned)s << 32);
+        const int q1 = lower_bound_key(hit_keys, nh, (unsigned long long)(unsigned)(s + 1) << 32);
+        double cs = 0.0;
+        for (int j = obs.sys_off[s]; j < obs.sys_off[s + 1]; j++) cs += contrib[j];
+        chi2_sys[s] = q1 > q0 ? cs : INFINITY;
+    }
+    __syncthreads();
+    if (t == 0) {
+        double tot = 0.0;
+        for (int s = 0; s < obs.n_sys; s++) tot += chi2_sys[s];
+        chi2[0] = tot;
+    }
+}
+
+// ============================================================== cosmology
+
+// D_LS / D_OS in a flat universe, one workgroup per source: composite Simpson
+// quadrature of 1/E(z) for the comoving distances to the lens and the source,
+// (chi_s - chi_l) / chi_s; fixed-order reduction.
+__device__ double comoving_block(double z, double om, double ol, double* red)
+{
+    const int n = 1 << 18;  // even number of panels
+    const double h = z / n;
+    double s = 0.0;
+    for (int k = threadIdx.x; k <= n; k += blockDim.x) {
+        const double a = 1.0 + k * h;
+        const double f = 1.0 / sqrt(om * a * a * a + ol);
+        const double wgt = (k == 0 || k == n) ? 1.0 : ((k & 1) ? 4.0 : 2.0);
+        s += wgt * f;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int m = blockDim.x >> 1; m >= 1; m >>= 1) {
+        if ((int)threadIdx.x < m) red[threadIdx.x] += red[threadIdx.x + m];
+        __syncthreads();
+    }
+    const double out = red[0] * h / 3.0;
+    __syncthreads();
+    return out;
+}
+
+__global__ __launch_bounds__(256) void k_dls(double zl, const double* __restrict__ zs, int n, double om, double ol,
+                                             double* __restrict__ out)
+{
+    __shared__ double red[256];
+    const int s = blockIdx.x;
+    if (s >= n) return;
+    const double z = zs[s];
+    const double cl = comoving_block(zl, om, ol, red);
+    const double cs = comoving_block(z, om, ol, red);
+    if (threadIdx.x == 0) out[s] = z > zl ? (cs - cl) / cs : 0.0;
+}
+
+// ============================================================== exports
+
+__global__ void k_export(const double* __restrict__ sysrow, int nsys, const EvalState* __restrict__ st,
+                         double* __restrict__ bar_x, double* __restrict__ bar_y, int* __restrict__ status)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s == 0 && status) *status = st->status;
+    if (s < nsys && bar_x) {
+        bar_x[s] = sysrow[(size_t)s * SYS_STRIDE + SYS_BX];
+        bar_y[s] = sysrow[(size_t)s * SYS_STRIDE + SYS_BY];
+    }
+}
+
+// ============================================================== launchers
+
+static inline unsigned cdiv(long long a, long long b) { return (unsigned)((a + b - 1) / b); }
+
+hipError_t launch_prep(const PotPtrs& pot, const GridDesc& g, double* tab64, float* tab32, double* bterm,
+                       hipStream_t s)
+{
+    if (pot.n > 0) k_prep<<<cdiv(pot.n, 256), 256, 0, s>>>(pot, g, tab64, tab32, bterm);
+    return hipGetLastError();
+}
+
+hipError_t launch_src(const double* tab64, int np, const ObsPtrs& obs, double* bx, double* by, hipStream_t s)
+{
+    if (obs.n_img > 0) k_src<<<cdiv((long long)obs.n_img * 64, 256), 256, 0, s>>>(tab64, np, obs, bx, by);
+    return hipGetLastError();
+}
+
+hipError_t launch_bound(const double* bterm, int np, const GridDesc& g, const ObsPtrs& obs, const double* bx,
+                        const double* by, double* sysrow, EvalState* st, hipStream_t s)
+{
+    k_bound<<<1, 1024, 0, s>>>(bterm, np, g, obs, bx, by, sysrow, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_field32(const float* tab32, int np, const GridDesc& g, float* ax, float* ay,
+                          const EvalState* st, int npl, hipStream_t s)
+{
+    switch (npl) {
+    case 1: k_field32<1><<<dim3(cdiv(g.nx, 256), g.ny), 256, 0, s>>>(tab32, np, g.nx, g.ny, ax, ay, st); break;
+    case 2: k_field32<2><<<dim3(cdiv(g.nx, 512), g.ny), 256, 0, s>>>(tab32, np, g.nx, g.ny, ax, ay, st); break;
+    case 4: k_field32<4><<<dim3(cdiv(g.nx, 1024), g.ny), 256, 0, s>>>(tab32, np, g.nx, g.ny, ax, ay, st); break;
+    default: k_field32<8><<<dim3(cdiv(g.nx, 2048), g.ny), 256, 0, s>>>(tab32, np, g.nx, g.ny, ax, ay, st); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_field64(const double* tab64, int np, const GridDesc& g, double* ax, double* ay,
+                          const EvalState* st, hipStream_t s)
+{
+    k_field64<<<dim3(cdiv(g.nx, 256), g.ny), 256, 0, s>>>(tab64, np, g, ax, ay, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_tri32(const float* ax, const float* ay, const GridDesc& g, int nsys, const double* sysrow,
+                        EvalState* st, int mode, float tau, unsigned long long* hit_keys, long long hit_cap,
+                        unsigned long long* flag_keys, long long flag_cap, hipStream_t s)
+{
+    k_tri32<<<dim3(cdiv(g.nx - 1, TX), cdiv(g.ny - 1, TY)), 256, 0, s>>>(ax, ay, g, nsys, sysrow, st, mode, tau,
+                                                                           hit_keys, hit_cap, flag_keys, flag_cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_tri64(const double* ax, const double* ay, const GridDesc& g, int nsys, const double* sysrow,
+                        EvalState* st, unsigned long long* hit_keys, long long hit_cap, hipStream_t s)
+{
+    k_tri64<<<dim3(cdiv(g.nx - 1, TX), cdiv(g.ny - 1, TY)), 256, 0, s>>>(ax, ay, g, nsys, sysrow, st, hit_keys,
+                                                                           hit_cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_fb(const double* tab64, int np, const GridDesc& g, const double* sysrow, EvalState* st,
+                     const unsigned long long* flag_keys, long long flag_cap, unsigned long long* hit_keys,
+                     long long hit_cap, hipStream_t s)
+{
+    k_fb<<<256, 256, 0, s>>>(tab64, np, g, sysrow, st, flag_keys, flag_cap, hit_keys, hit_cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_sort(unsigned long long* hit_keys, EvalState* st, long long flag_cap, int hit_capacity, int nsys,
+                       int* out_hits, int* n_pred, hipStream_t s)
+{
+    k_sort<<<1, 1024, 0, s>>>(hit_keys, st, flag_cap, hit_capacity, nsys, out_hits, n_pred);
+    return hipGetLastError();
+}
+
+hipError_t launch_pos(const double* tab64, int np, const GridDesc& g, const double* sysrow, const EvalState* st,
+                      int hit_capacity, const unsigned long long* hit_keys, double* img_xy, hipStream_t s)
+{
+    k_pos<<<128, 256, 0, s>>>(tab64, np, g, sysrow, st, hit_capacity, hit_keys, img_xy);
+    return hipGetLastError();
+}
+
+hipError_t launch_chi2(const ObsPtrs& obs, const EvalState* st, int hit_capacity,
+                       const unsigned long long* hit_keys, const double* img_xy, double* contrib, double* chi2,
+                       double* chi2_sys, int* match, long long* stats, long long n_tests, hipStream_t s)
+{
+    k_chi2<<<1, 1024, 0, s>>>(obs, st, hit_capacity, hit_keys, img_xy, contrib, chi2, chi2_sys, match, stats,
+                              n_tests);
+    return hipGetLastError();
+}
+
+hipError_t launch_dls(double zl, const double* zs, int n, double om, double ol, double* out, hipStream_t s)
+{
+    if (n > 0) k_dls<<<n, 256, 0, s>>>(zl, zs, n, om, ol, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_export(const double* sysrow, int nsys, const EvalState* st, double* bar_x, double* bar_y,
+                         int* status, hipStream_t s)
+{
+    k_export<<<cdiv(nsys > 0 ? nsys : 1, 256), 256, 0, s>>>(sysrow, nsys, st, bar_x, bar_y, status);
+    return hipGetLastError();
+}
+
+}  // namespace lens

@@ -1,0 +1,92 @@
+"""The C-ABI library loads and exports every entry point that include/lens.h
+declares, and rejects bad host-side arguments before touching the device.
+No GPU is needed: no call here reaches a kernel launch."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lens.h")
+LIB = os.path.join(ROOT, "paper_1902_03252_amd", "liblens.so")
+
+
+def declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lens_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("liblens.so is not built (python -m paper_1902_03252_amd.build)")
+    return C.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for n in ("lens_create", "lens_destroy", "lens_deflect", "lens_source_positions", "lens_image_chi2",
+              "lens_dls_dos", "lens_strerror"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (lens_[a-z0-9_]+)", out))
+    missing = [n for n in declared() if n not in exported]
+    assert not missing, missing
+    for n in declared():
+        getattr(lib, n)
+
+
+def test_python_binding_covers_the_boundary():
+    from paper_1902_03252_amd import _lib as L
+    assert set(L.EXPORTS) == set(declared())
+
+
+def test_strerror(lib):
+    lib.lens_strerror.restype = C.c_char_p
+    assert lib.lens_strerror(0) == b"ok"
+    assert b"invalid" in lib.lens_strerror(1)
+    assert b"capacity" in lib.lens_strerror(3)
+
+
+def test_host_validation_rejects_before_any_device_call(lib):
+    from paper_1902_03252_amd import _lib as L
+    L._lib = None
+    L.load(LIB)
+    lb = L._lib
+    ctx = C.c_void_p(1)  # never dereferenced: validation fails first
+    pot = L.LensPotentials(-1, None, None, None, None, None, None, None)
+    grid = L.LensGrid(0.0, 0.0, 1.0, 16, 16)
+    buf = C.c_void_p(8)
+    assert lb.lens_deflect(None, C.byref(pot), C.byref(grid), 0, buf, buf, None, None) == L.LENS_ERR_INVALID
+    assert lb.lens_deflect(ctx, C.byref(pot), C.byref(grid), 0, buf, buf, None, None) == L.LENS_ERR_INVALID
+    pot = L.LensPotentials(1, None, None, None, None, None, None, None)  # null parameter rows
+    assert lb.lens_deflect(ctx, C.byref(pot), C.byref(grid), 0, buf, buf, None, None) == L.LENS_ERR_INVALID
+    pot = L.LensPotentials(0, None, None, None, None, None, None, None)
+    for g in (L.LensGrid(0, 0, 1.0, 1, 16), L.LensGrid(0, 0, 0.0, 16, 16), L.LensGrid(0, 0, float("nan"), 16, 16),
+              L.LensGrid(float("inf"), 0, 1.0, 16, 16), L.LensGrid(0, 0, 1.0, 16, 70000)):
+        assert lb.lens_deflect(ctx, C.byref(pot), C.byref(g), 0, buf, buf, None, None) == L.LENS_ERR_INVALID
+    assert lb.lens_deflect(ctx, C.byref(pot), C.byref(grid), 7, buf, buf, None, None) == L.LENS_ERR_INVALID
+    obs = L.LensObs(0, 0, buf, buf, buf, buf, buf)  # no systems
+    opts = L.LensChi2Opts(2, 0, 0.0, 16)
+    out = L.LensChi2Out(buf, buf, buf, buf, buf, buf, buf)
+    assert lb.lens_image_chi2(ctx, C.byref(pot), C.byref(grid), C.byref(obs), C.byref(opts), C.byref(out),
+                              None) == L.LENS_ERR_INVALID
+    obs = L.LensObs(1, 2, buf, buf, buf, buf, buf)
+    for o in (L.LensChi2Opts(1, 0, 0.0, 16),          # FP32 is a field-only precision
+              L.LensChi2Opts(2, 0, 0.0, 0),           # no hit capacity
+              L.LensChi2Opts(2, 0, 0.0, 1 << 20),     # beyond the sortable hit list
+              L.LensChi2Opts(2, 1, -1.0, 16),         # negative literal threshold
+              L.LensChi2Opts(2, 5, 0.0, 16)):         # unknown fallback mode
+        assert lb.lens_image_chi2(ctx, C.byref(pot), C.byref(grid), C.byref(obs), C.byref(o), C.byref(out),
+                                  None) == L.LENS_ERR_INVALID
+    out_null = L.LensChi2Out(None, buf, buf, buf, buf, buf, buf)
+    assert lb.lens_image_chi2(ctx, C.byref(pot), C.byref(grid), C.byref(obs), C.byref(opts), C.byref(out_null),
+                              None) == L.LENS_ERR_INVALID
+    assert lb.lens_dls_dos(ctx, 0.3, buf, 1, 0.5, 0.7, buf, None) == L.LENS_ERR_INVALID  # not flat
+    assert lb.lens_create(None, 0) == L.LENS_ERR_INVALID
