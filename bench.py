@@ -1,0 +1,243 @@
+"""Throughput of the image-plane chi^2 on one MI355X.
+
+One step = one complete chi^2 evaluation (source positions, deflection field,
+triangle containment, FP64 fallback, image positions, matching, chi^2) of the
+cluster workload (1 cluster halo + 49 galaxy potentials, 1024^2 grid over
++-80", 20 multiple-image systems), inputs resident in HBM.  The mixed path is
+the headline; the FP64 path is measured beside it, and the 4096^2 /
+200-potential / 100-system workload is reported as an extra.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+
+Prints one JSON line.  The CPU baseline is the plain FP64 oracle on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "image-plane χ² evals/sec and grid triangles/s, mixed vs FP64, 1 MI355X"
+PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector peak
+PEAK_FP64_TFLOPS = 78.6    # MI355X FP64 vector peak
+FLOPS_PER_EVAL = 34        # algorithmic flops per pixel-potential evaluation (see DESIGN)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_field32_cluster.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1902_03252_amd", "csrc", f) for f in ("lens_kernels.hip", "lens_device.hpp")]
+
+
+def load_workload(config: int):
+    import synthlens as S
+    d = np.load(os.path.join(ROOT, "tests", "golden", f"config{config}_inputs.npz"))
+    x0, y0, h, nx, ny = d["grid"]
+    grid = S.Grid(float(x0), float(y0), float(h), int(nx), int(ny))
+    obs = dict(sys_off=d["sys_off"].astype(np.int32), x=d["x"], y=d["y"], sigma=d["sigma"], dls=d["dls"])
+    return d["params"], grid, obs
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_per_launch():
+    """HBM bytes per launch of the field kernel from the committed rocprofv3 PMC
+    summary, or None when it was taken on a different kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256_16") != kernel_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def time_steps(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def gpu_bench(args):
+    import torch
+    import paper_1902_03252_amd as lens
+
+    ctx = lens.context(0)
+    prm, grid, obs_np = load_workload(2)
+    p = torch.as_tensor(prm, dtype=torch.float64, device="cuda")
+    obs = lens.Obs.from_numpy(obs_np)
+    n_tri = grid.n_triangles
+    res = {}
+    for prec in ("mixed", "fp64"):
+        out = lens.chi2_buffers(obs, 4096, "cuda")
+        step = lambda: lens.lens_image_chi2(p, grid, obs, prec=prec, out=out, ctx=ctx)
+        # eager, with the field kernel bracketed by HIP events on the call's stream
+        ctx.set_timing(True)
+        ctx.field_timing(reset=True)
+        eager_s = time_steps(torch, step, args.steps, args.warmup)
+        kern_ms, launches = ctx.field_timing(reset=True)
+        ctx.set_timing(False)
+        eager = out.host()
+        # the same step captured once into a HIP graph and replayed
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            step()
+        torch.cuda.current_stream().wait_stream(s)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            step()
+        graph_s = time_steps(torch, g.replay, args.steps, args.warmup)
+        replay = out.host()
+        same = (replay["chi2"] == eager["chi2"] and np.array_equal(replay["hit_tid"], eager["hit_tid"])
+                and np.array_equal(replay["hit_x"], eager["hit_x"]))
+        res[prec] = dict(eager_s=eager_s, graph_s=graph_s, kern_ms=kern_ms / max(launches, 1),
+                         launches=launches, result=eager, graph_matches_eager=bool(same))
+        del g
+    # larger workload, for context
+    large = {}
+    prm3, grid3, obs3_np = load_workload(3)
+    p3 = torch.as_tensor(prm3, dtype=torch.float64, device="cuda")
+    obs3 = lens.Obs.from_numpy(obs3_np)
+    for prec in ("mixed", "fp64"):
+        out = lens.chi2_buffers(obs3, 4096, "cuda")
+        ctx.set_timing(True)
+        ctx.field_timing(reset=True)
+        dt = time_steps(torch, lambda: lens.lens_image_chi2(p3, grid3, obs3, prec=prec, out=out, ctx=ctx),
+                        max(args.steps // 20, 5), 2)
+        kms, nl = ctx.field_timing(reset=True)
+        ctx.set_timing(False)
+        st = out.host()["stats"]
+        evals = grid3.nx * grid3.ny * prm3.shape[1]
+        peak = PEAK_FP32_TFLOPS if prec == "mixed" else PEAK_FP64_TFLOPS
+        large[prec] = dict(chi2_evals_per_s=1.0 / dt, ms_per_eval=dt * 1e3,
+                           grid_triangles_per_s=grid3.n_triangles / dt,
+                           field_kernel_ms=kms / max(nl, 1),
+                           field_tflops=FLOPS_PER_EVAL * evals / (kms / max(nl, 1)) / 1e9,
+                           field_frac_of_peak=FLOPS_PER_EVAL * evals / (kms / max(nl, 1)) / 1e9 / peak,
+                           flagged_tests=int(st[1]), fallback_rate=float(st[1]) / float(st[6]),
+                           hits=int(st[0]))
+    large["speedup_mixed_vs_fp64"] = large["fp64"]["ms_per_eval"] / large["mixed"]["ms_per_eval"]
+    return prm, grid, obs_np, n_tri, res, large
+
+
+def cpu_baseline(prm, grid, obs_np, budget_s: float):
+    import oracle
+    threads = oracle.default_threads()
+    t0 = time.perf_counter()
+    n = 0
+    want = None
+    while True:
+        want = oracle.image_chi2(prm, grid, obs_np, nthreads=threads)
+        n += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return dict(value=n / dt, unit="chi2 evals/s", cores=threads, kind="oracle",
+                sample=f"{n} full chi^2 evaluations of the cluster workload (FP64, {threads} threads, {dt:.1f} s)"), want
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for the baseline")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy 256 MiB device-to-device 3 times (a known-size kernel that calibrates the "
+                         "rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (this path has no multi-GPU form); got --gpus {args.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    prm, grid, obs_np, n_tri, res, large = gpu_bench(args)
+    mixed, fp64 = res["mixed"], res["fp64"]
+    step_s = mixed["graph_s"]
+    evals = grid.nx * grid.ny * prm.shape[1]
+    flops = FLOPS_PER_EVAL * evals
+    kern_s = mixed["kern_ms"] / 1e3
+    achieved = flops / kern_s / 1e12
+    traffic = traffic_per_launch()
+
+    cpu, want = (None, None) if args.no_cpu else cpu_baseline(prm, grid, obs_np, args.cpu_budget)
+    parity = None
+    if want is not None:
+        got = mixed["result"]
+        parity = dict(hit_set_equal_to_oracle=bool(np.array_equal(got["hit_tid"], want["hit_tid"])
+                                                    and np.array_equal(got["hit_sys"], want["hit_sys"])),
+                      chi2_rel_err=abs(got["chi2"] - want["chi2"]) / abs(want["chi2"]),
+                      fp64_hit_set_equal_to_oracle=bool(np.array_equal(fp64["result"]["hit_tid"], want["hit_tid"])))
+
+    st = mixed["result"]["stats"]
+    line = {
+        "metric": METRIC,
+        "value": 1.0 / step_s,
+        "unit": "chi2 evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": step_s * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "cluster: 1 halo + 49 galaxy potentials, 1024^2 grid over +-80 arcsec, "
+                               "20 multiple-image systems",
+                   "grid": f"{grid.nx}x{grid.ny}", "potentials": int(prm.shape[1]), "systems": len(obs_np["dls"]),
+                   "precision": "mixed (FP32 bulk, FP64 fallback/positions/chi2)",
+                   "mode": "HIP graph replay of one evaluation"},
+        "grid_triangles_per_s": n_tri / step_s,
+        "eager_chi2_evals_per_s": 1.0 / mixed["eager_s"],
+        "fp64": {"chi2_evals_per_s": 1.0 / fp64["graph_s"], "eager_chi2_evals_per_s": 1.0 / fp64["eager_s"],
+                 "grid_triangles_per_s": n_tri / fp64["graph_s"], "field_kernel_ms": fp64["kern_ms"],
+                 "field_frac_of_fp64_peak": flops / (fp64["kern_ms"] / 1e3) / 1e12 / PEAK_FP64_TFLOPS},
+        "speedup_mixed_vs_fp64": fp64["graph_s"] / step_s,
+        "graph_replay_matches_eager": mixed["graph_matches_eager"] and fp64["graph_matches_eager"],
+        "fallback": {"flagged_tests": int(st[1]), "tests": int(st[6]), "rate": float(st[1]) / float(st[6]),
+                     "fallback_hits": int(st[5]), "hits": int(st[0])},
+        "roofline": {"bound": "alu", "kernel": "k_field32 (FP32 deflection field)",
+                     "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
+                     "flops_per_launch": flops, "avg_launch_ms": mixed["kern_ms"], "launches_timed": mixed["launches"]},
+        "large": large,
+        "cpu_baseline": cpu,
+        "parity": parity,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

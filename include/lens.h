@@ -165,6 +165,16 @@ int lens_image_chi2(lens_ctx *ctx, const lens_potentials *pot, const lens_grid *
                     const lens_obs *obs, const lens_chi2_opts *opts, lens_chi2_out *out,
                     hipStream_t stream);
 
+/* Kernel timing (instrumentation, for roofline measurement).  While enabled,
+ * every launch of the deflection-field kernel (the dominant kernel of
+ * lens_deflect and lens_image_chi2) is bracketed by HIP events recorded on
+ * the call's stream.  lens_field_timing waits for the recorded events and
+ * returns the summed kernel time in milliseconds and the number of launches
+ * since the last reset (reset != 0 clears the totals).  Do not enable while a
+ * stream is being captured into a graph. */
+int lens_set_timing(lens_ctx *ctx, int enable);
+int lens_field_timing(lens_ctx *ctx, double *total_ms, int64_t *launches, int reset);
+
 /* Human-readable name of a return code (static string). */
 const char *lens_strerror(int code);
 

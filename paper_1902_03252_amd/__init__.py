@@ -104,6 +104,17 @@ class Context:
     def stream(self):
         return L.stream_handle(self.device)
 
+    def set_timing(self, enable: bool):
+        """Bracket every deflection-field kernel launch with HIP events."""
+        L.check(self._lib.lens_set_timing(self._h, int(bool(enable))), "lens_set_timing")
+
+    def field_timing(self, reset: bool = True):
+        """(total kernel milliseconds, number of launches) since the last reset."""
+        ms, n = C.c_double(), C.c_int64()
+        L.check(self._lib.lens_field_timing(self._h, C.byref(ms), C.byref(n), int(bool(reset))),
+                "lens_field_timing")
+        return ms.value, n.value
+
 
 _contexts: dict[int, Context] = {}
 

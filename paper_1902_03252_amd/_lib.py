@@ -20,7 +20,7 @@ STAT_HITS, STAT_FLAGGED, STAT_TILE_PASS, STAT_BBOX_PASS, STAT_STATUS, STAT_FB_HI
 STAT_N = 8
 
 EXPORTS = ("lens_create", "lens_destroy", "lens_dls_dos", "lens_deflect", "lens_source_positions",
-           "lens_image_chi2", "lens_strerror")
+           "lens_image_chi2", "lens_set_timing", "lens_field_timing", "lens_strerror")
 
 
 class LensPotentials(C.Structure):
@@ -72,6 +72,10 @@ def load(path: str = LIB_PATH):
     lib.lens_image_chi2.argtypes = [vp, C.POINTER(LensPotentials), C.POINTER(LensGrid), C.POINTER(LensObs),
                                     C.POINTER(LensChi2Opts), C.POINTER(LensChi2Out), vp]
     lib.lens_image_chi2.restype = C.c_int
+    lib.lens_set_timing.argtypes = [vp, C.c_int]
+    lib.lens_set_timing.restype = C.c_int
+    lib.lens_field_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]
+    lib.lens_field_timing.restype = C.c_int
     lib.lens_strerror.argtypes = [C.c_int]
     lib.lens_strerror.restype = C.c_char_p
     _lib = lib

@@ -13,14 +13,24 @@ using namespace lens;
 
 namespace {
 
-enum Buf { B_TAB64, B_TAB32, B_BTERM, B_FIELD, B_BX, B_BY, B_SYS, B_STATE, B_HITS, B_FLAGS, B_CONTRIB, B_NBUF };
+enum Buf { B_TAB64, B_TAB32, B_BTERM, B_FIELD, B_BX, B_BY, B_SYS, B_STATE, B_HITS, B_FLAGS, B_POS, B_CONTRIB,
+           B_PART, B_NBUF };
 
 }  // namespace
+
+constexpr int kMaxPending = 1024;  // event pairs awaiting lens_field_timing
 
 struct lens_ctx {
     int device;
     void* buf[B_NBUF];
     size_t cap[B_NBUF];
+    // field-kernel timing
+    int timing;
+    int n_pending;
+    hipEvent_t ev_start[kMaxPending], ev_stop[kMaxPending];
+    int n_events;  // events created so far (pairs)
+    double total_ms;
+    long long launches;
 };
 
 namespace {
@@ -58,6 +68,7 @@ int ensure(lens_ctx* c, int which, size_t bytes)
     }
     void* p = nullptr;
     if (hipMalloc(&p, nb) != hipSuccess) return LENS_ERR_DEVICE;
+    if (which == B_STATE && hipMemset(p, 0, nb) != hipSuccess) return LENS_ERR_DEVICE;  // ticket starts at 0
     c->buf[which] = p;
     c->cap[which] = nb;
     return LENS_OK;
@@ -84,7 +95,8 @@ int check_grid(const lens_grid* g)
 
 int check_obs(const lens_obs* o)
 {
-    if (!o || o->n_sys < 1 || o->n_img < 0 || !o->sys_off || !o->dls_dos) return LENS_ERR_INVALID;
+    if (!o || o->n_sys < 1 || o->n_sys >= kMaxSystems || o->n_img < 0 || !o->sys_off || !o->dls_dos)
+        return LENS_ERR_INVALID;
     if (o->n_img > 0 && (!o->x || !o->y || !o->sigma)) return LENS_ERR_INVALID;
     return LENS_OK;
 }
@@ -150,7 +162,49 @@ int field_npl(const GridDesc& g)
     return 1;
 }
 
-// Runs prep (+ source positions) + bound: the common head of every entry point.
+// Folds every recorded (start, stop) pair into the totals.
+int fold_timing(lens_ctx* c)
+{
+    for (int k = 0; k < c->n_pending; k++) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(c->ev_stop[k]) != hipSuccess) return LENS_ERR_DEVICE;
+        if (hipEventElapsedTime(&ms, c->ev_start[k], c->ev_stop[k]) != hipSuccess) return LENS_ERR_DEVICE;
+        c->total_ms += ms;
+        c->launches++;
+    }
+    c->n_pending = 0;
+    return LENS_OK;
+}
+
+// Event pair for the next timed launch (nullptr if timing is off).
+int timing_begin(lens_ctx* c, hipStream_t s, int* slot)
+{
+    *slot = -1;
+    if (!c->timing) return LENS_OK;
+    if (c->n_pending == kMaxPending) {
+        int rc = fold_timing(c);
+        if (rc) return rc;
+    }
+    const int k = c->n_pending;
+    if (k >= c->n_events) {
+        if (hipEventCreate(&c->ev_start[k]) != hipSuccess || hipEventCreate(&c->ev_stop[k]) != hipSuccess)
+            return LENS_ERR_DEVICE;
+        c->n_events = k + 1;
+    }
+    if (hipEventRecord(c->ev_start[k], s) != hipSuccess) return LENS_ERR_DEVICE;
+    *slot = k;
+    return LENS_OK;
+}
+
+int timing_end(lens_ctx* c, hipStream_t s, int slot)
+{
+    if (slot < 0) return LENS_OK;
+    if (hipEventRecord(c->ev_stop[slot], s) != hipSuccess) return LENS_ERR_DEVICE;
+    c->n_pending = slot + 1;
+    return LENS_OK;
+}
+
+// Constants, source positions, barycentres and bound: the head of every entry point.
 int head(lens_ctx* c, const lens_potentials* pot, const GridDesc& g, const ObsPtrs& obs, double* bx, double* by,
          hipStream_t s)
 {
@@ -161,12 +215,9 @@ int head(lens_ctx* c, const lens_potentials* pot, const GridDesc& g, const ObsPt
         (rc = ensure(c, B_SYS, (size_t)(obs.n_sys > 0 ? obs.n_sys : 1) * SYS_STRIDE * 8)) ||
         (rc = ensure(c, B_STATE, sizeof(EvalState))))
         return rc;
-    double* tab64 = (double*)c->buf[B_TAB64];
-    if (launch_prep(pot_ptrs(pot), g, tab64, (float*)c->buf[B_TAB32], (double*)c->buf[B_BTERM], s) != hipSuccess)
-        return LENS_ERR_DEVICE;
-    if (obs.n_img > 0 && launch_src(tab64, np, obs, bx, by, s) != hipSuccess) return LENS_ERR_DEVICE;
-    if (launch_bound((double*)c->buf[B_BTERM], np, g, obs, bx, by, (double*)c->buf[B_SYS],
-                     (EvalState*)c->buf[B_STATE], s) != hipSuccess)
+    if (launch_head(pot_ptrs(pot), g, obs, (double*)c->buf[B_TAB64], (float*)c->buf[B_TAB32],
+                    (double*)c->buf[B_BTERM], bx, by, (double*)c->buf[B_SYS], (EvalState*)c->buf[B_STATE],
+                    s) != hipSuccess)
         return LENS_ERR_DEVICE;
     return LENS_OK;
 }
@@ -197,8 +248,34 @@ void lens_destroy(lens_ctx* ctx)
         (void)hipDeviceSynchronize();
         for (int k = 0; k < B_NBUF; k++)
             if (ctx->buf[k]) (void)hipFree(ctx->buf[k]);
+        for (int k = 0; k < ctx->n_events; k++) {
+            (void)hipEventDestroy(ctx->ev_start[k]);
+            (void)hipEventDestroy(ctx->ev_stop[k]);
+        }
     }
     free(ctx);
+}
+
+int lens_set_timing(lens_ctx* ctx, int enable)
+{
+    if (!ctx) return LENS_ERR_INVALID;
+    ctx->timing = enable != 0;
+    return LENS_OK;
+}
+
+int lens_field_timing(lens_ctx* ctx, double* total_ms, int64_t* launches, int reset)
+{
+    if (!ctx || !total_ms || !launches) return LENS_ERR_INVALID;
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return LENS_ERR_DEVICE;
+    const int rc = fold_timing(ctx);
+    *total_ms = ctx->total_ms;
+    *launches = ctx->launches;
+    if (reset) {
+        ctx->total_ms = 0.0;
+        ctx->launches = 0;
+    }
+    return rc;
 }
 
 const char* lens_strerror(int code)
@@ -234,6 +311,8 @@ int lens_deflect(lens_ctx* ctx, const lens_potentials* pot, const lens_grid* gri
     int rc = head(ctx, pot, g, no_obs(), nullptr, nullptr, stream);
     if (rc) return rc;
     const EvalState* st = (const EvalState*)ctx->buf[B_STATE];
+    int slot;
+    if ((rc = timing_begin(ctx, stream, &slot))) return rc;
     hipError_t e;
     if (prec == LENS_FP64)
         e = launch_field64((const double*)ctx->buf[B_TAB64], pot->n, g, (double*)ax, (double*)ay, st, stream);
@@ -241,6 +320,7 @@ int lens_deflect(lens_ctx* ctx, const lens_potentials* pot, const lens_grid* gri
         e = launch_field32((const float*)ctx->buf[B_TAB32], pot->n, g, (float*)ax, (float*)ay, st, field_npl(g),
                            stream);
     if (e != hipSuccess) return LENS_ERR_DEVICE;
+    if ((rc = timing_end(ctx, stream, slot))) return rc;
     if (status && launch_export(nullptr, 0, st, nullptr, nullptr, status, stream) != hipSuccess)
         return LENS_ERR_DEVICE;
     return LENS_OK;
@@ -287,40 +367,50 @@ int lens_image_chi2(lens_ctx* ctx, const lens_potentials* pot, const lens_grid* 
     const size_t nn = (size_t)g.nx * g.ny;
     int rc;
     if ((rc = ensure(ctx, B_FIELD, nn * 2 * (mixed ? 4 : 8))) || (rc = ensure(ctx, B_BX, (size_t)o.n_img * 8)) ||
-        (rc = ensure(ctx, B_BY, (size_t)o.n_img * 8)) || (rc = ensure(ctx, B_HITS, (size_t)kHitScratch * 8)) ||
+        (rc = ensure(ctx, B_BY, (size_t)o.n_img * 8)) || (rc = ensure(ctx, B_HITS, (size_t)kHitScratch * 2 * 8)) ||
         (rc = ensure(ctx, B_FLAGS, (size_t)(mixed ? kFlagScratch : 1) * 8)) ||
-        (rc = ensure(ctx, B_CONTRIB, (size_t)o.n_img * 8)))
+        (rc = ensure(ctx, B_POS, (size_t)kHitScratch * 4 * 8)) || (rc = ensure(ctx, B_CONTRIB, (size_t)o.n_img * 8)))
         return rc;
+    const long long n_parts = (long long)((g.nx - 2) / kTileX + 1) * ((g.ny - 2) / kTileY + 1);
+    if ((rc = ensure(ctx, B_PART, (size_t)n_parts * 2 * 4))) return rc;
+    unsigned* part = (unsigned*)ctx->buf[B_PART];
     if ((rc = head(ctx, pot, g, o, (double*)ctx->buf[B_BX], (double*)ctx->buf[B_BY], stream))) return rc;
 
     const double* tab64 = (const double*)ctx->buf[B_TAB64];
     const double* sysrow = (const double*)ctx->buf[B_SYS];
     EvalState* st = (EvalState*)ctx->buf[B_STATE];
     unsigned long long* hits = (unsigned long long*)ctx->buf[B_HITS];
+    unsigned long long* fb_hits = hits + kHitScratch;
     unsigned long long* flags = (unsigned long long*)ctx->buf[B_FLAGS];
+    double* pos = (double*)ctx->buf[B_POS];
+    double* fb_pos = pos + 2 * kHitScratch;
     const long long flag_cap = mixed ? kFlagScratch : 0;
+    int slot;
+    if ((rc = timing_begin(ctx, stream, &slot))) return rc;
     hipError_t e;
     if (mixed) {
         float* ax = (float*)ctx->buf[B_FIELD];
         float* ay = ax + nn;
         e = launch_field32((const float*)ctx->buf[B_TAB32], np, g, ax, ay, nullptr, field_npl(g), stream);
+        if (e == hipSuccess && (rc = timing_end(ctx, stream, slot))) return rc;
         if (e == hipSuccess)
             e = launch_tri32(ax, ay, g, o.n_sys, sysrow, st, opts->fb_mode, (float)(opts->fb_tau * g.h * g.h), hits,
-                             kHitScratch, flags, flag_cap, stream);
-        if (e == hipSuccess) e = launch_fb(tab64, np, g, sysrow, st, flags, flag_cap, hits, kHitScratch, stream);
+                             kHitScratch, flags, flag_cap, part, stream);
     } else {
         double* ax = (double*)ctx->buf[B_FIELD];
         double* ay = ax + nn;
         e = launch_field64(tab64, np, g, ax, ay, nullptr, stream);
-        if (e == hipSuccess) e = launch_tri64(ax, ay, g, o.n_sys, sysrow, st, hits, kHitScratch, stream);
+        if (e == hipSuccess && (rc = timing_end(ctx, stream, slot))) return rc;
+        if (e == hipSuccess) e = launch_tri64(ax, ay, g, o.n_sys, sysrow, st, hits, kHitScratch, part, stream);
     }
     if (e == hipSuccess)
-        e = launch_sort(hits, st, flag_cap, opts->hit_capacity, o.n_sys, out->hits, out->n_pred, stream);
-    if (e == hipSuccess) e = launch_pos(tab64, np, g, sysrow, st, opts->hit_capacity, hits, out->img_xy, stream);
+        e = launch_fbpos(tab64, np, g, sysrow, st, hits, kHitScratch, flags, flag_cap, fb_hits, kHitScratch, pos,
+                         fb_pos, stream);
     const long long n_tests = 2ll * (g.nx - 1) * (g.ny - 1) * o.n_sys;
     if (e == hipSuccess)
-        e = launch_chi2(o, st, opts->hit_capacity, hits, out->img_xy, (double*)ctx->buf[B_CONTRIB], out->chi2,
-                        out->chi2_sys, out->match, (long long*)out->stats, n_tests, stream);
+        e = launch_tail(o, st, kHitScratch, flag_cap, kHitScratch, opts->hit_capacity, hits, fb_hits, pos, fb_pos,
+                        out->hits, out->img_xy, out->n_pred, (double*)ctx->buf[B_CONTRIB], out->chi2, out->chi2_sys,
+                        out->match, (long long*)out->stats, n_tests, part, (int)n_parts, stream);
     return e == hipSuccess ? LENS_OK : LENS_ERR_DEVICE;
 }
 

@@ -55,7 +55,8 @@ enum : int {
     SYS_BX = 0, SYS_BY, SYS_BXH, SYS_BXL, SYS_BYH, SYS_BYL, SYS_R, SYS_EB, SYS_STRIDE = 8
 };
 
-// Device-side state of one evaluation (zeroed by the bound kernel).
+// Device-side state of one evaluation (zeroed by the head kernel; head_ticket is
+// zero between launches).
 struct EvalState {
     unsigned long long n_hits;       // hits appended (FP32-certain + fallback)
     unsigned long long n_flags;      // tests sent to the fallback
@@ -63,7 +64,7 @@ struct EvalState {
     unsigned long long n_bbox_pass;  // triangle tests surviving bbox rejection
     unsigned long long n_fb_hits;    // hits found by the fallback
     int status;                      // LENS_OK / LENS_ERR_INVALID / LENS_ERR_CAPACITY
-    int pad;
+    unsigned head_ticket;            // workgroups of the head kernel that finished
     double e_alpha;                  // bound on |alpha_fp32 - alpha| per component
     double w_sum;                    // sum of per-potential deflection bounds
 };

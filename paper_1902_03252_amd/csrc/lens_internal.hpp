@@ -25,34 +25,32 @@ struct ObsPtrs {
 
 struct EvalState;
 
-constexpr int kTileX = 64, kTileY = 16;  // cells per triangle-stage tile
-constexpr long long kHitScratch = 8192;   // largest hit list sorted in LDS
+constexpr int kTileX = 32, kTileY = 8;  // cells per triangle-stage tile
+constexpr long long kHitScratch = 8192;   // largest hit list sorted in LDS (2^13)
 constexpr long long kFlagScratch = 1 << 20;
+constexpr int kMaxSystems = 1 << 19;      // systems fit the packed sort key
 
-hipError_t launch_prep(const PotPtrs& pot, const GridDesc& g, double* tab64, float* tab32, double* bterm,
-                       hipStream_t s);
-hipError_t launch_src(const double* tab64, int np, const ObsPtrs& obs, double* bx, double* by, hipStream_t s);
-hipError_t launch_bound(const double* bterm, int np, const GridDesc& g, const ObsPtrs& obs, const double* bx,
-                        const double* by, double* sysrow, EvalState* st, hipStream_t s);
+hipError_t launch_head(const PotPtrs& pot, const GridDesc& g, const ObsPtrs& obs, double* tab64, float* tab32,
+                       double* bterm, double* bx, double* by, double* sysrow, EvalState* st, hipStream_t s);
 hipError_t launch_field32(const float* tab32, int np, const GridDesc& g, float* ax, float* ay,
                           const EvalState* st, int npl, hipStream_t s);
 hipError_t launch_field64(const double* tab64, int np, const GridDesc& g, double* ax, double* ay,
                           const EvalState* st, hipStream_t s);
 hipError_t launch_tri32(const float* ax, const float* ay, const GridDesc& g, int nsys, const double* sysrow,
                         EvalState* st, int mode, float tau, unsigned long long* hit_keys, long long hit_cap,
-                        unsigned long long* flag_keys, long long flag_cap, hipStream_t s);
+                        unsigned long long* flag_keys, long long flag_cap, unsigned* part, hipStream_t s);
 hipError_t launch_tri64(const double* ax, const double* ay, const GridDesc& g, int nsys, const double* sysrow,
-                        EvalState* st, unsigned long long* hit_keys, long long hit_cap, hipStream_t s);
-hipError_t launch_fb(const double* tab64, int np, const GridDesc& g, const double* sysrow, EvalState* st,
-                     const unsigned long long* flag_keys, long long flag_cap, unsigned long long* hit_keys,
-                     long long hit_cap, hipStream_t s);
-hipError_t launch_sort(unsigned long long* hit_keys, EvalState* st, long long flag_cap, int hit_capacity, int nsys,
-                       int* out_hits, int* n_pred, hipStream_t s);
-hipError_t launch_pos(const double* tab64, int np, const GridDesc& g, const double* sysrow, const EvalState* st,
-                      int hit_capacity, const unsigned long long* hit_keys, double* img_xy, hipStream_t s);
-hipError_t launch_chi2(const ObsPtrs& obs, const EvalState* st, int hit_capacity,
-                       const unsigned long long* hit_keys, const double* img_xy, double* contrib, double* chi2,
-                       double* chi2_sys, int* match, long long* stats, long long n_tests, hipStream_t s);
+                        EvalState* st, unsigned long long* hit_keys, long long hit_cap, unsigned* part,
+                        hipStream_t s);
+hipError_t launch_fbpos(const double* tab64, int np, const GridDesc& g, const double* sysrow, EvalState* st,
+                        const unsigned long long* hit_keys, long long hit_cap, const unsigned long long* flag_keys,
+                        long long flag_cap, unsigned long long* fb_keys, long long fb_cap, double* pos,
+                        double* fb_pos, hipStream_t s);
+hipError_t launch_tail(const ObsPtrs& obs, EvalState* st, long long hit_cap, long long flag_cap, long long fb_cap,
+                       int hit_capacity, const unsigned long long* hit_keys, const unsigned long long* fb_keys,
+                       const double* pos, const double* fb_pos, int* out_hits, double* img_xy, int* n_pred,
+                       double* contrib, double* chi2, double* chi2_sys, int* match, long long* stats,
+                       long long n_tests, const unsigned* part, int n_parts, hipStream_t s);
 hipError_t launch_dls(double zl, const double* zs, int n, double om, double ol, double* out, hipStream_t s);
 hipError_t launch_export(const double* sysrow, int nsys, const EvalState* st, double* bar_x, double* bar_y,
                          int* status, hipStream_t s);

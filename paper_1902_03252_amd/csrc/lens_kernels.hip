@@ -1,16 +1,17 @@
 // HIP kernels of the image-plane chi^2 path for gfx950 (MI355X).
 //
-// One chi^2 evaluation (Rexroth et al. 2019, Sec. 2.2.1-2.2.2, Fig. 1) runs as
-//   k_prep   per-potential constants (FP64) + domain checks
-//   k_src    observed images -> source plane (FP64, one wave per image)
-//   k_bound  barycentres, FP32 error bound, counters (one workgroup)
-//   k_field  deflection at every grid node (FP32 or FP64)        <- the time
+// One chi^2 evaluation (Rexroth et al. 2019, Sec. 2.2.1-2.2.2, Fig. 1) is five
+// launches on one stream:
+//   k_head   one workgroup: per-potential constants (FP64) and domain checks,
+//            observed images -> source plane (FP64), barycentres, the FP32
+//            error bound, counters
+//   k_field  deflection at every grid node (FP32 or FP64)          <- the time
 //   k_tri    tiles of cells: cull (tile, system) pairs, triangle containment,
-//            ballot/prefix-sum compaction of hits and undecided tests
-//   k_fb     FP64 re-test of the undecided FP32 tests (mixed path only)
-//   k_sort   bitonic sort of the hit keys (system, triangle id) in LDS
-//   k_pos    predicted image positions from FP64 vertex deflections
-//   k_chi2   nearest-image matching and the FP64 chi^2 sum, fixed order
+//            ballot/prefix-sum compaction of hits and of undecided FP32 tests
+//   k_fbpos  one wave per item: FP64 re-test of each undecided test (mixed
+//            path) and the FP64 image position of every hit
+//   k_tail   one workgroup: sort of the hits in LDS, per-system counts,
+//            nearest-image matching and the FP64 chi^2 in a fixed order
 #include "lens_device.hpp"
 #include "lens_internal.hpp"
 
@@ -24,39 +25,34 @@ constexpr double kArcsecPerRad = 206264.80624709636;  // 180 * 3600 / pi
 constexpr double kU32 = 5.9604644775390625e-08;       // 2^-24, unit roundoff of FP32
 constexpr double kNodeSplitErr = 2.9802322387695312e-08;  // 2^-25 node units
 
-// ============================================================== prep
+// ============================================================== head
 
-// One thread per potential: domain check, FP64 and FP32 constant rows, and the
-// two per-potential terms of the FP32 error bound:
+// Per-potential constants of potential p: domain check, FP64 and FP32 rows,
+// and the two per-potential terms of the FP32 error bound:
 //   w_p  >= |grad Psi_p| anywhere:  K (1+eps) / sqrt(1-eps)
 //   j_p  >= |Jacobian of grad Psi_p| x (absolute error of the FP32 offset):
 //          2 K (1+eps) / ((1-eps) (sqrt(a^2+rho^2)+a)) * err,  rho = elliptical
 //          distance from the centre to the nearest lattice node.
-__global__ void k_prep(PotPtrs pot, GridDesc g, double* __restrict__ tab64, float* __restrict__ tab32,
-                       double* __restrict__ bterm)
+// FP64 table row of potential p (arcsec units), computed from the raw
+// parameters; returns whether the parameters lie in the model's domain.
+__device__ __forceinline__ bool row64(const PotPtrs& pot, int p, double* t, double& K, double& a1, double& a2)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= pot.n) return;
     const double xc = pot.x[p], yc = pot.y[p], eps = pot.eps[p], phi = pot.phi[p];
     const double a = pot.r_core[p], s = pot.r_cut[p], sig = pot.sigma_v[p];
-    bool ok = isfinite(xc) && isfinite(yc) && isfinite(eps) && isfinite(phi) && isfinite(a) &&
-              isfinite(sig) && eps >= 0.0 && eps < 1.0 && a >= 0.0 && sig >= 0.0 && s > a;
+    const bool ok = isfinite(xc) && isfinite(yc) && isfinite(eps) && isfinite(phi) && isfinite(a) &&
+                    isfinite(sig) && eps >= 0.0 && eps < 1.0 && a >= 0.0 && sig >= 0.0 && s > a;
     const bool sinf = isinf(s);
     const double c = cos(phi), sn = sin(phi);
-    const double a1 = 1.0 - eps, a2 = 1.0 + eps;
-    const double A = a1 * c * c + a2 * sn * sn;
-    const double B = -2.0 * eps * c * sn;
-    const double C = a1 * sn * sn + a2 * c * c;
+    a1 = 1.0 - eps;
+    a2 = 1.0 + eps;
     const double ratio = sig / kCkms;
     const double b0 = 4.0 * kPi * ratio * ratio * kArcsecPerRad;
-    const double K = sinf ? b0 : b0 * s / (s - a);
-
-    double* t = tab64 + (size_t)p * T64_STRIDE;
+    K = sinf ? b0 : b0 * s / (s - a);
     t[T64_XC] = xc;
     t[T64_YC] = yc;
-    t[T64_A] = A;
-    t[T64_B] = B;
-    t[T64_C] = C;
+    t[T64_A] = a1 * c * c + a2 * sn * sn;
+    t[T64_B] = -2.0 * eps * c * sn;
+    t[T64_C] = a1 * sn * sn + a2 * c * c;
     t[T64_A2] = a * a;
     t[T64_S2] = sinf ? 0.0 : s * s;
     t[T64_RA] = a;
@@ -64,7 +60,19 @@ __global__ void k_prep(PotPtrs pot, GridDesc g, double* __restrict__ tab64, floa
     t[T64_K] = K;
     t[T64_SINF] = sinf ? 1.0 : 0.0;
     for (int k = T64_SINF + 1; k < T64_STRIDE; k++) t[k] = 0.0;
+    return ok;
+}
 
+__device__ void prep_one(const PotPtrs& pot, const GridDesc& g, int p, double* __restrict__ tab64,
+                         float* __restrict__ tab32, double* __restrict__ bterm)
+{
+    double row[T64_STRIDE], K, a1, a2;
+    bool ok = row64(pot, p, row, K, a1, a2);
+    double* t = tab64 + (size_t)p * T64_STRIDE;
+    for (int k = 0; k < T64_STRIDE; k++) t[k] = row[k];
+    const double xc = row[T64_XC], yc = row[T64_YC], A = row[T64_A], B = row[T64_B], C = row[T64_C];
+    const double a = row[T64_RA], s = pot.r_cut[p];
+    const bool sinf = row[T64_SINF] != 0.0;
     const double cxn = (xc - g.x0) / g.h, cyn = (yc - g.y0) / g.h;
     ok = ok && fabs(cxn) < 4194304.0 && fabs(cyn) < 4194304.0;  // |centre| < 2^22 nodes
     const double cxh = rint(cxn), cyh = rint(cyn);
@@ -86,7 +94,6 @@ __global__ void k_prep(PotPtrs pot, GridDesc g, double* __restrict__ tab64, floa
     u[T32_KIND] = (float)((a == 0.0 ? 2 : 0) + (sinf ? 1 : 0));
     for (int k = T32_KIND + 1; k < T32_STRIDE; k++) u[k] = 0.0f;
 
-    // error-bound terms
     const double w = K * a2 / sqrt(a1);
     const double rho = sqrt(a1) * g.h * sqrt(cxl * cxl + cyl * cyl);
     const double den = a1 * (sqrt(a * a + rho * rho) + a);
@@ -100,11 +107,9 @@ __global__ void k_prep(PotPtrs pot, GridDesc g, double* __restrict__ tab64, floa
     bterm[3 * p + 2] = ok ? 0.0 : 1.0;
 }
 
-// ============================================================== source positions
-
 // Index of the system that owns observed image j: sys_off is non-decreasing
 // for valid input; the search is clamped so that invalid input stays in range
-// (it is then reported by k_bound).
+// (it is then reported as invalid).
 __device__ __forceinline__ int system_of(const int* __restrict__ sys_off, int nsys, int j)
 {
     int lo = 0, hi = nsys - 1;
@@ -115,45 +120,69 @@ __device__ __forceinline__ int system_of(const int* __restrict__ sys_off, int ns
     return lo;
 }
 
-// One wave per observed image: beta_ij = theta_ij - r_i grad Psi(theta_ij), FP64
-// (Sec. 2.2.2), grad Psi evaluated at the observed position itself.
-__global__ __launch_bounds__(256) void k_src(const double* __restrict__ tab64, int np, ObsPtrs obs,
-                                             double* __restrict__ beta_x, double* __restrict__ beta_y)
+// Head of every evaluation, one wave per observed image (at least one
+// workgroup of 4 waves), in two phases:
+//  1. every thread with a potential index writes that potential's constants
+//     (prep_one); every wave with an observed image j computes its source
+//     position beta_ij = theta_ij - r_i grad Psi(theta_ij) in FP64 (Sec. 2.2.2),
+//     grad Psi evaluated at the observed position itself from the raw
+//     parameters (the same row64 arithmetic as the table), potentials over the
+//     lanes;
+//  2. the last workgroup to finish (atomic ticket) reduces the bound terms in a
+//     fixed order and writes one row per system: barycentre (unweighted mean of
+//     its beta_ij), its node-unit split, D_LS/D_OS and the FP32 error bound E_B
+//     of source-plane offsets:
+//       E_alpha = u (64 + P) sum_p w_p + sum_p j_p + 1e-9
+//       E_B     = r E_alpha + 4u Theta + 2u r (W + E_alpha) + 2^-25 h + 1e-9
+//     with u = 2^-24, W = sum_p w_p and Theta = max |theta - barycentre| over
+//     the grid.  64 u w_p bounds the rounding of one potential's FP32
+//     evaluation (about 30 u w_p by operation count, doubled), (P-1) u W the
+//     sequential FP32 sum over potentials, sum_p j_p the Jacobian-amplified
+//     absolute offset error.  It also zeroes the counters and resets the ticket.
+__global__ __launch_bounds__(256) void k_head(PotPtrs pot, GridDesc g, ObsPtrs obs, double* __restrict__ tab64,
+                                              float* __restrict__ tab32, double* __restrict__ bterm,
+                                              double* __restrict__ beta_x, double* __restrict__ beta_y,
+                                              double* __restrict__ sysrow, EvalState* __restrict__ st)
 {
-    const int j = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    if (j >= obs.n_img) return;
-    const double t1 = obs.x[j], t2 = obs.y[j];
-    double a1, a2;
-    alpha64_wave(tab64, np, t1, t2, a1, a2);
-    const int s = system_of(obs.sys_off, obs.n_sys, j);
-    const double r = obs.dls[s];
-    if (lane_id() == 0) {
-        beta_x[j] = t1 - r * a1;
-        beta_y[j] = t2 - r * a2;
-    }
-}
-
-// ============================================================== bound / barycentres
-
-// One workgroup of 1024 threads.  Zeroes the evaluation state, reduces the
-// per-potential bound terms in a fixed order, and writes one row per system:
-// barycentre (unweighted mean of its beta_ij, Sec. 2.2.2), its node-unit split,
-// D_LS/D_OS and the FP32 error bound E_B of source-plane offsets:
-//   E_alpha = u (64 + P) sum_p w_p + sum_p j_p + 1e-9
-//   E_B     = r E_alpha + 4u Theta + 2u r (W + E_alpha) + 2^-25 h + 1e-9
-// with u = 2^-24, W = sum_p w_p and Theta = max |theta - barycentre| over the
-// grid.  64 u w_p bounds the rounding of one potential's FP32 evaluation
-// (about 30 u w_p by operation count, doubled), (P-1) u W the sequential FP32
-// sum over potentials, sum_p j_p the Jacobian-amplified absolute offset error.
-__global__ __launch_bounds__(1024) void k_bound(const double* __restrict__ bterm, int np, GridDesc g,
-                                                ObsPtrs obs, const double* __restrict__ beta_x,
-                                                const double* __restrict__ beta_y, double* __restrict__ sysrow,
-                                                EvalState* __restrict__ st)
-{
-    __shared__ double sw[1024], sj[1024], sb[1024];
+    __shared__ double sw[256], sj[256], sb[256];
+    __shared__ int sys_bad, last;
     const int t = threadIdx.x;
+    const int np = pot.n;
+    const int nthreads = gridDim.x * 256;
+    for (int p = blockIdx.x * 256 + t; p < np; p += nthreads) prep_one(pot, g, p, tab64, tab32, bterm);
+
+    const int nwaves = gridDim.x * 4;
+    for (int j = blockIdx.x * 4 + (t >> 6); j < obs.n_img; j += nwaves) {
+        const double t1 = obs.x[j], t2 = obs.y[j];
+        double s1 = 0.0, s2 = 0.0;
+        for (int p = lane_id(); p < np; p += 64) {
+            double row[T64_STRIDE], K, a1, a2;
+            row64(pot, p, row, K, a1, a2);
+            add_alpha64(row, t1, t2, s1, s2);
+        }
+        const double a1 = wave_sum(s1), a2 = wave_sum(s2);
+        const int s = system_of(obs.sys_off, obs.n_sys, j);
+        const double r = obs.dls[s];
+        if (lane_id() == 0) {
+            beta_x[j] = t1 - r * a1;
+            beta_y[j] = t2 - r * a2;
+        }
+    }
+
+    // the last workgroup to arrive continues with the reductions
+    __threadfence();
+    __syncthreads();
+    if (t == 0) {
+        const unsigned ticket = atomicAdd(&st->head_ticket, 1u);
+        last = ticket == gridDim.x - 1;
+        sys_bad = 0;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+
     double w = 0.0, jt = 0.0, bad = 0.0;
-    for (int p = t; p < np; p += 1024) {
+    for (int p = t; p < np; p += 256) {
         w += bterm[3 * p + 0];
         jt += bterm[3 * p + 1];
         bad += bterm[3 * p + 2];
@@ -162,7 +191,7 @@ __global__ __launch_bounds__(1024) void k_bound(const double* __restrict__ bterm
     sj[t] = jt;
     sb[t] = bad;
     __syncthreads();
-    for (int m = 512; m >= 1; m >>= 1) {
+    for (int m = 128; m >= 1; m >>= 1) {
         if (t < m) {
             sw[t] += sw[t + m];
             sj[t] += sj[t + m];
@@ -172,9 +201,8 @@ __global__ __launch_bounds__(1024) void k_bound(const double* __restrict__ bterm
     }
     const double W = sw[0];
     const double e_alpha = kU32 * (64.0 + np) * W + sj[0] + 1e-9;
-    __shared__ int sys_bad;
     if (t == 0) {
-        sys_bad = 0;
+        st->head_ticket = 0;
         st->n_hits = 0;
         st->n_flags = 0;
         st->n_tile_pass = 0;
@@ -182,11 +210,10 @@ __global__ __launch_bounds__(1024) void k_bound(const double* __restrict__ bterm
         st->n_fb_hits = 0;
         st->e_alpha = e_alpha;
         st->w_sum = W;
-        if (obs.n_sys > 0 && (obs.sys_off[0] != 0 || obs.sys_off[obs.n_sys] != obs.n_img)) sys_bad = 1;
+        if (obs.n_sys > 0 && (obs.sys_off[0] != 0 || obs.sys_off[obs.n_sys] != obs.n_img)) atomicOr(&sys_bad, 1);
     }
-    __syncthreads();
     const double xlo = g.x0, xhi = g.x0 + (g.nx - 1) * g.h, ylo = g.y0, yhi = g.y0 + (g.ny - 1) * g.h;
-    for (int s = t; s < obs.n_sys; s += 1024) {
+    for (int s = t; s < obs.n_sys; s += 256) {
         const int j0 = obs.sys_off[s], j1 = obs.sys_off[s + 1];
         bool ok = j0 <= j1 && j0 >= 0 && j1 <= obs.n_img;
         double bx = 0.0, by = 0.0;
@@ -326,8 +353,12 @@ __global__ __launch_bounds__(256) void k_field64(const double* __restrict__ tab6
 
 // ============================================================== triangle stage
 
-constexpr int TX = kTileX, TY = kTileY;  // cells per tile
-constexpr int TNX = TX + 1, TNY = TY + 1; // nodes per tile (one-node halo)
+constexpr int TX = kTileX, TY = kTileY;    // cells per tile
+constexpr int TNX = TX + 1, TNY = TY + 1;   // nodes per tile (one-node halo)
+constexpr int TLOADS = (TNX * TNY + 255) / 256;
+constexpr int kCellIters = (TX * TY + 255) / 256;  // cells per thread
+static_assert(TX * TY % 256 == 0, "a tile is a whole number of cells per thread");
+constexpr int SYS_CHUNK = 128;              // systems staged in LDS at a time
 
 enum : int { kMiss = 0, kHit = 1, kFlag = 2 };
 
@@ -397,70 +428,102 @@ __device__ __forceinline__ int decide32(const float* dx, const float* dy, float 
     return kFlag;
 }
 
-// Block-wide min/max of a tile's deflection, result broadcast through LDS.
-__device__ __forceinline__ void tile_range(float& vmin, float& vmax, float* red /* [2*4] */)
+// Block-wide min/max, result broadcast through LDS.
+template <typename T>
+__device__ __forceinline__ void tile_range(T& vmin, T& vmax, T* red /* [8] */)
 {
-    vmin = wave_min(vmin);
-    vmax = wave_max(vmax);
+    for (int m = 32; m >= 1; m >>= 1) {
+        const T a = __shfl_xor(vmin, m, 64), b = __shfl_xor(vmax, m, 64);
+        vmin = a < vmin ? a : vmin;
+        vmax = b > vmax ? b : vmax;
+    }
     const int w = threadIdx.x >> 6;
     if (lane_id() == 0) {
         red[2 * w] = vmin;
         red[2 * w + 1] = vmax;
     }
     __syncthreads();
-    vmin = fminf(fminf(red[0], red[2]), fminf(red[4], red[6]));
-    vmax = fmaxf(fmaxf(red[1], red[3]), fmaxf(red[5], red[7]));
+    vmin = red[0];
+    vmax = red[1];
+    for (int k = 1; k < 4; k++) {
+        vmin = red[2 * k] < vmin ? red[2 * k] : vmin;
+        vmax = red[2 * k + 1] > vmax ? red[2 * k + 1] : vmax;
+    }
     __syncthreads();
 }
 
-__device__ __forceinline__ void tile_range64(double& vmin, double& vmax, double* red)
+// Per-system data of one chunk of systems, staged in LDS by the tile kernels.
+struct SysChunk {
+    double bx[SYS_CHUNK], by[SYS_CHUNK], r[SYS_CHUNK], eb[SYS_CHUNK];
+    float f[SYS_CHUNK][6];  // r, E_B, bx_hi, bx_lo, by_hi, by_lo as float
+};
+
+__device__ __forceinline__ void load_chunk(SysChunk& c, const double* __restrict__ sysrow, int nsys, int base)
 {
-    for (int m = 32; m >= 1; m >>= 1) {
-        vmin = fmin(vmin, __shfl_xor(vmin, m, 64));
-        vmax = fmax(vmax, __shfl_xor(vmax, m, 64));
+    const int t = threadIdx.x;
+    const int s = base + t;
+    if (t < SYS_CHUNK && s < nsys) {
+        const double* row = sysrow + (size_t)s * SYS_STRIDE;
+        const double bx = row[SYS_BX], by = row[SYS_BY], r = row[SYS_R], eb = row[SYS_EB];
+        c.bx[t] = bx;
+        c.by[t] = by;
+        c.r[t] = r;
+        c.eb[t] = eb;
+        c.f[t][0] = (float)r;
+        c.f[t][1] = (float)eb;
+        c.f[t][2] = (float)row[SYS_BXH];
+        c.f[t][3] = (float)row[SYS_BXL];
+        c.f[t][4] = (float)row[SYS_BYH];
+        c.f[t][5] = (float)row[SYS_BYL];
     }
-    const int w = threadIdx.x >> 6;
-    if (lane_id() == 0) {
-        red[2 * w] = vmin;
-        red[2 * w + 1] = vmax;
-    }
-    __syncthreads();
-    vmin = fmin(fmin(red[0], red[2]), fmin(red[4], red[6]));
-    vmax = fmax(fmax(red[1], red[3]), fmax(red[5], red[7]));
-    __syncthreads();
 }
 
 // Mixed path, one workgroup (4 waves) per tile of TX x TY cells.  The tile's
-// FP32 deflections (with a one-node halo) are staged in LDS; the box
-//   [theta_min - r alpha_max, theta_max - r alpha_min] (per axis, widened by E_B)
-// contains every source-plane vertex of the tile, so a system whose barycentre
-// lies outside it is skipped for the whole tile.  Systems are tested 64 at a
-// time, one per lane, and the survivors enumerated from the ballot mask.
+// FP32 deflections (with a one-node halo) are staged in LDS -- every load of
+// the tile is issued before the first wait -- together with the systems.  The
+// box [theta_min - r alpha_max, theta_max - r alpha_min] (per axis, widened by
+// E_B) contains every source-plane vertex of the tile, so a system whose
+// barycentre lies outside it is skipped for the whole tile.  Systems are
+// tested 64 at a time, one per lane, and the survivors enumerated from the
+// ballot mask.
 __global__ __launch_bounds__(256) void k_tri32(const float* __restrict__ ax, const float* __restrict__ ay,
                                                GridDesc g, int nsys, const double* __restrict__ sysrow,
                                                EvalState* __restrict__ st, int mode, float tau,
                                                unsigned long long* __restrict__ hit_keys, long long hit_cap,
-                                               unsigned long long* __restrict__ flag_keys, long long flag_cap)
+                                               unsigned long long* __restrict__ flag_keys, long long flag_cap,
+                                               unsigned* __restrict__ part)
 {
     __shared__ float sx[TNY][TNX], sy[TNY][TNX];
     __shared__ float red[8];
+    __shared__ SysChunk chunk;
     const int ci0 = blockIdx.x * TX, cj0 = blockIdx.y * TY;
     const int ncx = min(TX, g.nx - 1 - ci0), ncy = min(TY, g.ny - 1 - cj0);
-    float xmn = INFINITY, xmx = -INFINITY, ymn = INFINITY, ymx = -INFINITY;
-    for (int q = threadIdx.x; q < TNX * TNY; q += 256) {
+    float vx[TLOADS], vy[TLOADS];
+#pragma unroll
+    for (int k = 0; k < TLOADS; k++) {
+        const int q = threadIdx.x + 256 * k;
         const int li = q % TNX, lj = q / TNX;
-        float vx = 0.0f, vy = 0.0f;
-        if (li <= ncx && lj <= ncy) {
-            const size_t n = (size_t)(cj0 + lj) * g.nx + (ci0 + li);
-            vx = ax[n];
-            vy = ay[n];
-            xmn = fminf(xmn, vx);
-            xmx = fmaxf(xmx, vx);
-            ymn = fminf(ymn, vy);
-            ymx = fmaxf(ymx, vy);
+        const bool in = q < TNX * TNY && li <= ncx && lj <= ncy;
+        const size_t n = in ? (size_t)(cj0 + lj) * g.nx + (ci0 + li) : 0;
+        vx[k] = in ? ax[n] : 0.0f;
+        vy[k] = in ? ay[n] : 0.0f;
+    }
+    load_chunk(chunk, sysrow, nsys, 0);
+    float xmn = INFINITY, xmx = -INFINITY, ymn = INFINITY, ymx = -INFINITY;
+#pragma unroll
+    for (int k = 0; k < TLOADS; k++) {
+        const int q = threadIdx.x + 256 * k;
+        const int li = q % TNX, lj = q / TNX;
+        if (q < TNX * TNY) {
+            sx[lj][li] = vx[k];
+            sy[lj][li] = vy[k];
+            if (li <= ncx && lj <= ncy) {
+                xmn = fminf(xmn, vx[k]);
+                xmx = fmaxf(xmx, vx[k]);
+                ymn = fminf(ymn, vy[k]);
+                ymx = fmaxf(ymx, vy[k]);
+            }
         }
-        sx[lj][li] = vx;
-        sy[lj][li] = vy;
     }
     __syncthreads();
     tile_range(xmn, xmx, red);
@@ -469,58 +532,70 @@ __global__ __launch_bounds__(256) void k_tri32(const float* __restrict__ ax, con
     const double ty0 = g.y0 + cj0 * g.h, ty1 = g.y0 + (cj0 + ncy) * g.h;
     const float h32 = (float)g.h;
     const int lane = lane_id();
-    unsigned nbbox = 0;
-    for (int sbase = 0; sbase < nsys; sbase += 64) {
-        const int s = sbase + lane;
-        bool pass = false;
-        if (s < nsys) {
-            const double* row = sysrow + (size_t)s * SYS_STRIDE;
-            const double r = row[SYS_R], eb = row[SYS_EB], bx = row[SYS_BX], by = row[SYS_BY];
-            pass = bx >= tx0 - r * xmx - eb && bx <= tx1 - r * xmn + eb && by >= ty0 - r * ymx - eb &&
-                   by <= ty1 - r * ymn + eb;
+    unsigned nbbox = 0, ntile = 0;
+    for (int cbase = 0; cbase < nsys; cbase += SYS_CHUNK) {
+        if (cbase > 0) {
+            __syncthreads();
+            load_chunk(chunk, sysrow, nsys, cbase);
+            __syncthreads();
         }
-        unsigned long long m = __ballot(pass);
-        if (threadIdx.x == 0 && m) atomicAdd(&st->n_tile_pass, (unsigned long long)__popcll(m));
-        while (m) {
-            const int sb = __ffsll((long long)m) - 1;
-            m &= m - 1;
-            const int sys = sbase + sb;
-            const double* row = sysrow + (size_t)sys * SYS_STRIDE;
-            const float r = (float)row[SYS_R];
-            const float E = (float)row[SYS_EB];
-            const float bxh = (float)row[SYS_BXH], bxl = (float)row[SYS_BXL];
-            const float byh = (float)row[SYS_BYH], byl = (float)row[SYS_BYL];
+        const int nc = min(SYS_CHUNK, nsys - cbase);
+        for (int sbase = 0; sbase < nc; sbase += 64) {
+            const int sl = sbase + lane;
+            bool pass = false;
+            if (sl < nc) {
+                const double r = chunk.r[sl], eb = chunk.eb[sl], bx = chunk.bx[sl], by = chunk.by[sl];
+                pass = bx >= tx0 - r * xmx - eb && bx <= tx1 - r * xmn + eb && by >= ty0 - r * ymx - eb &&
+                       by <= ty1 - r * ymn + eb;
+            }
+            unsigned long long m = __ballot(pass);
+            ntile += __popcll(m);
+            while (m) {
+                const int sb = __ffsll((long long)m) - 1;
+                m &= m - 1;
+                const int s = sbase + sb;
+                const int sys = cbase + s;
+                const float r = chunk.f[s][0], E = chunk.f[s][1];
+                const float bxh = chunk.f[s][2], bxl = chunk.f[s][3], byh = chunk.f[s][4], byl = chunk.f[s][5];
 #pragma unroll
-            for (int it = 0; it < (TX * TY) / 256; it++) {
-                const int cidx = threadIdx.x + 256 * it;
-                const int li = cidx % TX, lj = cidx / TX;
-                const bool valid = li < ncx && lj < ncy;
-                const int gi = ci0 + li, gj = cj0 + lj;
-                // offsets theta - barycentre in node units (exact hi part), then arcsec
-                const float ex0 = (((float)gi - bxh) - bxl) * h32, ex1 = (((float)(gi + 1) - bxh) - bxl) * h32;
-                const float ey0 = (((float)gj - byh) - byl) * h32, ey1 = (((float)(gj + 1) - byh) - byl) * h32;
-                const float d00x = fmaf(-r, sx[lj][li], ex0), d00y = fmaf(-r, sy[lj][li], ey0);
-                const float d10x = fmaf(-r, sx[lj][li + 1], ex1), d10y = fmaf(-r, sy[lj][li + 1], ey0);
-                const float d01x = fmaf(-r, sx[lj + 1][li], ex0), d01y = fmaf(-r, sy[lj + 1][li], ey1);
-                const float d11x = fmaf(-r, sx[lj + 1][li + 1], ex1), d11y = fmaf(-r, sy[lj + 1][li + 1], ey1);
-                int res0 = kMiss, res1 = kMiss;
-                if (valid) {
-                    const float tx[3] = {d00x, d10x, d01x}, ty[3] = {d00y, d10y, d01y};
-                    const float ux[3] = {d11x, d01x, d10x}, uy[3] = {d11y, d01y, d10y};
-                    res0 = decide32(tx, ty, E, mode, tau, nbbox);
-                    res1 = decide32(ux, uy, E, mode, tau, nbbox);
+                for (int it = 0; it < kCellIters; it++) {
+                    const int cidx = threadIdx.x + 256 * it;
+                    const int li = cidx % TX, lj = cidx / TX;
+                    const bool valid = li < ncx && lj < ncy;
+                    const int gi = ci0 + li, gj = cj0 + lj;
+                    // offsets theta - barycentre in node units (exact hi part), then arcsec
+                    const float ex0 = (((float)gi - bxh) - bxl) * h32, ex1 = (((float)(gi + 1) - bxh) - bxl) * h32;
+                    const float ey0 = (((float)gj - byh) - byl) * h32, ey1 = (((float)(gj + 1) - byh) - byl) * h32;
+                    const float d00x = fmaf(-r, sx[lj][li], ex0), d00y = fmaf(-r, sy[lj][li], ey0);
+                    const float d10x = fmaf(-r, sx[lj][li + 1], ex1), d10y = fmaf(-r, sy[lj][li + 1], ey0);
+                    const float d01x = fmaf(-r, sx[lj + 1][li], ex0), d01y = fmaf(-r, sy[lj + 1][li], ey1);
+                    const float d11x = fmaf(-r, sx[lj + 1][li + 1], ex1), d11y = fmaf(-r, sy[lj + 1][li + 1], ey1);
+                    int res0 = kMiss, res1 = kMiss;
+                    if (valid) {
+                        const float tx[3] = {d00x, d10x, d01x}, ty[3] = {d00y, d10y, d01y};
+                        const float ux[3] = {d11x, d01x, d10x}, uy[3] = {d11y, d01y, d10y};
+                        res0 = decide32(tx, ty, E, mode, tau, nbbox);
+                        res1 = decide32(ux, uy, E, mode, tau, nbbox);
+                    }
+                    const int tid0 = 2 * (gj * (g.nx - 1) + gi);
+                    wave_append(res0 == kHit, hit_key(sys, tid0), &st->n_hits, hit_keys, hit_cap);
+                    wave_append(res1 == kHit, hit_key(sys, tid0 + 1), &st->n_hits, hit_keys, hit_cap);
+                    wave_append(res0 == kFlag, hit_key(sys, tid0), &st->n_flags, flag_keys, flag_cap);
+                    wave_append(res1 == kFlag, hit_key(sys, tid0 + 1), &st->n_flags, flag_keys, flag_cap);
                 }
-                const int tid0 = 2 * (gj * (g.nx - 1) + gi);
-                wave_append(res0 == kHit, hit_key(sys, tid0), &st->n_hits, hit_keys, hit_cap);
-                wave_append(res1 == kHit, hit_key(sys, tid0 + 1), &st->n_hits, hit_keys, hit_cap);
-                wave_append(res0 == kFlag, hit_key(sys, tid0), &st->n_flags, flag_keys, flag_cap);
-                wave_append(res1 == kFlag, hit_key(sys, tid0 + 1), &st->n_flags, flag_keys, flag_cap);
             }
         }
     }
-    unsigned long long nb = nbbox;
-    for (int m = 32; m >= 1; m >>= 1) nb += __shfl_xor(nb, m, 64);
-    if (lane == 0 && nb) atomicAdd(&st->n_bbox_pass, nb);
+    // per-workgroup statistics without a contended global atomic
+    for (int m = 32; m >= 1; m >>= 1) nbbox += __shfl_xor(nbbox, m, 64);
+    __shared__ unsigned sbb[4];
+    if (lane == 0) sbb[threadIdx.x >> 6] = nbbox;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const size_t b = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+        part[2 * b + 0] = ntile;
+        part[2 * b + 1] = sbb[0] + sbb[1] + sbb[2] + sbb[3];
+    }
 }
 
 // FP64 path: same tiling, FP64 deflections in LDS, every surviving triangle
@@ -528,97 +603,125 @@ __global__ __launch_bounds__(256) void k_tri32(const float* __restrict__ ax, con
 __global__ __launch_bounds__(256) void k_tri64(const double* __restrict__ ax, const double* __restrict__ ay,
                                                GridDesc g, int nsys, const double* __restrict__ sysrow,
                                                EvalState* __restrict__ st,
-                                               unsigned long long* __restrict__ hit_keys, long long hit_cap)
+                                               unsigned long long* __restrict__ hit_keys, long long hit_cap,
+                                               unsigned* __restrict__ part)
 {
     __shared__ double sx[TNY][TNX], sy[TNY][TNX];
     __shared__ double red[8];
+    __shared__ SysChunk chunk;
     const int ci0 = blockIdx.x * TX, cj0 = blockIdx.y * TY;
     const int ncx = min(TX, g.nx - 1 - ci0), ncy = min(TY, g.ny - 1 - cj0);
-    double xmn = INFINITY, xmx = -INFINITY, ymn = INFINITY, ymx = -INFINITY;
-    for (int q = threadIdx.x; q < TNX * TNY; q += 256) {
+    double vx[TLOADS], vy[TLOADS];
+#pragma unroll
+    for (int k = 0; k < TLOADS; k++) {
+        const int q = threadIdx.x + 256 * k;
         const int li = q % TNX, lj = q / TNX;
-        double vx = 0.0, vy = 0.0;
-        if (li <= ncx && lj <= ncy) {
-            const size_t n = (size_t)(cj0 + lj) * g.nx + (ci0 + li);
-            vx = ax[n];
-            vy = ay[n];
-            xmn = fmin(xmn, vx);
-            xmx = fmax(xmx, vx);
-            ymn = fmin(ymn, vy);
-            ymx = fmax(ymx, vy);
-        }
-        sx[lj][li] = vx;
-        sy[lj][li] = vy;
+        const bool in = q < TNX * TNY && li <= ncx && lj <= ncy;
+        const size_t n = in ? (size_t)(cj0 + lj) * g.nx + (ci0 + li) : 0;
+        vx[k] = in ? ax[n] : 0.0;
+        vy[k] = in ? ay[n] : 0.0;
     }
-    __syncthreads();
-    tile_range64(xmn, xmx, red);
-    tile_range64(ymn, ymx, red);
-    const double tx0 = g.x0 + ci0 * g.h, tx1 = g.x0 + (ci0 + ncx) * g.h;
-    const double ty0 = g.y0 + cj0 * g.h, ty1 = g.y0 + (cj0 + ncy) * g.h;
-    const int lane = lane_id();
-    unsigned nbbox = 0;
-    for (int sbase = 0; sbase < nsys; sbase += 64) {
-        const int s = sbase + lane;
-        bool pass = false;
-        if (s < nsys) {
-            const double* row = sysrow + (size_t)s * SYS_STRIDE;
-            const double r = row[SYS_R], bx = row[SYS_BX], by = row[SYS_BY];
-            const double eb = 1e-9;  // FP64 rounding of the box, far below this margin
-            pass = bx >= tx0 - r * xmx - eb && bx <= tx1 - r * xmn + eb && by >= ty0 - r * ymx - eb &&
-                   by <= ty1 - r * ymn + eb;
-        }
-        unsigned long long m = __ballot(pass);
-        if (threadIdx.x == 0 && m) atomicAdd(&st->n_tile_pass, (unsigned long long)__popcll(m));
-        while (m) {
-            const int sb = __ffsll((long long)m) - 1;
-            m &= m - 1;
-            const int sys = sbase + sb;
-            const double* row = sysrow + (size_t)sys * SYS_STRIDE;
-            const double r = row[SYS_R], bx = row[SYS_BX], by = row[SYS_BY];
-#pragma unroll 1
-            for (int it = 0; it < (TX * TY) / 256; it++) {
-                const int cidx = threadIdx.x + 256 * it;
-                const int li = cidx % TX, lj = cidx / TX;
-                const bool valid = li < ncx && lj < ncy;
-                const int gi = ci0 + li, gj = cj0 + lj;
-                bool h0 = false, h1 = false;
-                if (valid) {
-                    const double t0x = g.x0 + gi * g.h, t1x = g.x0 + (gi + 1) * g.h;
-                    const double t0y = g.y0 + gj * g.h, t1y = g.y0 + (gj + 1) * g.h;
-                    const double b00x = t0x - r * sx[lj][li], b00y = t0y - r * sy[lj][li];
-                    const double b10x = t1x - r * sx[lj][li + 1], b10y = t0y - r * sy[lj][li + 1];
-                    const double b01x = t0x - r * sx[lj + 1][li], b01y = t1y - r * sy[lj + 1][li];
-                    const double b11x = t1x - r * sx[lj + 1][li + 1], b11y = t1y - r * sy[lj + 1][li + 1];
-                    const double vx0[3] = {b00x, b10x, b01x}, vy0[3] = {b00y, b10y, b01y};
-                    const double vx1[3] = {b11x, b01x, b10x}, vy1[3] = {b11y, b01y, b10y};
-                    const double lo0 = fmin(vx0[0], fmin(vx0[1], vx0[2])), hi0 = fmax(vx0[0], fmax(vx0[1], vx0[2]));
-                    const double lo1 = fmin(vy0[0], fmin(vy0[1], vy0[2])), hi1 = fmax(vy0[0], fmax(vy0[1], vy0[2]));
-                    if (!(bx < lo0 || bx > hi0 || by < lo1 || by > hi1)) {
-                        nbbox++;
-                        h0 = contains_exact(vx0, vy0, bx, by);
-                    }
-                    const double lo2 = fmin(vx1[0], fmin(vx1[1], vx1[2])), hi2 = fmax(vx1[0], fmax(vx1[1], vx1[2]));
-                    const double lo3 = fmin(vy1[0], fmin(vy1[1], vy1[2])), hi3 = fmax(vy1[0], fmax(vy1[1], vy1[2]));
-                    if (!(bx < lo2 || bx > hi2 || by < lo3 || by > hi3)) {
-                        nbbox++;
-                        h1 = contains_exact(vx1, vy1, bx, by);
-                    }
-                }
-                const int tid0 = 2 * (gj * (g.nx - 1) + gi);
-                wave_append(h0, hit_key(sys, tid0), &st->n_hits, hit_keys, hit_cap);
-                wave_append(h1, hit_key(sys, tid0 + 1), &st->n_hits, hit_keys, hit_cap);
+    load_chunk(chunk, sysrow, nsys, 0);
+    double xmn = INFINITY, xmx = -INFINITY, ymn = INFINITY, ymx = -INFINITY;
+#pragma unroll
+    for (int k = 0; k < TLOADS; k++) {
+        const int q = threadIdx.x + 256 * k;
+        const int li = q % TNX, lj = q / TNX;
+        if (q < TNX * TNY) {
+            sx[lj][li] = vx[k];
+            sy[lj][li] = vy[k];
+            if (li <= ncx && lj <= ncy) {
+                xmn = fmin(xmn, vx[k]);
+                xmx = fmax(xmx, vx[k]);
+                ymn = fmin(ymn, vy[k]);
+                ymx = fmax(ymx, vy[k]);
             }
         }
     }
-    unsigned long long nb = nbbox;
-    for (int m = 32; m >= 1; m >>= 1) nb += __shfl_xor(nb, m, 64);
-    if (lane == 0 && nb) atomicAdd(&st->n_bbox_pass, nb);
+    __syncthreads();
+    tile_range(xmn, xmx, red);
+    tile_range(ymn, ymx, red);
+    const double tx0 = g.x0 + ci0 * g.h, tx1 = g.x0 + (ci0 + ncx) * g.h;
+    const double ty0 = g.y0 + cj0 * g.h, ty1 = g.y0 + (cj0 + ncy) * g.h;
+    const int lane = lane_id();
+    unsigned nbbox = 0, ntile = 0;
+    for (int cbase = 0; cbase < nsys; cbase += SYS_CHUNK) {
+        if (cbase > 0) {
+            __syncthreads();
+            load_chunk(chunk, sysrow, nsys, cbase);
+            __syncthreads();
+        }
+        const int nc = min(SYS_CHUNK, nsys - cbase);
+        for (int sbase = 0; sbase < nc; sbase += 64) {
+            const int sl = sbase + lane;
+            bool pass = false;
+            if (sl < nc) {
+                const double r = chunk.r[sl], bx = chunk.bx[sl], by = chunk.by[sl];
+                const double eb = 1e-9;  // FP64 rounding of the box, far below this margin
+                pass = bx >= tx0 - r * xmx - eb && bx <= tx1 - r * xmn + eb && by >= ty0 - r * ymx - eb &&
+                       by <= ty1 - r * ymn + eb;
+            }
+            unsigned long long m = __ballot(pass);
+            ntile += __popcll(m);
+            while (m) {
+                const int sb = __ffsll((long long)m) - 1;
+                m &= m - 1;
+                const int s = sbase + sb;
+                const int sys = cbase + s;
+                const double r = chunk.r[s], bx = chunk.bx[s], by = chunk.by[s];
+#pragma unroll 1
+                for (int it = 0; it < kCellIters; it++) {
+                    const int cidx = threadIdx.x + 256 * it;
+                    const int li = cidx % TX, lj = cidx / TX;
+                    const bool valid = li < ncx && lj < ncy;
+                    const int gi = ci0 + li, gj = cj0 + lj;
+                    bool h0 = false, h1 = false;
+                    if (valid) {
+                        const double t0x = g.x0 + gi * g.h, t1x = g.x0 + (gi + 1) * g.h;
+                        const double t0y = g.y0 + gj * g.h, t1y = g.y0 + (gj + 1) * g.h;
+                        const double b00x = t0x - r * sx[lj][li], b00y = t0y - r * sy[lj][li];
+                        const double b10x = t1x - r * sx[lj][li + 1], b10y = t0y - r * sy[lj][li + 1];
+                        const double b01x = t0x - r * sx[lj + 1][li], b01y = t1y - r * sy[lj + 1][li];
+                        const double b11x = t1x - r * sx[lj + 1][li + 1], b11y = t1y - r * sy[lj + 1][li + 1];
+                        const double vx0[3] = {b00x, b10x, b01x}, vy0[3] = {b00y, b10y, b01y};
+                        const double vx1[3] = {b11x, b01x, b10x}, vy1[3] = {b11y, b01y, b10y};
+                        const double lo0 = fmin(vx0[0], fmin(vx0[1], vx0[2])), hi0 = fmax(vx0[0], fmax(vx0[1], vx0[2]));
+                        const double lo1 = fmin(vy0[0], fmin(vy0[1], vy0[2])), hi1 = fmax(vy0[0], fmax(vy0[1], vy0[2]));
+                        if (!(bx < lo0 || bx > hi0 || by < lo1 || by > hi1)) {
+                            nbbox++;
+                            h0 = contains_exact(vx0, vy0, bx, by);
+                        }
+                        const double lo2 = fmin(vx1[0], fmin(vx1[1], vx1[2])), hi2 = fmax(vx1[0], fmax(vx1[1], vx1[2]));
+                        const double lo3 = fmin(vy1[0], fmin(vy1[1], vy1[2])), hi3 = fmax(vy1[0], fmax(vy1[1], vy1[2]));
+                        if (!(bx < lo2 || bx > hi2 || by < lo3 || by > hi3)) {
+                            nbbox++;
+                            h1 = contains_exact(vx1, vy1, bx, by);
+                        }
+                    }
+                    const int tid0 = 2 * (gj * (g.nx - 1) + gi);
+                    wave_append(h0, hit_key(sys, tid0), &st->n_hits, hit_keys, hit_cap);
+                    wave_append(h1, hit_key(sys, tid0 + 1), &st->n_hits, hit_keys, hit_cap);
+                }
+            }
+        }
+    }
+    // per-workgroup statistics without a contended global atomic
+    for (int m = 32; m >= 1; m >>= 1) nbbox += __shfl_xor(nbbox, m, 64);
+    __shared__ unsigned sbb[4];
+    if (lane == 0) sbb[threadIdx.x >> 6] = nbbox;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const size_t b = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+        part[2 * b + 0] = ntile;
+        part[2 * b + 1] = sbb[0] + sbb[1] + sbb[2] + sbb[3];
+    }
 }
 
-// ============================================================== FP64 fallback
+// ============================================================== FP64 fallback and positions
 
-// FP64 vertex offsets B_k - barycentre of triangle `tid` for system row `row`:
-// grad Psi at the three vertices with the potentials spread over the wave.
+// FP64 source-plane vertices B_k of triangle `tid` for a system with distance
+// ratio r: grad Psi at the three vertices with the potentials spread over the
+// wave (fixed butterfly reduction); tx, ty are the image-plane vertices.
 __device__ __forceinline__ void vertices64(const double* __restrict__ tab64, int np, GridDesc g, int tid,
                                            double r, double* vx, double* vy, double* tx, double* ty)
 {
@@ -642,118 +745,66 @@ __device__ __forceinline__ void vertices64(const double* __restrict__ tab64, int
     }
 }
 
-// Persistent waves over the undecided tests of the mixed path.
-__global__ __launch_bounds__(256) void k_fb(const double* __restrict__ tab64, int np, GridDesc g,
-                                            const double* __restrict__ sysrow, EvalState* __restrict__ st,
-                                            const unsigned long long* __restrict__ flag_keys, long long flag_cap,
-                                            unsigned long long* __restrict__ hit_keys, long long hit_cap)
+// Predicted image position (Sec. 2.2.2, READING: barycentric interpolation):
+// image-plane vertices weighted by lambda_k = c_{k+1} / (c_0 + c_1 + c_2),
+// c_k = (B_k - p) x (B_{k+1} - p) from the FP64 source-plane triangle.
+__device__ __forceinline__ void image_position(const double* vx, const double* vy, const double* tx,
+                                               const double* ty, double px, double py, double& ox, double& oy)
 {
-    const long long nwaves = (long long)gridDim.x * (blockDim.x >> 6);
-    const long long w0 = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const long long nf = (long long)min((unsigned long long)flag_cap, st->n_flags);
-    for (long long q = w0; q < nf; q += nwaves) {
-        const unsigned long long key = flag_keys[q];
-        const int sys = (int)(key >> 32), tid = (int)(key & 0xffffffffu);
-        const double* row = sysrow + (size_t)sys * SYS_STRIDE;
-        double vx[3], vy[3], tx[3], ty[3];
-        vertices64(tab64, np, g, tid, row[SYS_R], vx, vy, tx, ty);
-        if (lane_id() == 0 && contains_exact(vx, vy, row[SYS_BX], row[SYS_BY])) {
-            const unsigned long long slot = atomicAdd(&st->n_hits, 1ull);
-            if ((long long)slot < hit_cap) hit_keys[slot] = key;
-            atomicAdd(&st->n_fb_hits, 1ull);
-        }
+    double c[3];
+#pragma unroll
+    for (int v = 0; v < 3; v++) {
+        const int w = v == 2 ? 0 : v + 1;
+        c[v] = (vx[v] - px) * (vy[w] - py) - (vy[v] - py) * (vx[w] - px);
     }
+    const double sum = c[0] + c[1] + c[2];
+    const double l0 = c[1] / sum, l1 = c[2] / sum, l2 = c[0] / sum;
+    ox = l0 * tx[0] + l1 * tx[1] + l2 * tx[2];
+    oy = l0 * ty[0] + l1 * ty[1] + l2 * ty[2];
 }
 
-// ============================================================== sort
-
-constexpr int kSortCap = (int)kHitScratch;
-
-// One workgroup of 1024 threads: bitonic sort of the hit keys (system in the
-// high word, triangle id in the low word) in LDS, then the sorted pairs and
-// the per-system counts.  Sets the capacity status if the hits (or the
-// undecided tests of the mixed path) overflowed their buffers.
-__global__ __launch_bounds__(1024) void k_sort(unsigned long long* __restrict__ hit_keys,
-                                               EvalState* __restrict__ st, long long flag_cap,
-                                               int hit_capacity, int nsys, int* __restrict__ out_hits,
-                                               int* __restrict__ n_pred)
-{
-    __shared__ unsigned long long key[kSortCap];
-    const int t = threadIdx.x;
-    const unsigned long long nh = st->n_hits;
-    const bool over = nh > (unsigned long long)hit_capacity || nh > (unsigned long long)kSortCap ||
-                      st->n_flags > (unsigned long long)flag_cap;
-    for (int s = t; s < nsys; s += 1024) n_pred[s] = 0;
-    if (over || st->status != kStatusOk) {
-        if (t == 0 && over && st->status == kStatusOk) st->status = kStatusCapacity;
-        return;
-    }
-    const int n = (int)nh;
-    int npad = 1;
-    while (npad < n) npad <<= 1;
-    for (int q = t; q < npad; q += 1024) key[q] = q < n ? hit_keys[q] : ~0ull;
-    __syncthreads();
-    for (int size = 2; size <= npad; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int q = t; q < npad / 2; q += 1024) {
-                const int lo = 2 * q - (q & (stride - 1));
-                const int hi = lo + stride;
-                const bool up = (lo & size) == 0;
-                const unsigned long long a = key[lo], b = key[hi];
-                if ((a > b) == up) {
-                    key[lo] = b;
-                    key[hi] = a;
-                }
-            }
-            __syncthreads();
-        }
-    }
-    for (int q = t; q < n; q += 1024) {
-        const unsigned long long k = key[q];
-        hit_keys[q] = k;
-        out_hits[2 * q + 0] = (int)(k >> 32);
-        out_hits[2 * q + 1] = (int)(k & 0xffffffffu);
-    }
-    __syncthreads();
-    for (int q = t; q < n; q += 1024) atomicAdd(&n_pred[(int)(key[q] >> 32)], 1);
-}
-
-// ============================================================== positions
-
-// Persistent waves over the sorted hits: barycentric interpolation of the
-// image-plane vertices with weights from the FP64 source-plane triangle,
-// lambda_k = c_{k+1} / (c_0 + c_1 + c_2), c_k = (B_k - p) x (B_{k+1} - p).
-__global__ __launch_bounds__(256) void k_pos(const double* __restrict__ tab64, int np, GridDesc g,
-                                             const double* __restrict__ sysrow, const EvalState* __restrict__ st,
-                                             int hit_capacity, const unsigned long long* __restrict__ hit_keys,
-                                             double* __restrict__ img_xy)
+// Persistent waves over the items [certain hits..., undecided tests...]:
+// the position of every certain hit goes to pos[item]; each undecided test is
+// decided exactly on its FP64 vertices and, if it is a hit, appended with its
+// position to the fallback list.
+__global__ __launch_bounds__(256) void k_fbpos(const double* __restrict__ tab64, int np, GridDesc g,
+                                               const double* __restrict__ sysrow, EvalState* __restrict__ st,
+                                               const unsigned long long* __restrict__ hit_keys, long long hit_cap,
+                                               const unsigned long long* __restrict__ flag_keys, long long flag_cap,
+                                               unsigned long long* __restrict__ fb_keys, long long fb_cap,
+                                               double* __restrict__ pos, double* __restrict__ fb_pos)
 {
     if (st->status != kStatusOk) return;
     const long long nwaves = (long long)gridDim.x * (blockDim.x >> 6);
     const long long w0 = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const long long nh = (long long)min(st->n_hits, (unsigned long long)hit_capacity);
-    for (long long q = w0; q < nh; q += nwaves) {
-        const unsigned long long key = hit_keys[q];
+    const long long nc = (long long)min((unsigned long long)hit_cap, st->n_hits);
+    const long long nf = (long long)min((unsigned long long)flag_cap, st->n_flags);
+    for (long long item = w0; item < nc + nf; item += nwaves) {
+        const bool flagged = item >= nc;
+        const unsigned long long key = flagged ? flag_keys[item - nc] : hit_keys[item];
         const int sys = (int)(key >> 32), tid = (int)(key & 0xffffffffu);
         const double* row = sysrow + (size_t)sys * SYS_STRIDE;
         double vx[3], vy[3], tx[3], ty[3];
         vertices64(tab64, np, g, tid, row[SYS_R], vx, vy, tx, ty);
         if (lane_id() == 0) {
             const double px = row[SYS_BX], py = row[SYS_BY];
-            double c[3];
-            for (int v = 0; v < 3; v++) {
-                const int w = v == 2 ? 0 : v + 1;
-                c[v] = (vx[v] - px) * (vy[w] - py) - (vy[v] - py) * (vx[w] - px);
+            if (!flagged) {
+                image_position(vx, vy, tx, ty, px, py, pos[2 * item], pos[2 * item + 1]);
+            } else if (contains_exact(vx, vy, px, py)) {
+                const unsigned long long slot = atomicAdd(&st->n_fb_hits, 1ull);
+                if ((long long)slot < fb_cap) {
+                    fb_keys[slot] = key;
+                    image_position(vx, vy, tx, ty, px, py, fb_pos[2 * slot], fb_pos[2 * slot + 1]);
+                }
             }
-            const double sum = c[0] + c[1] + c[2];
-            const double l0 = c[1] / sum, l1 = c[2] / sum, l2 = c[0] / sum;
-            img_xy[2 * q + 0] = l0 * tx[0] + l1 * tx[1] + l2 * tx[2];
-            img_xy[2 * q + 1] = l0 * ty[0] + l1 * ty[1] + l2 * ty[2];
         }
     }
 }
 
-// ============================================================== chi^2
+// ============================================================== tail
+
+constexpr int kSortCap = (int)kHitScratch;  // 8192 = 2^13
+constexpr int kIdxBits = 13;
 
 __device__ __forceinline__ int lower_bound_key(const unsigned long long* k, int n, unsigned long long v)
 {
@@ -765,41 +816,198 @@ __device__ __forceinline__ int lower_bound_key(const unsigned long long* k, int 
     return lo;
 }
 
-// One workgroup of 1024 threads.  Each observed image is paired with the
-// nearest predicted image of its system (ties to the lower triangle id); then
+// One workgroup of 1024 threads.  Merges the certain and the fallback hits,
+// sorts them by (system, triangle id) -- rank sort of packed keys
+// (system << 44 | triangle id << 13 | source index) in LDS for up to 1024
+// hits, bitonic sort beyond -- and writes the sorted (system, id) pairs with
+// their positions.  Then each observed image is paired with the nearest
+// predicted image of its system (ties to the lower triangle id),
 // chi2_i = sum_j |x_obs - x|^2 / sigma^2 in image order, +inf without any
 // predicted image, and chi^2 = sum_i chi2_i in system order (Sec. 2.2.1).
-__global__ __launch_bounds__(1024) void k_chi2(ObsPtrs obs, const EvalState* __restrict__ st, int hit_capacity,
+// Everything the matching touches is staged in LDS when it fits (up to 1024
+// hits, images and systems), so no dependent chain of global loads remains.
+// Reports capacity overflow of any list.
+constexpr int kTailStage = 1024;
+
+__global__ __launch_bounds__(1024) void k_tail(ObsPtrs obs, EvalState* __restrict__ st, long long hit_cap,
+                                               long long flag_cap, long long fb_cap, int hit_capacity,
                                                const unsigned long long* __restrict__ hit_keys,
-                                               const double* __restrict__ img_xy, double* __restrict__ contrib,
+                                               const unsigned long long* __restrict__ fb_keys,
+                                               const double* __restrict__ pos, const double* __restrict__ fb_pos,
+                                               int* __restrict__ out_hits, double* __restrict__ img_xy,
+                                               int* __restrict__ n_pred, double* __restrict__ contrib,
                                                double* __restrict__ chi2, double* __restrict__ chi2_sys,
                                                int* __restrict__ match, long long* __restrict__ stats,
-                                               long long n_tests)
+                                               long long n_tests, const unsigned* __restrict__ part, int n_parts)
 {
+    __shared__ unsigned long long key[kSortCap];
+    __shared__ double spx[kTailStage], spy[kTailStage];            // sorted image positions
+    __shared__ double sox[kTailStage], soy[kTailStage], ssg[kTailStage], scon[kTailStage];
+    __shared__ int soff[kTailStage + 1];
+    __shared__ double scs[kTailStage];
+    __shared__ int s_status;
+    __shared__ unsigned long long s_tile, s_bbox;
     const int t = threadIdx.x;
-    const bool ok = st->status == kStatusOk;
-    const int nh = ok ? (int)st->n_hits : 0;
+    const int nimg = obs.n_img, nsys = obs.n_sys;
+    const bool staged = nimg <= kTailStage && nsys <= kTailStage;
     if (t == 0) {
-        stats[0] = (long long)st->n_hits;
-        stats[1] = (long long)st->n_flags;
-        stats[2] = (long long)st->n_tile_pass;
-        stats[3] = (long long)st->n_bbox_pass;
-        stats[4] = st->status;
-        stats[5] = (long long)st->n_fb_hits;
+        s_tile = 0;
+        s_bbox = 0;
+    }
+    // independent loads first
+    if (staged) {
+        if (t < nimg) {
+            sox[t] = obs.x[t];
+            soy[t] = obs.y[t];
+            ssg[t] = obs.sigma[t];
+        }
+        if (t <= nsys) soff[t] = obs.sys_off[t];
+    }
+    __syncthreads();
+    {
+        unsigned long long a = 0, b = 0;
+        for (int q = t; q < n_parts; q += 1024) {
+            a += part[2 * q];
+            b += part[2 * q + 1];
+        }
+        if (a) atomicAdd(&s_tile, a);
+        if (b) atomicAdd(&s_bbox, b);
+    }
+    const unsigned long long nc = st->n_hits, nf = st->n_flags, nfb = st->n_fb_hits;
+    const unsigned long long total = nc + nfb;
+    __syncthreads();
+    if (t == 0) {
+        int status = st->status;
+        const bool over = nc > (unsigned long long)hit_cap || nf > (unsigned long long)flag_cap ||
+                          nfb > (unsigned long long)fb_cap || total > (unsigned long long)hit_capacity ||
+                          total > (unsigned long long)kSortCap;
+        if (status == kStatusOk && over) status = kStatusCapacity;
+        st->status = status;
+        s_status = status;
+        stats[0] = (long long)total;
+        stats[1] = (long long)nf;
+        stats[2] = (long long)s_tile;
+        stats[3] = (long long)s_bbox;
+        stats[4] = status;
+        stats[5] = (long long)nfb;
         stats[6] = n_tests;
         stats[7] = 0;
     }
-    if (!ok) {
-        for (int s = t; s < obs.n_sys; s += 1024) chi2_sys[s] = __builtin_nan("");
-        for (int j = t; j < obs.n_img; j += 1024)
+    __syncthreads();
+    if (s_status != kStatusOk) {
+        for (int s = t; s < nsys; s += 1024) {
+            chi2_sys[s] = __builtin_nan("");
+            n_pred[s] = 0;
+        }
+        for (int j = t; j < nimg; j += 1024)
             if (match) match[j] = -1;
         if (t == 0) chi2[0] = __builtin_nan("");
         return;
     }
-    for (int j = t; j < obs.n_img; j += 1024) {
-        const int s = system_of(obs.sys_off, obs.n_sys, j);
-        const int q0 = lower_bound_key(hit_keys, nh, (unsigned long long)(unsigned)s << 32);
-        const int q1 = lower_bound_key(hit_keys, nh, (unsigned long long)(unsigned)(s + 1) << 32);
+    const int n = (int)total, ncert = (int)nc;
+    int npad = 1;
+    while (npad < n) npad <<= 1;
+    for (int q = t; q < npad; q += 1024) {
+        unsigned long long k = ~0ull;
+        if (q < n) {
+            const unsigned long long h = q < ncert ? hit_keys[q] : fb_keys[q - ncert];
+            k = ((h >> 32) << 44) | ((h & 0x7fffffffull) << kIdxBits) | (unsigned long long)q;
+        }
+        key[q] = k;
+    }
+    __syncthreads();
+    if (n <= 1024) {
+        // rank sort (keys are unique): one barrier instead of log^2 of them
+        unsigned long long mine = 0;
+        int rank = 0;
+        if (t < n) {
+            mine = key[t];
+            for (int q = 0; q < n; q++) rank += key[q] < mine;
+        }
+        __syncthreads();
+        if (t < n) key[rank] = mine;
+        __syncthreads();
+    } else {
+        for (int size = 2; size <= npad; size <<= 1) {
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                for (int q = t; q < npad / 2; q += 1024) {
+                    const int lo = 2 * q - (q & (stride - 1));
+                    const int hi = lo + stride;
+                    const bool up = (lo & size) == 0;
+                    const unsigned long long a = key[lo], b = key[hi];
+                    if ((a > b) == up) {
+                        key[lo] = b;
+                        key[hi] = a;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+    }
+    const bool lds_pos = staged && n <= kTailStage;
+    for (int q = t; q < n; q += 1024) {
+        const unsigned long long k = key[q];
+        const int idx = (int)(k & ((1ull << kIdxBits) - 1));
+        out_hits[2 * q + 0] = (int)(k >> 44);
+        out_hits[2 * q + 1] = (int)((k >> kIdxBits) & 0x7fffffffull);
+        const double* src = idx < ncert ? pos + 2 * idx : fb_pos + 2 * (idx - ncert);
+        const double px = src[0], py = src[1];
+        img_xy[2 * q + 0] = px;
+        img_xy[2 * q + 1] = py;
+        if (lds_pos) {
+            spx[q] = px;
+            spy[q] = py;
+        }
+    }
+    __syncthreads();
+    if (lds_pos) {
+        // fast path: every operand in LDS
+        if (t < nimg) {
+            int lo = 0, hi = nsys - 1;  // system of image t
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (soff[mid] <= t) lo = mid; else hi = mid - 1;
+            }
+            const int q0 = lower_bound_key(key, n, (unsigned long long)lo << 44);
+            const int q1 = lower_bound_key(key, n, (unsigned long long)(lo + 1) << 44);
+            int best = -1;
+            double bd = 0.0;
+            for (int q = q0; q < q1; q++) {
+                const double dx = sox[t] - spx[q], dy = soy[t] - spy[q];
+                const double d2 = dx * dx + dy * dy;
+                if (best < 0 || d2 < bd) {
+                    best = q;
+                    bd = d2;
+                }
+            }
+            if (match) match[t] = best;
+            scon[t] = best >= 0 ? bd / (ssg[t] * ssg[t]) : 0.0;
+        }
+        __syncthreads();
+        if (t < nsys) {
+            const int q0 = lower_bound_key(key, n, (unsigned long long)t << 44);
+            const int q1 = lower_bound_key(key, n, (unsigned long long)(t + 1) << 44);
+            double cs = 0.0;
+            for (int j = soff[t]; j < soff[t + 1]; j++) cs += scon[j];
+            cs = q1 > q0 ? cs : INFINITY;
+            chi2_sys[t] = cs;
+            n_pred[t] = q1 - q0;
+            scs[t] = cs;
+        }
+        __syncthreads();
+        if (t < 64) {  // one wave: fixed-order sum of the systems
+            double v = 0.0;
+            for (int s = t; s < nsys; s += 64) v += scs[s];
+            v = wave_sum(v);
+            if (t == 0) chi2[0] = v;
+        }
+        return;
+    }
+    // general path (more than 1024 hits, images or systems)
+    for (int j = t; j < nimg; j += 1024) {
+        const int s = system_of(obs.sys_off, nsys, j);
+        const int q0 = lower_bound_key(key, n, (unsigned long long)s << 44);
+        const int q1 = lower_bound_key(key, n, (unsigned long long)(s + 1) << 44);
         int best = -1;
         double bd = 0.0;
         for (int q = q0; q < q1; q++) {
@@ -814,18 +1022,20 @@ __global__ __launch_bounds__(1024) void k_chi2(ObsPtrs obs, const EvalState* __r
         contrib[j] = best >= 0 ? bd / (obs.sigma[j] * obs.sigma[j]) : 0.0;
     }
     __syncthreads();
-    for (int s = t; s < obs.n_sys; s += 1024) {
-        const int q0 = lower_bound_key(hit_keys, nh, (unsigned long long)(unsigned)s << 32);
-        const int q1 = lower_bound_key(hit_keys, nh, (unsigned long long)(unsigned)(s + 1) << 32);
+    for (int s = t; s < nsys; s += 1024) {
+        const int q0 = lower_bound_key(key, n, (unsigned long long)s << 44);
+        const int q1 = lower_bound_key(key, n, (unsigned long long)(s + 1) << 44);
         double cs = 0.0;
         for (int j = obs.sys_off[s]; j < obs.sys_off[s + 1]; j++) cs += contrib[j];
         chi2_sys[s] = q1 > q0 ? cs : INFINITY;
+        n_pred[s] = q1 - q0;
     }
     __syncthreads();
-    if (t == 0) {
-        double tot = 0.0;
-        for (int s = 0; s < obs.n_sys; s++) tot += chi2_sys[s];
-        chi2[0] = tot;
+    if (t < 64) {
+        double v = 0.0;
+        for (int s = t; s < nsys; s += 64) v += chi2_sys[s];
+        v = wave_sum(v);
+        if (t == 0) chi2[0] = v;
     }
 }
 
@@ -885,23 +1095,14 @@ __global__ void k_export(const double* __restrict__ sysrow, int nsys, const Eval
 
 static inline unsigned cdiv(long long a, long long b) { return (unsigned)((a + b - 1) / b); }
 
-hipError_t launch_prep(const PotPtrs& pot, const GridDesc& g, double* tab64, float* tab32, double* bterm,
-                       hipStream_t s)
+hipError_t launch_head(const PotPtrs& pot, const GridDesc& g, const ObsPtrs& obs, double* tab64, float* tab32,
+                       double* bterm, double* bx, double* by, double* sysrow, EvalState* st, hipStream_t s)
 {
-    if (pot.n > 0) k_prep<<<cdiv(pot.n, 256), 256, 0, s>>>(pot, g, tab64, tab32, bterm);
-    return hipGetLastError();
-}
-
-hipError_t launch_src(const double* tab64, int np, const ObsPtrs& obs, double* bx, double* by, hipStream_t s)
-{
-    if (obs.n_img > 0) k_src<<<cdiv((long long)obs.n_img * 64, 256), 256, 0, s>>>(tab64, np, obs, bx, by);
-    return hipGetLastError();
-}
-
-hipError_t launch_bound(const double* bterm, int np, const GridDesc& g, const ObsPtrs& obs, const double* bx,
-                        const double* by, double* sysrow, EvalState* st, hipStream_t s)
-{
-    k_bound<<<1, 1024, 0, s>>>(bterm, np, g, obs, bx, by, sysrow, st);
+    long long nb = cdiv(obs.n_img, 4);
+    if (nb < cdiv(pot.n, 256)) nb = cdiv(pot.n, 256);
+    if (nb < 1) nb = 1;
+    if (nb > 1024) nb = 1024;  // grid-stride loops cover the rest
+    k_head<<<(unsigned)nb, 256, 0, s>>>(pot, g, obs, tab64, tab32, bterm, bx, by, sysrow, st);
     return hipGetLastError();
 }
 
@@ -926,49 +1127,42 @@ hipError_t launch_field64(const double* tab64, int np, const GridDesc& g, double
 
 hipError_t launch_tri32(const float* ax, const float* ay, const GridDesc& g, int nsys, const double* sysrow,
                         EvalState* st, int mode, float tau, unsigned long long* hit_keys, long long hit_cap,
-                        unsigned long long* flag_keys, long long flag_cap, hipStream_t s)
+                        unsigned long long* flag_keys, long long flag_cap, unsigned* part, hipStream_t s)
 {
     k_tri32<<<dim3(cdiv(g.nx - 1, TX), cdiv(g.ny - 1, TY)), 256, 0, s>>>(ax, ay, g, nsys, sysrow, st, mode, tau,
-                                                                           hit_keys, hit_cap, flag_keys, flag_cap);
+                                                                           hit_keys, hit_cap, flag_keys, flag_cap,
+                                                                           part);
     return hipGetLastError();
 }
 
 hipError_t launch_tri64(const double* ax, const double* ay, const GridDesc& g, int nsys, const double* sysrow,
-                        EvalState* st, unsigned long long* hit_keys, long long hit_cap, hipStream_t s)
+                        EvalState* st, unsigned long long* hit_keys, long long hit_cap, unsigned* part,
+                        hipStream_t s)
 {
     k_tri64<<<dim3(cdiv(g.nx - 1, TX), cdiv(g.ny - 1, TY)), 256, 0, s>>>(ax, ay, g, nsys, sysrow, st, hit_keys,
-                                                                           hit_cap);
+                                                                           hit_cap, part);
     return hipGetLastError();
 }
 
-hipError_t launch_fb(const double* tab64, int np, const GridDesc& g, const double* sysrow, EvalState* st,
-                     const unsigned long long* flag_keys, long long flag_cap, unsigned long long* hit_keys,
-                     long long hit_cap, hipStream_t s)
+hipError_t launch_fbpos(const double* tab64, int np, const GridDesc& g, const double* sysrow, EvalState* st,
+                        const unsigned long long* hit_keys, long long hit_cap, const unsigned long long* flag_keys,
+                        long long flag_cap, unsigned long long* fb_keys, long long fb_cap, double* pos,
+                        double* fb_pos, hipStream_t s)
 {
-    k_fb<<<256, 256, 0, s>>>(tab64, np, g, sysrow, st, flag_keys, flag_cap, hit_keys, hit_cap);
+    k_fbpos<<<256, 256, 0, s>>>(tab64, np, g, sysrow, st, hit_keys, hit_cap, flag_keys, flag_cap, fb_keys, fb_cap,
+                                pos, fb_pos);
     return hipGetLastError();
 }
 
-hipError_t launch_sort(unsigned long long* hit_keys, EvalState* st, long long flag_cap, int hit_capacity, int nsys,
-                       int* out_hits, int* n_pred, hipStream_t s)
+hipError_t launch_tail(const ObsPtrs& obs, EvalState* st, long long hit_cap, long long flag_cap, long long fb_cap,
+                       int hit_capacity, const unsigned long long* hit_keys, const unsigned long long* fb_keys,
+                       const double* pos, const double* fb_pos, int* out_hits, double* img_xy, int* n_pred,
+                       double* contrib, double* chi2, double* chi2_sys, int* match, long long* stats,
+                       long long n_tests, const unsigned* part, int n_parts, hipStream_t s)
 {
-    k_sort<<<1, 1024, 0, s>>>(hit_keys, st, flag_cap, hit_capacity, nsys, out_hits, n_pred);
-    return hipGetLastError();
-}
-
-hipError_t launch_pos(const double* tab64, int np, const GridDesc& g, const double* sysrow, const EvalState* st,
-                      int hit_capacity, const unsigned long long* hit_keys, double* img_xy, hipStream_t s)
-{
-    k_pos<<<128, 256, 0, s>>>(tab64, np, g, sysrow, st, hit_capacity, hit_keys, img_xy);
-    return hipGetLastError();
-}
-
-hipError_t launch_chi2(const ObsPtrs& obs, const EvalState* st, int hit_capacity,
-                       const unsigned long long* hit_keys, const double* img_xy, double* contrib, double* chi2,
-                       double* chi2_sys, int* match, long long* stats, long long n_tests, hipStream_t s)
-{
-    k_chi2<<<1, 1024, 0, s>>>(obs, st, hit_capacity, hit_keys, img_xy, contrib, chi2, chi2_sys, match, stats,
-                              n_tests);
+    k_tail<<<1, 1024, 0, s>>>(obs, st, hit_cap, flag_cap, fb_cap, hit_capacity, hit_keys, fb_keys, pos, fb_pos,
+                              out_hits, img_xy, n_pred, contrib, chi2, chi2_sys, match, stats, n_tests, part,
+                              n_parts);
     return hipGetLastError();
 }
 
