@@ -139,13 +139,6 @@ ObsPtrs obs_ptrs(const lens_obs* o)
     return q;
 }
 
-ObsPtrs no_obs()
-{
-    ObsPtrs q;
-    memset(&q, 0, sizeof q);
-    return q;
-}
-
 // Nodes per thread of the FP32 field kernel: enough waves to fill 256 CUs,
 // as many nodes per thread as that allows (amortises the per-row work and
 // overlaps the transcendental latency).  LENS_FIELD_NPL overrides.
@@ -204,7 +197,8 @@ int timing_end(lens_ctx* c, hipStream_t s, int slot)
     return LENS_OK;
 }
 
-// Constants, source positions, barycentres and bound: the head of every entry point.
+// Constants, source positions, barycentres and error bound: the head of every
+// entry point (obs may have no systems and no images).
 int head(lens_ctx* c, const lens_potentials* pot, const GridDesc& g, const ObsPtrs& obs, double* bx, double* by,
          hipStream_t s)
 {
@@ -220,6 +214,13 @@ int head(lens_ctx* c, const lens_potentials* pot, const GridDesc& g, const ObsPt
                     s) != hipSuccess)
         return LENS_ERR_DEVICE;
     return LENS_OK;
+}
+
+ObsPtrs no_obs()
+{
+    ObsPtrs q;
+    memset(&q, 0, sizeof q);
+    return q;
 }
 
 }  // namespace
@@ -371,13 +372,15 @@ int lens_image_chi2(lens_ctx* ctx, const lens_potentials* pot, const lens_grid* 
         (rc = ensure(ctx, B_FLAGS, (size_t)(mixed ? kFlagScratch : 1) * 8)) ||
         (rc = ensure(ctx, B_POS, (size_t)kHitScratch * 4 * 8)) || (rc = ensure(ctx, B_CONTRIB, (size_t)o.n_img * 8)))
         return rc;
-    const long long n_parts = (long long)((g.nx - 2) / kTileX + 1) * ((g.ny - 2) / kTileY + 1);
-    if ((rc = ensure(ctx, B_PART, (size_t)n_parts * 2 * 4))) return rc;
+    const int n_parts = tri_blocks(g);
+    if ((rc = ensure(ctx, B_PART, (size_t)n_parts * 2 * 4)) ||
+        (rc = ensure(ctx, B_SYS, (size_t)o.n_sys * SYS_STRIDE * 8)))
+        return rc;
     unsigned* part = (unsigned*)ctx->buf[B_PART];
     if ((rc = head(ctx, pot, g, o, (double*)ctx->buf[B_BX], (double*)ctx->buf[B_BY], stream))) return rc;
 
     const double* tab64 = (const double*)ctx->buf[B_TAB64];
-    const double* sysrow = (const double*)ctx->buf[B_SYS];
+    double* sysrow = (double*)ctx->buf[B_SYS];
     EvalState* st = (EvalState*)ctx->buf[B_STATE];
     unsigned long long* hits = (unsigned long long*)ctx->buf[B_HITS];
     unsigned long long* fb_hits = hits + kHitScratch;
@@ -385,32 +388,47 @@ int lens_image_chi2(lens_ctx* ctx, const lens_potentials* pot, const lens_grid* 
     double* pos = (double*)ctx->buf[B_POS];
     double* fb_pos = pos + 2 * kHitScratch;
     const long long flag_cap = mixed ? kFlagScratch : 0;
+
     int slot;
     if ((rc = timing_begin(ctx, stream, &slot))) return rc;
     hipError_t e;
-    if (mixed) {
-        float* ax = (float*)ctx->buf[B_FIELD];
-        float* ay = ax + nn;
-        e = launch_field32((const float*)ctx->buf[B_TAB32], np, g, ax, ay, nullptr, field_npl(g), stream);
-        if (e == hipSuccess && (rc = timing_end(ctx, stream, slot))) return rc;
-        if (e == hipSuccess)
-            e = launch_tri32(ax, ay, g, o.n_sys, sysrow, st, opts->fb_mode, (float)(opts->fb_tau * g.h * g.h), hits,
-                             kHitScratch, flags, flag_cap, part, stream);
-    } else {
-        double* ax = (double*)ctx->buf[B_FIELD];
-        double* ay = ax + nn;
-        e = launch_field64(tab64, np, g, ax, ay, nullptr, stream);
-        if (e == hipSuccess && (rc = timing_end(ctx, stream, slot))) return rc;
-        if (e == hipSuccess) e = launch_tri64(ax, ay, g, o.n_sys, sysrow, st, hits, kHitScratch, part, stream);
-    }
-    if (e == hipSuccess)
-        e = launch_fbpos(tab64, np, g, sysrow, st, hits, kHitScratch, flags, flag_cap, fb_hits, kHitScratch, pos,
-                         fb_pos, stream);
-    const long long n_tests = 2ll * (g.nx - 1) * (g.ny - 1) * o.n_sys;
-    if (e == hipSuccess)
-        e = launch_tail(o, st, kHitScratch, flag_cap, kHitScratch, opts->hit_capacity, hits, fb_hits, pos, fb_pos,
-                        out->hits, out->img_xy, out->n_pred, (double*)ctx->buf[B_CONTRIB], out->chi2, out->chi2_sys,
-                        out->match, (long long*)out->stats, n_tests, part, (int)n_parts, stream);
+    void* field = ctx->buf[B_FIELD];
+    if (mixed)
+        e = launch_field32((const float*)ctx->buf[B_TAB32], np, g, (float*)field, (float*)field + nn, nullptr,
+                           field_npl(g), stream);
+    else
+        e = launch_field64(tab64, np, g, (double*)field, (double*)field + nn, nullptr, stream);
+    if (e != hipSuccess) return LENS_ERR_DEVICE;
+    if ((rc = timing_end(ctx, stream, slot))) return rc;
+
+    if (mixed)
+        e = launch_tri32((const float*)field, (const float*)field + nn, g, o.n_sys, sysrow, st, opts->fb_mode,
+                         (float)(opts->fb_tau * g.h * g.h), hits, kHitScratch, flags, flag_cap, part, stream);
+    else
+        e = launch_tri64((const double*)field, (const double*)field + nn, g, o.n_sys, sysrow, st, hits, kHitScratch,
+                         part, stream);
+    if (e != hipSuccess) return LENS_ERR_DEVICE;
+    TailLaunch tl;
+    tl.obs = o;
+    tl.hit_cap = kHitScratch;
+    tl.flag_cap = flag_cap;
+    tl.fb_cap = kHitScratch;
+    tl.hit_capacity = opts->hit_capacity;
+    tl.hit_keys = hits;
+    tl.out_hits = out->hits;
+    tl.img_xy = out->img_xy;
+    tl.n_pred = out->n_pred;
+    tl.contrib = (double*)ctx->buf[B_CONTRIB];
+    tl.chi2 = out->chi2;
+    tl.chi2_sys = out->chi2_sys;
+    tl.match = out->match;
+    tl.stats = (long long*)out->stats;
+    tl.n_tests = 2ll * (g.nx - 1) * (g.ny - 1) * o.n_sys;
+    tl.part = part;
+    tl.n_parts = n_parts;
+    e = launch_fbpos(tab64, np, g, sysrow, st, hits, kHitScratch, flags, flag_cap, fb_hits, kHitScratch, pos, fb_pos,
+                     stream);
+    if (e == hipSuccess) e = launch_tail(tl, st, fb_hits, pos, fb_pos, stream);
     return e == hipSuccess ? LENS_OK : LENS_ERR_DEVICE;
 }
 

@@ -55,16 +55,13 @@ enum : int {
     SYS_BX = 0, SYS_BY, SYS_BXH, SYS_BXL, SYS_BYH, SYS_BYL, SYS_R, SYS_EB, SYS_STRIDE = 8
 };
 
-// Device-side state of one evaluation (zeroed by the head kernel; head_ticket is
-// zero between launches).
+// Device-side state of one evaluation (counters zeroed by the prep kernel).
 struct EvalState {
-    unsigned long long n_hits;       // hits appended (FP32-certain + fallback)
-    unsigned long long n_flags;      // tests sent to the fallback
-    unsigned long long n_tile_pass;  // (tile, system) pairs surviving the cull
-    unsigned long long n_bbox_pass;  // triangle tests surviving bbox rejection
+    unsigned long long n_hits;       // certain hits appended by the triangle stage
+    unsigned long long n_flags;      // undecided FP32 tests sent to the fallback
     unsigned long long n_fb_hits;    // hits found by the fallback
     int status;                      // LENS_OK / LENS_ERR_INVALID / LENS_ERR_CAPACITY
-    unsigned head_ticket;            // workgroups of the head kernel that finished
+    unsigned head_ticket;            // "last workgroup" ticket, zero between launches
     double e_alpha;                  // bound on |alpha_fp32 - alpha| per component
     double w_sum;                    // sum of per-potential deflection bounds
 };

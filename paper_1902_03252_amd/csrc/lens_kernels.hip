@@ -1,17 +1,18 @@
 // HIP kernels of the image-plane chi^2 path for gfx950 (MI355X).
 //
-// One chi^2 evaluation (Rexroth et al. 2019, Sec. 2.2.1-2.2.2, Fig. 1) is five
-// launches on one stream:
-//   k_head   one workgroup: per-potential constants (FP64) and domain checks,
-//            observed images -> source plane (FP64), barycentres, the FP32
-//            error bound, counters
+// One chi^2 evaluation (Rexroth et al. 2019, Sec. 2.2.1-2.2.2, Fig. 1):
+//   k_head   per-potential constants (FP64 and FP32 tables), domain checks,
+//            observed images -> source plane in FP64; the last workgroup
+//            forms the barycentres, the FP32 error bound and one row per
+//            system, and resets the counters
 //   k_field  deflection at every grid node (FP32 or FP64)          <- the time
-//   k_tri    tiles of cells: cull (tile, system) pairs, triangle containment,
-//            ballot/prefix-sum compaction of hits and of undecided FP32 tests
+//   k_tri    persistent workgroups over tiles of cells: cull (tile, system)
+//            pairs, triangle containment, ballot/prefix-sum compaction of hits
+//            and of undecided FP32 tests
 //   k_fbpos  one wave per item: FP64 re-test of each undecided test (mixed
 //            path) and the FP64 image position of every hit
-//   k_tail   one workgroup: sort of the hits in LDS, per-system counts,
-//            nearest-image matching and the FP64 chi^2 in a fixed order
+//   k_tail   one workgroup: sort of the hits, matching of observed to
+//            predicted images, FP64 chi^2 in a fixed order
 #include "lens_device.hpp"
 #include "lens_internal.hpp"
 
@@ -25,14 +26,24 @@ constexpr double kArcsecPerRad = 206264.80624709636;  // 180 * 3600 / pi
 constexpr double kU32 = 5.9604644775390625e-08;       // 2^-24, unit roundoff of FP32
 constexpr double kNodeSplitErr = 2.9802322387695312e-08;  // 2^-25 node units
 
-// ============================================================== head
+// Ticket of the "last workgroup finishes the job" pattern: every workgroup
+// publishes its global writes, then takes a ticket; the one that takes the
+// last ticket sees every other workgroup's writes and resets the ticket for
+// the next launch.
+__device__ __forceinline__ bool last_workgroup(unsigned* ticket, int* s_flag)
+{
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) *s_flag = atomicAdd(ticket, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (!*s_flag) return false;
+    __threadfence();
+    if (threadIdx.x == 0) *ticket = 0;
+    return true;
+}
 
-// Per-potential constants of potential p: domain check, FP64 and FP32 rows,
-// and the two per-potential terms of the FP32 error bound:
-//   w_p  >= |grad Psi_p| anywhere:  K (1+eps) / sqrt(1-eps)
-//   j_p  >= |Jacobian of grad Psi_p| x (absolute error of the FP32 offset):
-//          2 K (1+eps) / ((1-eps) (sqrt(a^2+rho^2)+a)) * err,  rho = elliptical
-//          distance from the centre to the nearest lattice node.
+// ============================================================== prep
+
 // FP64 table row of potential p (arcsec units), computed from the raw
 // parameters; returns whether the parameters lie in the model's domain.
 __device__ __forceinline__ bool row64(const PotPtrs& pot, int p, double* t, double& K, double& a1, double& a2)
@@ -120,37 +131,35 @@ __device__ __forceinline__ int system_of(const int* __restrict__ sys_off, int ns
     return lo;
 }
 
-// Head of every evaluation, one wave per observed image (at least one
-// workgroup of 4 waves), in two phases:
+// Head of every evaluation, one wave per observed image (at least enough
+// workgroups of 4 waves for one thread per potential), in two phases:
 //  1. every thread with a potential index writes that potential's constants
 //     (prep_one); every wave with an observed image j computes its source
 //     position beta_ij = theta_ij - r_i grad Psi(theta_ij) in FP64 (Sec. 2.2.2),
 //     grad Psi evaluated at the observed position itself from the raw
 //     parameters (the same row64 arithmetic as the table), potentials over the
 //     lanes;
-//  2. the last workgroup to finish (atomic ticket) reduces the bound terms in a
-//     fixed order and writes one row per system: barycentre (unweighted mean of
-//     its beta_ij), its node-unit split, D_LS/D_OS and the FP32 error bound E_B
-//     of source-plane offsets:
-//       E_alpha = u (64 + P) sum_p w_p + sum_p j_p + 1e-9
-//       E_B     = r E_alpha + 4u Theta + 2u r (W + E_alpha) + 2^-25 h + 1e-9
-//     with u = 2^-24, W = sum_p w_p and Theta = max |theta - barycentre| over
-//     the grid.  64 u w_p bounds the rounding of one potential's FP32
-//     evaluation (about 30 u w_p by operation count, doubled), (P-1) u W the
-//     sequential FP32 sum over potentials, sum_p j_p the Jacobian-amplified
-//     absolute offset error.  It also zeroes the counters and resets the ticket.
+//  2. the last workgroup to finish reduces the bound terms in a fixed order,
+//       E_alpha = u (64 + P) sum_p w_p + sum_p j_p + 1e-9,   u = 2^-24,
+//     (64 u w_p bounds the rounding of one potential's FP32 evaluation --
+//     about 30 u w_p by operation count, doubled -- (P-1) u W the sequential
+//     FP32 sum over potentials, sum_p j_p the Jacobian-amplified absolute
+//     offset error), and writes one row per system: barycentre (unweighted
+//     mean of its beta_ij), its node-unit split, D_LS/D_OS and the FP32 error
+//     bound of source-plane offsets
+//       E_B = r E_alpha + 4u Theta + 2u r (W + E_alpha) + 2^-25 h + 1e-9,
+//     W = sum_p w_p, Theta = max |theta - barycentre| over the grid; it sets
+//     the status from every domain check and zeroes the counters.
 __global__ __launch_bounds__(256) void k_head(PotPtrs pot, GridDesc g, ObsPtrs obs, double* __restrict__ tab64,
                                               float* __restrict__ tab32, double* __restrict__ bterm,
                                               double* __restrict__ beta_x, double* __restrict__ beta_y,
                                               double* __restrict__ sysrow, EvalState* __restrict__ st)
 {
     __shared__ double sw[256], sj[256], sb[256];
-    __shared__ int sys_bad, last;
+    __shared__ int last, sys_bad;
     const int t = threadIdx.x;
     const int np = pot.n;
-    const int nthreads = gridDim.x * 256;
-    for (int p = blockIdx.x * 256 + t; p < np; p += nthreads) prep_one(pot, g, p, tab64, tab32, bterm);
-
+    for (int p = blockIdx.x * 256 + t; p < np; p += gridDim.x * 256) prep_one(pot, g, p, tab64, tab32, bterm);
     const int nwaves = gridDim.x * 4;
     for (int j = blockIdx.x * 4 + (t >> 6); j < obs.n_img; j += nwaves) {
         const double t1 = obs.x[j], t2 = obs.y[j];
@@ -168,18 +177,7 @@ __global__ __launch_bounds__(256) void k_head(PotPtrs pot, GridDesc g, ObsPtrs o
             beta_y[j] = t2 - r * a2;
         }
     }
-
-    // the last workgroup to arrive continues with the reductions
-    __threadfence();
-    __syncthreads();
-    if (t == 0) {
-        const unsigned ticket = atomicAdd(&st->head_ticket, 1u);
-        last = ticket == gridDim.x - 1;
-        sys_bad = 0;
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
+    if (!last_workgroup(&st->head_ticket, &last)) return;
 
     double w = 0.0, jt = 0.0, bad = 0.0;
     for (int p = t; p < np; p += 256) {
@@ -190,6 +188,7 @@ __global__ __launch_bounds__(256) void k_head(PotPtrs pot, GridDesc g, ObsPtrs o
     sw[t] = w;
     sj[t] = jt;
     sb[t] = bad;
+    if (t == 0) sys_bad = obs.n_sys > 0 && (obs.sys_off[0] != 0 || obs.sys_off[obs.n_sys] != obs.n_img);
     __syncthreads();
     for (int m = 128; m >= 1; m >>= 1) {
         if (t < m) {
@@ -201,17 +200,6 @@ __global__ __launch_bounds__(256) void k_head(PotPtrs pot, GridDesc g, ObsPtrs o
     }
     const double W = sw[0];
     const double e_alpha = kU32 * (64.0 + np) * W + sj[0] + 1e-9;
-    if (t == 0) {
-        st->head_ticket = 0;
-        st->n_hits = 0;
-        st->n_flags = 0;
-        st->n_tile_pass = 0;
-        st->n_bbox_pass = 0;
-        st->n_fb_hits = 0;
-        st->e_alpha = e_alpha;
-        st->w_sum = W;
-        if (obs.n_sys > 0 && (obs.sys_off[0] != 0 || obs.sys_off[obs.n_sys] != obs.n_img)) atomicOr(&sys_bad, 1);
-    }
     const double xlo = g.x0, xhi = g.x0 + (g.nx - 1) * g.h, ylo = g.y0, yhi = g.y0 + (g.ny - 1) * g.h;
     for (int s = t; s < obs.n_sys; s += 256) {
         const int j0 = obs.sys_off[s], j1 = obs.sys_off[s + 1];
@@ -247,7 +235,14 @@ __global__ __launch_bounds__(256) void k_head(PotPtrs pot, GridDesc g, ObsPtrs o
         if (!ok) atomicOr(&sys_bad, 1);
     }
     __syncthreads();
-    if (t == 0) st->status = (sb[0] != 0.0 || sys_bad) ? kStatusInvalid : kStatusOk;
+    if (t == 0) {
+        st->n_hits = 0;
+        st->n_flags = 0;
+        st->n_fb_hits = 0;
+        st->w_sum = W;
+        st->e_alpha = e_alpha;
+        st->status = (sb[0] != 0.0 || sys_bad) ? kStatusInvalid : kStatusOk;
+    }
 }
 
 // ============================================================== deflection field
@@ -428,30 +423,6 @@ __device__ __forceinline__ int decide32(const float* dx, const float* dy, float 
     return kFlag;
 }
 
-// Block-wide min/max, result broadcast through LDS.
-template <typename T>
-__device__ __forceinline__ void tile_range(T& vmin, T& vmax, T* red /* [8] */)
-{
-    for (int m = 32; m >= 1; m >>= 1) {
-        const T a = __shfl_xor(vmin, m, 64), b = __shfl_xor(vmax, m, 64);
-        vmin = a < vmin ? a : vmin;
-        vmax = b > vmax ? b : vmax;
-    }
-    const int w = threadIdx.x >> 6;
-    if (lane_id() == 0) {
-        red[2 * w] = vmin;
-        red[2 * w + 1] = vmax;
-    }
-    __syncthreads();
-    vmin = red[0];
-    vmax = red[1];
-    for (int k = 1; k < 4; k++) {
-        vmin = red[2 * k] < vmin ? red[2 * k] : vmin;
-        vmax = red[2 * k + 1] > vmax ? red[2 * k + 1] : vmax;
-    }
-    __syncthreads();
-}
-
 // Per-system data of one chunk of systems, staged in LDS by the tile kernels.
 struct SysChunk {
     double bx[SYS_CHUNK], by[SYS_CHUNK], r[SYS_CHUNK], eb[SYS_CHUNK];
@@ -478,38 +449,46 @@ __device__ __forceinline__ void load_chunk(SysChunk& c, const double* __restrict
     }
 }
 
-// Mixed path, one workgroup (4 waves) per tile of TX x TY cells.  The tile's
-// FP32 deflections (with a one-node halo) are staged in LDS -- every load of
-// the tile is issued before the first wait -- together with the systems.  The
-// box [theta_min - r alpha_max, theta_max - r alpha_min] (per axis, widened by
-// E_B) contains every source-plane vertex of the tile, so a system whose
-// barycentre lies outside it is skipped for the whole tile.  Systems are
-// tested 64 at a time, one per lane, and the survivors enumerated from the
-// ballot mask.
-__global__ __launch_bounds__(256) void k_tri32(const float* __restrict__ ax, const float* __restrict__ ay,
-                                               GridDesc g, int nsys, const double* __restrict__ sysrow,
-                                               EvalState* __restrict__ st, int mode, float tau,
-                                               unsigned long long* __restrict__ hit_keys, long long hit_cap,
-                                               unsigned long long* __restrict__ flag_keys, long long flag_cap,
-                                               unsigned* __restrict__ part)
+// Tile geometry from a linear tile index.
+struct Tile {
+    int ci0, cj0, ncx, ncy;
+};
+
+__device__ __forceinline__ Tile tile_of(const GridDesc& g, int tiles_x, int tile)
 {
-    __shared__ float sx[TNY][TNX], sy[TNY][TNX];
-    __shared__ float red[8];
-    __shared__ SysChunk chunk;
-    const int ci0 = blockIdx.x * TX, cj0 = blockIdx.y * TY;
-    const int ncx = min(TX, g.nx - 1 - ci0), ncy = min(TY, g.ny - 1 - cj0);
-    float vx[TLOADS], vy[TLOADS];
+    Tile T;
+    T.ci0 = (tile % tiles_x) * TX;
+    T.cj0 = (tile / tiles_x) * TY;
+    T.ncx = min(TX, g.nx - 1 - T.ci0);
+    T.ncy = min(TY, g.ny - 1 - T.cj0);
+    return T;
+}
+
+// Issues every load of a tile's node values (with the one-node halo) into
+// registers; nothing waits for them here.
+template <typename V>
+__device__ __forceinline__ void load_tile(const V* __restrict__ ax, const V* __restrict__ ay, const GridDesc& g,
+                                          const Tile& T, V* vx, V* vy)
+{
 #pragma unroll
     for (int k = 0; k < TLOADS; k++) {
         const int q = threadIdx.x + 256 * k;
         const int li = q % TNX, lj = q / TNX;
-        const bool in = q < TNX * TNY && li <= ncx && lj <= ncy;
-        const size_t n = in ? (size_t)(cj0 + lj) * g.nx + (ci0 + li) : 0;
-        vx[k] = in ? ax[n] : 0.0f;
-        vy[k] = in ? ay[n] : 0.0f;
+        const bool in = q < TNX * TNY && li <= T.ncx && lj <= T.ncy;
+        const size_t n = in ? (size_t)(T.cj0 + lj) * g.nx + (T.ci0 + li) : 0;
+        vx[k] = in ? ax[n] : V(0);
+        vy[k] = in ? ay[n] : V(0);
     }
-    load_chunk(chunk, sysrow, nsys, 0);
-    float xmn = INFINITY, xmx = -INFINITY, ymn = INFINITY, ymx = -INFINITY;
+}
+
+// Stores the registers of a tile to LDS and leaves the tile's deflection range
+// (min/max of each component over its nodes) in rng[0..3] for every thread.
+// Contains the workgroup barrier that publishes the LDS tile.
+template <typename V>
+__device__ __forceinline__ void stage_tile(const Tile& T, const V* vx, const V* vy, V (*sx)[TNX], V (*sy)[TNX],
+                                           V (*wred)[4], V* rng)
+{
+    V xmn = V(INFINITY), xmx = V(-INFINITY), ymn = V(INFINITY), ymx = V(-INFINITY);
 #pragma unroll
     for (int k = 0; k < TLOADS; k++) {
         const int q = threadIdx.x + 256 * k;
@@ -517,204 +496,253 @@ __global__ __launch_bounds__(256) void k_tri32(const float* __restrict__ ax, con
         if (q < TNX * TNY) {
             sx[lj][li] = vx[k];
             sy[lj][li] = vy[k];
-            if (li <= ncx && lj <= ncy) {
-                xmn = fminf(xmn, vx[k]);
-                xmx = fmaxf(xmx, vx[k]);
-                ymn = fminf(ymn, vy[k]);
-                ymx = fmaxf(ymx, vy[k]);
+            if (li <= T.ncx && lj <= T.ncy) {
+                xmn = vx[k] < xmn ? vx[k] : xmn;
+                xmx = vx[k] > xmx ? vx[k] : xmx;
+                ymn = vy[k] < ymn ? vy[k] : ymn;
+                ymx = vy[k] > ymx ? vy[k] : ymx;
             }
         }
     }
-    __syncthreads();
-    tile_range(xmn, xmx, red);
-    tile_range(ymn, ymx, red);
-    const double tx0 = g.x0 + ci0 * g.h, tx1 = g.x0 + (ci0 + ncx) * g.h;
-    const double ty0 = g.y0 + cj0 * g.h, ty1 = g.y0 + (cj0 + ncy) * g.h;
-    const float h32 = (float)g.h;
-    const int lane = lane_id();
-    unsigned nbbox = 0, ntile = 0;
-    for (int cbase = 0; cbase < nsys; cbase += SYS_CHUNK) {
-        if (cbase > 0) {
-            __syncthreads();
-            load_chunk(chunk, sysrow, nsys, cbase);
-            __syncthreads();
-        }
-        const int nc = min(SYS_CHUNK, nsys - cbase);
-        for (int sbase = 0; sbase < nc; sbase += 64) {
-            const int sl = sbase + lane;
-            bool pass = false;
-            if (sl < nc) {
-                const double r = chunk.r[sl], eb = chunk.eb[sl], bx = chunk.bx[sl], by = chunk.by[sl];
-                pass = bx >= tx0 - r * xmx - eb && bx <= tx1 - r * xmn + eb && by >= ty0 - r * ymx - eb &&
-                       by <= ty1 - r * ymn + eb;
-            }
-            unsigned long long m = __ballot(pass);
-            ntile += __popcll(m);
-            while (m) {
-                const int sb = __ffsll((long long)m) - 1;
-                m &= m - 1;
-                const int s = sbase + sb;
-                const int sys = cbase + s;
-                const float r = chunk.f[s][0], E = chunk.f[s][1];
-                const float bxh = chunk.f[s][2], bxl = chunk.f[s][3], byh = chunk.f[s][4], byl = chunk.f[s][5];
-#pragma unroll
-                for (int it = 0; it < kCellIters; it++) {
-                    const int cidx = threadIdx.x + 256 * it;
-                    const int li = cidx % TX, lj = cidx / TX;
-                    const bool valid = li < ncx && lj < ncy;
-                    const int gi = ci0 + li, gj = cj0 + lj;
-                    // offsets theta - barycentre in node units (exact hi part), then arcsec
-                    const float ex0 = (((float)gi - bxh) - bxl) * h32, ex1 = (((float)(gi + 1) - bxh) - bxl) * h32;
-                    const float ey0 = (((float)gj - byh) - byl) * h32, ey1 = (((float)(gj + 1) - byh) - byl) * h32;
-                    const float d00x = fmaf(-r, sx[lj][li], ex0), d00y = fmaf(-r, sy[lj][li], ey0);
-                    const float d10x = fmaf(-r, sx[lj][li + 1], ex1), d10y = fmaf(-r, sy[lj][li + 1], ey0);
-                    const float d01x = fmaf(-r, sx[lj + 1][li], ex0), d01y = fmaf(-r, sy[lj + 1][li], ey1);
-                    const float d11x = fmaf(-r, sx[lj + 1][li + 1], ex1), d11y = fmaf(-r, sy[lj + 1][li + 1], ey1);
-                    int res0 = kMiss, res1 = kMiss;
-                    if (valid) {
-                        const float tx[3] = {d00x, d10x, d01x}, ty[3] = {d00y, d10y, d01y};
-                        const float ux[3] = {d11x, d01x, d10x}, uy[3] = {d11y, d01y, d10y};
-                        res0 = decide32(tx, ty, E, mode, tau, nbbox);
-                        res1 = decide32(ux, uy, E, mode, tau, nbbox);
-                    }
-                    const int tid0 = 2 * (gj * (g.nx - 1) + gi);
-                    wave_append(res0 == kHit, hit_key(sys, tid0), &st->n_hits, hit_keys, hit_cap);
-                    wave_append(res1 == kHit, hit_key(sys, tid0 + 1), &st->n_hits, hit_keys, hit_cap);
-                    wave_append(res0 == kFlag, hit_key(sys, tid0), &st->n_flags, flag_keys, flag_cap);
-                    wave_append(res1 == kFlag, hit_key(sys, tid0 + 1), &st->n_flags, flag_keys, flag_cap);
-                }
-            }
-        }
+    for (int m = 32; m >= 1; m >>= 1) {
+        const V a = __shfl_xor(xmn, m, 64), b = __shfl_xor(xmx, m, 64);
+        const V c = __shfl_xor(ymn, m, 64), d = __shfl_xor(ymx, m, 64);
+        xmn = a < xmn ? a : xmn;
+        xmx = b > xmx ? b : xmx;
+        ymn = c < ymn ? c : ymn;
+        ymx = d > ymx ? d : ymx;
     }
-    // per-workgroup statistics without a contended global atomic
-    for (int m = 32; m >= 1; m >>= 1) nbbox += __shfl_xor(nbbox, m, 64);
-    __shared__ unsigned sbb[4];
-    if (lane == 0) sbb[threadIdx.x >> 6] = nbbox;
+    if (lane_id() == 0) {
+        const int w = threadIdx.x >> 6;
+        wred[w][0] = xmn;
+        wred[w][1] = xmx;
+        wred[w][2] = ymn;
+        wred[w][3] = ymx;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        const size_t b = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
-        part[2 * b + 0] = ntile;
-        part[2 * b + 1] = sbb[0] + sbb[1] + sbb[2] + sbb[3];
+    rng[0] = wred[0][0];
+    rng[1] = wred[0][1];
+    rng[2] = wred[0][2];
+    rng[3] = wred[0][3];
+    for (int w = 1; w < 4; w++) {
+        rng[0] = wred[w][0] < rng[0] ? wred[w][0] : rng[0];
+        rng[1] = wred[w][1] > rng[1] ? wred[w][1] : rng[1];
+        rng[2] = wred[w][2] < rng[2] ? wred[w][2] : rng[2];
+        rng[3] = wred[w][3] > rng[3] ? wred[w][3] : rng[3];
     }
 }
 
-// FP64 path: same tiling, FP64 deflections in LDS, every surviving triangle
+// Writes the workgroup's statistics to its own slot (no contended atomic).
+__device__ __forceinline__ void write_part(unsigned* part, unsigned ntile, unsigned nbbox, unsigned* sbb)
+{
+    for (int m = 32; m >= 1; m >>= 1) nbbox += __shfl_xor(nbbox, m, 64);
+    if (lane_id() == 0) sbb[threadIdx.x >> 6] = nbbox;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x + 0] = ntile;
+        part[2 * blockIdx.x + 1] = sbb[0] + sbb[1] + sbb[2] + sbb[3];
+    }
+}
+
+// Mixed path.  Persistent workgroups (4 waves) walk the tiles of TX x TY
+// cells; the loads of the next tile are in flight while the current one is
+// processed.  A tile's FP32 deflections (with a one-node halo) are staged in
+// LDS.  The box [theta_min - r alpha_max, theta_max - r alpha_min] (per axis,
+// widened by E_B) contains every source-plane vertex of the tile, so a system
+// whose barycentre lies outside it is skipped for the whole tile.  Systems
+// are tested 64 at a time, one per lane, and the survivors enumerated from
+// the ballot mask.
+__global__ __launch_bounds__(256) void k_tri32(const float* __restrict__ ax, const float* __restrict__ ay,
+                                               GridDesc g, int tiles_x, int n_tiles, int nsys,
+                                               const double* __restrict__ sysrow, EvalState* __restrict__ st,
+                                               int mode, float tau, unsigned long long* __restrict__ hit_keys,
+                                               long long hit_cap, unsigned long long* __restrict__ flag_keys,
+                                               long long flag_cap, unsigned* __restrict__ part)
+{
+    __shared__ float sx[TNY][TNX], sy[TNY][TNX];
+    __shared__ float wred[4][4];
+    __shared__ SysChunk chunk;
+    __shared__ unsigned sbb[4];
+    const bool one_chunk = nsys <= SYS_CHUNK;
+    if (one_chunk) load_chunk(chunk, sysrow, nsys, 0);
+    const float h32 = (float)g.h;
+    const int lane = lane_id();
+    unsigned nbbox = 0, ntile = 0;
+    float vx[TLOADS], vy[TLOADS];
+    int tile = blockIdx.x;
+    Tile T = tile_of(g, tiles_x, tile);
+    if (tile < n_tiles) load_tile(ax, ay, g, T, vx, vy);
+    for (; tile < n_tiles; tile += gridDim.x) {
+        float rng[4];
+        stage_tile(T, vx, vy, sx, sy, wred, rng);
+        const Tile cur = T;
+        const int next = tile + gridDim.x;
+        if (next < n_tiles) {
+            T = tile_of(g, tiles_x, next);
+            load_tile(ax, ay, g, T, vx, vy);
+        }
+        const double tx0 = g.x0 + cur.ci0 * g.h, tx1 = g.x0 + (cur.ci0 + cur.ncx) * g.h;
+        const double ty0 = g.y0 + cur.cj0 * g.h, ty1 = g.y0 + (cur.cj0 + cur.ncy) * g.h;
+        const double xmn = rng[0], xmx = rng[1], ymn = rng[2], ymx = rng[3];
+        for (int cbase = 0; cbase < nsys; cbase += SYS_CHUNK) {
+            if (!one_chunk) {
+                __syncthreads();
+                load_chunk(chunk, sysrow, nsys, cbase);
+                __syncthreads();
+            }
+            const int nc = min(SYS_CHUNK, nsys - cbase);
+            for (int sbase = 0; sbase < nc; sbase += 64) {
+                const int sl = sbase + lane;
+                bool pass = false;
+                if (sl < nc) {
+                    const double r = chunk.r[sl], eb = chunk.eb[sl], bx = chunk.bx[sl], by = chunk.by[sl];
+                    pass = bx >= tx0 - r * xmx - eb && bx <= tx1 - r * xmn + eb && by >= ty0 - r * ymx - eb &&
+                           by <= ty1 - r * ymn + eb;
+                }
+                unsigned long long m = __ballot(pass);
+                ntile += __popcll(m);
+                while (m) {
+                    const int sb = __ffsll((long long)m) - 1;
+                    m &= m - 1;
+                    const int s = sbase + sb;
+                    const int sys = cbase + s;
+                    const float r = chunk.f[s][0], E = chunk.f[s][1];
+                    const float bxh = chunk.f[s][2], bxl = chunk.f[s][3], byh = chunk.f[s][4], byl = chunk.f[s][5];
+#pragma unroll
+                    for (int it = 0; it < kCellIters; it++) {
+                        const int cidx = threadIdx.x + 256 * it;
+                        const int li = cidx % TX, lj = cidx / TX;
+                        const bool valid = li < cur.ncx && lj < cur.ncy;
+                        const int gi = cur.ci0 + li, gj = cur.cj0 + lj;
+                        // offsets theta - barycentre in node units (exact hi part), then arcsec
+                        const float ex0 = (((float)gi - bxh) - bxl) * h32;
+                        const float ex1 = (((float)(gi + 1) - bxh) - bxl) * h32;
+                        const float ey0 = (((float)gj - byh) - byl) * h32;
+                        const float ey1 = (((float)(gj + 1) - byh) - byl) * h32;
+                        const float d00x = fmaf(-r, sx[lj][li], ex0), d00y = fmaf(-r, sy[lj][li], ey0);
+                        const float d10x = fmaf(-r, sx[lj][li + 1], ex1), d10y = fmaf(-r, sy[lj][li + 1], ey0);
+                        const float d01x = fmaf(-r, sx[lj + 1][li], ex0), d01y = fmaf(-r, sy[lj + 1][li], ey1);
+                        const float d11x = fmaf(-r, sx[lj + 1][li + 1], ex1);
+                        const float d11y = fmaf(-r, sy[lj + 1][li + 1], ey1);
+                        int res0 = kMiss, res1 = kMiss;
+                        if (valid) {
+                            const float tx[3] = {d00x, d10x, d01x}, ty[3] = {d00y, d10y, d01y};
+                            const float ux[3] = {d11x, d01x, d10x}, uy[3] = {d11y, d01y, d10y};
+                            res0 = decide32(tx, ty, E, mode, tau, nbbox);
+                            res1 = decide32(ux, uy, E, mode, tau, nbbox);
+                        }
+                        const int tid0 = 2 * (gj * (g.nx - 1) + gi);
+                        wave_append(res0 == kHit, hit_key(sys, tid0), &st->n_hits, hit_keys, hit_cap);
+                        wave_append(res1 == kHit, hit_key(sys, tid0 + 1), &st->n_hits, hit_keys, hit_cap);
+                        wave_append(res0 == kFlag, hit_key(sys, tid0), &st->n_flags, flag_keys, flag_cap);
+                        wave_append(res1 == kFlag, hit_key(sys, tid0 + 1), &st->n_flags, flag_keys, flag_cap);
+                    }
+                }
+            }
+        }
+        __syncthreads();  // the LDS tile is overwritten by the next iteration
+    }
+    write_part(part, ntile, nbbox, sbb);
+}
+
+// FP64 path: same walk, FP64 deflections in LDS, every surviving triangle
 // decided exactly (exact bounding box, then exact orientation signs).
 __global__ __launch_bounds__(256) void k_tri64(const double* __restrict__ ax, const double* __restrict__ ay,
-                                               GridDesc g, int nsys, const double* __restrict__ sysrow,
-                                               EvalState* __restrict__ st,
+                                               GridDesc g, int tiles_x, int n_tiles, int nsys,
+                                               const double* __restrict__ sysrow, EvalState* __restrict__ st,
                                                unsigned long long* __restrict__ hit_keys, long long hit_cap,
                                                unsigned* __restrict__ part)
 {
     __shared__ double sx[TNY][TNX], sy[TNY][TNX];
-    __shared__ double red[8];
+    __shared__ double wred[4][4];
     __shared__ SysChunk chunk;
-    const int ci0 = blockIdx.x * TX, cj0 = blockIdx.y * TY;
-    const int ncx = min(TX, g.nx - 1 - ci0), ncy = min(TY, g.ny - 1 - cj0);
-    double vx[TLOADS], vy[TLOADS];
-#pragma unroll
-    for (int k = 0; k < TLOADS; k++) {
-        const int q = threadIdx.x + 256 * k;
-        const int li = q % TNX, lj = q / TNX;
-        const bool in = q < TNX * TNY && li <= ncx && lj <= ncy;
-        const size_t n = in ? (size_t)(cj0 + lj) * g.nx + (ci0 + li) : 0;
-        vx[k] = in ? ax[n] : 0.0;
-        vy[k] = in ? ay[n] : 0.0;
-    }
-    load_chunk(chunk, sysrow, nsys, 0);
-    double xmn = INFINITY, xmx = -INFINITY, ymn = INFINITY, ymx = -INFINITY;
-#pragma unroll
-    for (int k = 0; k < TLOADS; k++) {
-        const int q = threadIdx.x + 256 * k;
-        const int li = q % TNX, lj = q / TNX;
-        if (q < TNX * TNY) {
-            sx[lj][li] = vx[k];
-            sy[lj][li] = vy[k];
-            if (li <= ncx && lj <= ncy) {
-                xmn = fmin(xmn, vx[k]);
-                xmx = fmax(xmx, vx[k]);
-                ymn = fmin(ymn, vy[k]);
-                ymx = fmax(ymx, vy[k]);
-            }
-        }
-    }
-    __syncthreads();
-    tile_range(xmn, xmx, red);
-    tile_range(ymn, ymx, red);
-    const double tx0 = g.x0 + ci0 * g.h, tx1 = g.x0 + (ci0 + ncx) * g.h;
-    const double ty0 = g.y0 + cj0 * g.h, ty1 = g.y0 + (cj0 + ncy) * g.h;
+    __shared__ unsigned sbb[4];
+    const bool one_chunk = nsys <= SYS_CHUNK;
+    if (one_chunk) load_chunk(chunk, sysrow, nsys, 0);
     const int lane = lane_id();
     unsigned nbbox = 0, ntile = 0;
-    for (int cbase = 0; cbase < nsys; cbase += SYS_CHUNK) {
-        if (cbase > 0) {
-            __syncthreads();
-            load_chunk(chunk, sysrow, nsys, cbase);
-            __syncthreads();
+    double vx[TLOADS], vy[TLOADS];
+    int tile = blockIdx.x;
+    Tile T = tile_of(g, tiles_x, tile);
+    if (tile < n_tiles) load_tile(ax, ay, g, T, vx, vy);
+    for (; tile < n_tiles; tile += gridDim.x) {
+        double rng[4];
+        stage_tile(T, vx, vy, sx, sy, wred, rng);
+        const Tile cur = T;
+        const int next = tile + gridDim.x;
+        if (next < n_tiles) {
+            T = tile_of(g, tiles_x, next);
+            load_tile(ax, ay, g, T, vx, vy);
         }
-        const int nc = min(SYS_CHUNK, nsys - cbase);
-        for (int sbase = 0; sbase < nc; sbase += 64) {
-            const int sl = sbase + lane;
-            bool pass = false;
-            if (sl < nc) {
-                const double r = chunk.r[sl], bx = chunk.bx[sl], by = chunk.by[sl];
-                const double eb = 1e-9;  // FP64 rounding of the box, far below this margin
-                pass = bx >= tx0 - r * xmx - eb && bx <= tx1 - r * xmn + eb && by >= ty0 - r * ymx - eb &&
-                       by <= ty1 - r * ymn + eb;
+        const double tx0 = g.x0 + cur.ci0 * g.h, tx1 = g.x0 + (cur.ci0 + cur.ncx) * g.h;
+        const double ty0 = g.y0 + cur.cj0 * g.h, ty1 = g.y0 + (cur.cj0 + cur.ncy) * g.h;
+        for (int cbase = 0; cbase < nsys; cbase += SYS_CHUNK) {
+            if (!one_chunk) {
+                __syncthreads();
+                load_chunk(chunk, sysrow, nsys, cbase);
+                __syncthreads();
             }
-            unsigned long long m = __ballot(pass);
-            ntile += __popcll(m);
-            while (m) {
-                const int sb = __ffsll((long long)m) - 1;
-                m &= m - 1;
-                const int s = sbase + sb;
-                const int sys = cbase + s;
-                const double r = chunk.r[s], bx = chunk.bx[s], by = chunk.by[s];
+            const int nc = min(SYS_CHUNK, nsys - cbase);
+            for (int sbase = 0; sbase < nc; sbase += 64) {
+                const int sl = sbase + lane;
+                bool pass = false;
+                if (sl < nc) {
+                    const double r = chunk.r[sl], bx = chunk.bx[sl], by = chunk.by[sl];
+                    const double eb = 1e-9;  // FP64 rounding of the box, far below this margin
+                    pass = bx >= tx0 - r * rng[1] - eb && bx <= tx1 - r * rng[0] + eb &&
+                           by >= ty0 - r * rng[3] - eb && by <= ty1 - r * rng[2] + eb;
+                }
+                unsigned long long m = __ballot(pass);
+                ntile += __popcll(m);
+                while (m) {
+                    const int sb = __ffsll((long long)m) - 1;
+                    m &= m - 1;
+                    const int s = sbase + sb;
+                    const int sys = cbase + s;
+                    const double r = chunk.r[s], bx = chunk.bx[s], by = chunk.by[s];
 #pragma unroll 1
-                for (int it = 0; it < kCellIters; it++) {
-                    const int cidx = threadIdx.x + 256 * it;
-                    const int li = cidx % TX, lj = cidx / TX;
-                    const bool valid = li < ncx && lj < ncy;
-                    const int gi = ci0 + li, gj = cj0 + lj;
-                    bool h0 = false, h1 = false;
-                    if (valid) {
-                        const double t0x = g.x0 + gi * g.h, t1x = g.x0 + (gi + 1) * g.h;
-                        const double t0y = g.y0 + gj * g.h, t1y = g.y0 + (gj + 1) * g.h;
-                        const double b00x = t0x - r * sx[lj][li], b00y = t0y - r * sy[lj][li];
-                        const double b10x = t1x - r * sx[lj][li + 1], b10y = t0y - r * sy[lj][li + 1];
-                        const double b01x = t0x - r * sx[lj + 1][li], b01y = t1y - r * sy[lj + 1][li];
-                        const double b11x = t1x - r * sx[lj + 1][li + 1], b11y = t1y - r * sy[lj + 1][li + 1];
-                        const double vx0[3] = {b00x, b10x, b01x}, vy0[3] = {b00y, b10y, b01y};
-                        const double vx1[3] = {b11x, b01x, b10x}, vy1[3] = {b11y, b01y, b10y};
-                        const double lo0 = fmin(vx0[0], fmin(vx0[1], vx0[2])), hi0 = fmax(vx0[0], fmax(vx0[1], vx0[2]));
-                        const double lo1 = fmin(vy0[0], fmin(vy0[1], vy0[2])), hi1 = fmax(vy0[0], fmax(vy0[1], vy0[2]));
-                        if (!(bx < lo0 || bx > hi0 || by < lo1 || by > hi1)) {
-                            nbbox++;
-                            h0 = contains_exact(vx0, vy0, bx, by);
+                    for (int it = 0; it < kCellIters; it++) {
+                        const int cidx = threadIdx.x + 256 * it;
+                        const int li = cidx % TX, lj = cidx / TX;
+                        const bool valid = li < cur.ncx && lj < cur.ncy;
+                        const int gi = cur.ci0 + li, gj = cur.cj0 + lj;
+                        bool h0 = false, h1 = false;
+                        if (valid) {
+                            const double t0x = g.x0 + gi * g.h, t1x = g.x0 + (gi + 1) * g.h;
+                            const double t0y = g.y0 + gj * g.h, t1y = g.y0 + (gj + 1) * g.h;
+                            const double b00x = t0x - r * sx[lj][li], b00y = t0y - r * sy[lj][li];
+                            const double b10x = t1x - r * sx[lj][li + 1], b10y = t0y - r * sy[lj][li + 1];
+                            const double b01x = t0x - r * sx[lj + 1][li], b01y = t1y - r * sy[lj + 1][li];
+                            const double b11x = t1x - r * sx[lj + 1][li + 1], b11y = t1y - r * sy[lj + 1][li + 1];
+                            const double vx0[3] = {b00x, b10x, b01x}, vy0[3] = {b00y, b10y, b01y};
+                            const double vx1[3] = {b11x, b01x, b10x}, vy1[3] = {b11y, b01y, b10y};
+                            const double lo0 = fmin(vx0[0], fmin(vx0[1], vx0[2]));
+                            const double hi0 = fmax(vx0[0], fmax(vx0[1], vx0[2]));
+                            const double lo1 = fmin(vy0[0], fmin(vy0[1], vy0[2]));
+                            const double hi1 = fmax(vy0[0], fmax(vy0[1], vy0[2]));
+                            if (!(bx < lo0 || bx > hi0 || by < lo1 || by > hi1)) {
+                                nbbox++;
+                                h0 = contains_exact(vx0, vy0, bx, by);
+                            }
+                            const double lo2 = fmin(vx1[0], fmin(vx1[1], vx1[2]));
+                            const double hi2 = fmax(vx1[0], fmax(vx1[1], vx1[2]));
+                            const double lo3 = fmin(vy1[0], fmin(vy1[1], vy1[2]));
+                            const double hi3 = fmax(vy1[0], fmax(vy1[1], vy1[2]));
+                            if (!(bx < lo2 || bx > hi2 || by < lo3 || by > hi3)) {
+                                nbbox++;
+                                h1 = contains_exact(vx1, vy1, bx, by);
+                            }
                         }
-                        const double lo2 = fmin(vx1[0], fmin(vx1[1], vx1[2])), hi2 = fmax(vx1[0], fmax(vx1[1], vx1[2]));
-                        const double lo3 = fmin(vy1[0], fmin(vy1[1], vy1[2])), hi3 = fmax(vy1[0], fmax(vy1[1], vy1[2]));
-                        if (!(bx < lo2 || bx > hi2 || by < lo3 || by > hi3)) {
-                            nbbox++;
-                            h1 = contains_exact(vx1, vy1, bx, by);
-                        }
+                        const int tid0 = 2 * (gj * (g.nx - 1) + gi);
+                        wave_append(h0, hit_key(sys, tid0), &st->n_hits, hit_keys, hit_cap);
+                        wave_append(h1, hit_key(sys, tid0 + 1), &st->n_hits, hit_keys, hit_cap);
                     }
-                    const int tid0 = 2 * (gj * (g.nx - 1) + gi);
-                    wave_append(h0, hit_key(sys, tid0), &st->n_hits, hit_keys, hit_cap);
-                    wave_append(h1, hit_key(sys, tid0 + 1), &st->n_hits, hit_keys, hit_cap);
                 }
             }
         }
+        __syncthreads();
     }
-    // per-workgroup statistics without a contended global atomic
-    for (int m = 32; m >= 1; m >>= 1) nbbox += __shfl_xor(nbbox, m, 64);
-    __shared__ unsigned sbb[4];
-    if (lane == 0) sbb[threadIdx.x >> 6] = nbbox;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const size_t b = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
-        part[2 * b + 0] = ntile;
-        part[2 * b + 1] = sbb[0] + sbb[1] + sbb[2] + sbb[3];
-    }
+    write_part(part, ntile, nbbox, sbb);
 }
 
 // ============================================================== FP64 fallback and positions
@@ -763,6 +791,12 @@ __device__ __forceinline__ void image_position(const double* vx, const double* v
     oy = l0 * ty[0] + l1 * ty[1] + l2 * ty[2];
 }
 
+// ---------------------------------------------------------------- fallback and positions
+
+constexpr int kSortCap = (int)kHitScratch;  // 8192 = 2^13
+constexpr int kIdxBits = 13;
+constexpr int kTailStage = 1024;            // hits, images and systems staged in LDS
+
 // Persistent waves over the items [certain hits..., undecided tests...]:
 // the position of every certain hit goes to pos[item]; each undecided test is
 // decided exactly on its FP64 vertices and, if it is a hit, appended with its
@@ -801,10 +835,7 @@ __global__ __launch_bounds__(256) void k_fbpos(const double* __restrict__ tab64,
     }
 }
 
-// ============================================================== tail
-
-constexpr int kSortCap = (int)kHitScratch;  // 8192 = 2^13
-constexpr int kIdxBits = 13;
+// ---------------------------------------------------------------- tail
 
 __device__ __forceinline__ int lower_bound_key(const unsigned long long* k, int n, unsigned long long v)
 {
@@ -816,19 +847,18 @@ __device__ __forceinline__ int lower_bound_key(const unsigned long long* k, int 
     return lo;
 }
 
-// One workgroup of 1024 threads.  Merges the certain and the fallback hits,
-// sorts them by (system, triangle id) -- rank sort of packed keys
-// (system << 44 | triangle id << 13 | source index) in LDS for up to 1024
-// hits, bitonic sort beyond -- and writes the sorted (system, id) pairs with
-// their positions.  Then each observed image is paired with the nearest
-// predicted image of its system (ties to the lower triangle id),
-// chi2_i = sum_j |x_obs - x|^2 / sigma^2 in image order, +inf without any
-// predicted image, and chi^2 = sum_i chi2_i in system order (Sec. 2.2.1).
-// Everything the matching touches is staged in LDS when it fits (up to 1024
-// hits, images and systems), so no dependent chain of global loads remains.
-// Reports capacity overflow of any list.
-constexpr int kTailStage = 1024;
 
+// One workgroup of 1024 threads after every hit is known.  Merges the certain
+// and the fallback hits, sorts them by (system, triangle id) -- rank sort of
+// packed keys (system << 44 | triangle id << 13 | source index) for up to 1024
+// hits, bitonic sort beyond -- and writes the sorted (system, id) pairs with
+// their positions.  Each observed image is paired with the nearest predicted
+// image of its system (ties to the lower triangle id), chi2_i = sum_j
+// |x_obs - x|^2 / sigma^2 in image order, +inf without any predicted image,
+// and chi^2 = sum_i chi2_i in a fixed order (Sec. 2.2.1).  Two rounds of
+// independent global loads (the counters, then every key, position and
+// observation at once); everything after that works in LDS.  Reports capacity
+// overflow of any list.
 __global__ __launch_bounds__(1024) void k_tail(ObsPtrs obs, EvalState* __restrict__ st, long long hit_cap,
                                                long long flag_cap, long long fb_cap, int hit_capacity,
                                                const unsigned long long* __restrict__ hit_keys,
@@ -841,20 +871,23 @@ __global__ __launch_bounds__(1024) void k_tail(ObsPtrs obs, EvalState* __restric
                                                long long n_tests, const unsigned* __restrict__ part, int n_parts)
 {
     __shared__ unsigned long long key[kSortCap];
-    __shared__ double spx[kTailStage], spy[kTailStage];            // sorted image positions
+    __shared__ double upx[kTailStage], upy[kTailStage];  // positions in unsorted order
     __shared__ double sox[kTailStage], soy[kTailStage], ssg[kTailStage], scon[kTailStage];
     __shared__ int soff[kTailStage + 1];
+    __shared__ int sfirst[kTailStage], send[kTailStage];
     __shared__ double scs[kTailStage];
-    __shared__ int s_status;
     __shared__ unsigned long long s_tile, s_bbox;
     const int t = threadIdx.x;
     const int nimg = obs.n_img, nsys = obs.n_sys;
     const bool staged = nimg <= kTailStage && nsys <= kTailStage;
-    if (t == 0) {
-        s_tile = 0;
-        s_bbox = 0;
+    // round 1: counters, statistics partials, observations (all independent)
+    const unsigned long long nc = st->n_hits, nf = st->n_flags, nfb = st->n_fb_hits;
+    const int status0 = st->status;
+    unsigned long long pt = 0, pb = 0;
+    for (int q = t; q < n_parts; q += 1024) {
+        pt += part[2 * q];
+        pb += part[2 * q + 1];
     }
-    // independent loads first
     if (staged) {
         if (t < nimg) {
             sox[t] = obs.x[t];
@@ -862,28 +895,44 @@ __global__ __launch_bounds__(1024) void k_tail(ObsPtrs obs, EvalState* __restric
             ssg[t] = obs.sigma[t];
         }
         if (t <= nsys) soff[t] = obs.sys_off[t];
+        if (t < nsys) {
+            sfirst[t] = 0;
+            send[t] = 0;
+        }
+    }
+    if (t == 0) {
+        s_tile = 0;
+        s_bbox = 0;
     }
     __syncthreads();
-    {
-        unsigned long long a = 0, b = 0;
-        for (int q = t; q < n_parts; q += 1024) {
-            a += part[2 * q];
-            b += part[2 * q + 1];
-        }
-        if (a) atomicAdd(&s_tile, a);
-        if (b) atomicAdd(&s_bbox, b);
-    }
-    const unsigned long long nc = st->n_hits, nf = st->n_flags, nfb = st->n_fb_hits;
+    if (pt) atomicAdd(&s_tile, pt);
+    if (pb) atomicAdd(&s_bbox, pb);
     const unsigned long long total = nc + nfb;
+    const bool over = nc > (unsigned long long)hit_cap || nf > (unsigned long long)flag_cap ||
+                      nfb > (unsigned long long)fb_cap || total > (unsigned long long)hit_capacity ||
+                      total > (unsigned long long)kSortCap;
+    const int status = (status0 == kStatusOk && over) ? kStatusCapacity : status0;
+    const int n = status == kStatusOk ? (int)total : 0, ncert = (int)nc;
+    const bool fast = staged && n <= kTailStage;
+    // round 2: keys and positions
+    int npad = 1;
+    while (npad < n) npad <<= 1;
+    for (int q = t; q < npad; q += 1024) {
+        unsigned long long k = ~0ull;
+        if (q < n) {
+            const unsigned long long h = q < ncert ? hit_keys[q] : fb_keys[q - ncert];
+            k = ((h >> 32) << 44) | ((h & 0x7fffffffull) << kIdxBits) | (unsigned long long)q;
+            if (fast) {
+                const double* src = q < ncert ? pos + 2 * q : fb_pos + 2 * (q - ncert);
+                upx[q] = src[0];
+                upy[q] = src[1];
+            }
+        }
+        key[q] = k;
+    }
     __syncthreads();
     if (t == 0) {
-        int status = st->status;
-        const bool over = nc > (unsigned long long)hit_cap || nf > (unsigned long long)flag_cap ||
-                          nfb > (unsigned long long)fb_cap || total > (unsigned long long)hit_capacity ||
-                          total > (unsigned long long)kSortCap;
-        if (status == kStatusOk && over) status = kStatusCapacity;
         st->status = status;
-        s_status = status;
         stats[0] = (long long)total;
         stats[1] = (long long)nf;
         stats[2] = (long long)s_tile;
@@ -893,8 +942,7 @@ __global__ __launch_bounds__(1024) void k_tail(ObsPtrs obs, EvalState* __restric
         stats[6] = n_tests;
         stats[7] = 0;
     }
-    __syncthreads();
-    if (s_status != kStatusOk) {
+    if (status != kStatusOk) {
         for (int s = t; s < nsys; s += 1024) {
             chi2_sys[s] = __builtin_nan("");
             n_pred[s] = 0;
@@ -904,25 +952,18 @@ __global__ __launch_bounds__(1024) void k_tail(ObsPtrs obs, EvalState* __restric
         if (t == 0) chi2[0] = __builtin_nan("");
         return;
     }
-    const int n = (int)total, ncert = (int)nc;
-    int npad = 1;
-    while (npad < n) npad <<= 1;
-    for (int q = t; q < npad; q += 1024) {
-        unsigned long long k = ~0ull;
-        if (q < n) {
-            const unsigned long long h = q < ncert ? hit_keys[q] : fb_keys[q - ncert];
-            k = ((h >> 32) << 44) | ((h & 0x7fffffffull) << kIdxBits) | (unsigned long long)q;
-        }
-        key[q] = k;
-    }
-    __syncthreads();
     if (n <= 1024) {
         // rank sort (keys are unique): one barrier instead of log^2 of them
         unsigned long long mine = 0;
         int rank = 0;
         if (t < n) {
             mine = key[t];
-            for (int q = 0; q < n; q++) rank += key[q] < mine;
+            int q = 0;
+            for (; q + 8 <= n; q += 8) {
+#pragma unroll
+                for (int u = 0; u < 8; u++) rank += key[q + u] < mine;
+            }
+            for (; q < n; q++) rank += key[q] < mine;
         }
         __syncthreads();
         if (t < n) key[rank] = mine;
@@ -944,36 +985,33 @@ __global__ __launch_bounds__(1024) void k_tail(ObsPtrs obs, EvalState* __restric
             }
         }
     }
-    const bool lds_pos = staged && n <= kTailStage;
-    for (int q = t; q < n; q += 1024) {
-        const unsigned long long k = key[q];
-        const int idx = (int)(k & ((1ull << kIdxBits) - 1));
-        out_hits[2 * q + 0] = (int)(k >> 44);
-        out_hits[2 * q + 1] = (int)((k >> kIdxBits) & 0x7fffffffull);
-        const double* src = idx < ncert ? pos + 2 * idx : fb_pos + 2 * (idx - ncert);
-        const double px = src[0], py = src[1];
-        img_xy[2 * q + 0] = px;
-        img_xy[2 * q + 1] = py;
-        if (lds_pos) {
-            spx[q] = px;
-            spy[q] = py;
+    if (fast) {
+        // sorted output, and the [first, end) range of every system from the
+        // boundaries of the sorted list
+        if (t < n) {
+            const unsigned long long k = key[t];
+            const int idx = (int)(k & ((1ull << kIdxBits) - 1));
+            const int s = (int)(k >> 44);
+            out_hits[2 * t + 0] = s;
+            out_hits[2 * t + 1] = (int)((k >> kIdxBits) & 0x7fffffffull);
+            img_xy[2 * t + 0] = upx[idx];
+            img_xy[2 * t + 1] = upy[idx];
+            if (t == 0 || (int)(key[t - 1] >> 44) != s) sfirst[s] = t;
+            if (t == n - 1 || (int)(key[t + 1] >> 44) != s) send[s] = t + 1;
         }
-    }
-    __syncthreads();
-    if (lds_pos) {
-        // fast path: every operand in LDS
+        __syncthreads();
         if (t < nimg) {
             int lo = 0, hi = nsys - 1;  // system of image t
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
                 if (soff[mid] <= t) lo = mid; else hi = mid - 1;
             }
-            const int q0 = lower_bound_key(key, n, (unsigned long long)lo << 44);
-            const int q1 = lower_bound_key(key, n, (unsigned long long)(lo + 1) << 44);
+            const int q0 = sfirst[lo], q1 = send[lo];
             int best = -1;
             double bd = 0.0;
             for (int q = q0; q < q1; q++) {
-                const double dx = sox[t] - spx[q], dy = soy[t] - spy[q];
+                const int idx = (int)(key[q] & ((1ull << kIdxBits) - 1));
+                const double dx = sox[t] - upx[idx], dy = soy[t] - upy[idx];
                 const double d2 = dx * dx + dy * dy;
                 if (best < 0 || d2 < bd) {
                     best = q;
@@ -985,8 +1023,7 @@ __global__ __launch_bounds__(1024) void k_tail(ObsPtrs obs, EvalState* __restric
         }
         __syncthreads();
         if (t < nsys) {
-            const int q0 = lower_bound_key(key, n, (unsigned long long)t << 44);
-            const int q1 = lower_bound_key(key, n, (unsigned long long)(t + 1) << 44);
+            const int q0 = sfirst[t], q1 = send[t];
             double cs = 0.0;
             for (int j = soff[t]; j < soff[t + 1]; j++) cs += scon[j];
             cs = q1 > q0 ? cs : INFINITY;
@@ -995,7 +1032,7 @@ __global__ __launch_bounds__(1024) void k_tail(ObsPtrs obs, EvalState* __restric
             scs[t] = cs;
         }
         __syncthreads();
-        if (t < 64) {  // one wave: fixed-order sum of the systems
+        if (t < 64) {  // one wave: fixed-order sum over the systems
             double v = 0.0;
             for (int s = t; s < nsys; s += 64) v += scs[s];
             v = wave_sum(v);
@@ -1003,7 +1040,17 @@ __global__ __launch_bounds__(1024) void k_tail(ObsPtrs obs, EvalState* __restric
         }
         return;
     }
-    // general path (more than 1024 hits, images or systems)
+    // general path (more than 1024 hits, images or systems): global operands
+    for (int q = t; q < n; q += 1024) {
+        const unsigned long long k = key[q];
+        const int idx = (int)(k & ((1ull << kIdxBits) - 1));
+        out_hits[2 * q + 0] = (int)(k >> 44);
+        out_hits[2 * q + 1] = (int)((k >> kIdxBits) & 0x7fffffffull);
+        const double* src = idx < ncert ? pos + 2 * idx : fb_pos + 2 * (idx - ncert);
+        img_xy[2 * q + 0] = src[0];
+        img_xy[2 * q + 1] = src[1];
+    }
+    __syncthreads();
     for (int j = t; j < nimg; j += 1024) {
         const int s = system_of(obs.sys_off, nsys, j);
         const int q0 = lower_bound_key(key, n, (unsigned long long)s << 44);
@@ -1095,14 +1142,14 @@ __global__ void k_export(const double* __restrict__ sysrow, int nsys, const Eval
 
 static inline unsigned cdiv(long long a, long long b) { return (unsigned)((a + b - 1) / b); }
 
+static inline unsigned clampu(long long v, long long lo, long long hi) { return (unsigned)(v < lo ? lo : v > hi ? hi : v); }
+
 hipError_t launch_head(const PotPtrs& pot, const GridDesc& g, const ObsPtrs& obs, double* tab64, float* tab32,
                        double* bterm, double* bx, double* by, double* sysrow, EvalState* st, hipStream_t s)
 {
     long long nb = cdiv(obs.n_img, 4);
     if (nb < cdiv(pot.n, 256)) nb = cdiv(pot.n, 256);
-    if (nb < 1) nb = 1;
-    if (nb > 1024) nb = 1024;  // grid-stride loops cover the rest
-    k_head<<<(unsigned)nb, 256, 0, s>>>(pot, g, obs, tab64, tab32, bterm, bx, by, sysrow, st);
+    k_head<<<clampu(nb, 1, 1024), 256, 0, s>>>(pot, g, obs, tab64, tab32, bterm, bx, by, sysrow, st);
     return hipGetLastError();
 }
 
@@ -1125,13 +1172,20 @@ hipError_t launch_field64(const double* tab64, int np, const GridDesc& g, double
     return hipGetLastError();
 }
 
+int tri_blocks(const GridDesc& g)
+{
+    const long long n_tiles = (long long)cdiv(g.nx - 1, TX) * cdiv(g.ny - 1, TY);
+    return (int)(n_tiles < kTriBlocks ? n_tiles : kTriBlocks);
+}
+
 hipError_t launch_tri32(const float* ax, const float* ay, const GridDesc& g, int nsys, const double* sysrow,
                         EvalState* st, int mode, float tau, unsigned long long* hit_keys, long long hit_cap,
                         unsigned long long* flag_keys, long long flag_cap, unsigned* part, hipStream_t s)
 {
-    k_tri32<<<dim3(cdiv(g.nx - 1, TX), cdiv(g.ny - 1, TY)), 256, 0, s>>>(ax, ay, g, nsys, sysrow, st, mode, tau,
-                                                                           hit_keys, hit_cap, flag_keys, flag_cap,
-                                                                           part);
+    const int tiles_x = (int)cdiv(g.nx - 1, TX);
+    const int n_tiles = tiles_x * (int)cdiv(g.ny - 1, TY);
+    k_tri32<<<tri_blocks(g), 256, 0, s>>>(ax, ay, g, tiles_x, n_tiles, nsys, sysrow, st, mode, tau, hit_keys,
+                                          hit_cap, flag_keys, flag_cap, part);
     return hipGetLastError();
 }
 
@@ -1139,8 +1193,9 @@ hipError_t launch_tri64(const double* ax, const double* ay, const GridDesc& g, i
                         EvalState* st, unsigned long long* hit_keys, long long hit_cap, unsigned* part,
                         hipStream_t s)
 {
-    k_tri64<<<dim3(cdiv(g.nx - 1, TX), cdiv(g.ny - 1, TY)), 256, 0, s>>>(ax, ay, g, nsys, sysrow, st, hit_keys,
-                                                                           hit_cap, part);
+    const int tiles_x = (int)cdiv(g.nx - 1, TX);
+    const int n_tiles = tiles_x * (int)cdiv(g.ny - 1, TY);
+    k_tri64<<<tri_blocks(g), 256, 0, s>>>(ax, ay, g, tiles_x, n_tiles, nsys, sysrow, st, hit_keys, hit_cap, part);
     return hipGetLastError();
 }
 
@@ -1154,15 +1209,12 @@ hipError_t launch_fbpos(const double* tab64, int np, const GridDesc& g, const do
     return hipGetLastError();
 }
 
-hipError_t launch_tail(const ObsPtrs& obs, EvalState* st, long long hit_cap, long long flag_cap, long long fb_cap,
-                       int hit_capacity, const unsigned long long* hit_keys, const unsigned long long* fb_keys,
-                       const double* pos, const double* fb_pos, int* out_hits, double* img_xy, int* n_pred,
-                       double* contrib, double* chi2, double* chi2_sys, int* match, long long* stats,
-                       long long n_tests, const unsigned* part, int n_parts, hipStream_t s)
+hipError_t launch_tail(const TailLaunch& tl, EvalState* st, const unsigned long long* fb_keys, const double* pos,
+                       const double* fb_pos, hipStream_t s)
 {
-    k_tail<<<1, 1024, 0, s>>>(obs, st, hit_cap, flag_cap, fb_cap, hit_capacity, hit_keys, fb_keys, pos, fb_pos,
-                              out_hits, img_xy, n_pred, contrib, chi2, chi2_sys, match, stats, n_tests, part,
-                              n_parts);
+    k_tail<<<1, 1024, 0, s>>>(tl.obs, st, tl.hit_cap, tl.flag_cap, tl.fb_cap, tl.hit_capacity, tl.hit_keys, fb_keys,
+                              pos, fb_pos, tl.out_hits, tl.img_xy, tl.n_pred, tl.contrib, tl.chi2, tl.chi2_sys,
+                              tl.match, tl.stats, tl.n_tests, tl.part, tl.n_parts);
     return hipGetLastError();
 }
 
