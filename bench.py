@@ -29,7 +29,9 @@ sys.path.insert(0, ROOT)
 METRIC = "image-plane χ² evals/sec and grid triangles/s, mixed vs FP64, 1 MI355X"
 PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector peak
 PEAK_FP64_TFLOPS = 78.6    # MI355X FP64 vector peak
-FLOPS_PER_EVAL = 34        # algorithmic flops per pixel-potential evaluation (see DESIGN)
+FLOPS_PER_EVAL = 34        # flops of one cored/cut pixel-potential evaluation, counted on the formula
+                           # (+,-,x = 1, fma = 2, sqrt = 1, div = 1): translate 2, rotate 6, R^2 5,
+                           # two square roots 4, f 5, lens-frame gradient 4, rotate back + sum 8
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_field32_cluster.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1902_03252_amd", "csrc", f) for f in ("lens_kernels.hip", "lens_device.hpp")]
 

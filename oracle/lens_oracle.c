@@ -21,8 +21,8 @@
  *   - chi^2 re-lensing of Sec. 2.2.1 / 2.2.2 and Fig. 1: observed images to the
  *     source plane, barycentre, two triangles per grid cell, containment test,
  *     predicted images, chi^2 sum.
- * Readings of points the paper leaves open are marked READING and are listed
- * in the design notes of the repository.
+ * Readings of points the paper leaves open are marked READING where they are
+ * taken.
  *
  * Compiled with -O2 -ffp-contract=off: no fused multiply-adds, so every
  * operation rounds exactly as written.

@@ -16,8 +16,9 @@ a float64 array of shape [7, P] whose rows are
     5 r_cut    cut radius s, arcsec (+inf for an uncut profile)
     6 sigma_v  velocity dispersion, km/s
 
-The workloads below follow the five configurations of the benchmark plan; every
-choice the plan leaves open is marked "reading" and listed in the design doc.
+The workloads below follow the five benchmark configurations; every choice they
+leave open (centred halo, uniform core/cut radii, source disk radius, ...) is
+marked "reading" where it is made.
 """
 from __future__ import annotations
 
