@@ -5,7 +5,8 @@ triangle containment, FP64 fallback, image positions, matching, chi^2) of the
 cluster workload (1 cluster halo + 49 galaxy potentials, 1024^2 grid over
 +-80", 20 multiple-image systems), inputs resident in HBM.  The mixed path is
 the headline; the FP64 path is measured beside it, and the 4096^2 /
-200-potential / 100-system workload is reported as an extra.
+200-potential / 100-system workload and a batch of 1024 sampler proposals
+(uneven potential counts and grids, one batched call) are reported as extras.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 
@@ -33,7 +34,8 @@ FLOPS_PER_EVAL = 34        # flops of one cored/cut pixel-potential evaluation, 
                            # (+,-,x = 1, fma = 2, sqrt = 1, div = 1): translate 2, rotate 6, R^2 5,
                            # two square roots 4, f 5, lens-frame gradient 4, rotate back + sum 8
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_field32_cluster.txt")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_1902_03252_amd", "csrc", f) for f in ("lens_kernels.hip", "lens_device.hpp")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1902_03252_amd", "csrc", f)
+                  for f in ("lens_kernels.hip", "lens_path.hpp", "lens_device.hpp")]
 
 
 def load_workload(config: int):
@@ -141,7 +143,57 @@ def gpu_bench(args):
                            flagged_tests=int(st[1]), fallback_rate=float(st[1]) / float(st[6]),
                            hits=int(st[0]))
     large["speedup_mixed_vs_fp64"] = large["fp64"]["ms_per_eval"] / large["mixed"]["ms_per_eval"]
-    return prm, grid, obs_np, n_tri, res, large
+    batched = batched_bench(torch, lens, ctx, obs, obs_np, args) if args.batch > 0 else None
+    return prm, grid, obs_np, n_tri, res, large, batched
+
+
+def batched_bench(torch, lens, ctx, obs, obs_np, args):
+    """A sampler's batch: n lens models with P ~ U{10..200} potentials and grid
+    sides drawn from {256, 512, 1024, 2048} over +-80", evaluated by one batched
+    call, captured into a HIP graph and replayed."""
+    import synthlens as S
+    params, pot_off, grids = S.batch_samples(args.batch)
+    p = torch.as_tensor(params, dtype=torch.float64, device="cuda")
+    layout = lens.BatchLayout(pot_off, grids)
+    nodes = np.array([g.nx * g.ny for g in grids], dtype=np.float64)
+    n_pot = np.diff(pot_off).astype(np.float64)
+    tri = float(sum(g.n_triangles for g in grids))
+    flops = FLOPS_PER_EVAL * float((nodes * n_pot).sum())
+    out_res = {}
+    for prec in ("mixed", "fp64"):
+        out = lens.batch_buffers(layout.n, obs, "cuda")
+        step = lambda: lens.lens_image_chi2_batched(p, layout, obs, prec=prec, out=out, ctx=ctx)
+        ctx.set_timing(True)
+        step()  # builds and caches the plan
+        torch.cuda.synchronize()
+        ctx.field_timing(reset=True)
+        eager_s = time_steps(torch, step, 3, 1)
+        kms, nl = ctx.field_timing(reset=True)
+        ctx.set_timing(False)
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            step()
+        torch.cuda.current_stream().wait_stream(s)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            step()
+        dt = time_steps(torch, g.replay, args.batch_steps, 1)
+        st = out.stats.cpu().numpy()
+        status = out.status.cpu().numpy()
+        field_s = kms / 1e3 / 4.0  # field kernels of one batch (1 warm-up + 3 timed calls)
+        peak = PEAK_FP32_TFLOPS if prec == "mixed" else PEAK_FP64_TFLOPS
+        out_res[prec] = dict(chi2_evals_per_s=args.batch / dt, ms_per_batch=dt * 1e3,
+                             eager_ms_per_batch=eager_s * 1e3, grid_triangles_per_s=tri / dt,
+                             field_ms_per_batch=field_s * 1e3, field_tflops=flops / field_s / 1e12,
+                             field_frac_of_peak=flops / field_s / 1e12 / peak,
+                             samples_ok=int((status == 0).sum()), hits=int(st[0]), flagged_tests=int(st[1]),
+                             fallback_rate=float(st[1]) / float(st[6]))
+        del g
+    out_res["speedup_mixed_vs_fp64"] = out_res["fp64"]["ms_per_batch"] / out_res["mixed"]["ms_per_batch"]
+    out_res["workload"] = (f"{args.batch} samples, P ~ U{{10..200}} (mean {n_pot.mean():.1f}), grid sides "
+                           f"{{256, 512, 1024, 2048}}, {nodes.sum() / 1e9:.2f} G nodes, 20 systems")
+    return out_res
 
 
 def cpu_baseline(prm, grid, obs_np, budget_s: float):
@@ -167,6 +219,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for the baseline")
+    ap.add_argument("--batch", type=int, default=1024, help="samples of the batched leg (0 skips it)")
+    ap.add_argument("--batch-steps", type=int, default=5, help="timed replays of the batched leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 256 MiB device-to-device 3 times (a known-size kernel that calibrates the "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
@@ -184,7 +238,7 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    prm, grid, obs_np, n_tri, res, large = gpu_bench(args)
+    prm, grid, obs_np, n_tri, res, large, batched = gpu_bench(args)
     mixed, fp64 = res["mixed"], res["fp64"]
     step_s = mixed["graph_s"]
     evals = grid.nx * grid.ny * prm.shape[1]
@@ -235,6 +289,7 @@ def main():
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
                      "flops_per_launch": flops, "avg_launch_ms": mixed["kern_ms"], "launches_timed": mixed["launches"]},
         "large": large,
+        "batched": batched,
         "cpu_baseline": cpu,
         "parity": parity,
     }

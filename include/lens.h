@@ -109,7 +109,11 @@ typedef struct {
                              to the FP64 path).  1: literal threshold, a test is sent
                              to FP64 when min_k |c_k| < fb_tau * h^2                 */
     double fb_tau;        /* literal-mode factor (e.g. 1e-6); ignored in mode 0    */
-    int32_t hit_capacity; /* rows of out->hits / out->img_xy, >= 1                */
+    int32_t hit_capacity; /* rows of out->hits / out->img_xy, 1 .. 8192            */
+    int32_t field_npl;    /* grid nodes per thread of the FP32 field kernel: 1, 2, 4 or
+                             8; 0 = chosen from the grid size                        */
+    int32_t tile;         /* cells per triangle-stage tile: 1 = 32x8, 2 = 64x16,
+                             3 = 64x8, 4 = 32x16; 0 = 32x8                           */
 } lens_chi2_opts;
 
 typedef struct {
@@ -164,6 +168,31 @@ int lens_source_positions(lens_ctx *ctx, const lens_potentials *pot, const lens_
 int lens_image_chi2(lens_ctx *ctx, const lens_potentials *pot, const lens_grid *grid,
                     const lens_obs *obs, const lens_chi2_opts *opts, lens_chi2_out *out,
                     hipStream_t stream);
+
+/* Outputs of the batched chi^2 (device arrays). */
+typedef struct {
+    double *chi2;       /* [n_samples]          total chi^2 of each sample                 */
+    double *chi2_sys;   /* [n_samples * n_sys]  per-system chi^2                           */
+    int32_t *n_pred;    /* [n_samples * n_sys]  predicted images per system                */
+    int32_t *status;    /* [n_samples]          LENS_OK / LENS_ERR_INVALID / _CAPACITY      */
+    int64_t *stats;     /* [LENS_STAT_N] totals over the batch; stats[4] is 1 if any sample
+                           is not OK, stats[7] the number of such samples                 */
+} lens_batch_out;
+
+/* Batched image-plane chi^2: n_samples lens models -- the proposals of a
+ * sampler over the parameter space (Sec. 2.2.1) -- with their own potentials
+ * and grids, sharing the observed systems.  Sample s owns parameter columns
+ * [pot_off[s], pot_off[s+1]) of the concatenated structure of arrays `all`
+ * and the grid grids[s].  pot_off (n_samples + 1 entries, pot_off[0] = 0,
+ * non-decreasing, pot_off[n] = all->n) and grids are HOST arrays: they fix
+ * the work plan (heaviest samples first, memory-bounded chunks), which the
+ * context caches per distinct (pot_off, grids, opts) and uploads once; a
+ * captured HIP graph replays the plan of the captured call.  Each sample is
+ * evaluated exactly as lens_image_chi2 would; opts->hit_capacity (<= 1024) is
+ * per sample, and a batch needs n_img <= 1024, n_sys <= 1024. */
+int lens_image_chi2_batched(lens_ctx *ctx, const lens_potentials *all, int32_t n_samples,
+                            const int32_t *pot_off, const lens_grid *grids, const lens_obs *obs,
+                            const lens_chi2_opts *opts, lens_batch_out *out, hipStream_t stream);
 
 /* Kernel timing (instrumentation, for roofline measurement).  While enabled,
  * every launch of the deflection-field kernel (the dominant kernel of

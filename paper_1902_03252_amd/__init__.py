@@ -200,14 +200,15 @@ def chi2_buffers(obs: Obs, hit_capacity: int, device) -> Chi2Result:
 
 def lens_image_chi2(params: torch.Tensor, grid, obs: Obs, prec: str = "mixed", fb_mode: int = 0,
                     fb_tau: float = 1e-6, hit_capacity: int = 4096, out: Chi2Result | None = None,
-                    ctx: Context | None = None) -> Chi2Result:
+                    ctx: Context | None = None, field_npl: int = 0, tile: int = 0) -> Chi2Result:
     """Image-plane chi^2 (asynchronous; outputs valid after stream sync)."""
     ctx = ctx or context(params.device.index)
     if prec not in ("fp64", "mixed"):
         raise ValueError("prec must be 'fp64' or 'mixed'")
     p, o = _pots(params), _obs(obs)
     out = out or chi2_buffers(obs, hit_capacity, params.device)
-    opts = L.LensChi2Opts(_PREC[prec], int(fb_mode), float(fb_tau), int(out.hits.shape[0]))
+    opts = L.LensChi2Opts(_PREC[prec], int(fb_mode), float(fb_tau), int(out.hits.shape[0]), int(field_npl),
+                          int(tile))
     co = L.LensChi2Out(out.chi2.data_ptr(), out.chi2_sys.data_ptr(), out.n_pred.data_ptr(), out.hits.data_ptr(),
                        out.img_xy.data_ptr(), out.match.data_ptr(), out.stats.data_ptr())
     L.check(ctx._lib.lens_image_chi2(ctx.handle, C.byref(p), C.byref(_grid(grid)), C.byref(o), C.byref(opts),
@@ -215,5 +216,55 @@ def lens_image_chi2(params: torch.Tensor, grid, obs: Obs, prec: str = "mixed", f
     return out
 
 
+class BatchLayout:
+    """Host description of a batch: sample s owns parameter columns
+    [pot_off[s], pot_off[s+1]) and is evaluated on grids[s].  Built once and
+    reused, it keeps the marshalled host arrays of repeated calls."""
+
+    def __init__(self, pot_off, grids):
+        off = [int(v) for v in pot_off]
+        if len(off) != len(grids) + 1:
+            raise ValueError("pot_off needs one entry more than grids")
+        self.n = len(grids)
+        self.pot_off = (C.c_int32 * len(off))(*off)
+        self.grids = (L.LensGrid * self.n)(*[_grid(g) for g in grids])
+
+
+@dataclasses.dataclass
+class BatchResult:
+    chi2: torch.Tensor      # [n] float64
+    chi2_sys: torch.Tensor  # [n, S] float64
+    n_pred: torch.Tensor    # [n, S] int32
+    status: torch.Tensor    # [n] int32
+    stats: torch.Tensor     # [8] int64, totals over the batch
+
+
+def batch_buffers(n: int, obs: Obs, device) -> BatchResult:
+    z = lambda *s, dt=torch.float64: torch.zeros(*s, dtype=dt, device=device)
+    return BatchResult(z(n), z(n, obs.n_sys), z(n, obs.n_sys, dt=torch.int32), z(n, dt=torch.int32),
+                       z(STAT_N, dt=torch.int64))
+
+
+def lens_image_chi2_batched(params: torch.Tensor, layout: BatchLayout, obs: Obs, prec: str = "mixed",
+                            fb_mode: int = 0, fb_tau: float = 1e-6, hit_capacity: int = 1024,
+                            out: BatchResult | None = None, ctx: Context | None = None, field_npl: int = 0,
+                            tile: int = 0) -> BatchResult:
+    """Image-plane chi^2 of every sample of a batch (asynchronous).  params is
+    the [7, sum P_s] concatenation of the samples' potentials."""
+    ctx = ctx or context(params.device.index)
+    if prec not in ("fp64", "mixed"):
+        raise ValueError("prec must be 'fp64' or 'mixed'")
+    p, o = _pots(params), _obs(obs)
+    out = out or batch_buffers(layout.n, obs, params.device)
+    opts = L.LensChi2Opts(_PREC[prec], int(fb_mode), float(fb_tau), int(hit_capacity), int(field_npl), int(tile))
+    bo = L.LensBatchOut(out.chi2.data_ptr(), out.chi2_sys.data_ptr(), out.n_pred.data_ptr(), out.status.data_ptr(),
+                        out.stats.data_ptr())
+    L.check(ctx._lib.lens_image_chi2_batched(ctx.handle, C.byref(p), layout.n, layout.pot_off, layout.grids,
+                                             C.byref(o), C.byref(opts), C.byref(bo), ctx.stream()),
+            "lens_image_chi2_batched")
+    return out
+
+
 __all__ = ["Obs", "Context", "context", "lens_dls_dos", "lens_deflect", "lens_source_positions",
-           "lens_image_chi2", "Chi2Result", "chi2_buffers"]
+           "lens_image_chi2", "Chi2Result", "chi2_buffers", "BatchLayout", "BatchResult", "batch_buffers",
+           "lens_image_chi2_batched"]

@@ -20,7 +20,8 @@ STAT_HITS, STAT_FLAGGED, STAT_TILE_PASS, STAT_BBOX_PASS, STAT_STATUS, STAT_FB_HI
 STAT_N = 8
 
 EXPORTS = ("lens_create", "lens_destroy", "lens_dls_dos", "lens_deflect", "lens_source_positions",
-           "lens_image_chi2", "lens_set_timing", "lens_field_timing", "lens_strerror")
+           "lens_image_chi2", "lens_image_chi2_batched", "lens_set_timing", "lens_field_timing",
+           "lens_strerror")
 
 
 class LensPotentials(C.Structure):
@@ -38,12 +39,18 @@ class LensObs(C.Structure):
 
 
 class LensChi2Opts(C.Structure):
-    _fields_ = [("prec", C.c_int), ("fb_mode", C.c_int32), ("fb_tau", C.c_double), ("hit_capacity", C.c_int32)]
+    _fields_ = [("prec", C.c_int), ("fb_mode", C.c_int32), ("fb_tau", C.c_double), ("hit_capacity", C.c_int32),
+                ("field_npl", C.c_int32), ("tile", C.c_int32)]
 
 
 class LensChi2Out(C.Structure):
     _fields_ = [("chi2", C.c_void_p), ("chi2_sys", C.c_void_p), ("n_pred", C.c_void_p), ("hits", C.c_void_p),
                 ("img_xy", C.c_void_p), ("match", C.c_void_p), ("stats", C.c_void_p)]
+
+
+class LensBatchOut(C.Structure):
+    _fields_ = [("chi2", C.c_void_p), ("chi2_sys", C.c_void_p), ("n_pred", C.c_void_p), ("status", C.c_void_p),
+                ("stats", C.c_void_p)]
 
 
 _lib = None
@@ -72,6 +79,9 @@ def load(path: str = LIB_PATH):
     lib.lens_image_chi2.argtypes = [vp, C.POINTER(LensPotentials), C.POINTER(LensGrid), C.POINTER(LensObs),
                                     C.POINTER(LensChi2Opts), C.POINTER(LensChi2Out), vp]
     lib.lens_image_chi2.restype = C.c_int
+    lib.lens_image_chi2_batched.argtypes = [vp, C.POINTER(LensPotentials), i32, C.POINTER(i32), C.POINTER(LensGrid),
+                                            C.POINTER(LensObs), C.POINTER(LensChi2Opts), C.POINTER(LensBatchOut), vp]
+    lib.lens_image_chi2_batched.restype = C.c_int
     lib.lens_set_timing.argtypes = [vp, C.c_int]
     lib.lens_set_timing.restype = C.c_int
     lib.lens_field_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]

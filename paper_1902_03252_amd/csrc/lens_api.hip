@@ -5,16 +5,49 @@
 #include "lens_device.hpp"
 #include "lens_internal.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <stdlib.h>
 #include <string.h>
+#include <vector>
 
 using namespace lens;
 
 namespace {
 
 enum Buf { B_TAB64, B_TAB32, B_BTERM, B_FIELD, B_BX, B_BY, B_SYS, B_STATE, B_HITS, B_FLAGS, B_POS, B_CONTRIB,
-           B_PART, B_NBUF };
+           B_PART, B_BCOUNT, B_NBUF };
+
+// Device work plan of one chunk of a batch (see lens_image_chi2_batched).
+struct PlanChunk {
+    int s0, n, np;            // first sample, samples, parameter columns
+    long long n_fitems, n_tiles, n_nodes, n_tests;
+    void* host_stage;         // pinned source of the plan upload, freed with the plan
+    void* dev_plan;
+    int* fmap;
+    int* tmap;
+    BatchPlan bp;
+};
+
+struct PlanEntry {
+    std::vector<int32_t> pot_off;
+    std::vector<double> grids;  // x0, y0, h, nx, ny per sample
+    int npl, shape, fp32;
+    std::vector<PlanChunk> chunks;
+};
+
+constexpr int kMaxPlans = 16;  // cached batch plans per context
+
+void release_plan(PlanEntry* e)
+{
+    for (PlanChunk& ch : e->chunks) {
+        (void)hipHostFree(ch.host_stage);
+        (void)hipFree(ch.dev_plan);
+        (void)hipFree(ch.fmap);
+        (void)hipFree(ch.tmap);
+    }
+    delete e;
+}
 
 }  // namespace
 
@@ -31,6 +64,7 @@ struct lens_ctx {
     int n_events;  // events created so far (pairs)
     double total_ms;
     long long launches;
+    std::vector<PlanEntry*>* plans;  // batch plans, one per distinct shape class
 };
 
 namespace {
@@ -237,6 +271,11 @@ int lens_create(lens_ctx** ctx, int device)
     lens_ctx* c = (lens_ctx*)calloc(1, sizeof(lens_ctx));
     if (!c) return LENS_ERR_DEVICE;
     c->device = device;
+    c->plans = new (std::nothrow) std::vector<PlanEntry*>();
+    if (!c->plans) {
+        free(c);
+        return LENS_ERR_DEVICE;
+    }
     *ctx = c;
     return LENS_OK;
 }
@@ -252,6 +291,10 @@ void lens_destroy(lens_ctx* ctx)
         for (int k = 0; k < ctx->n_events; k++) {
             (void)hipEventDestroy(ctx->ev_start[k]);
             (void)hipEventDestroy(ctx->ev_stop[k]);
+        }
+        if (ctx->plans) {
+            for (PlanEntry* e : *ctx->plans) release_plan(e);
+            delete ctx->plans;
         }
     }
     free(ctx);
@@ -357,6 +400,10 @@ int lens_image_chi2(lens_ctx* ctx, const lens_potentials* pot, const lens_grid* 
     if (opts->prec == LENS_MIXED && (opts->fb_mode < 0 || opts->fb_mode > 1)) return LENS_ERR_INVALID;
     if (opts->prec == LENS_MIXED && opts->fb_mode == 1 && !(opts->fb_tau >= 0.0 && is_fin(opts->fb_tau)))
         return LENS_ERR_INVALID;
+    if (!(opts->field_npl == 0 || opts->field_npl == 1 || opts->field_npl == 2 || opts->field_npl == 4 ||
+          opts->field_npl == 8) ||
+        opts->tile < 0 || opts->tile > 4)
+        return LENS_ERR_INVALID;
     if (!out->chi2 || !out->chi2_sys || !out->n_pred || !out->hits || !out->img_xy || !out->stats)
         return LENS_ERR_INVALID;
     DeviceGuard dg(ctx->device);
@@ -372,7 +419,9 @@ int lens_image_chi2(lens_ctx* ctx, const lens_potentials* pot, const lens_grid* 
         (rc = ensure(ctx, B_FLAGS, (size_t)(mixed ? kFlagScratch : 1) * 8)) ||
         (rc = ensure(ctx, B_POS, (size_t)kHitScratch * 4 * 8)) || (rc = ensure(ctx, B_CONTRIB, (size_t)o.n_img * 8)))
         return rc;
-    const int n_parts = tri_blocks(g);
+    const int shape = opts->tile ? opts->tile : 1;
+    const int npl = opts->field_npl ? opts->field_npl : field_npl(g);
+    const int n_parts = tri_blocks(g, shape);
     if ((rc = ensure(ctx, B_PART, (size_t)n_parts * 2 * 4)) ||
         (rc = ensure(ctx, B_SYS, (size_t)o.n_sys * SYS_STRIDE * 8)))
         return rc;
@@ -394,8 +443,8 @@ int lens_image_chi2(lens_ctx* ctx, const lens_potentials* pot, const lens_grid* 
     hipError_t e;
     void* field = ctx->buf[B_FIELD];
     if (mixed)
-        e = launch_field32((const float*)ctx->buf[B_TAB32], np, g, (float*)field, (float*)field + nn, nullptr,
-                           field_npl(g), stream);
+        e = launch_field32((const float*)ctx->buf[B_TAB32], np, g, (float*)field, (float*)field + nn, nullptr, npl,
+                           stream);
     else
         e = launch_field64(tab64, np, g, (double*)field, (double*)field + nn, nullptr, stream);
     if (e != hipSuccess) return LENS_ERR_DEVICE;
@@ -403,10 +452,10 @@ int lens_image_chi2(lens_ctx* ctx, const lens_potentials* pot, const lens_grid* 
 
     if (mixed)
         e = launch_tri32((const float*)field, (const float*)field + nn, g, o.n_sys, sysrow, st, opts->fb_mode,
-                         (float)(opts->fb_tau * g.h * g.h), hits, kHitScratch, flags, flag_cap, part, stream);
+                         (float)(opts->fb_tau * g.h * g.h), hits, kHitScratch, flags, flag_cap, part, shape, stream);
     else
         e = launch_tri64((const double*)field, (const double*)field + nn, g, o.n_sys, sysrow, st, hits, kHitScratch,
-                         part, stream);
+                         part, shape, stream);
     if (e != hipSuccess) return LENS_ERR_DEVICE;
     TailLaunch tl;
     tl.obs = o;
@@ -433,3 +482,281 @@ int lens_image_chi2(lens_ctx* ctx, const lens_potentials* pot, const lens_grid* 
 }
 
 }  // extern "C"
+
+namespace {
+
+// Triangle-stage tile dimensions of a tile-shape code (see lens_chi2_opts.tile).
+void tile_dims(int shape, int& tx, int& ty)
+{
+    switch (shape) {
+    case 2: tx = 64; ty = 16; break;
+    case 3: tx = 64; ty = 8; break;
+    case 4: tx = 32; ty = 16; break;
+    default: tx = 32; ty = 8; break;
+    }
+}
+
+size_t align8(size_t v) { return (v + 7) & ~(size_t)7; }
+
+
+// Bytes of field scratch per chunk (env LENS_BATCH_FIELD_BYTES, default 16 GiB).
+long long batch_field_budget()
+{
+    const char* env = getenv("LENS_BATCH_FIELD_BYTES");
+    const long long v = env ? atoll(env) : 0;
+    return v > 0 ? v : (16ll << 30);
+}
+
+// Builds (or finds) the plan of a batch: chunks of consecutive samples within
+// the field-memory budget; inside a chunk the samples are ordered by cost
+// P * nx * ny, heaviest first, and the work items of the field (row segments)
+// and triangle (tile) stages are enumerated in that order.  New plans are
+// uploaded on `s` from pinned staging that stays alive with the plan.
+int batch_plan(lens_ctx* c, int n_samples, const int32_t* pot_off, const lens_grid* grids, int npl, int shape,
+               bool fp32, hipStream_t s, PlanEntry** out)
+{
+    for (PlanEntry* e : *c->plans) {
+        if (e->npl != npl || e->shape != shape || e->fp32 != (int)fp32 ||
+            (int)e->pot_off.size() != n_samples + 1)
+            continue;
+        if (memcmp(e->pot_off.data(), pot_off, sizeof(int32_t) * (n_samples + 1)) != 0) continue;
+        bool same = true;
+        for (int i = 0; i < n_samples && same; i++) {
+            const double* gv = &e->grids[5 * (size_t)i];
+            same = gv[0] == grids[i].x0 && gv[1] == grids[i].y0 && gv[2] == grids[i].h && gv[3] == grids[i].nx &&
+                   gv[4] == grids[i].ny;
+        }
+        if (same) {
+            // most recently used last
+            std::vector<PlanEntry*>& v = *c->plans;
+            v.erase(std::find(v.begin(), v.end(), e));
+            v.push_back(e);
+            *out = e;
+            return LENS_OK;
+        }
+    }
+    if ((int)c->plans->size() >= kMaxPlans) {
+        // release the least recently used plan once no queued work can read it
+        if (hipDeviceSynchronize() != hipSuccess) return LENS_ERR_DEVICE;
+        release_plan(c->plans->front());
+        c->plans->erase(c->plans->begin());
+    }
+    PlanEntry* e = new (std::nothrow) PlanEntry();
+    if (!e) return LENS_ERR_DEVICE;
+    e->npl = npl;
+    e->shape = shape;
+    e->fp32 = (int)fp32;
+    e->pot_off.assign(pot_off, pot_off + n_samples + 1);
+    e->grids.resize(5 * (size_t)n_samples);
+    for (int i = 0; i < n_samples; i++) {
+        double* gv = &e->grids[5 * (size_t)i];
+        gv[0] = grids[i].x0;
+        gv[1] = grids[i].y0;
+        gv[2] = grids[i].h;
+        gv[3] = grids[i].nx;
+        gv[4] = grids[i].ny;
+    }
+    int tx, ty;
+    tile_dims(shape, tx, ty);
+    const int seg_nodes = 256 * (fp32 ? npl : 1);
+    const long long elem = fp32 ? 8 : 16;  // two planes
+    const long long budget = batch_field_budget();
+    int s0 = 0;
+    int rc = LENS_OK;
+    while (s0 < n_samples && rc == LENS_OK) {
+        int s1 = s0;
+        long long nodes = 0;
+        while (s1 < n_samples && s1 - s0 < (1 << 19)) {
+            const long long add = (long long)grids[s1].nx * grids[s1].ny;
+            if (s1 > s0 && (nodes + add) * elem > budget) break;
+            nodes += add;
+            s1++;
+        }
+        PlanChunk ch;
+        memset(&ch, 0, sizeof ch);
+        ch.s0 = s0;
+        ch.n = s1 - s0;
+        ch.np = pot_off[s1] - pot_off[s0];
+        const int n = ch.n;
+        std::vector<int> perm(n);
+        for (int k = 0; k < n; k++) perm[k] = k;
+        auto cost = [&](int k) {
+            const lens_grid& g = grids[s0 + k];
+            return (double)(pot_off[s0 + k + 1] - pot_off[s0 + k] + 1) * g.nx * g.ny;
+        };
+        std::stable_sort(perm.begin(), perm.end(), [&](int x, int y) { return cost(x) > cost(y); });
+        const size_t o_pot = 0, o_grid = align8(o_pot + 4 * (size_t)(n + 1)),
+                     o_perm = align8(o_grid + sizeof(GridDesc) * (size_t)n), o_fo = align8(o_perm + 4 * (size_t)n),
+                     o_to = o_fo + 8 * (size_t)(n + 1), o_no = o_to + 8 * (size_t)(n + 1),
+                     bytes = o_no + 8 * (size_t)n;
+        if (hipHostMalloc(&ch.host_stage, bytes, hipHostMallocDefault) != hipSuccess) {
+            rc = LENS_ERR_DEVICE;
+            break;
+        }
+        char* hb = (char*)ch.host_stage;
+        int32_t* h_pot = (int32_t*)(hb + o_pot);
+        GridDesc* h_grid = (GridDesc*)(hb + o_grid);
+        int32_t* h_perm = (int32_t*)(hb + o_perm);
+        long long* h_fo = (long long*)(hb + o_fo);
+        long long* h_to = (long long*)(hb + o_to);
+        long long* h_no = (long long*)(hb + o_no);
+        for (int k = 0; k <= n; k++) h_pot[k] = pot_off[s0 + k];
+        long long node = 0;
+        for (int k = 0; k < n; k++) {
+            const lens_grid& g = grids[s0 + k];
+            h_grid[k] = grid_desc(&g);
+            h_no[k] = node;
+            node += (long long)g.nx * g.ny;
+            ch.n_tests += 2ll * (g.nx - 1) * (g.ny - 1);
+        }
+        h_fo[0] = 0;
+        h_to[0] = 0;
+        for (int k = 0; k < n; k++) {
+            const lens_grid& g = grids[s0 + perm[k]];
+            h_perm[k] = perm[k];
+            h_fo[k + 1] = h_fo[k] + (long long)g.ny * ((g.nx + seg_nodes - 1) / seg_nodes);
+            h_to[k + 1] = h_to[k] + (long long)((g.nx - 2) / tx + 1) * ((g.ny - 2) / ty + 1);
+        }
+        ch.n_nodes = node;
+        ch.n_fitems = h_fo[n];
+        ch.n_tiles = h_to[n];
+        if (ch.n_fitems >= (1ll << 31) || ch.n_tiles >= (1ll << 31)) {
+            rc = LENS_ERR_INVALID;
+            (void)hipHostFree(ch.host_stage);
+            break;
+        }
+        if (hipMalloc(&ch.dev_plan, bytes) != hipSuccess || hipMalloc((void**)&ch.fmap, 4 * ch.n_fitems) != hipSuccess ||
+            hipMalloc((void**)&ch.tmap, 4 * ch.n_tiles) != hipSuccess) {
+            rc = LENS_ERR_DEVICE;
+            e->chunks.push_back(ch);
+            break;
+        }
+        char* db = (char*)ch.dev_plan;
+        ch.bp.n = n;
+        ch.bp.pot_off = (const int*)(db + o_pot);
+        ch.bp.grid = (const GridDesc*)(db + o_grid);
+        ch.bp.perm = (const int*)(db + o_perm);
+        ch.bp.fitem_off = (const long long*)(db + o_fo);
+        ch.bp.titem_off = (const long long*)(db + o_to);
+        ch.bp.node_off = (const long long*)(db + o_no);
+        if (hipMemcpyAsync(ch.dev_plan, ch.host_stage, bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
+            launch_bmap(ch.bp, ch.fmap, ch.tmap, s) != hipSuccess)
+            rc = LENS_ERR_DEVICE;
+        e->chunks.push_back(ch);
+        s0 = s1;
+    }
+    c->plans->push_back(e);  // kept even on failure so that destroy frees it
+    if (rc) {
+        e->pot_off.clear();  // never matches again
+        return rc;
+    }
+    *out = e;
+    return LENS_OK;
+}
+
+}  // namespace
+
+extern "C" int lens_image_chi2_batched(lens_ctx* ctx, const lens_potentials* all, int32_t n_samples,
+                                       const int32_t* pot_off, const lens_grid* grids, const lens_obs* obs,
+                                       const lens_chi2_opts* opts, lens_batch_out* out, hipStream_t stream)
+{
+    if (!ctx || check_pot(all) || n_samples < 1 || !pot_off || !grids || check_obs(obs) || !opts || !out)
+        return LENS_ERR_INVALID;
+    if (!out->chi2 || !out->chi2_sys || !out->n_pred || !out->status || !out->stats) return LENS_ERR_INVALID;
+    if (obs->n_img > kBatchMax || obs->n_sys > kBatchMax) return LENS_ERR_INVALID;
+    if (opts->prec != LENS_FP64 && opts->prec != LENS_MIXED) return LENS_ERR_INVALID;
+    if (opts->hit_capacity < 1 || opts->hit_capacity > kBatchMax) return LENS_ERR_INVALID;
+    if (opts->prec == LENS_MIXED && (opts->fb_mode < 0 || opts->fb_mode > 1)) return LENS_ERR_INVALID;
+    if (opts->prec == LENS_MIXED && opts->fb_mode == 1 && !(opts->fb_tau >= 0.0 && is_fin(opts->fb_tau)))
+        return LENS_ERR_INVALID;
+    if (!(opts->field_npl == 0 || opts->field_npl == 1 || opts->field_npl == 2 || opts->field_npl == 4) ||
+        opts->tile < 0 || opts->tile > 4)
+        return LENS_ERR_INVALID;
+    if (pot_off[0] != 0 || pot_off[n_samples] != all->n) return LENS_ERR_INVALID;
+    for (int i = 0; i < n_samples; i++) {
+        if (pot_off[i + 1] < pot_off[i] || check_grid(&grids[i])) return LENS_ERR_INVALID;
+    }
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return LENS_ERR_DEVICE;
+    const bool mixed = opts->prec == LENS_MIXED;
+    const int npl = mixed ? (opts->field_npl ? opts->field_npl : 2) : 1;
+    const int shape = opts->tile ? opts->tile : 1;
+    PlanEntry* plan = nullptr;
+    int rc = batch_plan(ctx, n_samples, pot_off, grids, npl, shape, mixed, stream, &plan);
+    if (rc) return rc;
+
+    // scratch sized for the largest chunk
+    long long max_n = 0, max_np = 0, max_nodes = 0, max_tiles = 0, n_tests = 0;
+    for (const PlanChunk& ch : plan->chunks) {
+        max_n = std::max(max_n, (long long)ch.n);
+        max_np = std::max(max_np, (long long)ch.np);
+        max_nodes = std::max(max_nodes, ch.n_nodes);
+        max_tiles = std::max(max_tiles, ch.n_tiles);
+        n_tests += ch.n_tests * obs->n_sys;
+    }
+    const int hcap = opts->hit_capacity;
+    const long long flag_cap = mixed ? kFlagScratch : 0;
+    const size_t per_sample_hits = (size_t)max_n * hcap;
+    if ((rc = ensure(ctx, B_TAB64, (size_t)max_np * T64_STRIDE * 8)) ||
+        (rc = ensure(ctx, B_TAB32, (size_t)max_np * T32_STRIDE * 4)) ||
+        (rc = ensure(ctx, B_BTERM, (size_t)max_np * 3 * 8)) ||
+        (rc = ensure(ctx, B_FIELD, (size_t)max_nodes * (mixed ? 8 : 16))) ||
+        (rc = ensure(ctx, B_BX, (size_t)max_n * obs->n_img * 8)) ||
+        (rc = ensure(ctx, B_BY, (size_t)max_n * obs->n_img * 8)) ||
+        (rc = ensure(ctx, B_SYS, (size_t)max_n * obs->n_sys * SYS_STRIDE * 8)) ||
+        (rc = ensure(ctx, B_HITS, per_sample_hits * 2 * 8)) ||
+        (rc = ensure(ctx, B_FLAGS, (size_t)(mixed ? kFlagScratch : 1) * 8)) ||
+        (rc = ensure(ctx, B_POS, per_sample_hits * 4 * 8)) || (rc = ensure(ctx, B_PART, (size_t)max_tiles * 2 * 4)) ||
+        (rc = ensure(ctx, B_BCOUNT, (size_t)max_n * 20 + 8 * 16)))
+        return rc;
+    unsigned long long* hits = (unsigned long long*)ctx->buf[B_HITS];
+    unsigned long long* fb = hits + per_sample_hits;
+    double* pos = (double*)ctx->buf[B_POS];
+    double* fb_pos = pos + 2 * per_sample_hits;
+    unsigned long long* flags = (unsigned long long*)ctx->buf[B_FLAGS];
+    unsigned long long* agg = (unsigned long long*)ctx->buf[B_BCOUNT];
+    BatchState bs;
+    bs.n_flags = agg + 8;
+    bs.n_hits = agg + 16;
+    bs.n_fb = bs.n_hits + max_n;
+    bs.status = (int*)(bs.n_fb + max_n);
+    const ObsPtrs o = obs_ptrs(obs);
+    const PotPtrs p = pot_ptrs(all);
+    double* bx = (double*)ctx->buf[B_BX];
+    double* by = (double*)ctx->buf[B_BY];
+    double* sysrow = (double*)ctx->buf[B_SYS];
+    void* field = ctx->buf[B_FIELD];
+    unsigned* part = (unsigned*)ctx->buf[B_PART];
+    if (launch_zero_u64(agg, 8, stream) != hipSuccess) return LENS_ERR_DEVICE;
+    for (const PlanChunk& ch : plan->chunks) {
+        const BatchPlan& bp = ch.bp;
+        hipError_t e = launch_bhead(bp, p, o, (double*)ctx->buf[B_TAB64], (float*)ctx->buf[B_TAB32],
+                                    (double*)ctx->buf[B_BTERM], bx, by, ch.np, stream);
+        if (e == hipSuccess) e = launch_bsys(bp, o, (double*)ctx->buf[B_BTERM], bx, by, sysrow, bs, stream);
+        int slot;
+        if ((rc = timing_begin(ctx, stream, &slot))) return rc;
+        if (e == hipSuccess) {
+            if (mixed)
+                e = launch_bfield32(bp, ch.fmap, ch.n_fitems, (const float*)ctx->buf[B_TAB32], (float*)field,
+                                    (float*)field + ch.n_nodes, npl, stream);
+            else
+                e = launch_bfield64(bp, ch.fmap, ch.n_fitems, (const double*)ctx->buf[B_TAB64], (double*)field,
+                                    (double*)field + ch.n_nodes, stream);
+        }
+        if (e != hipSuccess) return LENS_ERR_DEVICE;
+        if ((rc = timing_end(ctx, stream, slot))) return rc;
+        const void* fx = field;
+        const void* fy = mixed ? (const void*)((float*)field + ch.n_nodes) : (const void*)((double*)field + ch.n_nodes);
+        e = launch_btri(bp, ch.tmap, ch.n_tiles, o.n_sys, sysrow, fx, fy, mixed, bs, opts->fb_mode,
+                        (float)opts->fb_tau, hcap, hits, flags, flag_cap, part, shape, stream);
+        if (e == hipSuccess)
+            e = launch_bfbpos(bp, o.n_sys, (const double*)ctx->buf[B_TAB64], sysrow, bs, hcap, hits, flags, flag_cap,
+                              fb, pos, fb_pos, stream);
+        if (e == hipSuccess)
+            e = launch_btail(bp, o, bs, hcap, flag_cap, hits, fb, pos, fb_pos, out->chi2 + ch.s0,
+                             out->chi2_sys + (size_t)ch.s0 * o.n_sys, out->n_pred + (size_t)ch.s0 * o.n_sys,
+                             out->status + ch.s0, agg, part, ch.n_tiles, stream);
+        if (e != hipSuccess) return LENS_ERR_DEVICE;
+    }
+    return launch_bstats(agg, n_tests, (long long*)out->stats, stream) == hipSuccess ? LENS_OK : LENS_ERR_DEVICE;
+}

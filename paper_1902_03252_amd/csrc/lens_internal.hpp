@@ -25,11 +25,30 @@ struct ObsPtrs {
 
 struct EvalState;
 
-constexpr int kTileX = 32, kTileY = 8;  // cells per triangle-stage tile
+// Work plan of one chunk of a batch (device arrays), built on the host.
+struct BatchPlan {
+    int n;                        // samples in the chunk
+    const int* pot_off;           // [n+1] parameter columns of each sample (absolute)
+    const GridDesc* grid;         // [n]
+    const int* perm;              // [n] plan position -> sample (heaviest first)
+    const long long* fitem_off;   // [n+1] field work items, in plan order
+    const long long* titem_off;   // [n+1] triangle-stage tiles, in plan order
+    const long long* node_off;    // [n] offset of each sample's field (nodes)
+};
+
+// Per-sample counters and status of a batch chunk (device arrays).
+struct BatchState {
+    unsigned long long* n_hits;   // [n] certain hits
+    unsigned long long* n_fb;     // [n] fallback hits
+    unsigned long long* n_flags;  // [1] undecided tests of the chunk
+    int* status;                  // [n]
+};
+
 constexpr int kTriBlocks = 2048;         // persistent workgroups of the triangle stage
 constexpr long long kHitScratch = 8192;   // largest hit list sorted in LDS (2^13)
 constexpr long long kFlagScratch = 1 << 20;
 constexpr int kMaxSystems = 1 << 19;      // systems fit the packed sort key
+constexpr int kBatchMax = 1024;           // batch: per-sample hit capacity, images and systems
 
 hipError_t launch_head(const PotPtrs& pot, const GridDesc& g, const ObsPtrs& obs, double* tab64, float* tab32,
                        double* bterm, double* bx, double* by, double* sysrow, EvalState* st, hipStream_t s);
@@ -37,12 +56,12 @@ hipError_t launch_field32(const float* tab32, int np, const GridDesc& g, float* 
                           const EvalState* st, int npl, hipStream_t s);
 hipError_t launch_field64(const double* tab64, int np, const GridDesc& g, double* ax, double* ay,
                           const EvalState* st, hipStream_t s);
-int tri_blocks(const GridDesc& g);
+int tri_blocks(const GridDesc& g, int shape);
 hipError_t launch_tri32(const float* ax, const float* ay, const GridDesc& g, int nsys, const double* sysrow,
                         EvalState* st, int mode, float tau, unsigned long long* hit_keys, long long hit_cap,
-                        unsigned long long* flag_keys, long long flag_cap, unsigned* part, hipStream_t s);
+                        unsigned long long* flag_keys, long long flag_cap, unsigned* part, int shape, hipStream_t s);
 hipError_t launch_tri64(const double* ax, const double* ay, const GridDesc& g, int nsys, const double* sysrow,
-                        EvalState* st, unsigned long long* hit_keys, long long hit_cap, unsigned* part,
+                        EvalState* st, unsigned long long* hit_keys, long long hit_cap, unsigned* part, int shape,
                         hipStream_t s);
 
 // Outputs and lists of the tail of a chi^2 evaluation.
@@ -70,6 +89,29 @@ hipError_t launch_fbpos(const double* tab64, int np, const GridDesc& g, const do
                         double* fb_pos, hipStream_t s);
 hipError_t launch_tail(const TailLaunch& tl, EvalState* st, const unsigned long long* fb_keys, const double* pos,
                        const double* fb_pos, hipStream_t s);
+hipError_t launch_bhead(const BatchPlan& bp, const PotPtrs& pot, const ObsPtrs& obs, double* tab64, float* tab32,
+                        double* bterm, double* bx, double* by, int np_chunk, hipStream_t s);
+hipError_t launch_bsys(const BatchPlan& bp, const ObsPtrs& obs, const double* bterm, const double* bx,
+                       const double* by, double* sysrow, const BatchState& bs, hipStream_t s);
+hipError_t launch_bmap(const BatchPlan& bp, int* fmap, int* tmap, hipStream_t s);
+hipError_t launch_bfield32(const BatchPlan& bp, const int* fmap, long long n_items, const float* tab32, float* fx,
+                           float* fy, int npl, hipStream_t s);
+hipError_t launch_bfield64(const BatchPlan& bp, const int* fmap, long long n_items, const double* tab64, double* fx,
+                           double* fy, hipStream_t s);
+hipError_t launch_btri(const BatchPlan& bp, const int* tmap, long long n_items, int nsys, const double* sysrow,
+                       const void* fx, const void* fy, bool fp32, const BatchState& bs, int mode, float tau, int hcap,
+                       unsigned long long* hits, unsigned long long* flags, long long flag_cap, unsigned* part,
+                       int shape, hipStream_t s);
+hipError_t launch_bfbpos(const BatchPlan& bp, int nsys, const double* tab64, const double* sysrow,
+                         const BatchState& bs, int hcap, const unsigned long long* hits,
+                         const unsigned long long* flags, long long flag_cap, unsigned long long* fb, double* pos,
+                         double* fb_pos, hipStream_t s);
+hipError_t launch_btail(const BatchPlan& bp, const ObsPtrs& obs, const BatchState& bs, int hcap, long long flag_cap,
+                        const unsigned long long* hits, const unsigned long long* fb, const double* pos,
+                        const double* fb_pos, double* chi2, double* chi2_sys, int* n_pred, int* status,
+                        unsigned long long* agg, const unsigned* part, long long n_parts, hipStream_t s);
+hipError_t launch_bstats(const unsigned long long* agg, long long n_tests, long long* stats, hipStream_t s);
+hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s);
 hipError_t launch_dls(double zl, const double* zs, int n, double om, double ol, double* out, hipStream_t s);
 hipError_t launch_export(const double* sysrow, int nsys, const EvalState* st, double* bar_x, double* bar_y,
                          int* status, hipStream_t s);

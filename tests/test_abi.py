@@ -73,20 +73,42 @@ def test_host_validation_rejects_before_any_device_call(lib):
         assert lb.lens_deflect(ctx, C.byref(pot), C.byref(g), 0, buf, buf, None, None) == L.LENS_ERR_INVALID
     assert lb.lens_deflect(ctx, C.byref(pot), C.byref(grid), 7, buf, buf, None, None) == L.LENS_ERR_INVALID
     obs = L.LensObs(0, 0, buf, buf, buf, buf, buf)  # no systems
-    opts = L.LensChi2Opts(2, 0, 0.0, 16)
+    opts = L.LensChi2Opts(2, 0, 0.0, 16, 0, 0)
     out = L.LensChi2Out(buf, buf, buf, buf, buf, buf, buf)
     assert lb.lens_image_chi2(ctx, C.byref(pot), C.byref(grid), C.byref(obs), C.byref(opts), C.byref(out),
                               None) == L.LENS_ERR_INVALID
     obs = L.LensObs(1, 2, buf, buf, buf, buf, buf)
-    for o in (L.LensChi2Opts(1, 0, 0.0, 16),          # FP32 is a field-only precision
-              L.LensChi2Opts(2, 0, 0.0, 0),           # no hit capacity
-              L.LensChi2Opts(2, 0, 0.0, 1 << 20),     # beyond the sortable hit list
-              L.LensChi2Opts(2, 1, -1.0, 16),         # negative literal threshold
-              L.LensChi2Opts(2, 5, 0.0, 16)):         # unknown fallback mode
+    for o in (L.LensChi2Opts(1, 0, 0.0, 16, 0, 0),          # FP32 is a field-only precision
+              L.LensChi2Opts(2, 0, 0.0, 0, 0, 0),           # no hit capacity
+              L.LensChi2Opts(2, 0, 0.0, 1 << 20, 0, 0),     # beyond the sortable hit list
+              L.LensChi2Opts(2, 1, -1.0, 16, 0, 0),         # negative literal threshold
+              L.LensChi2Opts(2, 5, 0.0, 16, 0, 0),          # unknown fallback mode
+              L.LensChi2Opts(2, 0, 0.0, 16, 3, 0),          # nodes per thread not a power of two
+              L.LensChi2Opts(2, 0, 0.0, 16, 0, 9)):         # unknown tile shape
         assert lb.lens_image_chi2(ctx, C.byref(pot), C.byref(grid), C.byref(obs), C.byref(o), C.byref(out),
                                   None) == L.LENS_ERR_INVALID
     out_null = L.LensChi2Out(None, buf, buf, buf, buf, buf, buf)
     assert lb.lens_image_chi2(ctx, C.byref(pot), C.byref(grid), C.byref(obs), C.byref(opts), C.byref(out_null),
                               None) == L.LENS_ERR_INVALID
+    # batched entry point: sample layout and per-sample limits
+    bout = L.LensBatchOut(buf, buf, buf, buf, buf)
+    pot2 = L.LensPotentials(4, buf, buf, buf, buf, buf, buf, buf)
+    grids = (L.LensGrid * 2)(grid, grid)
+
+    def batched(off, o=opts, n=2, g=grids, ob=obs, out_=bout):
+        offs = (C.c_int32 * len(off))(*off)
+        return lb.lens_image_chi2_batched(ctx, C.byref(pot2), n, offs, g, C.byref(ob), C.byref(o), C.byref(out_),
+                                          None)
+
+    assert batched([0, 1, 3]) == L.LENS_ERR_INVALID          # last offset is not P
+    assert batched([1, 2, 4]) == L.LENS_ERR_INVALID          # first offset is not 0
+    assert batched([0, 3, 2, 4], n=3) == L.LENS_ERR_INVALID  # decreasing
+    assert batched([0, 4], n=0) == L.LENS_ERR_INVALID        # no samples
+    assert batched([0, 2, 4], g=(L.LensGrid * 2)(grid, L.LensGrid(0, 0, 1.0, 1, 16))) == L.LENS_ERR_INVALID
+    assert batched([0, 2, 4], o=L.LensChi2Opts(2, 0, 0.0, 2048, 0, 0)) == L.LENS_ERR_INVALID  # > 1024 per sample
+    assert batched([0, 2, 4], o=L.LensChi2Opts(1, 0, 0.0, 16, 0, 0)) == L.LENS_ERR_INVALID   # FP32
+    assert batched([0, 2, 4], o=L.LensChi2Opts(2, 0, 0.0, 16, 8, 0)) == L.LENS_ERR_INVALID   # 8 nodes/thread
+    assert batched([0, 2, 4], ob=L.LensObs(1, 2000, buf, buf, buf, buf, buf)) == L.LENS_ERR_INVALID
+    assert batched([0, 2, 4], out_=L.LensBatchOut(buf, buf, None, buf, buf)) == L.LENS_ERR_INVALID
     assert lb.lens_dls_dos(ctx, 0.3, buf, 1, 0.5, 0.7, buf, None) == L.LENS_ERR_INVALID  # not flat
     assert lb.lens_create(None, 0) == L.LENS_ERR_INVALID
