@@ -71,7 +71,7 @@ def _load():
         lib.orc_src_chi2.restype = d
         lib.orc_src_chi2.argtypes = [dp, i, i, ip, dp, dp, dp, dp]
         lib.orc_src_chi2_grad.argtypes = [dp, i, i, ip, dp, dp, dp, dp, dp]
-        lib.orc_alpha_vjp.argtypes = [dp, i, d, d, d, i, i, dp, dp, dp, i]
+        lib.orc_alpha_vjp.argtypes = [dp, i, d, d, d, i, i, dp, dp, dp, i, i]
         _lib = lib
     return _lib
 
@@ -300,12 +300,13 @@ def src_chi2_grad(prm, obs):
     return g
 
 
-def alpha_vjp(prm, grid, gx, gy, nthreads: int | None = None):
-    """sum over nodes of g . d(alpha)/d(q) for every parameter, shape [7, P]."""
+def alpha_vjp(prm, grid, gx, gy, nthreads: int | None = None, absolute: bool = False):
+    """sum over nodes of g . d(alpha)/d(q) for every parameter, shape [7, P];
+    absolute=True sums |gx d alpha_1/dq| + |gy d alpha_2/dq| instead."""
     prm, pp, n = _prm(prm)
     gx, gxp = _d(np.asarray(gx).reshape(grid.ny, grid.nx))
     gy, gyp = _d(np.asarray(gy).reshape(grid.ny, grid.nx))
     g = np.zeros((7, n))
     _load().orc_alpha_vjp(pp, n, grid.x0, grid.y0, grid.h, grid.nx, grid.ny, gxp, gyp, _d(g)[1],
-                          nthreads or default_threads())
+                          nthreads or default_threads(), int(bool(absolute)))
     return g

@@ -766,6 +766,7 @@ typedef struct {
     const double *prm; int np;
     double x0, y0, h; int nx, ny;
     const double *gx, *gy;
+    int absval;            /* 1: sum |gx d alpha_1/dq| + |gy d alpha_2/dq| instead */
     double *part;          /* [7*np] partial sums of this thread */
 } orc_vjp_job;
 
@@ -785,19 +786,23 @@ static void *orc_vjp_rows(void *arg)
                     if (k == 5 && !isfinite(creal(q[5]))) continue;
                     q[k] += ih * I;
                     orc_alpha1_c(q, t1, t2, &a1, &a2);
-                    jb->part[k * np + p] += jb->gx[n] * (cimag(a1) / ih) + jb->gy[n] * (cimag(a2) / ih);
+                    double t1v = jb->gx[n] * (cimag(a1) / ih), t2v = jb->gy[n] * (cimag(a2) / ih);
+                    if (jb->absval) { t1v = fabs(t1v); t2v = fabs(t2v); }
+                    jb->part[k * np + p] += t1v + t2v;
                 }
         }
     return NULL;
 }
 
+/* absval = 1 gives the magnitude sum over nodes of |gx d alpha_1/dq| +
+ * |gy d alpha_2/dq| (the scale of the rounding error of any evaluation order). */
 void orc_alpha_vjp(const double *prm, int np, double x0, double y0, double h, int nx, int ny,
-                   const double *gx, const double *gy, double *grad, int nthreads)
+                   const double *gx, const double *gy, double *grad, int nthreads, int absval)
 {
     nthreads = orc_clamp_threads(nthreads, ny);
     orc_vjp_job *jobs = (orc_vjp_job *)calloc(nthreads, sizeof(orc_vjp_job));
     for (int t = 0; t < nthreads; t++) {
-        orc_vjp_job jb = {{0, 0}, prm, np, x0, y0, h, nx, ny, gx, gy,
+        orc_vjp_job jb = {{0, 0}, prm, np, x0, y0, h, nx, ny, gx, gy, absval,
                           (double *)calloc(7 * np, sizeof(double))};
         jobs[t] = jb;
     }

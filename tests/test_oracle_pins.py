@@ -430,6 +430,26 @@ def test_alpha_vjp_against_finite_differences():
             assert vjp[k, pi] == pytest.approx(fd, rel=1e-5, abs=1e-6)
 
 
+def test_alpha_vjp_magnitude_mode_is_the_sum_of_node_magnitudes():
+    """absolute=True equals the sum over nodes of |gx d alpha_1/dq| + |gy d alpha_2/dq|,
+    each node's term taken from the signed VJP on a one-node grid with one cotangent
+    component at a time; it bounds the signed VJP."""
+    prm, _, _ = _small_cluster()
+    grid = S.Grid(-13.0, -7.5, 2.25, 5, 4)
+    g = np.random.default_rng(12)
+    gx, gy = g.normal(size=(grid.ny, grid.nx)), g.normal(size=(grid.ny, grid.nx))
+    mag = oracle.alpha_vjp(prm, grid, gx, gy, absolute=True)
+    want = np.zeros_like(mag)
+    one, zero = np.ones((1, 1)), np.zeros((1, 1))
+    for j in range(grid.ny):
+        for i in range(grid.nx):
+            node = S.Grid(grid.x0 + i * grid.h, grid.y0 + j * grid.h, 1.0, 1, 1)
+            want += np.abs(gx[j, i] * oracle.alpha_vjp(prm, node, one, zero))
+            want += np.abs(gy[j, i] * oracle.alpha_vjp(prm, node, zero, one))
+    np.testing.assert_allclose(mag, want, rtol=1e-12, atol=0)
+    assert (np.abs(oracle.alpha_vjp(prm, grid, gx, gy)) <= mag * (1 + 1e-12)).all()
+
+
 def _small_cluster():
     prm = S.cluster_potentials(3, 2)
     grid = S.square_grid(65, 40.0)
