@@ -194,9 +194,50 @@ int lens_image_chi2_batched(lens_ctx *ctx, const lens_potentials *all, int32_t n
                             const int32_t *pot_off, const lens_grid *grids, const lens_obs *obs,
                             const lens_chi2_opts *opts, lens_batch_out *out, hipStream_t stream);
 
+/* ---------------------------------------------------------------- backward form
+ *
+ * The paper has no derivatives.  These are the analytic derivatives of the
+ * deflection of Algorithm 1, generalised to the cored/cut profile
+ * (Sec. 2.2.2), with respect to the seven parameters of every potential, in
+ * the order of lens_potentials: x, y, eps, phi, r_core, r_cut, sigma_v.  A
+ * parameter gradient `grad` is a device double array [7 * n], row-major
+ * [parameter][potential], the layout of a [7, n] parameter table.  Derivatives
+ * with respect to an infinite r_cut are 0; the centre of a singular profile
+ * contributes nothing (as in the forward deflection).  Potentials outside the
+ * model's domain give NaN gradients and status LENS_ERR_INVALID. */
+
+/* Vector-Jacobian product of the deflection field:
+ *     grad[k*n + p] = sum over nodes of g_ax * d ax/d q + g_ay * d ay/d q,
+ * q = parameter k of potential p.  g_ax, g_ay: device double [ny*nx], the
+ * layout of lens_deflect's output.  prec = LENS_FP64: every product in FP64;
+ * LENS_FP32: per-node products in FP32 (node offsets from the same exact
+ * centre split as the FP32 field), summed per thread over 16 nodes in FP32
+ * and reduced in FP64.  Deterministic (fixed reduction order).  status:
+ * device int32 [1] or NULL. */
+int lens_deflect_backward(lens_ctx *ctx, const lens_potentials *pot, const lens_grid *grid,
+                          lens_precision prec, const double *g_ax, const double *g_ay, double *grad,
+                          int32_t *status, hipStream_t stream);
+
+/* Source-plane chi^2 of the observed systems (FP64): beta_ij = theta_ij -
+ * (D_LS/D_OS)_i grad Psi(theta_ij) (Sec. 2.2.2), bar_i the unweighted mean of
+ * system i's beta_ij, chi2 = sum_i sum_j |beta_ij - bar_i|^2 / sigma_ij^2,
+ * summed in a fixed order.  chi2: device double [1].  The paper's chi^2 is the
+ * image-plane one; this source-plane form is the differentiable companion of
+ * the backward form. */
+int lens_src_chi2(lens_ctx *ctx, const lens_potentials *pot, const lens_obs *obs, double *chi2,
+                  int32_t *status, hipStream_t stream);
+
+/* Gradient of the source-plane chi^2: grad = g_chi2 * d chi2/d q (FP64), with
+ * d beta_ij/d q = -(D_LS/D_OS)_i d grad Psi(theta_ij)/d q.  g_chi2: device
+ * double [1] (the upstream derivative) or NULL for 1.  Recomputes the
+ * forward pass. */
+int lens_src_chi2_backward(lens_ctx *ctx, const lens_potentials *pot, const lens_obs *obs,
+                           const double *g_chi2, double *grad, int32_t *status, hipStream_t stream);
+
 /* Kernel timing (instrumentation, for roofline measurement).  While enabled,
  * every launch of the deflection-field kernel (the dominant kernel of
- * lens_deflect and lens_image_chi2) is bracketed by HIP events recorded on
+ * lens_deflect and lens_image_chi2) and of the two kernels of
+ * lens_deflect_backward is bracketed by HIP events recorded on
  * the call's stream.  lens_field_timing waits for the recorded events and
  * returns the summed kernel time in milliseconds and the number of launches
  * since the last reset (reset != 0 clears the totals).  Do not enable while a

@@ -265,6 +265,92 @@ def lens_image_chi2_batched(params: torch.Tensor, layout: BatchLayout, obs: Obs,
     return out
 
 
+# ---------------------------------------------------------------- backward form
+
+def lens_deflect_backward(params: torch.Tensor, grid, g_ax: torch.Tensor, g_ay: torch.Tensor, prec: str = "fp64",
+                          ctx: Context | None = None, check: bool = True) -> torch.Tensor:
+    """sum over nodes of g . d(alpha)/d(params): gradient [7, P] float64.  prec 'fp64',
+    or 'fp32' (FP32 per-node products, FP64 accumulation)."""
+    ctx = ctx or context(params.device.index)
+    if prec not in ("fp64", "fp32"):
+        raise ValueError("prec must be 'fp64' or 'fp32'")
+    p = _pots(params)
+    for name, t in (("g_ax", g_ax), ("g_ay", g_ay)):
+        _require_cuda(t, torch.float64, name)
+        if t.numel() != grid.nx * grid.ny:
+            raise ValueError(f"{name} must have ny*nx elements")
+    grad = torch.empty_like(params)
+    status = torch.zeros(1, dtype=torch.int32, device=params.device)
+    L.check(ctx._lib.lens_deflect_backward(ctx.handle, C.byref(p), C.byref(_grid(grid)), _PREC[prec], L.ptr(g_ax),
+                                           L.ptr(g_ay), L.ptr(grad), L.ptr(status), ctx.stream()),
+            "lens_deflect_backward")
+    if check and int(status.item()) != L.LENS_OK:
+        raise RuntimeError(f"lens_deflect_backward: invalid potential parameters (status {int(status.item())})")
+    return grad
+
+
+def lens_src_chi2(params: torch.Tensor, obs: Obs, ctx: Context | None = None, status: torch.Tensor | None = None):
+    """Source-plane chi^2 (FP64), a [1] float64 tensor (asynchronous)."""
+    ctx = ctx or context(params.device.index)
+    p, o = _pots(params), _obs(obs)
+    out = torch.empty(1, dtype=torch.float64, device=params.device)
+    L.check(ctx._lib.lens_src_chi2(ctx.handle, C.byref(p), C.byref(o), L.ptr(out), L.ptr(status), ctx.stream()),
+            "lens_src_chi2")
+    return out
+
+
+def lens_src_chi2_backward(params: torch.Tensor, obs: Obs, g_chi2: torch.Tensor | None = None,
+                           ctx: Context | None = None, status: torch.Tensor | None = None) -> torch.Tensor:
+    """g_chi2 * d(chi2_src)/d(params), [7, P] float64 (g_chi2: [1] float64 device tensor or None)."""
+    ctx = ctx or context(params.device.index)
+    p, o = _pots(params), _obs(obs)
+    if g_chi2 is not None:
+        _require_cuda(g_chi2, torch.float64, "g_chi2")
+    grad = torch.empty_like(params)
+    L.check(ctx._lib.lens_src_chi2_backward(ctx.handle, C.byref(p), C.byref(o), L.ptr(g_chi2), L.ptr(grad),
+                                            L.ptr(status), ctx.stream()), "lens_src_chi2_backward")
+    return grad
+
+
+class DeflectFn(torch.autograd.Function):
+    """(ax, ay) = deflection field of params [7, P] on `grid`; differentiable in params.
+    prec 'fp64' (FP64 forward and backward) or 'mixed' (FP32 field, FP32 products with
+    FP64 accumulation in the backward pass)."""
+
+    @staticmethod
+    def forward(fctx, params, grid, prec="fp64"):
+        ax, ay = lens_deflect(params, grid, "fp64" if prec == "fp64" else "fp32")
+        fctx.save_for_backward(params)
+        fctx.grid, fctx.prec = grid, prec
+        return ax, ay
+
+    @staticmethod
+    def backward(fctx, g_ax, g_ay):
+        (params,) = fctx.saved_tensors
+        z = lambda g: (torch.zeros((fctx.grid.ny, fctx.grid.nx), dtype=torch.float64, device=params.device)
+                       if g is None else g.to(torch.float64).contiguous())
+        grad = lens_deflect_backward(params, fctx.grid, z(g_ax), z(g_ay),
+                                     "fp64" if fctx.prec == "fp64" else "fp32", check=False)
+        return grad, None, None
+
+
+class SrcChi2Fn(torch.autograd.Function):
+    """Source-plane chi^2 of params [7, P] against `obs` (a 0-d float64 tensor)."""
+
+    @staticmethod
+    def forward(fctx, params, obs):
+        fctx.save_for_backward(params)
+        fctx.obs = obs
+        return lens_src_chi2(params, obs).reshape(())
+
+    @staticmethod
+    def backward(fctx, g):
+        (params,) = fctx.saved_tensors
+        g1 = g.reshape(1).to(torch.float64).contiguous()
+        return lens_src_chi2_backward(params, fctx.obs, g1), None
+
+
 __all__ = ["Obs", "Context", "context", "lens_dls_dos", "lens_deflect", "lens_source_positions",
            "lens_image_chi2", "Chi2Result", "chi2_buffers", "BatchLayout", "BatchResult", "batch_buffers",
-           "lens_image_chi2_batched"]
+           "lens_image_chi2_batched", "lens_deflect_backward", "lens_src_chi2", "lens_src_chi2_backward",
+           "DeflectFn", "SrcChi2Fn"]

@@ -20,8 +20,8 @@ STAT_HITS, STAT_FLAGGED, STAT_TILE_PASS, STAT_BBOX_PASS, STAT_STATUS, STAT_FB_HI
 STAT_N = 8
 
 EXPORTS = ("lens_create", "lens_destroy", "lens_dls_dos", "lens_deflect", "lens_source_positions",
-           "lens_image_chi2", "lens_image_chi2_batched", "lens_set_timing", "lens_field_timing",
-           "lens_strerror")
+           "lens_image_chi2", "lens_image_chi2_batched", "lens_deflect_backward", "lens_src_chi2",
+           "lens_src_chi2_backward", "lens_set_timing", "lens_field_timing", "lens_strerror")
 
 
 class LensPotentials(C.Structure):
@@ -82,6 +82,13 @@ def load(path: str = LIB_PATH):
     lib.lens_image_chi2_batched.argtypes = [vp, C.POINTER(LensPotentials), i32, C.POINTER(i32), C.POINTER(LensGrid),
                                             C.POINTER(LensObs), C.POINTER(LensChi2Opts), C.POINTER(LensBatchOut), vp]
     lib.lens_image_chi2_batched.restype = C.c_int
+    lib.lens_deflect_backward.argtypes = [vp, C.POINTER(LensPotentials), C.POINTER(LensGrid), C.c_int, vp, vp, vp,
+                                          vp, vp]
+    lib.lens_deflect_backward.restype = C.c_int
+    lib.lens_src_chi2.argtypes = [vp, C.POINTER(LensPotentials), C.POINTER(LensObs), vp, vp, vp]
+    lib.lens_src_chi2.restype = C.c_int
+    lib.lens_src_chi2_backward.argtypes = [vp, C.POINTER(LensPotentials), C.POINTER(LensObs), vp, vp, vp, vp]
+    lib.lens_src_chi2_backward.restype = C.c_int
     lib.lens_set_timing.argtypes = [vp, C.c_int]
     lib.lens_set_timing.restype = C.c_int
     lib.lens_field_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]

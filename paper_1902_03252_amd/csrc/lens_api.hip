@@ -16,7 +16,7 @@ using namespace lens;
 namespace {
 
 enum Buf { B_TAB64, B_TAB32, B_BTERM, B_FIELD, B_BX, B_BY, B_SYS, B_STATE, B_HITS, B_FLAGS, B_POS, B_CONTRIB,
-           B_PART, B_BCOUNT, B_NBUF };
+           B_PART, B_BCOUNT, B_VJP, B_SRC, B_SRCST, B_NBUF };
 
 // Device work plan of one chunk of a batch (see lens_image_chi2_batched).
 struct PlanChunk {
@@ -102,7 +102,8 @@ int ensure(lens_ctx* c, int which, size_t bytes)
     }
     void* p = nullptr;
     if (hipMalloc(&p, nb) != hipSuccess) return LENS_ERR_DEVICE;
-    if (which == B_STATE && hipMemset(p, 0, nb) != hipSuccess) return LENS_ERR_DEVICE;  // ticket starts at 0
+    if ((which == B_STATE || which == B_SRCST) && hipMemset(p, 0, nb) != hipSuccess)
+        return LENS_ERR_DEVICE;  // tickets start at 0
     c->buf[which] = p;
     c->cap[which] = nb;
     return LENS_OK;
@@ -759,4 +760,60 @@ extern "C" int lens_image_chi2_batched(lens_ctx* ctx, const lens_potentials* all
         if (e != hipSuccess) return LENS_ERR_DEVICE;
     }
     return launch_bstats(agg, n_tests, (long long*)out->stats, stream) == hipSuccess ? LENS_OK : LENS_ERR_DEVICE;
+}
+
+// ---------------------------------------------------------------- backward form
+
+extern "C" int lens_deflect_backward(lens_ctx* ctx, const lens_potentials* pot, const lens_grid* grid,
+                                     lens_precision prec, const double* g_ax, const double* g_ay, double* grad,
+                                     int32_t* status, hipStream_t stream)
+{
+    if (!ctx || check_pot(pot) || check_grid(grid) || !g_ax || !g_ay || (pot->n > 0 && !grad))
+        return LENS_ERR_INVALID;
+    if (prec != LENS_FP64 && prec != LENS_FP32) return LENS_ERR_INVALID;
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return LENS_ERR_DEVICE;
+    const GridDesc g = grid_desc(grid);
+    int rc = ensure(ctx, B_VJP, (size_t)7 * pot->n * vjp_chunks(g) * 8);
+    if (rc) return rc;
+    int slot;
+    if ((rc = timing_begin(ctx, stream, &slot))) return rc;
+    if (launch_vjp(pot_ptrs(pot), g, prec == LENS_FP32, g_ax, g_ay, (double*)ctx->buf[B_VJP], grad, status,
+                   stream) != hipSuccess)
+        return LENS_ERR_DEVICE;
+    return timing_end(ctx, stream, slot);
+}
+
+namespace {
+
+int src_common(lens_ctx* ctx, const lens_potentials* pot, const lens_obs* obs, double* chi2, int32_t* status,
+               const double* g_chi2, double* grad, hipStream_t stream)
+{
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return LENS_ERR_DEVICE;
+    int rc;
+    const size_t ni = obs->n_img > 0 ? obs->n_img : 1;
+    if ((rc = ensure(ctx, B_SRC, (4 * ni + obs->n_sys) * 8)) || (rc = ensure(ctx, B_SRCST, sizeof(SrcState))))
+        return rc;
+    double* beta = (double*)ctx->buf[B_SRC];
+    if (launch_src(pot_ptrs(pot), obs_ptrs(obs), beta, beta + 2 * ni, beta + 4 * ni, (SrcState*)ctx->buf[B_SRCST],
+                   chi2, status, g_chi2, grad, stream) != hipSuccess)
+        return LENS_ERR_DEVICE;
+    return LENS_OK;
+}
+
+}  // namespace
+
+extern "C" int lens_src_chi2(lens_ctx* ctx, const lens_potentials* pot, const lens_obs* obs, double* chi2,
+                             int32_t* status, hipStream_t stream)
+{
+    if (!ctx || check_pot(pot) || check_obs(obs) || !chi2) return LENS_ERR_INVALID;
+    return src_common(ctx, pot, obs, chi2, status, nullptr, nullptr, stream);
+}
+
+extern "C" int lens_src_chi2_backward(lens_ctx* ctx, const lens_potentials* pot, const lens_obs* obs,
+                                      const double* g_chi2, double* grad, int32_t* status, hipStream_t stream)
+{
+    if (!ctx || check_pot(pot) || check_obs(obs) || (pot->n > 0 && !grad)) return LENS_ERR_INVALID;
+    return src_common(ctx, pot, obs, nullptr, status, g_chi2, grad, stream);
 }

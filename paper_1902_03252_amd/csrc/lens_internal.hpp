@@ -89,6 +89,20 @@ hipError_t launch_fbpos(const double* tab64, int np, const GridDesc& g, const do
                         double* fb_pos, hipStream_t s);
 hipError_t launch_tail(const TailLaunch& tl, EvalState* st, const unsigned long long* fb_keys, const double* pos,
                        const double* fb_pos, hipStream_t s);
+// Device state of the source-plane chi^2 (zeroed once at allocation).
+struct SrcState {
+    unsigned ticket;  // "last workgroup" ticket, zero between launches
+    int bad;          // a potential outside the model's domain (reset by the last workgroup)
+    int status;       // status of the latest forward pass
+    int pad;
+};
+
+int vjp_chunks(const GridDesc& g);
+hipError_t launch_vjp(const PotPtrs& pot, const GridDesc& g, bool fp32, const double* gx, const double* gy,
+                      double* part, double* grad, int* status, hipStream_t s);
+hipError_t launch_src(const PotPtrs& pot, const ObsPtrs& obs, double* beta, double* cot, double* csys,
+                      SrcState* st, double* chi2, int* status, const double* g_chi2, double* grad, hipStream_t s);
+
 hipError_t launch_bhead(const BatchPlan& bp, const PotPtrs& pot, const ObsPtrs& obs, double* tab64, float* tab32,
                         double* bterm, double* bx, double* by, int np_chunk, hipStream_t s);
 hipError_t launch_bsys(const BatchPlan& bp, const ObsPtrs& obs, const double* bterm, const double* bx,

@@ -110,5 +110,16 @@ def test_host_validation_rejects_before_any_device_call(lib):
     assert batched([0, 2, 4], o=L.LensChi2Opts(2, 0, 0.0, 16, 8, 0)) == L.LENS_ERR_INVALID   # 8 nodes/thread
     assert batched([0, 2, 4], ob=L.LensObs(1, 2000, buf, buf, buf, buf, buf)) == L.LENS_ERR_INVALID
     assert batched([0, 2, 4], out_=L.LensBatchOut(buf, buf, None, buf, buf)) == L.LENS_ERR_INVALID
+    # backward form
+    assert lb.lens_deflect_backward(ctx, C.byref(pot2), C.byref(grid), 2, buf, buf, buf, None, None) == \
+        L.LENS_ERR_INVALID  # mixed is not a backward precision
+    assert lb.lens_deflect_backward(ctx, C.byref(pot2), C.byref(grid), 0, None, buf, buf, None, None) == \
+        L.LENS_ERR_INVALID
+    assert lb.lens_deflect_backward(ctx, C.byref(pot2), C.byref(grid), 1, buf, buf, None, None, None) == \
+        L.LENS_ERR_INVALID
+    assert lb.lens_src_chi2(ctx, C.byref(pot2), C.byref(obs), None, None, None) == L.LENS_ERR_INVALID
+    assert lb.lens_src_chi2(ctx, C.byref(pot2), C.byref(L.LensObs(0, 0, buf, buf, buf, buf, buf)), buf, None,
+                            None) == L.LENS_ERR_INVALID
+    assert lb.lens_src_chi2_backward(ctx, C.byref(pot2), C.byref(obs), None, None, None, None) == L.LENS_ERR_INVALID
     assert lb.lens_dls_dos(ctx, 0.3, buf, 1, 0.5, 0.7, buf, None) == L.LENS_ERR_INVALID  # not flat
     assert lb.lens_create(None, 0) == L.LENS_ERR_INVALID
