@@ -33,6 +33,9 @@ PEAK_FP64_TFLOPS = 78.6    # MI355X FP64 vector peak
 FLOPS_PER_EVAL = 34        # flops of one cored/cut pixel-potential evaluation, counted on the formula
                            # (+,-,x = 1, fma = 2, sqrt = 1, div = 1): translate 2, rotate 6, R^2 5,
                            # two square roots 4, f 5, lens-frame gradient 4, rotate back + sum 8
+FLOPS_PER_VJP = 107        # flops of one cored/cut (node, potential) term of the deflection VJP, counted on the
+                           # formula as above: offsets and R^2 9, square roots and reciprocals 5 + 9, f and F' 11,
+                           # df/da, df/ds 3, g.m, Kf, KF' 5, x/y rows 18, eps/Phi rows 34, a/s/sigma rows 13
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_field32_cluster.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1902_03252_amd", "csrc", f)
                   for f in ("lens_kernels.hip", "lens_path.hpp", "lens_device.hpp")]
@@ -144,7 +147,38 @@ def gpu_bench(args):
                            hits=int(st[0]))
     large["speedup_mixed_vs_fp64"] = large["fp64"]["ms_per_eval"] / large["mixed"]["ms_per_eval"]
     batched = batched_bench(torch, lens, ctx, obs, obs_np, args) if args.batch > 0 else None
-    return prm, grid, obs_np, n_tri, res, large, batched
+    backward = backward_bench(torch, lens, ctx, obs, args) if args.backward else None
+    return prm, grid, obs_np, n_tri, res, large, batched, backward
+
+
+def backward_bench(torch, lens, ctx, obs, args):
+    """Differentiation workload: the 50 cluster potentials on a 512^2 grid over
+    +-80", N(0,1) cotangent; deflection VJP (FP64 and FP32 products) and the
+    source-plane chi^2 gradient of the 20 systems."""
+    import synthlens as S
+    w = S.WORKLOADS[5]
+    grid = w.grid
+    prm = S.potentials(5)
+    cot = S.cotangent(grid.nx * grid.ny)
+    p = torch.as_tensor(prm, dtype=torch.float64, device="cuda")
+    gx = torch.as_tensor(cot[0], dtype=torch.float64, device="cuda")
+    gy = torch.as_tensor(cot[1], dtype=torch.float64, device="cuda")
+    flops = FLOPS_PER_VJP * float(grid.nx * grid.ny * prm.shape[1])
+    out = {"workload": f"{prm.shape[1]} potentials, {grid.nx}^2 grid, 7 parameters each, N(0,1) cotangent"}
+    for prec in ("fp64", "fp32"):
+        step = lambda: lens.lens_deflect_backward(p, grid, gx, gy, prec, ctx=ctx, check=False)
+        ctx.set_timing(True)
+        ctx.field_timing(reset=True)
+        dt = time_steps(torch, step, 20, 3)
+        kms, nl = ctx.field_timing(reset=True)
+        ctx.set_timing(False)
+        kern_s = kms / 1e3 / max(nl, 1)
+        peak = PEAK_FP64_TFLOPS if prec == "fp64" else PEAK_FP32_TFLOPS
+        out[prec] = dict(ms_per_vjp=dt * 1e3, vjp_kernel_ms=kern_s * 1e3, tflops=flops / kern_s / 1e12,
+                         frac_of_peak=flops / kern_s / 1e12 / peak)
+    dt = time_steps(torch, lambda: lens.lens_src_chi2_backward(p, obs, ctx=ctx), 20, 3)
+    out["src_chi2_grad_ms"] = dt * 1e3
+    return out
 
 
 def batched_bench(torch, lens, ctx, obs, obs_np, args):
@@ -221,6 +255,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for the baseline")
     ap.add_argument("--batch", type=int, default=1024, help="samples of the batched leg (0 skips it)")
     ap.add_argument("--batch-steps", type=int, default=5, help="timed replays of the batched leg")
+    ap.add_argument("--no-backward", dest="backward", action="store_false", help="skip the backward leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 256 MiB device-to-device 3 times (a known-size kernel that calibrates the "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
@@ -238,7 +273,7 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    prm, grid, obs_np, n_tri, res, large, batched = gpu_bench(args)
+    prm, grid, obs_np, n_tri, res, large, batched, backward = gpu_bench(args)
     mixed, fp64 = res["mixed"], res["fp64"]
     step_s = mixed["graph_s"]
     evals = grid.nx * grid.ny * prm.shape[1]
@@ -290,6 +325,7 @@ def main():
                      "flops_per_launch": flops, "avg_launch_ms": mixed["kern_ms"], "launches_timed": mixed["launches"]},
         "large": large,
         "batched": batched,
+        "backward": backward,
         "cpu_baseline": cpu,
         "parity": parity,
     }

@@ -204,10 +204,12 @@ int fold_timing(lens_ctx* c)
     return LENS_OK;
 }
 
-// Event pair for the next timed launch (nullptr if timing is off).
-int timing_begin(lens_ctx* c, hipStream_t s, int* slot)
+// Event pair for the next timed kernel: *ev is null when timing is off, else
+// it points to the pair, which the kernel's dispatch records around itself.
+int timing_begin(lens_ctx* c, KernelEvents* store, const KernelEvents** ev, int* slot)
 {
     *slot = -1;
+    *ev = nullptr;
     if (!c->timing) return LENS_OK;
     if (c->n_pending == kMaxPending) {
         int rc = fold_timing(c);
@@ -219,17 +221,17 @@ int timing_begin(lens_ctx* c, hipStream_t s, int* slot)
             return LENS_ERR_DEVICE;
         c->n_events = k + 1;
     }
-    if (hipEventRecord(c->ev_start[k], s) != hipSuccess) return LENS_ERR_DEVICE;
+    store->start = c->ev_start[k];
+    store->stop = c->ev_stop[k];
+    *ev = store;
     *slot = k;
     return LENS_OK;
 }
 
-int timing_end(lens_ctx* c, hipStream_t s, int slot)
+// Marks the pair of a launched timed kernel as pending.
+void timing_end(lens_ctx* c, int slot)
 {
-    if (slot < 0) return LENS_OK;
-    if (hipEventRecord(c->ev_stop[slot], s) != hipSuccess) return LENS_ERR_DEVICE;
-    c->n_pending = slot + 1;
-    return LENS_OK;
+    if (slot >= 0) c->n_pending = slot + 1;
 }
 
 // Constants, source positions, barycentres and error bound: the head of every
@@ -357,15 +359,17 @@ int lens_deflect(lens_ctx* ctx, const lens_potentials* pot, const lens_grid* gri
     if (rc) return rc;
     const EvalState* st = (const EvalState*)ctx->buf[B_STATE];
     int slot;
-    if ((rc = timing_begin(ctx, stream, &slot))) return rc;
+    KernelEvents kev;
+    const KernelEvents* ev;
+    if ((rc = timing_begin(ctx, &kev, &ev, &slot))) return rc;
     hipError_t e;
     if (prec == LENS_FP64)
-        e = launch_field64((const double*)ctx->buf[B_TAB64], pot->n, g, (double*)ax, (double*)ay, st, stream);
+        e = launch_field64((const double*)ctx->buf[B_TAB64], pot->n, g, (double*)ax, (double*)ay, st, ev, stream);
     else
-        e = launch_field32((const float*)ctx->buf[B_TAB32], pot->n, g, (float*)ax, (float*)ay, st, field_npl(g),
+        e = launch_field32((const float*)ctx->buf[B_TAB32], pot->n, g, (float*)ax, (float*)ay, st, field_npl(g), ev,
                            stream);
     if (e != hipSuccess) return LENS_ERR_DEVICE;
-    if ((rc = timing_end(ctx, stream, slot))) return rc;
+    timing_end(ctx, slot);
     if (status && launch_export(nullptr, 0, st, nullptr, nullptr, status, stream) != hipSuccess)
         return LENS_ERR_DEVICE;
     return LENS_OK;
@@ -440,16 +444,18 @@ int lens_image_chi2(lens_ctx* ctx, const lens_potentials* pot, const lens_grid* 
     const long long flag_cap = mixed ? kFlagScratch : 0;
 
     int slot;
-    if ((rc = timing_begin(ctx, stream, &slot))) return rc;
+    KernelEvents kev;
+    const KernelEvents* ev;
+    if ((rc = timing_begin(ctx, &kev, &ev, &slot))) return rc;
     hipError_t e;
     void* field = ctx->buf[B_FIELD];
     if (mixed)
         e = launch_field32((const float*)ctx->buf[B_TAB32], np, g, (float*)field, (float*)field + nn, nullptr, npl,
-                           stream);
+                           ev, stream);
     else
-        e = launch_field64(tab64, np, g, (double*)field, (double*)field + nn, nullptr, stream);
+        e = launch_field64(tab64, np, g, (double*)field, (double*)field + nn, nullptr, ev, stream);
     if (e != hipSuccess) return LENS_ERR_DEVICE;
-    if ((rc = timing_end(ctx, stream, slot))) return rc;
+    timing_end(ctx, slot);
 
     if (mixed)
         e = launch_tri32((const float*)field, (const float*)field + nn, g, o.n_sys, sysrow, st, opts->fb_mode,
@@ -735,17 +741,19 @@ extern "C" int lens_image_chi2_batched(lens_ctx* ctx, const lens_potentials* all
                                     (double*)ctx->buf[B_BTERM], bx, by, ch.np, stream);
         if (e == hipSuccess) e = launch_bsys(bp, o, (double*)ctx->buf[B_BTERM], bx, by, sysrow, bs, stream);
         int slot;
-        if ((rc = timing_begin(ctx, stream, &slot))) return rc;
+        KernelEvents kev;
+        const KernelEvents* ev;
+        if ((rc = timing_begin(ctx, &kev, &ev, &slot))) return rc;
         if (e == hipSuccess) {
             if (mixed)
                 e = launch_bfield32(bp, ch.fmap, ch.n_fitems, (const float*)ctx->buf[B_TAB32], (float*)field,
-                                    (float*)field + ch.n_nodes, npl, stream);
+                                    (float*)field + ch.n_nodes, npl, ev, stream);
             else
                 e = launch_bfield64(bp, ch.fmap, ch.n_fitems, (const double*)ctx->buf[B_TAB64], (double*)field,
-                                    (double*)field + ch.n_nodes, stream);
+                                    (double*)field + ch.n_nodes, ev, stream);
         }
         if (e != hipSuccess) return LENS_ERR_DEVICE;
-        if ((rc = timing_end(ctx, stream, slot))) return rc;
+        timing_end(ctx, slot);
         const void* fx = field;
         const void* fy = mixed ? (const void*)((float*)field + ch.n_nodes) : (const void*)((double*)field + ch.n_nodes);
         e = launch_btri(bp, ch.tmap, ch.n_tiles, o.n_sys, sysrow, fx, fy, mixed, bs, opts->fb_mode,
@@ -777,11 +785,14 @@ extern "C" int lens_deflect_backward(lens_ctx* ctx, const lens_potentials* pot, 
     int rc = ensure(ctx, B_VJP, (size_t)7 * pot->n * vjp_chunks(g) * 8);
     if (rc) return rc;
     int slot;
-    if ((rc = timing_begin(ctx, stream, &slot))) return rc;
-    if (launch_vjp(pot_ptrs(pot), g, prec == LENS_FP32, g_ax, g_ay, (double*)ctx->buf[B_VJP], grad, status,
+    KernelEvents kev;
+    const KernelEvents* ev;
+    if ((rc = timing_begin(ctx, &kev, &ev, &slot))) return rc;
+    if (launch_vjp(pot_ptrs(pot), g, prec == LENS_FP32, g_ax, g_ay, (double*)ctx->buf[B_VJP], grad, status, ev,
                    stream) != hipSuccess)
         return LENS_ERR_DEVICE;
-    return timing_end(ctx, stream, slot);
+    timing_end(ctx, slot);
+    return LENS_OK;
 }
 
 namespace {

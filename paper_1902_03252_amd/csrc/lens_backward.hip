@@ -356,7 +356,7 @@ __global__ void k_status(int* status, int v)
 int vjp_chunks(const GridDesc& g) { return (int)(((long long)g.nx * g.ny + kVjpChunk - 1) / kVjpChunk); }
 
 hipError_t launch_vjp(const PotPtrs& pot, const GridDesc& g, bool fp32, const double* gx, const double* gy,
-                      double* part, double* grad, int* status, hipStream_t s)
+                      double* part, double* grad, int* status, const KernelEvents* ev, hipStream_t s)
 {
     if (pot.n == 0) {
         if (status) k_status<<<1, 64, 0, s>>>(status, kStatusOk);
@@ -364,11 +364,9 @@ hipError_t launch_vjp(const PotPtrs& pot, const GridDesc& g, bool fp32, const do
     }
     const int nc = vjp_chunks(g);
     const long long nb = (long long)nc * ((pot.n + kVjpGroup - 1) / kVjpGroup);
-    if (fp32)
-        k_vjp<float><<<(unsigned)nb, 256, 0, s>>>(pot, g, gx, gy, nc, part, status);
-    else
-        k_vjp<double><<<(unsigned)nb, 256, 0, s>>>(pot, g, gx, gy, nc, part, status);
-    hipError_t e = hipGetLastError();
+    hipError_t e = fp32 ? launch_ev(ev, k_vjp<float>, dim3((unsigned)nb), dim3(256), s, pot, g, gx, gy, nc, part, status)
+                        : launch_ev(ev, k_vjp<double>, dim3((unsigned)nb), dim3(256), s, pot, g, gx, gy, nc, part,
+                                    status);
     if (e != hipSuccess) return e;
     k_vjp_final<<<(unsigned)((7ll * pot.n + 3) / 4), 256, 0, s>>>(pot, part, nc, grad, status);
     return hipGetLastError();

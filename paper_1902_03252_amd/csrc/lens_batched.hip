@@ -357,9 +357,11 @@ __global__ __launch_bounds__(256) void k_btail(BatchPlan bp, ObsPtrs obs, BatchS
                                                const unsigned* __restrict__ part, long long n_parts)
 {
     constexpr int NT = 256, CAP = 2 * kTailStage;
-    if (blockIdx.x == 0) {  // chunk statistics: undecided tests, tile passes, bbox passes
+    {  // chunk statistics (tile passes, bbox passes), one slice of the tiles per workgroup
+        const long long per = (n_parts + gridDim.x - 1) / gridDim.x;
+        const long long q0 = (long long)blockIdx.x * per, q1 = min(n_parts, q0 + per);
         unsigned long long a = 0, b = 0;
-        for (long long q = threadIdx.x; q < n_parts; q += NT) {
+        for (long long q = q0 + threadIdx.x; q < q1; q += NT) {
             a += part[2 * q];
             b += part[2 * q + 1];
         }
@@ -367,11 +369,11 @@ __global__ __launch_bounds__(256) void k_btail(BatchPlan bp, ObsPtrs obs, BatchS
             a += __shfl_xor(a, m, 64);
             b += __shfl_xor(b, m, 64);
         }
-        if (lane_id() == 0) {
+        if (lane_id() == 0 && (a | b) != 0) {
             atomicAdd(&agg[4], a);
             atomicAdd(&agg[5], b);
         }
-        if (threadIdx.x == 0) atomicAdd(&agg[3], *bs.n_flags);
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&agg[3], *bs.n_flags);  // undecided tests
     }
     __shared__ unsigned long long key[CAP];
     __shared__ double upx[CAP], upy[CAP];
@@ -503,21 +505,20 @@ hipError_t launch_bmap(const BatchPlan& bp, int* fmap, int* tmap, hipStream_t s)
 }
 
 hipError_t launch_bfield32(const BatchPlan& bp, const int* fmap, long long n_items, const float* tab32, float* fx,
-                           float* fy, int npl, hipStream_t s)
+                           float* fy, int npl, const KernelEvents* ev, hipStream_t s)
 {
+    const dim3 grid((unsigned)n_items), block(256);
     switch (npl) {
-    case 1: k_bfield32<1><<<(unsigned)n_items, 256, 0, s>>>(bp, fmap, tab32, fx, fy); break;
-    case 4: k_bfield32<4><<<(unsigned)n_items, 256, 0, s>>>(bp, fmap, tab32, fx, fy); break;
-    default: k_bfield32<2><<<(unsigned)n_items, 256, 0, s>>>(bp, fmap, tab32, fx, fy); break;
+    case 1: return launch_ev(ev, k_bfield32<1>, grid, block, s, bp, fmap, tab32, fx, fy);
+    case 4: return launch_ev(ev, k_bfield32<4>, grid, block, s, bp, fmap, tab32, fx, fy);
+    default: return launch_ev(ev, k_bfield32<2>, grid, block, s, bp, fmap, tab32, fx, fy);
     }
-    return hipGetLastError();
 }
 
 hipError_t launch_bfield64(const BatchPlan& bp, const int* fmap, long long n_items, const double* tab64, double* fx,
-                           double* fy, hipStream_t s)
+                           double* fy, const KernelEvents* ev, hipStream_t s)
 {
-    k_bfield64<<<(unsigned)n_items, 256, 0, s>>>(bp, fmap, tab64, fx, fy);
-    return hipGetLastError();
+    return launch_ev(ev, k_bfield64, dim3((unsigned)n_items), dim3(256), s, bp, fmap, tab64, fx, fy);
 }
 
 template <class F>

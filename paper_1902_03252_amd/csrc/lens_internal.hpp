@@ -2,6 +2,7 @@
 // (lens_kernels.hip).  Plain structs of device pointers and host launchers.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -24,6 +25,23 @@ struct ObsPtrs {
 };
 
 struct EvalState;
+
+// Start/stop events recorded by the dispatch of one kernel itself, so that
+// their difference is the kernel's own duration.
+struct KernelEvents {
+    hipEvent_t start, stop;
+};
+
+// Launches `kernel`, timed by `ev` when it is not null.
+template <typename F, typename... Args>
+inline hipError_t launch_ev(const KernelEvents* ev, F kernel, dim3 grid, dim3 block, hipStream_t s, Args... args)
+{
+    if (ev)
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, s, ev->start, ev->stop, 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+    return hipGetLastError();
+}
 
 // Work plan of one chunk of a batch (device arrays), built on the host.
 struct BatchPlan {
@@ -53,9 +71,9 @@ constexpr int kBatchMax = 1024;           // batch: per-sample hit capacity, ima
 hipError_t launch_head(const PotPtrs& pot, const GridDesc& g, const ObsPtrs& obs, double* tab64, float* tab32,
                        double* bterm, double* bx, double* by, double* sysrow, EvalState* st, hipStream_t s);
 hipError_t launch_field32(const float* tab32, int np, const GridDesc& g, float* ax, float* ay,
-                          const EvalState* st, int npl, hipStream_t s);
+                          const EvalState* st, int npl, const KernelEvents* ev, hipStream_t s);
 hipError_t launch_field64(const double* tab64, int np, const GridDesc& g, double* ax, double* ay,
-                          const EvalState* st, hipStream_t s);
+                          const EvalState* st, const KernelEvents* ev, hipStream_t s);
 int tri_blocks(const GridDesc& g, int shape);
 hipError_t launch_tri32(const float* ax, const float* ay, const GridDesc& g, int nsys, const double* sysrow,
                         EvalState* st, int mode, float tau, unsigned long long* hit_keys, long long hit_cap,
@@ -99,7 +117,7 @@ struct SrcState {
 
 int vjp_chunks(const GridDesc& g);
 hipError_t launch_vjp(const PotPtrs& pot, const GridDesc& g, bool fp32, const double* gx, const double* gy,
-                      double* part, double* grad, int* status, hipStream_t s);
+                      double* part, double* grad, int* status, const KernelEvents* ev, hipStream_t s);
 hipError_t launch_src(const PotPtrs& pot, const ObsPtrs& obs, double* beta, double* cot, double* csys,
                       SrcState* st, double* chi2, int* status, const double* g_chi2, double* grad, hipStream_t s);
 
@@ -109,9 +127,9 @@ hipError_t launch_bsys(const BatchPlan& bp, const ObsPtrs& obs, const double* bt
                        const double* by, double* sysrow, const BatchState& bs, hipStream_t s);
 hipError_t launch_bmap(const BatchPlan& bp, int* fmap, int* tmap, hipStream_t s);
 hipError_t launch_bfield32(const BatchPlan& bp, const int* fmap, long long n_items, const float* tab32, float* fx,
-                           float* fy, int npl, hipStream_t s);
+                           float* fy, int npl, const KernelEvents* ev, hipStream_t s);
 hipError_t launch_bfield64(const BatchPlan& bp, const int* fmap, long long n_items, const double* tab64, double* fx,
-                           double* fy, hipStream_t s);
+                           double* fy, const KernelEvents* ev, hipStream_t s);
 hipError_t launch_btri(const BatchPlan& bp, const int* tmap, long long n_items, int nsys, const double* sysrow,
                        const void* fx, const void* fy, bool fp32, const BatchState& bs, int mode, float tau, int hcap,
                        unsigned long long* hits, unsigned long long* flags, long long flag_cap, unsigned* part,

@@ -656,22 +656,20 @@ hipError_t launch_head(const PotPtrs& pot, const GridDesc& g, const ObsPtrs& obs
 }
 
 hipError_t launch_field32(const float* tab32, int np, const GridDesc& g, float* ax, float* ay,
-                          const EvalState* st, int npl, hipStream_t s)
+                          const EvalState* st, int npl, const KernelEvents* ev, hipStream_t s)
 {
     switch (npl) {
-    case 1: k_field32<1><<<dim3(cdiv(g.nx, 256), g.ny), 256, 0, s>>>(tab32, np, g.nx, g.ny, ax, ay, st); break;
-    case 2: k_field32<2><<<dim3(cdiv(g.nx, 512), g.ny), 256, 0, s>>>(tab32, np, g.nx, g.ny, ax, ay, st); break;
-    case 4: k_field32<4><<<dim3(cdiv(g.nx, 1024), g.ny), 256, 0, s>>>(tab32, np, g.nx, g.ny, ax, ay, st); break;
-    default: k_field32<8><<<dim3(cdiv(g.nx, 2048), g.ny), 256, 0, s>>>(tab32, np, g.nx, g.ny, ax, ay, st); break;
+    case 1: return launch_ev(ev, k_field32<1>, dim3(cdiv(g.nx, 256), g.ny), dim3(256), s, tab32, np, g.nx, g.ny, ax, ay, st);
+    case 2: return launch_ev(ev, k_field32<2>, dim3(cdiv(g.nx, 512), g.ny), dim3(256), s, tab32, np, g.nx, g.ny, ax, ay, st);
+    case 4: return launch_ev(ev, k_field32<4>, dim3(cdiv(g.nx, 1024), g.ny), dim3(256), s, tab32, np, g.nx, g.ny, ax, ay, st);
+    default: return launch_ev(ev, k_field32<8>, dim3(cdiv(g.nx, 2048), g.ny), dim3(256), s, tab32, np, g.nx, g.ny, ax, ay, st);
     }
-    return hipGetLastError();
 }
 
 hipError_t launch_field64(const double* tab64, int np, const GridDesc& g, double* ax, double* ay,
-                          const EvalState* st, hipStream_t s)
+                          const EvalState* st, const KernelEvents* ev, hipStream_t s)
 {
-    k_field64<<<dim3(cdiv(g.nx, 256), g.ny), 256, 0, s>>>(tab64, np, g, ax, ay, st);
-    return hipGetLastError();
+    return launch_ev(ev, k_field64, dim3(cdiv(g.nx, 256), g.ny), dim3(256), s, tab64, np, g, ax, ay, st);
 }
 
 // Tile shapes selectable per call (lens_chi2_opts.tile): 1 = 32x8 (default),
