@@ -16,7 +16,7 @@ using namespace lens;
 namespace {
 
 enum Buf { B_TAB64, B_TAB32, B_BTERM, B_FIELD, B_BX, B_BY, B_SYS, B_STATE, B_HITS, B_FLAGS, B_POS, B_CONTRIB,
-           B_PART, B_BCOUNT, B_VJP, B_SRC, B_SRCST, B_NBUF };
+           B_PART, B_BCOUNT, B_VJP, B_SRC, B_SRCST, B_RR, B_NBUF };
 
 // Device work plan of one chunk of a batch (see lens_image_chi2_batched).
 struct PlanChunk {
@@ -366,8 +366,8 @@ int lens_deflect(lens_ctx* ctx, const lens_potentials* pot, const lens_grid* gri
     if (prec == LENS_FP64)
         e = launch_field64((const double*)ctx->buf[B_TAB64], pot->n, g, (double*)ax, (double*)ay, st, ev, stream);
     else
-        e = launch_field32((const float*)ctx->buf[B_TAB32], pot->n, g, (float*)ax, (float*)ay, st, field_npl(g), ev,
-                           stream);
+        e = launch_field32((const float*)ctx->buf[B_TAB32], pot->n, g, (float*)ax, (float*)ay, st, field_npl(g),
+                           nullptr, 5, 1, ev, stream);
     if (e != hipSuccess) return LENS_ERR_DEVICE;
     timing_end(ctx, slot);
     if (status && launch_export(nullptr, 0, st, nullptr, nullptr, status, stream) != hipSuccess)
@@ -426,10 +426,16 @@ int lens_image_chi2(lens_ctx* ctx, const lens_potentials* pot, const lens_grid* 
         return rc;
     const int shape = opts->tile ? opts->tile : 1;
     const int npl = opts->field_npl ? opts->field_npl : field_npl(g);
-    const int n_parts = tri_blocks(g, shape);
+    const int n_parts = tri_blocks(g, shape, mixed);
+    int tile_x, tile_y;
+    tile_dims(shape, tile_x, tile_y);
+    const int tx_shift = tile_x == 64 ? 6 : 5;
+    const int tiles_x = (g.nx - 2) / tile_x + 1;
     if ((rc = ensure(ctx, B_PART, (size_t)n_parts * 2 * 4)) ||
-        (rc = ensure(ctx, B_SYS, (size_t)o.n_sys * SYS_STRIDE * 8)))
+        (rc = ensure(ctx, B_SYS, (size_t)o.n_sys * SYS_STRIDE * 8)) ||
+        (rc = ensure(ctx, B_RR, mixed ? (size_t)g.ny * tiles_x * 16 : 16)))
         return rc;
+    float* rr = (float*)ctx->buf[B_RR];
     unsigned* part = (unsigned*)ctx->buf[B_PART];
     if ((rc = head(ctx, pot, g, o, (double*)ctx->buf[B_BX], (double*)ctx->buf[B_BY], stream))) return rc;
 
@@ -451,14 +457,14 @@ int lens_image_chi2(lens_ctx* ctx, const lens_potentials* pot, const lens_grid* 
     void* field = ctx->buf[B_FIELD];
     if (mixed)
         e = launch_field32((const float*)ctx->buf[B_TAB32], np, g, (float*)field, (float*)field + nn, nullptr, npl,
-                           ev, stream);
+                           rr, tx_shift, tiles_x, ev, stream);
     else
         e = launch_field64(tab64, np, g, (double*)field, (double*)field + nn, nullptr, ev, stream);
     if (e != hipSuccess) return LENS_ERR_DEVICE;
     timing_end(ctx, slot);
 
     if (mixed)
-        e = launch_tri32((const float*)field, (const float*)field + nn, g, o.n_sys, sysrow, st, opts->fb_mode,
+        e = launch_tri32((const float*)field, (const float*)field + nn, rr, g, o.n_sys, sysrow, st, opts->fb_mode,
                          (float)(opts->fb_tau * g.h * g.h), hits, kHitScratch, flags, flag_cap, part, shape, stream);
     else
         e = launch_tri64((const double*)field, (const double*)field + nn, g, o.n_sys, sysrow, st, hits, kHitScratch,
@@ -491,17 +497,6 @@ int lens_image_chi2(lens_ctx* ctx, const lens_potentials* pot, const lens_grid* 
 }  // extern "C"
 
 namespace {
-
-// Triangle-stage tile dimensions of a tile-shape code (see lens_chi2_opts.tile).
-void tile_dims(int shape, int& tx, int& ty)
-{
-    switch (shape) {
-    case 2: tx = 64; ty = 16; break;
-    case 3: tx = 64; ty = 8; break;
-    case 4: tx = 32; ty = 16; break;
-    default: tx = 32; ty = 8; break;
-    }
-}
 
 size_t align8(size_t v) { return (v + 7) & ~(size_t)7; }
 

@@ -172,14 +172,7 @@ __global__ __launch_bounds__(256) void k_bfield32(BatchPlan bp, const int* __res
         sx[q] = 0.0f;
         sy[q] = 0.0f;
     }
-    for (int p = 0; p < np; p++) {
-        const float* c = tab + (size_t)p * T32_STRIDE;
-        const int kind = (int)c[T32_KIND];
-        if (kind == 0) field32_pot<0, NPL>(c, fj, fi, sx, sy);
-        else if (kind == 1) field32_pot<1, NPL>(c, fj, fi, sx, sy);
-        else if (kind == 2) field32_pot<2, NPL>(c, fj, fi, sx, sy);
-        else field32_pot<3, NPL>(c, fj, fi, sx, sy);
-    }
+    field32_all<NPL>(tab, np, fj, fi, sx, sy);
     const size_t row = (size_t)bp.node_off[s] + (size_t)j * g.nx;
 #pragma unroll
     for (int q = 0; q < NPL; q++) {

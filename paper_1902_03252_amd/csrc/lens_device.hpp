@@ -45,7 +45,7 @@ enum : int {
     T32_S2A2,                                // s^2 - a^2
     T32_RA, T32_RS,                          // a, s (arcsec)
     T32_K,                                   // K / h
-    T32_KIND,                                // 0: a>0,s<inf  1: a>0,s=inf  2: a=0,s<inf  3: a=0,s=inf
+    T32_KIND,                                // int bits: 0: a>0,s<inf  1: a>0,s=inf  2: a=0,s<inf  3: a=0,s=inf
     T32_STRIDE = 16
 };
 

@@ -71,11 +71,13 @@ constexpr int kBatchMax = 1024;           // batch: per-sample hit capacity, ima
 hipError_t launch_head(const PotPtrs& pot, const GridDesc& g, const ObsPtrs& obs, double* tab64, float* tab32,
                        double* bterm, double* bx, double* by, double* sysrow, EvalState* st, hipStream_t s);
 hipError_t launch_field32(const float* tab32, int np, const GridDesc& g, float* ax, float* ay,
-                          const EvalState* st, int npl, const KernelEvents* ev, hipStream_t s);
+                          const EvalState* st, int npl, float* rr, int tx_shift, int tiles_x,
+                          const KernelEvents* ev, hipStream_t s);
 hipError_t launch_field64(const double* tab64, int np, const GridDesc& g, double* ax, double* ay,
                           const EvalState* st, const KernelEvents* ev, hipStream_t s);
-int tri_blocks(const GridDesc& g, int shape);
-hipError_t launch_tri32(const float* ax, const float* ay, const GridDesc& g, int nsys, const double* sysrow,
+int tri_blocks(const GridDesc& g, int shape, bool fp32);
+void tile_dims(int shape, int& tx, int& ty);
+hipError_t launch_tri32(const float* ax, const float* ay, const float* rr, const GridDesc& g, int nsys, const double* sysrow,
                         EvalState* st, int mode, float tau, unsigned long long* hit_keys, long long hit_cap,
                         unsigned long long* flag_keys, long long flag_cap, unsigned* part, int shape, hipStream_t s);
 hipError_t launch_tri64(const double* ax, const double* ay, const GridDesc& g, int nsys, const double* sysrow,

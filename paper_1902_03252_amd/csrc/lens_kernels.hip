@@ -135,15 +135,18 @@ __global__ __launch_bounds__(256) void k_head(PotPtrs pot, GridDesc g, ObsPtrs o
 
 // Each thread owns NPL consecutive nodes of one grid row; a workgroup of 256
 // threads covers 256*NPL nodes of that row, so the row offset is uniform and
-// every per-potential constant is a wave-uniform (scalar) operand.
+// every per-potential constant is a wave-uniform (scalar) operand.  With rr
+// set, the kernel also writes the triangle stage's per-(row, tile column)
+// deflection ranges (tile width 1 << tx_shift cells).
 template <int NPL>
 __global__ __launch_bounds__(256) void k_field32(const float* __restrict__ tab32, int np, int nx, int ny,
                                                  float* __restrict__ ax, float* __restrict__ ay,
-                                                 const EvalState* __restrict__ st)
+                                                 const EvalState* __restrict__ st, float* __restrict__ rr,
+                                                 int tx_shift, int tiles_x)
 {
     const int j = blockIdx.y;
     const int i0 = (blockIdx.x * 256 + threadIdx.x) * NPL;
-    if (i0 >= nx) return;
+    if ((int)(blockIdx.x * 256 * NPL) >= nx) return;  // whole workgroup beyond the row
     const float fj = (float)j;
     float fi[NPL], sx[NPL], sy[NPL];
 #pragma unroll
@@ -152,14 +155,8 @@ __global__ __launch_bounds__(256) void k_field32(const float* __restrict__ tab32
         sx[k] = 0.0f;
         sy[k] = 0.0f;
     }
-    for (int p = 0; p < np; p++) {
-        const float* c = tab32 + (size_t)p * T32_STRIDE;
-        const int kind = (int)c[T32_KIND];
-        if (kind == 0) field32_pot<0, NPL>(c, fj, fi, sx, sy);
-        else if (kind == 1) field32_pot<1, NPL>(c, fj, fi, sx, sy);
-        else if (kind == 2) field32_pot<2, NPL>(c, fj, fi, sx, sy);
-        else field32_pot<3, NPL>(c, fj, fi, sx, sy);
-    }
+    field32_all<NPL>(tab32, np, fj, fi, sx, sy);
+    if (rr) tile_partials<NPL>(sx, sy, i0, j, nx, tx_shift, tiles_x, rr);
     const bool bad = st != nullptr && st->status != kStatusOk;
     const size_t row = (size_t)j * nx;
 #pragma unroll
@@ -249,6 +246,73 @@ __global__ __launch_bounds__(256) void k_tri32(const float* __restrict__ ax, con
             }
         }
         __syncthreads();  // the LDS tile is overwritten by the next iteration
+    }
+    write_part(part, blockIdx.x, ntile, nbbox, sbb);
+}
+
+// Mixed path, one wave per tile: the tile's deflection range comes from the
+// field kernel's row partials (plus the halo column), so a tile that no
+// system's barycentre can reach costs a few small loads; only tiles with a
+// surviving system are staged (in a wave-private LDS tile) and tested.
+template <class S>
+__global__ __launch_bounds__(256) void k_tri32w(const float* __restrict__ ax, const float* __restrict__ ay,
+                                                const float* __restrict__ rr, GridDesc g, int tiles_x, int n_tiles,
+                                                int nsys, const double* __restrict__ sysrow,
+                                                EvalState* __restrict__ st, int mode, float tau,
+                                                unsigned long long* __restrict__ hit_keys, long long hit_cap,
+                                                unsigned long long* __restrict__ flag_keys, long long flag_cap,
+                                                unsigned* __restrict__ part)
+{
+    __shared__ float sx[4][S::TNY][S::TNX], sy[4][S::TNY][S::TNX];
+    __shared__ SysChunk chunk;
+    __shared__ unsigned sbb[4];
+    const int wave = threadIdx.x >> 6, lane = lane_id();
+    const int tile = blockIdx.x * 4 + wave;
+    const bool one_chunk = nsys <= SYS_CHUNK;
+    if (one_chunk) {
+        load_chunk(chunk, sysrow, nsys, 0);
+        __syncthreads();
+    }
+    unsigned nbbox = 0, ntile = 0;
+    const bool active = tile < n_tiles;
+    Tile T = {0, 0, 0, 0};
+    double rng[4] = {0.0, 0.0, 0.0, 0.0};
+    if (active) {
+        T = tile_of<S>(g, tiles_x, tile);
+        float r4[4];
+        tile_range_wave<S>(ax, ay, rr, g, tiles_x, T, r4);
+        rng[0] = r4[0];
+        rng[1] = r4[1];
+        rng[2] = r4[2];
+        rng[3] = r4[3];
+    }
+    bool staged = false;
+    for (int cbase = 0; cbase < nsys; cbase += SYS_CHUNK) {
+        if (!one_chunk) {
+            __syncthreads();
+            load_chunk(chunk, sysrow, nsys, cbase);
+            __syncthreads();
+        }
+        if (!active) continue;
+        const int nc = min(SYS_CHUNK, nsys - cbase);
+        for (int sbase = 0; sbase < nc; sbase += 64) {
+            const int sl = sbase + lane;
+            const bool pass = sl < nc && tile_box_contains(g, T, rng, chunk.r[sl], chunk.eb[sl], chunk.bx[sl],
+                                                           chunk.by[sl]);
+            unsigned long long m = __ballot(pass);
+            ntile += __popcll(m);
+            if (m != 0 && !staged) {
+                stage_tile_wave<S>(ax, ay, g, T, sx[wave], sy[wave]);
+                staged = true;
+            }
+            while (m) {
+                const int s = sbase + __ffsll((long long)m) - 1;
+                m &= m - 1;
+                const unsigned long long base = (unsigned long long)(cbase + s) << 32;
+                tri32_wave_system<S>(g, T, sx[wave], sy[wave], chunk.f[s], base, base, mode, tau, &st->n_hits,
+                                     hit_keys, hit_cap, &st->n_flags, flag_keys, flag_cap, nbbox);
+            }
+        }
     }
     write_part(part, blockIdx.x, ntile, nbbox, sbb);
 }
@@ -656,13 +720,14 @@ hipError_t launch_head(const PotPtrs& pot, const GridDesc& g, const ObsPtrs& obs
 }
 
 hipError_t launch_field32(const float* tab32, int np, const GridDesc& g, float* ax, float* ay,
-                          const EvalState* st, int npl, const KernelEvents* ev, hipStream_t s)
+                          const EvalState* st, int npl, float* rr, int tx_shift, int tiles_x,
+                          const KernelEvents* ev, hipStream_t s)
 {
     switch (npl) {
-    case 1: return launch_ev(ev, k_field32<1>, dim3(cdiv(g.nx, 256), g.ny), dim3(256), s, tab32, np, g.nx, g.ny, ax, ay, st);
-    case 2: return launch_ev(ev, k_field32<2>, dim3(cdiv(g.nx, 512), g.ny), dim3(256), s, tab32, np, g.nx, g.ny, ax, ay, st);
-    case 4: return launch_ev(ev, k_field32<4>, dim3(cdiv(g.nx, 1024), g.ny), dim3(256), s, tab32, np, g.nx, g.ny, ax, ay, st);
-    default: return launch_ev(ev, k_field32<8>, dim3(cdiv(g.nx, 2048), g.ny), dim3(256), s, tab32, np, g.nx, g.ny, ax, ay, st);
+    case 1: return launch_ev(ev, k_field32<1>, dim3(cdiv(g.nx, 256), g.ny), dim3(256), s, tab32, np, g.nx, g.ny, ax, ay, st, rr, tx_shift, tiles_x);
+    case 2: return launch_ev(ev, k_field32<2>, dim3(cdiv(g.nx, 512), g.ny), dim3(256), s, tab32, np, g.nx, g.ny, ax, ay, st, rr, tx_shift, tiles_x);
+    case 4: return launch_ev(ev, k_field32<4>, dim3(cdiv(g.nx, 1024), g.ny), dim3(256), s, tab32, np, g.nx, g.ny, ax, ay, st, rr, tx_shift, tiles_x);
+    default: return launch_ev(ev, k_field32<8>, dim3(cdiv(g.nx, 2048), g.ny), dim3(256), s, tab32, np, g.nx, g.ny, ax, ay, st, rr, tx_shift, tiles_x);
     }
 }
 
@@ -685,7 +750,7 @@ static hipError_t with_shape(int shape, F f)
     }
 }
 
-static void shape_dims(int shape, int& tx, int& ty)
+void tile_dims(int shape, int& tx, int& ty)
 {
     switch (shape) {
     case 2: tx = 64; ty = 16; break;
@@ -695,24 +760,28 @@ static void shape_dims(int shape, int& tx, int& ty)
     }
 }
 
-int tri_blocks(const GridDesc& g, int shape)
+// Workgroups of the triangle stage: FP32, one wave per tile; FP64, persistent.
+int tri_blocks(const GridDesc& g, int shape, bool fp32)
 {
     int tx, ty;
-    shape_dims(shape, tx, ty);
+    tile_dims(shape, tx, ty);
     const long long n_tiles = (long long)cdiv(g.nx - 1, tx) * cdiv(g.ny - 1, ty);
+    if (fp32) return (int)cdiv(n_tiles, 4);
     return (int)(n_tiles < kTriBlocks ? n_tiles : kTriBlocks);
 }
 
-hipError_t launch_tri32(const float* ax, const float* ay, const GridDesc& g, int nsys, const double* sysrow,
-                        EvalState* st, int mode, float tau, unsigned long long* hit_keys, long long hit_cap,
-                        unsigned long long* flag_keys, long long flag_cap, unsigned* part, int shape, hipStream_t s)
+hipError_t launch_tri32(const float* ax, const float* ay, const float* rr, const GridDesc& g, int nsys,
+                        const double* sysrow, EvalState* st, int mode, float tau, unsigned long long* hit_keys,
+                        long long hit_cap, unsigned long long* flag_keys, long long flag_cap, unsigned* part,
+                        int shape, hipStream_t s)
 {
     return with_shape(shape, [&](auto sh) {
         using S = decltype(sh);
         const int tiles_x = (int)cdiv(g.nx - 1, S::TX);
         const int n_tiles = tiles_x * (int)cdiv(g.ny - 1, S::TY);
-        k_tri32<S><<<tri_blocks(g, shape), 256, 0, s>>>(ax, ay, g, tiles_x, n_tiles, nsys, sysrow, st, mode, tau,
-                                                        hit_keys, hit_cap, flag_keys, flag_cap, part);
+        k_tri32w<S><<<tri_blocks(g, shape, true), 256, 0, s>>>(ax, ay, rr, g, tiles_x, n_tiles, nsys, sysrow, st,
+                                                               mode, tau, hit_keys, hit_cap, flag_keys, flag_cap,
+                                                               part);
         return hipGetLastError();
     });
 }
@@ -725,7 +794,7 @@ hipError_t launch_tri64(const double* ax, const double* ay, const GridDesc& g, i
         using S = decltype(sh);
         const int tiles_x = (int)cdiv(g.nx - 1, S::TX);
         const int n_tiles = tiles_x * (int)cdiv(g.ny - 1, S::TY);
-        k_tri64<S><<<tri_blocks(g, shape), 256, 0, s>>>(ax, ay, g, tiles_x, n_tiles, nsys, sysrow, st, hit_keys,
+        k_tri64<S><<<tri_blocks(g, shape, false), 256, 0, s>>>(ax, ay, g, tiles_x, n_tiles, nsys, sysrow, st, hit_keys,
                                                         hit_cap, part);
         return hipGetLastError();
     });

@@ -89,11 +89,11 @@ static __device__ void prep_one(const PotPtrs& pot, const GridDesc& g, int p, in
     u[T32_B] = (float)(B * h2);
     u[T32_C] = (float)(C * h2);
     u[T32_A2] = (float)(a * a);
-    u[T32_S2A2] = sinf ? 0.0f : (float)(s * s - a * a);
+    u[T32_S2A2] = sinf ? 1e36f : (float)(s * s - a * a);  // uncut: s = 1e18 (see field32_pot)
     u[T32_RA] = (float)a;
-    u[T32_RS] = sinf ? 0.0f : (float)s;
+    u[T32_RS] = sinf ? 1e18f : (float)s;
     u[T32_K] = (float)(K / g.h);
-    u[T32_KIND] = (float)((a == 0.0 ? 2 : 0) + (sinf ? 1 : 0));
+    reinterpret_cast<int*>(u)[T32_KIND] = (a == 0.0 ? 2 : 0) + (sinf ? 1 : 0);
     for (int k = T32_KIND + 1; k < T32_STRIDE; k++) u[k] = 0.0f;
 
     const double w = K * a2 / sqrt(a1);
@@ -124,14 +124,18 @@ __device__ __forceinline__ int system_of(const int* __restrict__ sys_off, int ns
 
 // ---------------------------------------------------------------- field
 
-// FP32 contribution of one potential row `c` (node units) for NPL nodes of a
-// row.  KIND selects the radial profile at compile time: bit 0 = no cut
-// radius, bit 1 = no core.  f = (B_ - A_) / (A_ B_) with A_ = sqrt(a^2+R^2)+a,
-// B_ = sqrt(s^2+R^2)+s; without a cut f = 1/A_; for the singular uncut case
-// f = 1/R = rsq(R^2).  Offsets from the centre use the exact hi/lo split
-// (see the FP32 table); hardware sqrt/rcp/rsq (1 ulp) are accounted for in
-// the error bound.
-template <int KIND, int NPL>
+// FP32 contribution of one potential row `c` for NPL nodes of a row, one
+// branch-free formula for all four radial-profile kinds:
+//     f = (B_ - A_) / (A_ B_),  A_ = sqrt(a^2 + R^2) + a,  B_ = sqrt(s^2 + R^2) + s.
+// An uncut profile is stored with s = 1e18 (s^2 - a^2 = 1e36): B_ = 2e18 in
+// FP32, B_ - A_ rounds to B_, and f = 1/A_ to a few ulps.  a^2 + R^2 is
+// clamped below at 1e-30 arcsec^2, which only matters at the centre of a
+// singular profile: there the offsets are exactly zero, so the contribution
+// is exactly zero (the centre convention); elsewhere the clamp is inactive or
+// inside the FP32 error bound (its Jacobian term).  Offsets from the centre
+// use the exact hi/lo split (see the FP32 table); hardware sqrt/rcp (1 ulp)
+// are accounted for in the error bound.
+template <int NPL>
 __device__ __forceinline__ void field32_pot(const float* __restrict__ c, float fj, const float* fi, float* sx,
                                             float* sy)
 {
@@ -145,26 +149,57 @@ __device__ __forceinline__ void field32_pot(const float* __restrict__ c, float f
         const float nxv = (fi[k] - cxh) - cxl;
         const float m1 = fmaf(A, nxv, bny);
         const float m2 = fmaf(B, nxv, cny);
-        const float qa2 = fmaf(nxv, m1, fmaf(nyv, m2, a2));  // a^2 + R^2 (node units^2 * h^2)
-        float f;
-        if constexpr (KIND == 0) {          // cored, cut
-            const float qa = __builtin_amdgcn_sqrtf(qa2) + ra;
-            const float qs = __builtin_amdgcn_sqrtf(qa2 + s2a2) + rs;
-            f = (qs - qa) * __builtin_amdgcn_rcpf(qa * qs);
-        } else if constexpr (KIND == 1) {   // cored, uncut
-            f = __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(qa2) + ra);
-        } else if constexpr (KIND == 2) {   // singular, cut
-            const float R2 = fmaxf(qa2, 0.0f);
-            const float qa = __builtin_amdgcn_sqrtf(R2);
-            const float qs = __builtin_amdgcn_sqrtf(R2 + s2a2) + rs;
-            f = R2 > 0.0f ? (qs - qa) * __builtin_amdgcn_rcpf(qa * qs) : 0.0f;
-        } else {                            // singular isothermal ellipsoid
-            const float R2 = fmaxf(qa2, 0.0f);
-            f = R2 > 0.0f ? __builtin_amdgcn_rsqf(R2) : 0.0f;
-        }
-        const float kf = K * f;
+        const float qa2 = fmaxf(fmaf(nxv, m1, fmaf(nyv, m2, a2)), 1e-30f);  // a^2 + R^2
+        const float qa = __builtin_amdgcn_sqrtf(qa2) + ra;
+        const float qs = __builtin_amdgcn_sqrtf(qa2 + s2a2) + rs;
+        const float kf = K * ((qs - qa) * __builtin_amdgcn_rcpf(qa * qs));
         sx[k] = fmaf(kf, m1, sx[k]);
         sy[k] = fmaf(kf, m2, sy[k]);
+    }
+}
+
+// Deflection of NPL nodes of one row by every potential of the FP32 table.
+template <int NPL>
+__device__ __forceinline__ void field32_all(const float* __restrict__ tab, int np, float fj, const float* fi,
+                                            float* sx, float* sy)
+{
+    for (int p = 0; p < np; p++) field32_pot<NPL>(tab + (size_t)p * T32_STRIDE, fj, fi, sx, sy);
+}
+
+// Range partials of the triangle stage, written by the field kernel: for grid
+// row j and tile column c, the min/max of each deflection component over the
+// nodes [c*TX, c*TX + TX) of the row (the tile's halo column is read by the
+// consumer).  rr is [rows][tiles_x][4] floats (min ax, max ax, min ay, max ay).
+// The lanes of a column are an aligned group of TX/NPL lanes of one wave; all
+// 64 lanes must call this together.  Nodes at i >= nx do not count.
+template <int NPL>
+__device__ __forceinline__ void tile_partials(const float* sx, const float* sy, int i0, int j, int nx,
+                                              int tx_shift, int tiles_x, float* __restrict__ rr)
+{
+    float mnx = INFINITY, mxx = -INFINITY, mny = INFINITY, mxy = -INFINITY;
+#pragma unroll
+    for (int k = 0; k < NPL; k++) {
+        if (i0 + k < nx) {
+            mnx = fminf(mnx, sx[k]);
+            mxx = fmaxf(mxx, sx[k]);
+            mny = fminf(mny, sy[k]);
+            mxy = fmaxf(mxy, sy[k]);
+        }
+    }
+    const int seg = (1 << tx_shift) / NPL;  // lanes per tile column, a power of two <= 64
+    for (int m = 1; m < seg; m <<= 1) {
+        mnx = fminf(mnx, __shfl_xor(mnx, m, 64));
+        mxx = fmaxf(mxx, __shfl_xor(mxx, m, 64));
+        mny = fminf(mny, __shfl_xor(mny, m, 64));
+        mxy = fmaxf(mxy, __shfl_xor(mxy, m, 64));
+    }
+    const int col = i0 >> tx_shift;
+    if ((i0 & ((1 << tx_shift) - 1)) == 0 && i0 < nx && col < tiles_x) {
+        float* q = rr + ((size_t)j * tiles_x + col) * 4;
+        q[0] = mnx;
+        q[1] = mxx;
+        q[2] = mny;
+        q[3] = mxy;
     }
 }
 
@@ -360,6 +395,109 @@ __device__ __forceinline__ void stage_tile(const Tile& T, const V* vx, const V* 
         rng[1] = wred[w][1] > rng[1] ? wred[w][1] : rng[1];
         rng[2] = wred[w][2] < rng[2] ? wred[w][2] : rng[2];
         rng[3] = wred[w][3] > rng[3] ? wred[w][3] : rng[3];
+    }
+}
+
+// Deflection range of tile T (with its halo) for every lane of a wave, from
+// the field kernel's row partials plus the halo column read directly.
+template <class S>
+__device__ __forceinline__ void tile_range_wave(const float* __restrict__ ax, const float* __restrict__ ay,
+                                                const float* __restrict__ rr, const GridDesc& g, int tiles_x,
+                                                const Tile& T, float* rng)
+{
+    const int lane = lane_id();
+    const int col = T.ci0 / S::TX;
+    float mnx = INFINITY, mxx = -INFINITY, mny = INFINITY, mxy = -INFINITY;
+    if (lane <= T.ncy) {
+        const int j = T.cj0 + lane;
+        const float* q = rr + ((size_t)j * tiles_x + col) * 4;
+        mnx = q[0];
+        mxx = q[1];
+        mny = q[2];
+        mxy = q[3];
+        if (T.ncx == S::TX) {  // halo column: first node of the next column group
+            const size_t n = (size_t)j * g.nx + T.ci0 + S::TX;
+            const float vx = ax[n], vy = ay[n];
+            mnx = fminf(mnx, vx);
+            mxx = fmaxf(mxx, vx);
+            mny = fminf(mny, vy);
+            mxy = fmaxf(mxy, vy);
+        }
+    }
+    for (int m = 32; m >= 1; m >>= 1) {
+        mnx = fminf(mnx, __shfl_xor(mnx, m, 64));
+        mxx = fmaxf(mxx, __shfl_xor(mxx, m, 64));
+        mny = fminf(mny, __shfl_xor(mny, m, 64));
+        mxy = fmaxf(mxy, __shfl_xor(mxy, m, 64));
+    }
+    rng[0] = mnx;
+    rng[1] = mxx;
+    rng[2] = mny;
+    rng[3] = mxy;
+}
+
+// Loads tile T's nodes (with the halo) into a wave-private LDS tile.
+template <class S>
+__device__ __forceinline__ void stage_tile_wave(const float* __restrict__ ax, const float* __restrict__ ay,
+                                                const GridDesc& g, const Tile& T, float (*sx)[S::TNX],
+                                                float (*sy)[S::TNX])
+{
+    const int lane = lane_id();
+    constexpr int N = S::TNX * S::TNY;
+#pragma unroll
+    for (int k = 0; k < (N + 63) / 64; k++) {
+        const int q = lane + 64 * k;
+        const int li = q % S::TNX, lj = q / S::TNX;
+        if (q < N && li <= T.ncx && lj <= T.ncy) {
+            const size_t n = (size_t)(T.cj0 + lj) * g.nx + (T.ci0 + li);
+            sx[lj][li] = ax[n];
+            sy[lj][li] = ay[n];
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+}
+
+// All triangles of a wave-private FP32 tile against one system: the cells are
+// strided over the 64 lanes.  Same decisions as tri32_system.
+template <class S>
+__device__ __forceinline__ void tri32_wave_system(const GridDesc& g, const Tile& T, const float (*sx)[S::TNX],
+                                                  const float (*sy)[S::TNX], const float* fr,
+                                                  unsigned long long hit_base, unsigned long long flag_base,
+                                                  int mode, float tau, unsigned long long* hit_counter,
+                                                  unsigned long long* hit_keys, long long hit_cap,
+                                                  unsigned long long* flag_counter, unsigned long long* flag_keys,
+                                                  long long flag_cap, unsigned& nbbox)
+{
+    const float r = fr[0], E = fr[1], bxh = fr[2], bxl = fr[3], byh = fr[4], byl = fr[5];
+    const float h32 = (float)g.h;
+    const int lane = lane_id();
+#pragma unroll 2
+    for (int it = 0; it < S::TX * S::TY / 64; it++) {
+        const int cidx = lane + 64 * it;
+        const int li = cidx % S::TX, lj = cidx / S::TX;
+        const bool valid = li < T.ncx && lj < T.ncy;
+        const int gi = T.ci0 + li, gj = T.cj0 + lj;
+        int res0 = kMiss, res1 = kMiss;
+        if (valid) {
+            const float ex0 = (((float)gi - bxh) - bxl) * h32;
+            const float ex1 = (((float)(gi + 1) - bxh) - bxl) * h32;
+            const float ey0 = (((float)gj - byh) - byl) * h32;
+            const float ey1 = (((float)(gj + 1) - byh) - byl) * h32;
+            const float d00x = fmaf(-r, sx[lj][li], ex0), d00y = fmaf(-r, sy[lj][li], ey0);
+            const float d10x = fmaf(-r, sx[lj][li + 1], ex1), d10y = fmaf(-r, sy[lj][li + 1], ey0);
+            const float d01x = fmaf(-r, sx[lj + 1][li], ex0), d01y = fmaf(-r, sy[lj + 1][li], ey1);
+            const float d11x = fmaf(-r, sx[lj + 1][li + 1], ex1), d11y = fmaf(-r, sy[lj + 1][li + 1], ey1);
+            const float tx[3] = {d00x, d10x, d01x}, ty[3] = {d00y, d10y, d01y};
+            const float ux[3] = {d11x, d01x, d10x}, uy[3] = {d11y, d01y, d10y};
+            res0 = decide32(tx, ty, E, mode, tau, nbbox);
+            res1 = decide32(ux, uy, E, mode, tau, nbbox);
+        }
+        const unsigned tid0 = (unsigned)(2 * (gj * (g.nx - 1) + gi));
+        wave_append(res0 == kHit, hit_base | tid0, hit_counter, hit_keys, hit_cap);
+        wave_append(res1 == kHit, hit_base | (tid0 + 1), hit_counter, hit_keys, hit_cap);
+        wave_append(res0 == kFlag, flag_base | tid0, flag_counter, flag_keys, flag_cap);
+        wave_append(res1 == kFlag, flag_base | (tid0 + 1), flag_counter, flag_keys, flag_cap);
     }
 }
 

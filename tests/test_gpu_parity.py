@@ -165,6 +165,23 @@ def test_chi2_parity(lens, config, n, prec):
     compare_chi2(got, want, 1e-9 if prec == "fp64" else 1e-5, 1e-9 if prec == "fp64" else 1e-6)
 
 
+_RAGGED = {}
+
+
+@pytest.mark.parametrize("tile,npl", [(1, 1), (2, 2), (3, 4), (4, 8), (2, 8), (3, 1)])
+def test_chi2_tile_shapes_and_nodes_per_thread(lens, tile, npl):
+    """Every triangle-tile shape (32x8, 64x16, 64x8, 32x16) and field width (1..8 nodes per
+    thread) on a ragged grid: 333 x 338 nodes, so neither axis is a multiple of a tile."""
+    prm, grid, obs = load_inputs(2)
+    grid = S.Grid(grid.x0, grid.y0, grid.h * (grid.nx - 1) / 332, 333, 338)
+    if "r" not in _RAGGED:
+        _RAGGED["r"] = oracle.image_chi2(prm, grid, obs)
+    want = _RAGGED["r"]
+    for prec in ("mixed", "fp64"):
+        got = run_chi2(lens, prm, grid, obs, prec, tile=tile, field_npl=npl)
+        compare_chi2(got, want, 1e-9 if prec == "fp64" else 1e-5, 1e-9 if prec == "fp64" else 1e-6)
+
+
 def test_chi2_identity_lens_exact_images(lens):
     """No potentials: each system has one predicted image at its barycentre."""
     g = np.random.default_rng(11)
