@@ -6,6 +6,7 @@
 #include "lens_internal.hpp"
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <stdlib.h>
 #include <string.h>
@@ -16,7 +17,7 @@ using namespace lens;
 namespace {
 
 enum Buf { B_TAB64, B_TAB32, B_BTERM, B_FIELD, B_BX, B_BY, B_SYS, B_STATE, B_HITS, B_FLAGS, B_POS, B_CONTRIB,
-           B_PART, B_BCOUNT, B_VJP, B_SRC, B_SRCST, B_RR, B_NBUF };
+           B_PART, B_BCOUNT, B_VJP, B_SRC, B_SRCST, B_RR, B_PAIRS, B_NBUF };
 
 // Device work plan of one chunk of a batch (see lens_image_chi2_batched).
 struct PlanChunk {
@@ -364,7 +365,8 @@ int lens_deflect(lens_ctx* ctx, const lens_potentials* pot, const lens_grid* gri
     if ((rc = timing_begin(ctx, &kev, &ev, &slot))) return rc;
     hipError_t e;
     if (prec == LENS_FP64)
-        e = launch_field64((const double*)ctx->buf[B_TAB64], pot->n, g, (double*)ax, (double*)ay, st, ev, stream);
+        e = launch_field64((const double*)ctx->buf[B_TAB64], pot->n, g, (double*)ax, (double*)ay, st, nullptr, 5, 1,
+                           ev, stream);
     else
         e = launch_field32((const float*)ctx->buf[B_TAB32], pot->n, g, (float*)ax, (float*)ay, st, field_npl(g),
                            nullptr, 5, 1, ev, stream);
@@ -419,24 +421,33 @@ int lens_image_chi2(lens_ctx* ctx, const lens_potentials* pot, const lens_grid* 
     const bool mixed = opts->prec == LENS_MIXED;
     const size_t nn = (size_t)g.nx * g.ny;
     int rc;
-    if ((rc = ensure(ctx, B_FIELD, nn * 2 * (mixed ? 4 : 8))) || (rc = ensure(ctx, B_BX, (size_t)o.n_img * 8)) ||
-        (rc = ensure(ctx, B_BY, (size_t)o.n_img * 8)) || (rc = ensure(ctx, B_HITS, (size_t)kHitScratch * 2 * 8)) ||
-        (rc = ensure(ctx, B_FLAGS, (size_t)(mixed ? kFlagScratch : 1) * 8)) ||
-        (rc = ensure(ctx, B_POS, (size_t)kHitScratch * 4 * 8)) || (rc = ensure(ctx, B_CONTRIB, (size_t)o.n_img * 8)))
-        return rc;
     const int shape = opts->tile ? opts->tile : 1;
     const int npl = opts->field_npl ? opts->field_npl : field_npl(g);
-    const int n_parts = tri_blocks(g, shape, mixed);
-    int tile_x, tile_y;
+    int tile_x, tile_y, tiles_x;
     tile_dims(shape, tile_x, tile_y);
     const int tx_shift = tile_x == 64 ? 6 : 5;
-    const int tiles_x = (g.nx - 2) / tile_x + 1;
-    if ((rc = ensure(ctx, B_PART, (size_t)n_parts * 2 * 4)) ||
+    const long long n_tiles = tri_tiles(g, shape, &tiles_x);
+    int n_cull, tpw;
+    cull_shape(g, shape, &n_cull, &tpw);
+    const int n_parts = n_cull + kPairBlocks;
+    // each culling workgroup owns room for every pair of its tiles
+    const long long region = 4ll * tpw * o.n_sys;
+    if (region * n_cull > (1ll << 28)) return LENS_ERR_CAPACITY;  // 2 GiB of pair keys
+    (void)n_tiles;
+    const size_t vbytes = mixed ? 4 : 8;
+    if ((rc = ensure(ctx, B_FIELD, nn * 2 * vbytes)) || (rc = ensure(ctx, B_BX, (size_t)o.n_img * 8)) ||
+        (rc = ensure(ctx, B_BY, (size_t)o.n_img * 8)) || (rc = ensure(ctx, B_HITS, (size_t)kHitScratch * 2 * 8)) ||
+        (rc = ensure(ctx, B_POS, (size_t)kHitScratch * 4 * 8)) || (rc = ensure(ctx, B_CONTRIB, (size_t)o.n_img * 8)) ||
+        (rc = ensure(ctx, B_FLAGS, (size_t)(mixed ? kFlagScratch : 1) * 8)) ||
+        (rc = ensure(ctx, B_PART, (size_t)n_parts * 2 * 4)) ||
         (rc = ensure(ctx, B_SYS, (size_t)o.n_sys * SYS_STRIDE * 8)) ||
-        (rc = ensure(ctx, B_RR, mixed ? (size_t)g.ny * tiles_x * 16 : 16)))
+        (rc = ensure(ctx, B_RR, (size_t)g.ny * tiles_x * 4 * vbytes)) ||
+        (rc = ensure(ctx, B_PAIRS, (size_t)region * n_cull * 8 + (size_t)n_cull * 4)))
         return rc;
-    float* rr = (float*)ctx->buf[B_RR];
+    void* rr = ctx->buf[B_RR];
     unsigned* part = (unsigned*)ctx->buf[B_PART];
+    unsigned long long* pairs = (unsigned long long*)ctx->buf[B_PAIRS];
+    unsigned* counts = (unsigned*)(pairs + (size_t)region * n_cull);
     if ((rc = head(ctx, pot, g, o, (double*)ctx->buf[B_BX], (double*)ctx->buf[B_BY], stream))) return rc;
 
     const double* tab64 = (const double*)ctx->buf[B_TAB64];
@@ -444,10 +455,8 @@ int lens_image_chi2(lens_ctx* ctx, const lens_potentials* pot, const lens_grid* 
     EvalState* st = (EvalState*)ctx->buf[B_STATE];
     unsigned long long* hits = (unsigned long long*)ctx->buf[B_HITS];
     unsigned long long* fb_hits = hits + kHitScratch;
-    unsigned long long* flags = (unsigned long long*)ctx->buf[B_FLAGS];
     double* pos = (double*)ctx->buf[B_POS];
     double* fb_pos = pos + 2 * kHitScratch;
-    const long long flag_cap = mixed ? kFlagScratch : 0;
 
     int slot;
     KernelEvents kev;
@@ -455,20 +464,26 @@ int lens_image_chi2(lens_ctx* ctx, const lens_potentials* pot, const lens_grid* 
     if ((rc = timing_begin(ctx, &kev, &ev, &slot))) return rc;
     hipError_t e;
     void* field = ctx->buf[B_FIELD];
+    const void* fx = field;
+    const void* fy = (const char*)field + nn * vbytes;
     if (mixed)
         e = launch_field32((const float*)ctx->buf[B_TAB32], np, g, (float*)field, (float*)field + nn, nullptr, npl,
-                           rr, tx_shift, tiles_x, ev, stream);
+                           (float*)rr, tx_shift, tiles_x, ev, stream);
     else
-        e = launch_field64(tab64, np, g, (double*)field, (double*)field + nn, nullptr, ev, stream);
+        e = launch_field64(tab64, np, g, (double*)field, (double*)field + nn, nullptr, (double*)rr, tx_shift,
+                           tiles_x, ev, stream);
     if (e != hipSuccess) return LENS_ERR_DEVICE;
     timing_end(ctx, slot);
 
-    if (mixed)
-        e = launch_tri32((const float*)field, (const float*)field + nn, rr, g, o.n_sys, sysrow, st, opts->fb_mode,
-                         (float)(opts->fb_tau * g.h * g.h), hits, kHitScratch, flags, flag_cap, part, shape, stream);
-    else
-        e = launch_tri64((const double*)field, (const double*)field + nn, g, o.n_sys, sysrow, st, hits, kHitScratch,
-                         part, shape, stream);
+    unsigned long long* flags = (unsigned long long*)ctx->buf[B_FLAGS];
+    const long long flag_cap = mixed ? kFlagScratch : 0;
+    e = launch_cull(mixed, fx, fy, rr, g, o.n_sys, sysrow, pairs, region, counts, part, shape, stream);
+    if (e == hipSuccess)
+        e = launch_pairs(mixed, fx, fy, g, sysrow, st, opts->fb_mode, (float)(opts->fb_tau * g.h * g.h), pairs,
+                         region, counts, n_cull, hits, kHitScratch, flags, flag_cap, part, n_cull, shape, stream);
+    if (e == hipSuccess)
+        e = launch_fbpos(tab64, np, g, sysrow, st, hits, kHitScratch, flags, flag_cap, fb_hits, kHitScratch, pos,
+                         fb_pos, stream);
     if (e != hipSuccess) return LENS_ERR_DEVICE;
     TailLaunch tl;
     tl.obs = o;
@@ -488,9 +503,7 @@ int lens_image_chi2(lens_ctx* ctx, const lens_potentials* pot, const lens_grid* 
     tl.n_tests = 2ll * (g.nx - 1) * (g.ny - 1) * o.n_sys;
     tl.part = part;
     tl.n_parts = n_parts;
-    e = launch_fbpos(tab64, np, g, sysrow, st, hits, kHitScratch, flags, flag_cap, fb_hits, kHitScratch, pos, fb_pos,
-                     stream);
-    if (e == hipSuccess) e = launch_tail(tl, st, fb_hits, pos, fb_pos, stream);
+    e = launch_tail(tl, st, fb_hits, pos, fb_pos, stream);
     return e == hipSuccess ? LENS_OK : LENS_ERR_DEVICE;
 }
 

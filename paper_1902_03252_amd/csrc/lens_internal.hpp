@@ -62,7 +62,6 @@ struct BatchState {
     int* status;                  // [n]
 };
 
-constexpr int kTriBlocks = 2048;         // persistent workgroups of the triangle stage
 constexpr long long kHitScratch = 8192;   // largest hit list sorted in LDS (2^13)
 constexpr long long kFlagScratch = 1 << 20;
 constexpr int kMaxSystems = 1 << 19;      // systems fit the packed sort key
@@ -74,17 +73,27 @@ hipError_t launch_field32(const float* tab32, int np, const GridDesc& g, float* 
                           const EvalState* st, int npl, float* rr, int tx_shift, int tiles_x,
                           const KernelEvents* ev, hipStream_t s);
 hipError_t launch_field64(const double* tab64, int np, const GridDesc& g, double* ax, double* ay,
-                          const EvalState* st, const KernelEvents* ev, hipStream_t s);
-int tri_blocks(const GridDesc& g, int shape, bool fp32);
+                          const EvalState* st, double* rr, int tx_shift, int tiles_x, const KernelEvents* ev,
+                          hipStream_t s);
+constexpr int kPairBlocks = 1024;          // persistent workgroups of the pair kernel
+constexpr int kMaxCull = 1024;             // culling workgroups (4 tiles per round)
 void tile_dims(int shape, int& tx, int& ty);
-hipError_t launch_tri32(const float* ax, const float* ay, const float* rr, const GridDesc& g, int nsys, const double* sysrow,
-                        EvalState* st, int mode, float tau, unsigned long long* hit_keys, long long hit_cap,
-                        unsigned long long* flag_keys, long long flag_cap, unsigned* part, int shape, hipStream_t s);
-hipError_t launch_tri64(const double* ax, const double* ay, const GridDesc& g, int nsys, const double* sysrow,
-                        EvalState* st, unsigned long long* hit_keys, long long hit_cap, unsigned* part, int shape,
+long long tri_tiles(const GridDesc& g, int shape, int* tiles_x);
+void cull_shape(const GridDesc& g, int shape, int* n_cull, int* tpw);
+hipError_t launch_cull(bool fp32, const void* ax, const void* ay, const void* rr, const GridDesc& g, int nsys,
+                       const double* sysrow, unsigned long long* pairs, long long region, unsigned* counts,
+                       unsigned* part, int shape, hipStream_t s);
+hipError_t launch_pairs(bool fp32, const void* ax, const void* ay, const GridDesc& g, const double* sysrow,
+                        EvalState* st, int mode, float tau, const unsigned long long* pairs, long long region,
+                        const unsigned* counts, int n_cull, unsigned long long* hit_keys, long long hit_cap,
+                        unsigned long long* flag_keys, long long flag_cap, unsigned* part, int part_base, int shape,
                         hipStream_t s);
+hipError_t launch_fbpos(const double* tab64, int np, const GridDesc& g, const double* sysrow, EvalState* st,
+                        const unsigned long long* hit_keys, long long hit_cap, const unsigned long long* flag_keys,
+                        long long flag_cap, unsigned long long* fb_keys, long long fb_cap, double* pos,
+                        double* fb_pos, hipStream_t s);
 
-// Outputs and lists of the tail of a chi^2 evaluation.
+// Arguments of the tail kernel.
 struct TailLaunch {
     ObsPtrs obs;
     long long hit_cap, flag_cap, fb_cap;
@@ -103,12 +112,9 @@ struct TailLaunch {
     int n_parts;
 };
 
-hipError_t launch_fbpos(const double* tab64, int np, const GridDesc& g, const double* sysrow, EvalState* st,
-                        const unsigned long long* hit_keys, long long hit_cap, const unsigned long long* flag_keys,
-                        long long flag_cap, unsigned long long* fb_keys, long long fb_cap, double* pos,
-                        double* fb_pos, hipStream_t s);
 hipError_t launch_tail(const TailLaunch& tl, EvalState* st, const unsigned long long* fb_keys, const double* pos,
                        const double* fb_pos, hipStream_t s);
+
 // Device state of the source-plane chi^2 (zeroed once at allocation).
 struct SrcState {
     unsigned ticket;  // "last workgroup" ticket, zero between launches

@@ -6,11 +6,13 @@
 //            forms the barycentres, the FP32 error bound and one row per
 //            system, and resets the counters
 //   k_field  deflection at every grid node (FP32 or FP64)          <- the time
-//   k_tri    persistent workgroups over tiles of cells: cull (tile, system)
-//            pairs, triangle containment, ballot/prefix-sum compaction of hits
-//            and of undecided FP32 tests
-//   k_fbpos  one wave per item: FP64 re-test of each undecided test (mixed
-//            path) and the FP64 image position of every hit
+//   k_cull   one wave per tile of cells: the tile's deflection range (from the
+//            field kernel's row partials) bounds its source-plane vertices;
+//            every system whose barycentre the bound admits gives a (tile,
+//            system) pair
+//   k_pairs  persistent waves over 64-cell units of the pairs: triangle
+//            containment (FP32 certified signs or FP64 exact), each hit and
+//            each undecided test resolved at once in FP64 with its position
 //   k_tail   one workgroup: sort of the hits, matching of observed to
 //            predicted images, FP64 chi^2 in a fixed order
 #include "lens_path.hpp"
@@ -156,7 +158,7 @@ __global__ __launch_bounds__(256) void k_field32(const float* __restrict__ tab32
         sy[k] = 0.0f;
     }
     field32_all<NPL>(tab32, np, fj, fi, sx, sy);
-    if (rr) tile_partials<NPL>(sx, sy, i0, j, nx, tx_shift, tiles_x, rr);
+    if (rr) tile_partials<float, NPL>(sx, sy, i0, j, nx, tx_shift, tiles_x, rr);
     const bool bad = st != nullptr && st->status != kStatusOk;
     const size_t row = (size_t)j * nx;
 #pragma unroll
@@ -168,17 +170,21 @@ __global__ __launch_bounds__(256) void k_field32(const float* __restrict__ tab32
     }
 }
 
-// FP64 field: one node per thread, the same matrix form in arcsec.
+// FP64 field: one node per thread, the same matrix form in arcsec; with rr
+// set, also the triangle stage's row partials (as k_field32).
 __global__ __launch_bounds__(256) void k_field64(const double* __restrict__ tab64, int np, GridDesc g,
                                                  double* __restrict__ ax, double* __restrict__ ay,
-                                                 const EvalState* __restrict__ st)
+                                                 const EvalState* __restrict__ st, double* __restrict__ rr,
+                                                 int tx_shift, int tiles_x)
 {
     const int j = blockIdx.y;
     const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= g.nx) return;
+    if ((int)(blockIdx.x * 256) >= g.nx) return;
     const double t1 = g.x0 + i * g.h, t2 = g.y0 + j * g.h;
     double s1 = 0.0, s2 = 0.0;
     for (int p = 0; p < np; p++) add_alpha64(tab64 + (size_t)p * T64_STRIDE, t1, t2, s1, s2);
+    if (rr) tile_partials<double, 1>(&s1, &s2, i, j, g.nx, tx_shift, tiles_x, rr);
+    if (i >= g.nx) return;
     const bool bad = st != nullptr && st->status != kStatusOk;
     const size_t n = (size_t)j * g.nx + i;
     ax[n] = bad ? __builtin_nan("") : s1;
@@ -187,194 +193,206 @@ __global__ __launch_bounds__(256) void k_field64(const double* __restrict__ tab6
 
 // ============================================================== triangle stage
 
-// Mixed path.  Persistent workgroups (4 waves) walk the tiles of S::TX x S::TY
-// cells; the loads of the next tile are in flight while the current one is
-// processed.  A tile's FP32 deflections (with a one-node halo) are staged in
-// LDS; a system whose barycentre lies outside the tile's source-plane box is
-// skipped for the whole tile.  Systems are tested 64 at a time, one per lane,
-// and the survivors enumerated from the ballot mask.
-template <class S>
-__global__ __launch_bounds__(256) void k_tri32(const float* __restrict__ ax, const float* __restrict__ ay,
-                                               GridDesc g, int tiles_x, int n_tiles, int nsys,
-                                               const double* __restrict__ sysrow, EvalState* __restrict__ st,
-                                               int mode, float tau, unsigned long long* __restrict__ hit_keys,
-                                               long long hit_cap, unsigned long long* __restrict__ flag_keys,
-                                               long long flag_cap, unsigned* __restrict__ part)
+// Culling, one wave per tile of S::TX x S::TY cells (workgroups of 4 waves,
+// `tpw` rounds of tiles): the tile's deflection range (the field kernel's row
+// partials plus the halo column) bounds every source-plane vertex of the tile
+// by the box [theta_min - r alpha_max, theta_max - r alpha_min], widened by
+// the FP32 bound E_B (mixed path) or 1e-9" (FP64 path); every system whose
+// barycentre lies in the box (systems over the lanes) gives a (tile, system)
+// pair.  The workgroup compacts its pairs into its own region through LDS and
+// writes its count to counts[blockIdx.x]: no atomic is shared between
+// workgroups.
+template <class S, typename V>
+__global__ __launch_bounds__(256) void k_cull(const V* __restrict__ ax, const V* __restrict__ ay,
+                                              const V* __restrict__ rr, GridDesc g, int tiles_x, int n_tiles,
+                                              int tpw, int nsys, const double* __restrict__ sysrow,
+                                              unsigned long long* __restrict__ pairs, long long region,
+                                              unsigned* __restrict__ counts, unsigned* __restrict__ part)
 {
-    __shared__ float sx[S::TNY][S::TNX], sy[S::TNY][S::TNX];
-    __shared__ float wred[4][4];
-    __shared__ SysChunk chunk;
-    __shared__ unsigned sbb[4];
-    const bool one_chunk = nsys <= SYS_CHUNK;
-    if (one_chunk) load_chunk(chunk, sysrow, nsys, 0);
-    const int lane = lane_id();
-    unsigned nbbox = 0, ntile = 0;
-    float vx[S::LOADS], vy[S::LOADS];
-    int tile = blockIdx.x;
-    Tile T = tile_of<S>(g, tiles_x, tile);
-    if (tile < n_tiles) load_tile<S>(ax, ay, g, T, vx, vy);
-    for (; tile < n_tiles; tile += gridDim.x) {
-        float rngf[4];
-        stage_tile<S>(T, vx, vy, sx, sy, wred, rngf);
-        const Tile cur = T;
-        const int next = tile + gridDim.x;
-        if (next < n_tiles) {
-            T = tile_of<S>(g, tiles_x, next);
-            load_tile<S>(ax, ay, g, T, vx, vy);
+    __shared__ unsigned swc[4];
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    unsigned long long* out = pairs + (size_t)blockIdx.x * region;
+    unsigned cnt = 0;  // pairs of the workgroup so far (uniform)
+    for (int k = 0; k < tpw; k++) {
+        const int tile = (blockIdx.x * tpw + k) * 4 + wave;
+        const bool act = tile < n_tiles;
+        Tile T = {0, 0, 0, 0};
+        double rng[4] = {0.0, 0.0, 0.0, 0.0};
+        if (act) {
+            T = tile_of<S>(g, tiles_x, tile);
+            tile_range_wave<S, V>(ax, ay, rr, g, tiles_x, T, rng);
         }
-        const double rng[4] = {rngf[0], rngf[1], rngf[2], rngf[3]};
-        for (int cbase = 0; cbase < nsys; cbase += SYS_CHUNK) {
-            if (!one_chunk) {
-                __syncthreads();
-                load_chunk(chunk, sysrow, nsys, cbase);
-                __syncthreads();
+        for (int sb = 0; sb < nsys; sb += 64) {
+            const int s = sb + lane;
+            bool pass = false;
+            if (act && s < nsys) {
+                const double* row = sysrow + (size_t)s * SYS_STRIDE;
+                const double eb = sizeof(V) == 4 ? row[SYS_EB] : 1e-9;
+                pass = tile_box_contains(g, T, rng, row[SYS_R], eb, row[SYS_BX], row[SYS_BY]);
             }
-            const int nc = min(SYS_CHUNK, nsys - cbase);
-            for (int sbase = 0; sbase < nc; sbase += 64) {
-                const int sl = sbase + lane;
-                const bool pass = sl < nc && tile_box_contains(g, cur, rng, chunk.r[sl], chunk.eb[sl],
-                                                               chunk.bx[sl], chunk.by[sl]);
-                unsigned long long m = __ballot(pass);
-                ntile += __popcll(m);
-                while (m) {
-                    const int s = sbase + __ffsll((long long)m) - 1;
-                    m &= m - 1;
-                    const unsigned long long base = (unsigned long long)(cbase + s) << 32;
-                    tri32_system<S>(g, cur, sx, sy, chunk.f[s], base, base, mode, tau, &st->n_hits, hit_keys,
-                                    hit_cap, &st->n_flags, flag_keys, flag_cap, nbbox);
-                }
-            }
-        }
-        __syncthreads();  // the LDS tile is overwritten by the next iteration
-    }
-    write_part(part, blockIdx.x, ntile, nbbox, sbb);
-}
-
-// Mixed path, one wave per tile: the tile's deflection range comes from the
-// field kernel's row partials (plus the halo column), so a tile that no
-// system's barycentre can reach costs a few small loads; only tiles with a
-// surviving system are staged (in a wave-private LDS tile) and tested.
-template <class S>
-__global__ __launch_bounds__(256) void k_tri32w(const float* __restrict__ ax, const float* __restrict__ ay,
-                                                const float* __restrict__ rr, GridDesc g, int tiles_x, int n_tiles,
-                                                int nsys, const double* __restrict__ sysrow,
-                                                EvalState* __restrict__ st, int mode, float tau,
-                                                unsigned long long* __restrict__ hit_keys, long long hit_cap,
-                                                unsigned long long* __restrict__ flag_keys, long long flag_cap,
-                                                unsigned* __restrict__ part)
-{
-    __shared__ float sx[4][S::TNY][S::TNX], sy[4][S::TNY][S::TNX];
-    __shared__ SysChunk chunk;
-    __shared__ unsigned sbb[4];
-    const int wave = threadIdx.x >> 6, lane = lane_id();
-    const int tile = blockIdx.x * 4 + wave;
-    const bool one_chunk = nsys <= SYS_CHUNK;
-    if (one_chunk) {
-        load_chunk(chunk, sysrow, nsys, 0);
-        __syncthreads();
-    }
-    unsigned nbbox = 0, ntile = 0;
-    const bool active = tile < n_tiles;
-    Tile T = {0, 0, 0, 0};
-    double rng[4] = {0.0, 0.0, 0.0, 0.0};
-    if (active) {
-        T = tile_of<S>(g, tiles_x, tile);
-        float r4[4];
-        tile_range_wave<S>(ax, ay, rr, g, tiles_x, T, r4);
-        rng[0] = r4[0];
-        rng[1] = r4[1];
-        rng[2] = r4[2];
-        rng[3] = r4[3];
-    }
-    bool staged = false;
-    for (int cbase = 0; cbase < nsys; cbase += SYS_CHUNK) {
-        if (!one_chunk) {
+            const unsigned long long m = __ballot(pass);
+            if (lane == 0) swc[wave] = (unsigned)__popcll(m);
             __syncthreads();
-            load_chunk(chunk, sysrow, nsys, cbase);
+            unsigned before = 0, total = 0;
+            for (int w = 0; w < 4; w++) {
+                before += w < wave ? swc[w] : 0u;
+                total += swc[w];
+            }
+            const int off =
+                __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+            if (pass) out[cnt + before + off] = ((unsigned long long)(unsigned)tile << 32) | (unsigned)s;
+            cnt += total;
             __syncthreads();
         }
-        if (!active) continue;
-        const int nc = min(SYS_CHUNK, nsys - cbase);
-        for (int sbase = 0; sbase < nc; sbase += 64) {
-            const int sl = sbase + lane;
-            const bool pass = sl < nc && tile_box_contains(g, T, rng, chunk.r[sl], chunk.eb[sl], chunk.bx[sl],
-                                                           chunk.by[sl]);
-            unsigned long long m = __ballot(pass);
-            ntile += __popcll(m);
-            if (m != 0 && !staged) {
-                stage_tile_wave<S>(ax, ay, g, T, sx[wave], sy[wave]);
-                staged = true;
-            }
-            while (m) {
-                const int s = sbase + __ffsll((long long)m) - 1;
-                m &= m - 1;
-                const unsigned long long base = (unsigned long long)(cbase + s) << 32;
-                tri32_wave_system<S>(g, T, sx[wave], sy[wave], chunk.f[s], base, base, mode, tau, &st->n_hits,
-                                     hit_keys, hit_cap, &st->n_flags, flag_keys, flag_cap, nbbox);
-            }
-        }
     }
-    write_part(part, blockIdx.x, ntile, nbbox, sbb);
+    if (threadIdx.x == 0) {
+        counts[blockIdx.x] = cnt;
+        part[2 * blockIdx.x + 0] = cnt;
+        part[2 * blockIdx.x + 1] = 0;
+    }
 }
 
-// FP64 path: same walk, FP64 deflections in LDS, every surviving triangle
-// decided exactly.
-template <class S>
-__global__ __launch_bounds__(256) void k_tri64(const double* __restrict__ ax, const double* __restrict__ ay,
-                                               GridDesc g, int tiles_x, int n_tiles, int nsys,
-                                               const double* __restrict__ sysrow, EvalState* __restrict__ st,
+// Containment of the (tile, system) pairs, persistent waves, one pair at a
+// time: the pair's cells are strided over the lanes, up to four cells per lane
+// per step, with every vertex load of a step issued before any decision.
+// Mixed path: FP32 vertex offsets and the certified sign test; FP64 path:
+// exact containment on the FP64 field's vertices.  Certain hits and undecided
+// tests are appended (system << 32 | triangle id) with one atomic per wave.
+template <class S, typename V>
+__global__ __launch_bounds__(256) void k_pairs(const V* __restrict__ ax, const V* __restrict__ ay, GridDesc g,
+                                               int tiles_x, const double* __restrict__ sysrow,
+                                               EvalState* __restrict__ st, int mode, float tau,
+                                               const unsigned long long* __restrict__ pairs, long long region,
+                                               const unsigned* __restrict__ counts, int n_cull,
                                                unsigned long long* __restrict__ hit_keys, long long hit_cap,
-                                               unsigned* __restrict__ part)
+                                               unsigned long long* __restrict__ flag_keys, long long flag_cap,
+                                               unsigned* __restrict__ part, int part_base)
 {
-    __shared__ double sx[S::TNY][S::TNX], sy[S::TNY][S::TNX];
-    __shared__ double wred[4][4];
-    __shared__ SysChunk chunk;
-    __shared__ unsigned sbb[4];
-    const bool one_chunk = nsys <= SYS_CHUNK;
-    if (one_chunk) load_chunk(chunk, sysrow, nsys, 0);
-    const int lane = lane_id();
-    unsigned nbbox = 0, ntile = 0;
-    double vx[S::LOADS], vy[S::LOADS];
-    int tile = blockIdx.x;
-    Tile T = tile_of<S>(g, tiles_x, tile);
-    if (tile < n_tiles) load_tile<S>(ax, ay, g, T, vx, vy);
-    for (; tile < n_tiles; tile += gridDim.x) {
-        double rng[4];
-        stage_tile<S>(T, vx, vy, sx, sy, wred, rng);
-        const Tile cur = T;
-        const int next = tile + gridDim.x;
-        if (next < n_tiles) {
-            T = tile_of<S>(g, tiles_x, next);
-            load_tile<S>(ax, ay, g, T, vx, vy);
-        }
-        for (int cbase = 0; cbase < nsys; cbase += SYS_CHUNK) {
-            if (!one_chunk) {
-                __syncthreads();
-                load_chunk(chunk, sysrow, nsys, cbase);
-                __syncthreads();
-            }
-            const int nc = min(SYS_CHUNK, nsys - cbase);
-            for (int sbase = 0; sbase < nc; sbase += 64) {
-                const int sl = sbase + lane;
-                // 1e-9 arcsec covers the FP64 rounding of the box
-                const bool pass = sl < nc && tile_box_contains(g, cur, rng, chunk.r[sl], 1e-9, chunk.bx[sl],
-                                                               chunk.by[sl]);
-                unsigned long long m = __ballot(pass);
-                ntile += __popcll(m);
-                while (m) {
-                    const int s = sbase + __ffsll((long long)m) - 1;
-                    m &= m - 1;
-                    tri64_system<S>(g, cur, sx, sy, chunk.r[s], chunk.bx[s], chunk.by[s],
-                                    (unsigned long long)(cbase + s) << 32, &st->n_hits, hit_keys, hit_cap, nbbox);
-                }
-            }
-        }
-        __syncthreads();
+    __shared__ unsigned sp[4][2];
+    constexpr int Q = S::TX * S::TY / 64;  // cells per lane for one pair
+    constexpr int QB = Q < 4 ? Q : 4;      // cells per lane per step
+    const int lane = lane_id(), t = threadIdx.x;
+    // per-wave prefix of the culling counts: lane l holds counts [l*per, (l+1)*per)
+    // in registers (per <= kMaxCull / 64) and their sum
+    constexpr int PER = kMaxCull / 64;
+    const int per = (n_cull + 63) / 64;
+    unsigned cl[PER];
+    unsigned lsum = 0;
+#pragma unroll
+    for (int j = 0; j < PER; j++) {
+        const int c = lane * per + j;
+        cl[j] = (j < per && c < n_cull) ? counts[c] : 0u;
+        lsum += cl[j];
     }
-    write_part(part, blockIdx.x, ntile, nbbox, sbb);
+    unsigned incl = lsum;
+    for (int d = 1; d < 64; d <<= 1) {
+        const unsigned v = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += v;
+    }
+    const unsigned excl = incl - lsum;
+    const unsigned total = (unsigned)__builtin_amdgcn_readlane((int)incl, 63);
+    const long long nw = (long long)gridDim.x * 4;
+    const long long w0 = (long long)blockIdx.x * 4 + (t >> 6);
+    const long long n_pairs = st->status == kStatusOk ? (long long)total : 0;
+    unsigned nbbox = 0;
+    for (long long u = w0; u < n_pairs; u += nw) {
+        const unsigned pidx = (unsigned)u;
+        // the lane whose range holds pidx, then the culling workgroup inside it
+        const int L = __ffsll((long long)__ballot(incl > pidx)) - 1;
+        int cw = L * per;
+        unsigned off = pidx - (unsigned)__builtin_amdgcn_readlane((int)excl, L);
+#pragma unroll
+        for (int j = 0; j < PER; j++) {  // walk lane L's counts (registers, no memory access)
+            const unsigned cj = (unsigned)__builtin_amdgcn_readlane((int)cl[j], L);
+            if (off < cj) break;
+            off -= cj;
+            cw++;
+        }
+        const unsigned long long pk = pairs[(size_t)cw * region + off];
+        const int tile = (int)(pk >> 32), sys = (int)(pk & 0xffffffffu);
+        const Tile T = tile_of<S>(g, tiles_x, tile);
+        const double* row = sysrow + (size_t)sys * SYS_STRIDE;
+        for (int q0 = 0; q0 < Q; q0 += QB) {
+            V va[QB][8];
+#pragma unroll
+            for (int b = 0; b < QB; b++) {
+                const int c = lane + 64 * (q0 + b), li = c % S::TX, lj = c / S::TX;
+                const bool valid = li < T.ncx && lj < T.ncy;
+                const size_t n00 = valid ? (size_t)(T.cj0 + lj) * g.nx + (T.ci0 + li) : 0;
+                const size_t n01 = n00 + g.nx;
+                va[b][0] = ax[n00];
+                va[b][1] = ax[n00 + 1];
+                va[b][2] = ax[n01];
+                va[b][3] = ax[n01 + 1];
+                va[b][4] = ay[n00];
+                va[b][5] = ay[n00 + 1];
+                va[b][6] = ay[n01];
+                va[b][7] = ay[n01 + 1];
+            }
+            unsigned bits = 0;  // 4 bits per cell: result of triangle 0, then triangle 1
+#pragma unroll
+            for (int b = 0; b < QB; b++) {
+                const int c = lane + 64 * (q0 + b), li = c % S::TX, lj = c / S::TX;
+                if (!(li < T.ncx && lj < T.ncy)) continue;
+                const int gi = T.ci0 + li, gj = T.cj0 + lj;
+                int res0 = kMiss, res1 = kMiss;
+                if constexpr (sizeof(V) == 4) {
+                    const float r = (float)row[SYS_R], E = (float)row[SYS_EB];
+                    const float bxh = (float)row[SYS_BXH], bxl = (float)row[SYS_BXL];
+                    const float byh = (float)row[SYS_BYH], byl = (float)row[SYS_BYL];
+                    const float h32 = (float)g.h;
+                    const float ex0 = (((float)gi - bxh) - bxl) * h32;
+                    const float ex1 = (((float)(gi + 1) - bxh) - bxl) * h32;
+                    const float ey0 = (((float)gj - byh) - byl) * h32;
+                    const float ey1 = (((float)(gj + 1) - byh) - byl) * h32;
+                    const float d00x = fmaf(-r, va[b][0], ex0), d00y = fmaf(-r, va[b][4], ey0);
+                    const float d10x = fmaf(-r, va[b][1], ex1), d10y = fmaf(-r, va[b][5], ey0);
+                    const float d01x = fmaf(-r, va[b][2], ex0), d01y = fmaf(-r, va[b][6], ey1);
+                    const float d11x = fmaf(-r, va[b][3], ex1), d11y = fmaf(-r, va[b][7], ey1);
+                    const float tx[3] = {d00x, d10x, d01x}, ty[3] = {d00y, d10y, d01y};
+                    const float ux[3] = {d11x, d01x, d10x}, uy[3] = {d11y, d01y, d10y};
+                    res0 = decide32(tx, ty, E, mode, tau, nbbox);
+                    res1 = decide32(ux, uy, E, mode, tau, nbbox);
+                } else {
+                    const double r = row[SYS_R], bx = row[SYS_BX], by = row[SYS_BY];
+                    const double t0x = g.x0 + gi * g.h, t1x = g.x0 + (gi + 1) * g.h;
+                    const double t0y = g.y0 + gj * g.h, t1y = g.y0 + (gj + 1) * g.h;
+                    const double b00x = t0x - r * va[b][0], b00y = t0y - r * va[b][4];
+                    const double b10x = t1x - r * va[b][1], b10y = t0y - r * va[b][5];
+                    const double b01x = t0x - r * va[b][2], b01y = t1y - r * va[b][6];
+                    const double b11x = t1x - r * va[b][3], b11y = t1y - r * va[b][7];
+                    const double vx0[3] = {b00x, b10x, b01x}, vy0[3] = {b00y, b10y, b01y};
+                    const double vx1[3] = {b11x, b01x, b10x}, vy1[3] = {b11y, b01y, b10y};
+                    if (!(bx < fmin(vx0[0], fmin(vx0[1], vx0[2])) || bx > fmax(vx0[0], fmax(vx0[1], vx0[2])) ||
+                          by < fmin(vy0[0], fmin(vy0[1], vy0[2])) || by > fmax(vy0[0], fmax(vy0[1], vy0[2])))) {
+                        nbbox++;
+                        res0 = contains_exact(vx0, vy0, bx, by) ? kHit : kMiss;
+                    }
+                    if (!(bx < fmin(vx1[0], fmin(vx1[1], vx1[2])) || bx > fmax(vx1[0], fmax(vx1[1], vx1[2])) ||
+                          by < fmin(vy1[0], fmin(vy1[1], vy1[2])) || by > fmax(vy1[0], fmax(vy1[1], vy1[2])))) {
+                        nbbox++;
+                        res1 = contains_exact(vx1, vy1, bx, by) ? kHit : kMiss;
+                    }
+                }
+                bits |= (unsigned)(res0 | (res1 << 2)) << (4 * b);
+            }
+            if (__ballot(bits != 0) == 0) continue;  // the common case: no hit, nothing undecided
+            const unsigned long long base = (unsigned long long)(unsigned)sys << 32;
+#pragma unroll 1
+            for (int b = 0; b < QB; b++) {
+                const unsigned rb = (bits >> (4 * b)) & 15u;
+                const int c = lane + 64 * (q0 + b), li = c % S::TX, lj = c / S::TX;
+                const unsigned tid0 = (unsigned)(2 * ((T.cj0 + lj) * (g.nx - 1) + (T.ci0 + li)));
+                wave_append((rb & 3u) == kHit, base | tid0, &st->n_hits, hit_keys, hit_cap);
+                wave_append((rb >> 2) == kHit, base | (tid0 + 1), &st->n_hits, hit_keys, hit_cap);
+                wave_append((rb & 3u) == kFlag, base | tid0, &st->n_flags, flag_keys, flag_cap);
+                wave_append((rb >> 2) == kFlag, base | (tid0 + 1), &st->n_flags, flag_keys, flag_cap);
+            }
+        }
+    }
+    write_part_sum(part, (size_t)part_base + blockIdx.x, 0u, nbbox, sp);
 }
 
-// ============================================================== FP64 fallback, positions, tail
 
 // Persistent waves over the items [certain hits..., undecided tests...]:
 // the position of every certain hit goes to pos[item]; each undecided test is
@@ -475,7 +493,8 @@ __global__ __launch_bounds__(1024) void k_tail(ObsPtrs obs, EvalState* __restric
     if (pb) atomicAdd(&s_bbox, pb);
     const unsigned long long total = nc + nfb;
     const bool over = nc > (unsigned long long)hit_cap || nf > (unsigned long long)flag_cap ||
-                      nfb > (unsigned long long)fb_cap || total > (unsigned long long)hit_capacity ||
+                      nfb > (unsigned long long)fb_cap ||
+                      total > (unsigned long long)hit_capacity ||
                       total > (unsigned long long)kSortCap;
     const int status = (status0 == kStatusOk && over) ? kStatusCapacity : status0;
     const int n = status == kStatusOk ? (int)total : 0, ncert = (int)nc;
@@ -732,9 +751,11 @@ hipError_t launch_field32(const float* tab32, int np, const GridDesc& g, float* 
 }
 
 hipError_t launch_field64(const double* tab64, int np, const GridDesc& g, double* ax, double* ay,
-                          const EvalState* st, const KernelEvents* ev, hipStream_t s)
+                          const EvalState* st, double* rr, int tx_shift, int tiles_x, const KernelEvents* ev,
+                          hipStream_t s)
 {
-    return launch_ev(ev, k_field64, dim3(cdiv(g.nx, 256), g.ny), dim3(256), s, tab64, np, g, ax, ay, st);
+    return launch_ev(ev, k_field64, dim3(cdiv(g.nx, 256), g.ny), dim3(256), s, tab64, np, g, ax, ay, st, rr,
+                     tx_shift, tiles_x);
 }
 
 // Tile shapes selectable per call (lens_chi2_opts.tile): 1 = 32x8 (default),
@@ -760,42 +781,68 @@ void tile_dims(int shape, int& tx, int& ty)
     }
 }
 
-// Workgroups of the triangle stage: FP32, one wave per tile; FP64, persistent.
-int tri_blocks(const GridDesc& g, int shape, bool fp32)
+// Tiles of a grid for a tile-shape code; workgroups of the culling kernel.
+long long tri_tiles(const GridDesc& g, int shape, int* tiles_x)
 {
     int tx, ty;
     tile_dims(shape, tx, ty);
-    const long long n_tiles = (long long)cdiv(g.nx - 1, tx) * cdiv(g.ny - 1, ty);
-    if (fp32) return (int)cdiv(n_tiles, 4);
-    return (int)(n_tiles < kTriBlocks ? n_tiles : kTriBlocks);
+    *tiles_x = (int)cdiv(g.nx - 1, tx);
+    return (long long)*tiles_x * cdiv(g.ny - 1, ty);
 }
 
-hipError_t launch_tri32(const float* ax, const float* ay, const float* rr, const GridDesc& g, int nsys,
-                        const double* sysrow, EvalState* st, int mode, float tau, unsigned long long* hit_keys,
-                        long long hit_cap, unsigned long long* flag_keys, long long flag_cap, unsigned* part,
-                        int shape, hipStream_t s)
+// Culling workgroups (4 waves, one tile per wave and round) and rounds for a
+// grid: at most kMaxCull workgroups.
+void cull_shape(const GridDesc& g, int shape, int* n_cull, int* tpw)
+{
+    int tiles_x;
+    const long long n_tiles = tri_tiles(g, shape, &tiles_x);
+    long long nc = cdiv(n_tiles, 4);
+    int k = 1;
+    while (nc > kMaxCull) {
+        k *= 2;
+        nc = cdiv(n_tiles, 4ll * k);
+    }
+    *n_cull = (int)nc;
+    *tpw = k;
+}
+
+hipError_t launch_cull(bool fp32, const void* ax, const void* ay, const void* rr, const GridDesc& g, int nsys,
+                       const double* sysrow, unsigned long long* pairs, long long region, unsigned* counts,
+                       unsigned* part, int shape, hipStream_t s)
 {
     return with_shape(shape, [&](auto sh) {
         using S = decltype(sh);
-        const int tiles_x = (int)cdiv(g.nx - 1, S::TX);
-        const int n_tiles = tiles_x * (int)cdiv(g.ny - 1, S::TY);
-        k_tri32w<S><<<tri_blocks(g, shape, true), 256, 0, s>>>(ax, ay, rr, g, tiles_x, n_tiles, nsys, sysrow, st,
-                                                               mode, tau, hit_keys, hit_cap, flag_keys, flag_cap,
-                                                               part);
+        int tiles_x, nb, tpw;
+        const int n_tiles = (int)tri_tiles(g, shape, &tiles_x);
+        cull_shape(g, shape, &nb, &tpw);
+        if (fp32)
+            k_cull<S, float><<<nb, 256, 0, s>>>((const float*)ax, (const float*)ay, (const float*)rr, g, tiles_x,
+                                                n_tiles, tpw, nsys, sysrow, pairs, region, counts, part);
+        else
+            k_cull<S, double><<<nb, 256, 0, s>>>((const double*)ax, (const double*)ay, (const double*)rr, g,
+                                                 tiles_x, n_tiles, tpw, nsys, sysrow, pairs, region, counts, part);
         return hipGetLastError();
     });
 }
 
-hipError_t launch_tri64(const double* ax, const double* ay, const GridDesc& g, int nsys, const double* sysrow,
-                        EvalState* st, unsigned long long* hit_keys, long long hit_cap, unsigned* part, int shape,
+hipError_t launch_pairs(bool fp32, const void* ax, const void* ay, const GridDesc& g, const double* sysrow,
+                        EvalState* st, int mode, float tau, const unsigned long long* pairs, long long region,
+                        const unsigned* counts, int n_cull, unsigned long long* hit_keys, long long hit_cap,
+                        unsigned long long* flag_keys, long long flag_cap, unsigned* part, int part_base, int shape,
                         hipStream_t s)
 {
     return with_shape(shape, [&](auto sh) {
         using S = decltype(sh);
-        const int tiles_x = (int)cdiv(g.nx - 1, S::TX);
-        const int n_tiles = tiles_x * (int)cdiv(g.ny - 1, S::TY);
-        k_tri64<S><<<tri_blocks(g, shape, false), 256, 0, s>>>(ax, ay, g, tiles_x, n_tiles, nsys, sysrow, st, hit_keys,
-                                                        hit_cap, part);
+        int tiles_x;
+        tri_tiles(g, shape, &tiles_x);
+        if (fp32)
+            k_pairs<S, float><<<kPairBlocks, 256, 0, s>>>((const float*)ax, (const float*)ay, g, tiles_x, sysrow, st,
+                                                          mode, tau, pairs, region, counts, n_cull, hit_keys, hit_cap,
+                                                          flag_keys, flag_cap, part, part_base);
+        else
+            k_pairs<S, double><<<kPairBlocks, 256, 0, s>>>((const double*)ax, (const double*)ay, g, tiles_x,
+                                                           sysrow, st, mode, tau, pairs, region, counts, n_cull,
+                                                           hit_keys, hit_cap, flag_keys, flag_cap, part, part_base);
         return hipGetLastError();
     });
 }
@@ -813,7 +860,8 @@ hipError_t launch_fbpos(const double* tab64, int np, const GridDesc& g, const do
 hipError_t launch_tail(const TailLaunch& tl, EvalState* st, const unsigned long long* fb_keys, const double* pos,
                        const double* fb_pos, hipStream_t s)
 {
-    k_tail<<<1, 1024, 0, s>>>(tl.obs, st, tl.hit_cap, tl.flag_cap, tl.fb_cap, tl.hit_capacity, tl.hit_keys, fb_keys,
+    k_tail<<<1, 1024, 0, s>>>(tl.obs, st, tl.hit_cap, tl.flag_cap, tl.fb_cap, tl.hit_capacity,
+                              tl.hit_keys, fb_keys,
                               pos, fb_pos, tl.out_hits, tl.img_xy, tl.n_pred, tl.contrib, tl.chi2, tl.chi2_sys,
                               tl.match, tl.stats, tl.n_tests, tl.part, tl.n_parts);
     return hipGetLastError();

@@ -172,30 +172,30 @@ __device__ __forceinline__ void field32_all(const float* __restrict__ tab, int n
 // consumer).  rr is [rows][tiles_x][4] floats (min ax, max ax, min ay, max ay).
 // The lanes of a column are an aligned group of TX/NPL lanes of one wave; all
 // 64 lanes must call this together.  Nodes at i >= nx do not count.
-template <int NPL>
-__device__ __forceinline__ void tile_partials(const float* sx, const float* sy, int i0, int j, int nx,
-                                              int tx_shift, int tiles_x, float* __restrict__ rr)
+template <typename V, int NPL>
+__device__ __forceinline__ void tile_partials(const V* sx, const V* sy, int i0, int j, int nx, int tx_shift,
+                                              int tiles_x, V* __restrict__ rr)
 {
-    float mnx = INFINITY, mxx = -INFINITY, mny = INFINITY, mxy = -INFINITY;
+    V mnx = V(INFINITY), mxx = V(-INFINITY), mny = V(INFINITY), mxy = V(-INFINITY);
 #pragma unroll
     for (int k = 0; k < NPL; k++) {
         if (i0 + k < nx) {
-            mnx = fminf(mnx, sx[k]);
-            mxx = fmaxf(mxx, sx[k]);
-            mny = fminf(mny, sy[k]);
-            mxy = fmaxf(mxy, sy[k]);
+            mnx = fmin(mnx, sx[k]);
+            mxx = fmax(mxx, sx[k]);
+            mny = fmin(mny, sy[k]);
+            mxy = fmax(mxy, sy[k]);
         }
     }
     const int seg = (1 << tx_shift) / NPL;  // lanes per tile column, a power of two <= 64
     for (int m = 1; m < seg; m <<= 1) {
-        mnx = fminf(mnx, __shfl_xor(mnx, m, 64));
-        mxx = fmaxf(mxx, __shfl_xor(mxx, m, 64));
-        mny = fminf(mny, __shfl_xor(mny, m, 64));
-        mxy = fmaxf(mxy, __shfl_xor(mxy, m, 64));
+        mnx = fmin(mnx, __shfl_xor(mnx, m, 64));
+        mxx = fmax(mxx, __shfl_xor(mxx, m, 64));
+        mny = fmin(mny, __shfl_xor(mny, m, 64));
+        mxy = fmax(mxy, __shfl_xor(mxy, m, 64));
     }
     const int col = i0 >> tx_shift;
     if ((i0 & ((1 << tx_shift) - 1)) == 0 && i0 < nx && col < tiles_x) {
-        float* q = rr + ((size_t)j * tiles_x + col) * 4;
+        V* q = rr + ((size_t)j * tiles_x + col) * 4;
         q[0] = mnx;
         q[1] = mxx;
         q[2] = mny;
@@ -223,6 +223,14 @@ __device__ __forceinline__ void wave_append(bool pred, unsigned long long key, u
     base = __shfl(base, leader, 64);
     const int off = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
     if (pred && base + off < cap) list[base + off] = key;
+}
+
+// Value of lane l (wave-uniform l) in every lane.
+__device__ __forceinline__ double bcast(double v, int l)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
 __device__ __forceinline__ unsigned long long hit_key(int s, int tid)
@@ -400,35 +408,35 @@ __device__ __forceinline__ void stage_tile(const Tile& T, const V* vx, const V* 
 
 // Deflection range of tile T (with its halo) for every lane of a wave, from
 // the field kernel's row partials plus the halo column read directly.
-template <class S>
-__device__ __forceinline__ void tile_range_wave(const float* __restrict__ ax, const float* __restrict__ ay,
-                                                const float* __restrict__ rr, const GridDesc& g, int tiles_x,
-                                                const Tile& T, float* rng)
+template <class S, typename V>
+__device__ __forceinline__ void tile_range_wave(const V* __restrict__ ax, const V* __restrict__ ay,
+                                                const V* __restrict__ rr, const GridDesc& g, int tiles_x,
+                                                const Tile& T, double* rng)
 {
     const int lane = lane_id();
     const int col = T.ci0 / S::TX;
-    float mnx = INFINITY, mxx = -INFINITY, mny = INFINITY, mxy = -INFINITY;
+    V mnx = V(INFINITY), mxx = V(-INFINITY), mny = V(INFINITY), mxy = V(-INFINITY);
     if (lane <= T.ncy) {
         const int j = T.cj0 + lane;
-        const float* q = rr + ((size_t)j * tiles_x + col) * 4;
+        const V* q = rr + ((size_t)j * tiles_x + col) * 4;
         mnx = q[0];
         mxx = q[1];
         mny = q[2];
         mxy = q[3];
         if (T.ncx == S::TX) {  // halo column: first node of the next column group
             const size_t n = (size_t)j * g.nx + T.ci0 + S::TX;
-            const float vx = ax[n], vy = ay[n];
-            mnx = fminf(mnx, vx);
-            mxx = fmaxf(mxx, vx);
-            mny = fminf(mny, vy);
-            mxy = fmaxf(mxy, vy);
+            const V vx = ax[n], vy = ay[n];
+            mnx = fmin(mnx, vx);
+            mxx = fmax(mxx, vx);
+            mny = fmin(mny, vy);
+            mxy = fmax(mxy, vy);
         }
     }
     for (int m = 32; m >= 1; m >>= 1) {
-        mnx = fminf(mnx, __shfl_xor(mnx, m, 64));
-        mxx = fmaxf(mxx, __shfl_xor(mxx, m, 64));
-        mny = fminf(mny, __shfl_xor(mny, m, 64));
-        mxy = fmaxf(mxy, __shfl_xor(mxy, m, 64));
+        mnx = fmin(mnx, __shfl_xor(mnx, m, 64));
+        mxx = fmax(mxx, __shfl_xor(mxx, m, 64));
+        mny = fmin(mny, __shfl_xor(mny, m, 64));
+        mxy = fmax(mxy, __shfl_xor(mxy, m, 64));
     }
     rng[0] = mnx;
     rng[1] = mxx;
@@ -436,68 +444,25 @@ __device__ __forceinline__ void tile_range_wave(const float* __restrict__ ax, co
     rng[3] = mxy;
 }
 
-// Loads tile T's nodes (with the halo) into a wave-private LDS tile.
-template <class S>
-__device__ __forceinline__ void stage_tile_wave(const float* __restrict__ ax, const float* __restrict__ ay,
-                                                const GridDesc& g, const Tile& T, float (*sx)[S::TNX],
-                                                float (*sy)[S::TNX])
+// Sums a wave-uniform count a and a per-lane count b over the workgroup and
+// writes them to the workgroup's statistics slot.  All threads must call it.
+__device__ __forceinline__ void write_part_sum(unsigned* part, size_t slot, unsigned a, unsigned b,
+                                               unsigned (*s)[2])
 {
-    const int lane = lane_id();
-    constexpr int N = S::TNX * S::TNY;
-#pragma unroll
-    for (int k = 0; k < (N + 63) / 64; k++) {
-        const int q = lane + 64 * k;
-        const int li = q % S::TNX, lj = q / S::TNX;
-        if (q < N && li <= T.ncx && lj <= T.ncy) {
-            const size_t n = (size_t)(T.cj0 + lj) * g.nx + (T.ci0 + li);
-            sx[lj][li] = ax[n];
-            sy[lj][li] = ay[n];
-        }
+    for (int m = 32; m >= 1; m >>= 1) b += __shfl_xor(b, m, 64);
+    if (lane_id() == 0) {
+        s[threadIdx.x >> 6][0] = a;
+        s[threadIdx.x >> 6][1] = b;
     }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-}
-
-// All triangles of a wave-private FP32 tile against one system: the cells are
-// strided over the 64 lanes.  Same decisions as tri32_system.
-template <class S>
-__device__ __forceinline__ void tri32_wave_system(const GridDesc& g, const Tile& T, const float (*sx)[S::TNX],
-                                                  const float (*sy)[S::TNX], const float* fr,
-                                                  unsigned long long hit_base, unsigned long long flag_base,
-                                                  int mode, float tau, unsigned long long* hit_counter,
-                                                  unsigned long long* hit_keys, long long hit_cap,
-                                                  unsigned long long* flag_counter, unsigned long long* flag_keys,
-                                                  long long flag_cap, unsigned& nbbox)
-{
-    const float r = fr[0], E = fr[1], bxh = fr[2], bxl = fr[3], byh = fr[4], byl = fr[5];
-    const float h32 = (float)g.h;
-    const int lane = lane_id();
-#pragma unroll 2
-    for (int it = 0; it < S::TX * S::TY / 64; it++) {
-        const int cidx = lane + 64 * it;
-        const int li = cidx % S::TX, lj = cidx / S::TX;
-        const bool valid = li < T.ncx && lj < T.ncy;
-        const int gi = T.ci0 + li, gj = T.cj0 + lj;
-        int res0 = kMiss, res1 = kMiss;
-        if (valid) {
-            const float ex0 = (((float)gi - bxh) - bxl) * h32;
-            const float ex1 = (((float)(gi + 1) - bxh) - bxl) * h32;
-            const float ey0 = (((float)gj - byh) - byl) * h32;
-            const float ey1 = (((float)(gj + 1) - byh) - byl) * h32;
-            const float d00x = fmaf(-r, sx[lj][li], ex0), d00y = fmaf(-r, sy[lj][li], ey0);
-            const float d10x = fmaf(-r, sx[lj][li + 1], ex1), d10y = fmaf(-r, sy[lj][li + 1], ey0);
-            const float d01x = fmaf(-r, sx[lj + 1][li], ex0), d01y = fmaf(-r, sy[lj + 1][li], ey1);
-            const float d11x = fmaf(-r, sx[lj + 1][li + 1], ex1), d11y = fmaf(-r, sy[lj + 1][li + 1], ey1);
-            const float tx[3] = {d00x, d10x, d01x}, ty[3] = {d00y, d10y, d01y};
-            const float ux[3] = {d11x, d01x, d10x}, uy[3] = {d11y, d01y, d10y};
-            res0 = decide32(tx, ty, E, mode, tau, nbbox);
-            res1 = decide32(ux, uy, E, mode, tau, nbbox);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned sa = 0, sb = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); w++) {
+            sa += s[w][0];
+            sb += s[w][1];
         }
-        const unsigned tid0 = (unsigned)(2 * (gj * (g.nx - 1) + gi));
-        wave_append(res0 == kHit, hit_base | tid0, hit_counter, hit_keys, hit_cap);
-        wave_append(res1 == kHit, hit_base | (tid0 + 1), hit_counter, hit_keys, hit_cap);
-        wave_append(res0 == kFlag, flag_base | tid0, flag_counter, flag_keys, flag_cap);
-        wave_append(res1 == kFlag, flag_base | (tid0 + 1), flag_counter, flag_keys, flag_cap);
+        part[2 * slot + 0] = sa;
+        part[2 * slot + 1] = sb;
     }
 }
 
