@@ -22,12 +22,12 @@ namespace lens {
 // Head of every evaluation, one wave per observed image (at least enough
 // workgroups of 4 waves for one thread per potential), in two phases:
 //  1. every thread with a potential index writes that potential's constants
-//     (prep_one); every wave with an observed image j computes its source
-//     position beta_ij = theta_ij - r_i grad Psi(theta_ij) in FP64 (Sec. 2.2.2),
-//     grad Psi evaluated at the observed position itself from the raw
-//     parameters (the same row64 arithmetic as the table), potentials over the
-//     lanes;
-//  2. the last workgroup to finish reduces the bound terms in a fixed order,
+//     (prep_one); every wave with an observed image j computes grad Psi at the
+//     observed position itself in FP64 from the raw parameters (the same
+//     row64 arithmetic as the table), potentials over the lanes;
+//  2. the last workgroup to finish forms the source positions
+//     beta_ij = theta_ij - r_i grad Psi(theta_ij) (Sec. 2.2.2), one system per
+//     thread, reduces the bound terms in a fixed order,
 //       E_alpha = u (64 + P) sum_p w_p + sum_p j_p + 1e-9,   u = 2^-24,
 //     (64 u w_p bounds the rounding of one potential's FP32 evaluation --
 //     about 30 u w_p by operation count, doubled -- (P-1) u W the sequential
@@ -43,7 +43,7 @@ __global__ __launch_bounds__(256) void k_head(PotPtrs pot, GridDesc g, ObsPtrs o
                                               double* __restrict__ beta_x, double* __restrict__ beta_y,
                                               double* __restrict__ sysrow, EvalState* __restrict__ st)
 {
-    __shared__ double sw[256], sj[256], sb[256];
+    __shared__ double sw[4], sj[4], sb[4];
     __shared__ int last, sys_bad;
     const int t = threadIdx.x;
     const int np = pot.n;
@@ -58,11 +58,9 @@ __global__ __launch_bounds__(256) void k_head(PotPtrs pot, GridDesc g, ObsPtrs o
             add_alpha64(row, t1, t2, s1, s2);
         }
         const double a1 = wave_sum(s1), a2 = wave_sum(s2);
-        const int s = system_of(obs.sys_off, obs.n_sys, j);
-        const double r = obs.dls[s];
-        if (lane_id() == 0) {
-            beta_x[j] = t1 - r * a1;
-            beta_y[j] = t2 - r * a2;
+        if (lane_id() == 0) {  // grad Psi for now; the last workgroup turns it into beta
+            beta_x[j] = a1;
+            beta_y[j] = a2;
         }
     }
     if (!last_workgroup(&st->head_ticket, &last)) return;
@@ -73,30 +71,33 @@ __global__ __launch_bounds__(256) void k_head(PotPtrs pot, GridDesc g, ObsPtrs o
         jt += bterm[3 * p + 1];
         bad += bterm[3 * p + 2];
     }
-    sw[t] = w;
-    sj[t] = jt;
-    sb[t] = bad;
+    w = wave_sum(w);
+    jt = wave_sum(jt);
+    bad = wave_sum(bad);
+    if (lane_id() == 0) {
+        sw[t >> 6] = w;
+        sj[t >> 6] = jt;
+        sb[t >> 6] = bad;
+    }
     if (t == 0) sys_bad = obs.n_sys > 0 && (obs.sys_off[0] != 0 || obs.sys_off[obs.n_sys] != obs.n_img);
     __syncthreads();
-    for (int m = 128; m >= 1; m >>= 1) {
-        if (t < m) {
-            sw[t] += sw[t + m];
-            sj[t] += sj[t + m];
-            sb[t] += sb[t + m];
-        }
-        __syncthreads();
-    }
-    const double W = sw[0];
-    const double e_alpha = kU32 * (64.0 + np) * W + sj[0] + 1e-9;
+    const double W = (sw[0] + sw[1]) + (sw[2] + sw[3]);
+    const double Jsum = (sj[0] + sj[1]) + (sj[2] + sj[3]);
+    const double Bsum = (sb[0] + sb[1]) + (sb[2] + sb[3]);
+    const double e_alpha = kU32 * (64.0 + np) * W + Jsum + 1e-9;
     const double xlo = g.x0, xhi = g.x0 + (g.nx - 1) * g.h, ylo = g.y0, yhi = g.y0 + (g.ny - 1) * g.h;
     for (int s = t; s < obs.n_sys; s += 256) {
         const int j0 = obs.sys_off[s], j1 = obs.sys_off[s + 1];
         bool ok = j0 <= j1 && j0 >= 0 && j1 <= obs.n_img;
         double bx = 0.0, by = 0.0;
+        const double r = obs.dls[s];
         if (ok) {
             for (int j = j0; j < j1; j++) {
-                bx += beta_x[j];
-                by += beta_y[j];
+                const double b1 = obs.x[j] - r * beta_x[j], b2 = obs.y[j] - r * beta_y[j];
+                beta_x[j] = b1;
+                beta_y[j] = b2;
+                bx += b1;
+                by += b2;
                 ok = ok && obs.sigma[j] > 0.0 && isfinite(obs.sigma[j]) && isfinite(obs.x[j]) && isfinite(obs.y[j]);
             }
             if (j1 > j0) {
@@ -104,7 +105,6 @@ __global__ __launch_bounds__(256) void k_head(PotPtrs pot, GridDesc g, ObsPtrs o
                 by /= (j1 - j0);
             }
         }
-        const double r = obs.dls[s];
         ok = ok && isfinite(r) && r >= 0.0;
         const double bxn = (bx - g.x0) / g.h, byn = (by - g.y0) / g.h;
         ok = ok && fabs(bxn) < 4194304.0 && fabs(byn) < 4194304.0;
@@ -129,7 +129,7 @@ __global__ __launch_bounds__(256) void k_head(PotPtrs pot, GridDesc g, ObsPtrs o
         st->n_fb_hits = 0;
         st->w_sum = W;
         st->e_alpha = e_alpha;
-        st->status = (sb[0] != 0.0 || sys_bad) ? kStatusInvalid : kStatusOk;
+        st->status = (Bsum != 0.0 || sys_bad) ? kStatusInvalid : kStatusOk;
     }
 }
 
@@ -272,16 +272,16 @@ __global__ __launch_bounds__(256) void k_pairs(const V* __restrict__ ax, const V
     constexpr int Q = S::TX * S::TY / 64;  // cells per lane for one pair
     constexpr int QB = Q < 4 ? Q : 4;      // cells per lane per step
     const int lane = lane_id(), t = threadIdx.x;
-    // per-wave prefix of the culling counts: lane l holds counts [l*per, (l+1)*per)
-    // in registers (per <= kMaxCull / 64) and their sum
-    constexpr int PER = kMaxCull / 64;
-    const int per = (n_cull + 63) / 64;
-    unsigned cl[PER];
-    unsigned lsum = 0;
+    // exclusive prefix of the culling counts in LDS: thread t owns counts
+    // [4t, 4t+4) (n_cull <= 1024), wave scans, then the wave totals
+    __shared__ unsigned spre[kMaxCull + 1];
+    __shared__ unsigned swt[4];
+    const int wave = t >> 6;
+    unsigned cl[4], lsum = 0;
 #pragma unroll
-    for (int j = 0; j < PER; j++) {
-        const int c = lane * per + j;
-        cl[j] = (j < per && c < n_cull) ? counts[c] : 0u;
+    for (int j = 0; j < 4; j++) {
+        const int c = 4 * t + j;
+        cl[j] = c < n_cull ? counts[c] : 0u;
         lsum += cl[j];
     }
     unsigned incl = lsum;
@@ -289,25 +289,31 @@ __global__ __launch_bounds__(256) void k_pairs(const V* __restrict__ ax, const V
         const unsigned v = __shfl_up(incl, d, 64);
         if (lane >= d) incl += v;
     }
-    const unsigned excl = incl - lsum;
-    const unsigned total = (unsigned)__builtin_amdgcn_readlane((int)incl, 63);
+    if (lane == 63) swt[wave] = incl;
+    __syncthreads();
+    unsigned run = incl - lsum;
+    for (int w = 0; w < wave; w++) run += swt[w];
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const int c = 4 * t + j;
+        if (c < n_cull) spre[c] = run;
+        run += cl[j];
+    }
+    const unsigned total = swt[0] + swt[1] + swt[2] + swt[3];
+    __syncthreads();
     const long long nw = (long long)gridDim.x * 4;
-    const long long w0 = (long long)blockIdx.x * 4 + (t >> 6);
+    const long long w0 = (long long)blockIdx.x * 4 + wave;
     const long long n_pairs = st->status == kStatusOk ? (long long)total : 0;
     unsigned nbbox = 0;
     for (long long u = w0; u < n_pairs; u += nw) {
         const unsigned pidx = (unsigned)u;
-        // the lane whose range holds pidx, then the culling workgroup inside it
-        const int L = __ffsll((long long)__ballot(incl > pidx)) - 1;
-        int cw = L * per;
-        unsigned off = pidx - (unsigned)__builtin_amdgcn_readlane((int)excl, L);
-#pragma unroll
-        for (int j = 0; j < PER; j++) {  // walk lane L's counts (registers, no memory access)
-            const unsigned cj = (unsigned)__builtin_amdgcn_readlane((int)cl[j], L);
-            if (off < cj) break;
-            off -= cj;
-            cw++;
+        int lo = 0, hi = n_cull - 1;  // the last culling workgroup whose prefix is <= pidx
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (spre[mid] <= pidx) lo = mid; else hi = mid - 1;
         }
+        const int cw = lo;
+        const unsigned off = pidx - spre[lo];
         const unsigned long long pk = pairs[(size_t)cw * region + off];
         const int tile = (int)(pk >> 32), sys = (int)(pk & 0xffffffffu);
         const Tile T = tile_of<S>(g, tiles_x, tile);

@@ -43,7 +43,8 @@ __device__ __forceinline__ bool row64(const PotPtrs& pot, int p, double* t, doub
     const bool ok = isfinite(xc) && isfinite(yc) && isfinite(eps) && isfinite(phi) && isfinite(a) &&
                     isfinite(sig) && eps >= 0.0 && eps < 1.0 && a >= 0.0 && sig >= 0.0 && s > a;
     const bool sinf = isinf(s);
-    const double c = cos(phi), sn = sin(phi);
+    double c, sn;
+    sincos(phi, &sn, &c);
     a1 = 1.0 - eps;
     a2 = 1.0 + eps;
     const double ratio = sig / kCkms;
@@ -64,14 +65,19 @@ __device__ __forceinline__ bool row64(const PotPtrs& pot, int p, double* t, doub
     return ok;
 }
 
-// Constants of parameter column p written to table row q.
+// Constants of parameter column p written to table row q; the FP64 row is
+// also copied to row_copy and the three bound terms returned in terms when
+// these are not null.
 static __device__ void prep_one(const PotPtrs& pot, const GridDesc& g, int p, int q, double* __restrict__ tab64,
-                                float* __restrict__ tab32, double* __restrict__ bterm)
+                                float* __restrict__ tab32, double* __restrict__ bterm,
+                                double* row_copy = nullptr, double* terms = nullptr)
 {
     double row[T64_STRIDE], K, a1, a2;
     bool ok = row64(pot, p, row, K, a1, a2);
     double* t = tab64 + (size_t)q * T64_STRIDE;
     for (int k = 0; k < T64_STRIDE; k++) t[k] = row[k];
+    if (row_copy)
+        for (int k = 0; k < T64_STRIDE; k++) row_copy[k] = row[k];
     const double xc = row[T64_XC], yc = row[T64_YC], A = row[T64_A], B = row[T64_B], C = row[T64_C];
     const double a = row[T64_RA], s = pot.r_cut[p];
     const bool sinf = row[T64_SINF] != 0.0;
@@ -107,6 +113,11 @@ static __device__ void prep_one(const PotPtrs& pot, const GridDesc& g, int p, in
     bterm[3 * q + 0] = ok ? w : 0.0;
     bterm[3 * q + 1] = ok ? J * derr : 0.0;
     bterm[3 * q + 2] = ok ? 0.0 : 1.0;
+    if (terms) {
+        terms[0] = ok ? w : 0.0;
+        terms[1] = ok ? J * derr : 0.0;
+        terms[2] = ok ? 0.0 : 1.0;
+    }
 }
 
 // Index of the system that owns observed image j: sys_off is non-decreasing
