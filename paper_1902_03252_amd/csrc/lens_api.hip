@@ -441,7 +441,7 @@ int lens_image_chi2(lens_ctx* ctx, const lens_potentials* pot, const lens_grid* 
         (rc = ensure(ctx, B_FLAGS, (size_t)(mixed ? kFlagScratch : 1) * 8)) ||
         (rc = ensure(ctx, B_PART, (size_t)n_parts * 2 * 4)) ||
         (rc = ensure(ctx, B_SYS, (size_t)o.n_sys * SYS_STRIDE * 8)) ||
-        (rc = ensure(ctx, B_RR, (size_t)g.ny * tiles_x * 4 * vbytes)) ||
+        (rc = ensure(ctx, B_RR, (size_t)g.ny * (tiles_x + 1) * kRR * vbytes)) ||
         (rc = ensure(ctx, B_PAIRS, (size_t)region * n_cull * 8 + (size_t)n_cull * 4)))
         return rc;
     void* rr = ctx->buf[B_RR];

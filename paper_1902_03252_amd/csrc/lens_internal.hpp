@@ -75,6 +75,7 @@ hipError_t launch_field32(const float* tab32, int np, const GridDesc& g, float* 
 hipError_t launch_field64(const double* tab64, int np, const GridDesc& g, double* ax, double* ay,
                           const EvalState* st, double* rr, int tx_shift, int tiles_x, const KernelEvents* ev,
                           hipStream_t s);
+constexpr int kRR = 8;                     // values per (row, column group) of the tile range partials
 constexpr int kPairBlocks = 512;           // persistent workgroups of the pair kernel
 constexpr int kMaxCull = 1024;             // culling workgroups (4 tiles per round)
 void tile_dims(int shape, int& tx, int& ty);

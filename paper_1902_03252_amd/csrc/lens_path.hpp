@@ -178,11 +178,15 @@ __device__ __forceinline__ void field32_all(const float* __restrict__ tab, int n
 }
 
 // Range partials of the triangle stage, written by the field kernel: for grid
-// row j and tile column c, the min/max of each deflection component over the
-// nodes [c*TX, c*TX + TX) of the row (the tile's halo column is read by the
-// consumer).  rr is [rows][tiles_x][4] floats (min ax, max ax, min ay, max ay).
-// The lanes of a column are an aligned group of TX/NPL lanes of one wave; all
-// 64 lanes must call this together.  Nodes at i >= nx do not count.
+// row j and column group c (nodes [c*TX, c*TX + TX) of the row), the min/max
+// of each deflection component over the group and the deflection at its first
+// node, which is the halo column of tile column c - 1.  rr is
+// [rows][tiles_x + 1][kRR] (min ax, max ax, min ay, max ay, ax, ay at the
+// first node, 2 unused); groups c <= tiles_x carry the first node, groups
+// c < tiles_x the ranges.  The lanes of a group are an aligned group of
+// TX/NPL lanes of one wave; all 64 lanes must call this together.  Nodes at
+// i >= nx do not count.  (kRR is declared with the launch interface.)
+
 template <typename V, int NPL>
 __device__ __forceinline__ void tile_partials(const V* sx, const V* sy, int i0, int j, int nx, int tx_shift,
                                               int tiles_x, V* __restrict__ rr)
@@ -205,12 +209,16 @@ __device__ __forceinline__ void tile_partials(const V* sx, const V* sy, int i0, 
         mxy = fmax(mxy, __shfl_xor(mxy, m, 64));
     }
     const int col = i0 >> tx_shift;
-    if ((i0 & ((1 << tx_shift) - 1)) == 0 && i0 < nx && col < tiles_x) {
-        V* q = rr + ((size_t)j * tiles_x + col) * 4;
-        q[0] = mnx;
-        q[1] = mxx;
-        q[2] = mny;
-        q[3] = mxy;
+    if ((i0 & ((1 << tx_shift) - 1)) == 0 && i0 < nx && col <= tiles_x) {
+        V* q = rr + ((size_t)j * (tiles_x + 1) + col) * kRR;
+        if (col < tiles_x) {
+            q[0] = mnx;
+            q[1] = mxx;
+            q[2] = mny;
+            q[3] = mxy;
+        }
+        q[4] = sx[0];
+        q[5] = sy[0];
     }
 }
 
@@ -429,14 +437,13 @@ __device__ __forceinline__ void tile_range_wave(const V* __restrict__ ax, const 
     V mnx = V(INFINITY), mxx = V(-INFINITY), mny = V(INFINITY), mxy = V(-INFINITY);
     if (lane <= T.ncy) {
         const int j = T.cj0 + lane;
-        const V* q = rr + ((size_t)j * tiles_x + col) * 4;
+        const V* q = rr + ((size_t)j * (tiles_x + 1) + col) * kRR;
         mnx = q[0];
         mxx = q[1];
         mny = q[2];
         mxy = q[3];
         if (T.ncx == S::TX) {  // halo column: first node of the next column group
-            const size_t n = (size_t)j * g.nx + T.ci0 + S::TX;
-            const V vx = ax[n], vy = ay[n];
+            const V vx = q[kRR + 4], vy = q[kRR + 5];
             mnx = fmin(mnx, vx);
             mxx = fmax(mxx, vx);
             mny = fmin(mny, vy);
