@@ -22,7 +22,7 @@ enum Buf { B_TAB64, B_TAB32, B_BTERM, B_FIELD, B_BX, B_BY, B_SYS, B_STATE, B_HIT
 // Device work plan of one chunk of a batch (see lens_image_chi2_batched).
 struct PlanChunk {
     int s0, n, np;            // first sample, samples, parameter columns
-    long long n_fitems, n_tiles, n_nodes, n_tests;
+    long long n_fitems, n_tiles, n_nodes, n_tests, n_rr;
     void* host_stage;         // pinned source of the plan upload, freed with the plan
     void* dev_plan;
     int* fmap;
@@ -603,7 +603,7 @@ int batch_plan(lens_ctx* c, int n_samples, const int32_t* pot_off, const lens_gr
         const size_t o_pot = 0, o_grid = align8(o_pot + 4 * (size_t)(n + 1)),
                      o_perm = align8(o_grid + sizeof(GridDesc) * (size_t)n), o_fo = align8(o_perm + 4 * (size_t)n),
                      o_to = o_fo + 8 * (size_t)(n + 1), o_no = o_to + 8 * (size_t)(n + 1),
-                     bytes = o_no + 8 * (size_t)n;
+                     o_rr = o_no + 8 * (size_t)n, bytes = o_rr + 8 * (size_t)n;
         if (hipHostMalloc(&ch.host_stage, bytes, hipHostMallocDefault) != hipSuccess) {
             rc = LENS_ERR_DEVICE;
             break;
@@ -615,15 +615,19 @@ int batch_plan(lens_ctx* c, int n_samples, const int32_t* pot_off, const lens_gr
         long long* h_fo = (long long*)(hb + o_fo);
         long long* h_to = (long long*)(hb + o_to);
         long long* h_no = (long long*)(hb + o_no);
+        long long* h_rr = (long long*)(hb + o_rr);
         for (int k = 0; k <= n; k++) h_pot[k] = pot_off[s0 + k];
-        long long node = 0;
+        long long node = 0, nrr = 0;
         for (int k = 0; k < n; k++) {
             const lens_grid& g = grids[s0 + k];
             h_grid[k] = grid_desc(&g);
             h_no[k] = node;
+            h_rr[k] = nrr;
             node += (long long)g.nx * g.ny;
+            nrr += (long long)g.ny * ((g.nx - 2) / tx + 2) * kRR;
             ch.n_tests += 2ll * (g.nx - 1) * (g.ny - 1);
         }
+        ch.n_rr = nrr;
         h_fo[0] = 0;
         h_to[0] = 0;
         for (int k = 0; k < n; k++) {
@@ -654,6 +658,8 @@ int batch_plan(lens_ctx* c, int n_samples, const int32_t* pot_off, const lens_gr
         ch.bp.fitem_off = (const long long*)(db + o_fo);
         ch.bp.titem_off = (const long long*)(db + o_to);
         ch.bp.node_off = (const long long*)(db + o_no);
+        ch.bp.rr_off = (const long long*)(db + o_rr);
+        ch.bp.tx_shift = tx == 64 ? 6 : 5;
         if (hipMemcpyAsync(ch.dev_plan, ch.host_stage, bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
             launch_bmap(ch.bp, ch.fmap, ch.tmap, s) != hipSuccess)
             rc = LENS_ERR_DEVICE;
@@ -701,12 +707,13 @@ extern "C" int lens_image_chi2_batched(lens_ctx* ctx, const lens_potentials* all
     if (rc) return rc;
 
     // scratch sized for the largest chunk
-    long long max_n = 0, max_np = 0, max_nodes = 0, max_tiles = 0, n_tests = 0;
+    long long max_n = 0, max_np = 0, max_nodes = 0, max_tiles = 0, n_tests = 0, max_rr = 0;
     for (const PlanChunk& ch : plan->chunks) {
         max_n = std::max(max_n, (long long)ch.n);
         max_np = std::max(max_np, (long long)ch.np);
         max_nodes = std::max(max_nodes, ch.n_nodes);
         max_tiles = std::max(max_tiles, ch.n_tiles);
+        max_rr = std::max(max_rr, ch.n_rr);
         n_tests += ch.n_tests * obs->n_sys;
     }
     const int hcap = opts->hit_capacity;
@@ -721,7 +728,8 @@ extern "C" int lens_image_chi2_batched(lens_ctx* ctx, const lens_potentials* all
         (rc = ensure(ctx, B_SYS, (size_t)max_n * obs->n_sys * SYS_STRIDE * 8)) ||
         (rc = ensure(ctx, B_HITS, per_sample_hits * 2 * 8)) ||
         (rc = ensure(ctx, B_FLAGS, (size_t)(mixed ? kFlagScratch : 1) * 8)) ||
-        (rc = ensure(ctx, B_POS, per_sample_hits * 4 * 8)) || (rc = ensure(ctx, B_PART, (size_t)max_tiles * 2 * 4)) ||
+        (rc = ensure(ctx, B_POS, per_sample_hits * 4 * 8)) || (rc = ensure(ctx, B_PART, (size_t)(max_tiles / 4 + 1) * 2 * 4)) ||
+        (rc = ensure(ctx, B_RR, (size_t)max_rr * (mixed ? 4 : 8))) ||
         (rc = ensure(ctx, B_BCOUNT, (size_t)max_n * 20 + 8 * 16)))
         return rc;
     unsigned long long* hits = (unsigned long long*)ctx->buf[B_HITS];
@@ -755,24 +763,24 @@ extern "C" int lens_image_chi2_batched(lens_ctx* ctx, const lens_potentials* all
         if (e == hipSuccess) {
             if (mixed)
                 e = launch_bfield32(bp, ch.fmap, ch.n_fitems, (const float*)ctx->buf[B_TAB32], (float*)field,
-                                    (float*)field + ch.n_nodes, npl, ev, stream);
+                                    (float*)field + ch.n_nodes, (float*)ctx->buf[B_RR], npl, ev, stream);
             else
                 e = launch_bfield64(bp, ch.fmap, ch.n_fitems, (const double*)ctx->buf[B_TAB64], (double*)field,
-                                    (double*)field + ch.n_nodes, ev, stream);
+                                    (double*)field + ch.n_nodes, (double*)ctx->buf[B_RR], ev, stream);
         }
         if (e != hipSuccess) return LENS_ERR_DEVICE;
         timing_end(ctx, slot);
         const void* fx = field;
         const void* fy = mixed ? (const void*)((float*)field + ch.n_nodes) : (const void*)((double*)field + ch.n_nodes);
-        e = launch_btri(bp, ch.tmap, ch.n_tiles, o.n_sys, sysrow, fx, fy, mixed, bs, opts->fb_mode,
-                        (float)opts->fb_tau, hcap, hits, flags, flag_cap, part, shape, stream);
+        e = launch_btri(bp, ch.tmap, ch.n_tiles, o.n_sys, sysrow, fx, fy, ctx->buf[B_RR], mixed, bs, opts->fb_mode,
+                        opts->fb_tau, hcap, hits, flags, flag_cap, part, shape, stream);
         if (e == hipSuccess)
             e = launch_bfbpos(bp, o.n_sys, (const double*)ctx->buf[B_TAB64], sysrow, bs, hcap, hits, flags, flag_cap,
                               fb, pos, fb_pos, stream);
         if (e == hipSuccess)
             e = launch_btail(bp, o, bs, hcap, flag_cap, hits, fb, pos, fb_pos, out->chi2 + ch.s0,
                              out->chi2_sys + (size_t)ch.s0 * o.n_sys, out->n_pred + (size_t)ch.s0 * o.n_sys,
-                             out->status + ch.s0, agg, part, ch.n_tiles, stream);
+                             out->status + ch.s0, agg, part, (ch.n_tiles + 3) / 4, stream);
         if (e != hipSuccess) return LENS_ERR_DEVICE;
     }
     return launch_bstats(agg, n_tests, (long long*)out->stats, stream) == hipSuccess ? LENS_OK : LENS_ERR_DEVICE;

@@ -146,11 +146,11 @@ __global__ __launch_bounds__(256) void k_bmap(BatchPlan bp, int* __restrict__ fm
 
 // One workgroup per (sample, row segment of 256*NPL nodes); the map gives the
 // sample (heaviest samples first).  Same inner loop as the single-evaluation
-// FP32 field.
+// FP32 field, and the same tile range partials (per sample).
 template <int NPL>
 __global__ __launch_bounds__(256) void k_bfield32(BatchPlan bp, const int* __restrict__ fmap,
                                                   const float* __restrict__ tab32, float* __restrict__ fx,
-                                                  float* __restrict__ fy)
+                                                  float* __restrict__ fy, float* __restrict__ rr)
 {
     const long long item = blockIdx.x;
     const int k = fmap[item];
@@ -160,7 +160,6 @@ __global__ __launch_bounds__(256) void k_bfield32(BatchPlan bp, const int* __res
     const long long local = item - bp.fitem_off[k];
     const int j = (int)(local / segs), seg = (int)(local % segs);
     const int i0 = (seg * 256 + threadIdx.x) * NPL;
-    if (i0 >= g.nx) return;
     const int p0 = bp.pot_off[0];
     const float* tab = tab32 + (size_t)(bp.pot_off[s] - p0) * T32_STRIDE;
     const int np = bp.pot_off[s + 1] - bp.pot_off[s];
@@ -173,6 +172,8 @@ __global__ __launch_bounds__(256) void k_bfield32(BatchPlan bp, const int* __res
         sy[q] = 0.0f;
     }
     field32_all<NPL>(tab, np, fj, fi, sx, sy);
+    const int tiles_x = (g.nx - 2) / (1 << bp.tx_shift) + 1;
+    tile_partials<float, NPL>(sx, sy, i0, j, g.nx, bp.tx_shift, tiles_x, rr + bp.rr_off[s]);
     const size_t row = (size_t)bp.node_off[s] + (size_t)j * g.nx;
 #pragma unroll
     for (int q = 0; q < NPL; q++) {
@@ -186,7 +187,7 @@ __global__ __launch_bounds__(256) void k_bfield32(BatchPlan bp, const int* __res
 // FP64 field: one workgroup per (sample, row segment of 256 nodes).
 __global__ __launch_bounds__(256) void k_bfield64(BatchPlan bp, const int* __restrict__ fmap,
                                                   const double* __restrict__ tab64, double* __restrict__ fx,
-                                                  double* __restrict__ fy)
+                                                  double* __restrict__ fy, double* __restrict__ rr)
 {
     const long long item = blockIdx.x;
     const int k = fmap[item];
@@ -195,13 +196,15 @@ __global__ __launch_bounds__(256) void k_bfield64(BatchPlan bp, const int* __res
     const int segs = (g.nx + 255) / 256;
     const long long local = item - bp.fitem_off[k];
     const int j = (int)(local / segs), i = (int)(local % segs) * 256 + threadIdx.x;
-    if (i >= g.nx) return;
     const int p0 = bp.pot_off[0];
     const double* tab = tab64 + (size_t)(bp.pot_off[s] - p0) * T64_STRIDE;
     const int np = bp.pot_off[s + 1] - bp.pot_off[s];
     const double t1 = g.x0 + i * g.h, t2 = g.y0 + j * g.h;
     double s1 = 0.0, s2 = 0.0;
     for (int p = 0; p < np; p++) add_alpha64(tab + (size_t)p * T64_STRIDE, t1, t2, s1, s2);
+    const int tiles_x = (g.nx - 2) / (1 << bp.tx_shift) + 1;
+    tile_partials<double, 1>(&s1, &s2, i, j, g.nx, bp.tx_shift, tiles_x, rr + bp.rr_off[s]);
+    if (i >= g.nx) return;
     const size_t n = (size_t)bp.node_off[s] + (size_t)j * g.nx + i;
     fx[n] = s1;
     fy[n] = s2;
@@ -209,69 +212,74 @@ __global__ __launch_bounds__(256) void k_bfield64(BatchPlan bp, const int* __res
 
 // ============================================================== triangles
 
-// One workgroup per (sample, tile).  The sample's systems are staged in LDS
-// with the tile; hits go to the sample's own list (system << 32 | triangle
-// id), undecided tests to the batch list (sample << 44 | system << 31 |
-// triangle id).
+// One wave per (sample, tile) work item (heaviest samples first): the tile's
+// deflection range from the sample's range partials culls the systems (one
+// per lane); a tile that a system survives is staged in the wave's own LDS
+// tile and its cells tested for each surviving system.  Hits go to the
+// sample's own list (system << 32 | triangle id), undecided tests to the batch
+// list (sample << 44 | system << 31 | triangle id).
 template <class S, typename V>
-__global__ __launch_bounds__(256) void k_btri(BatchPlan bp, const int* __restrict__ tmap, int nsys,
-                                              const double* __restrict__ sysrow, const V* __restrict__ fx,
-                                              const V* __restrict__ fy, BatchState bs, int mode, float tau,
-                                              int hcap, unsigned long long* __restrict__ hits,
+__global__ __launch_bounds__(256) void k_btri(BatchPlan bp, const int* __restrict__ tmap, long long n_items,
+                                              int nsys, const double* __restrict__ sysrow, const V* __restrict__ fx,
+                                              const V* __restrict__ fy, const V* __restrict__ rr, BatchState bs,
+                                              int mode, double tau, int hcap, unsigned long long* __restrict__ hits,
                                               unsigned long long* __restrict__ flags, long long flag_cap,
                                               unsigned* __restrict__ part)
 {
-    __shared__ V sx[S::TNY][S::TNX], sy[S::TNY][S::TNX];
-    __shared__ V wred[4][4];
-    __shared__ SysChunk chunk;
-    __shared__ unsigned sbb[4];
-    const long long item = blockIdx.x;
-    const int k = tmap[item];
-    const int s = bp.perm[k];
-    const GridDesc g = bp.grid[s];
-    const int tiles_x = (g.nx - 2) / S::TX + 1;
-    const Tile T = tile_of<S>(g, tiles_x, (int)(item - bp.titem_off[k]));
-    const double* rows = sysrow + (size_t)s * nsys * SYS_STRIDE;
-    V vx[S::LOADS], vy[S::LOADS];
-    load_tile<S>(fx + bp.node_off[s], fy + bp.node_off[s], g, T, vx, vy);
-    const bool one_chunk = nsys <= SYS_CHUNK;
-    if (one_chunk) load_chunk(chunk, rows, nsys, 0);
-    V rngv[4];
-    stage_tile<S>(T, vx, vy, sx, sy, wred, rngv);
-    const double rng[4] = {(double)rngv[0], (double)rngv[1], (double)rngv[2], (double)rngv[3]};
-    const int lane = lane_id();
-    unsigned nbbox = 0, ntile = 0;
-    for (int cbase = 0; cbase < nsys; cbase += SYS_CHUNK) {
-        if (!one_chunk) {
-            __syncthreads();
-            load_chunk(chunk, rows, nsys, cbase);
-            __syncthreads();
-        }
-        const int nc = min(SYS_CHUNK, nsys - cbase);
-        for (int sbase = 0; sbase < nc; sbase += 64) {
-            const int sl = sbase + lane;
-            const double eb = sizeof(V) == 4 ? (sl < nc ? chunk.eb[sl] : 0.0) : 1e-9;
-            const bool pass = sl < nc && tile_box_contains(g, T, rng, chunk.r[sl], eb, chunk.bx[sl], chunk.by[sl]);
+    __shared__ V sx[4][S::TNY][S::TNX], sy[4][S::TNY][S::TNX];
+    __shared__ unsigned sp[4][2];
+    const int wave = threadIdx.x >> 6, lane = lane_id();
+    const long long item = (long long)blockIdx.x * 4 + wave;
+    unsigned ntile = 0, nbbox = 0;
+    if (item < n_items) {
+        const int k = tmap[item];
+        const int s = bp.perm[k];
+        const GridDesc g = bp.grid[s];
+        const int tiles_x = (g.nx - 2) / S::TX + 1;
+        const Tile T = tile_of<S>(g, tiles_x, (int)(item - bp.titem_off[k]));
+        double rng[4];
+        tile_range_wave<S, V>(rr + bp.rr_off[s], tiles_x, T, rng);
+        const double* rows = sysrow + (size_t)s * nsys * SYS_STRIDE;
+        bool staged = false;
+        for (int sb = 0; sb < nsys; sb += 64) {
+            const int sl = sb + lane;
+            double r = 0.0, eb = 0.0, bx = 0.0, by = 0.0;
+            if (sl < nsys) {
+                const double* row = rows + (size_t)sl * SYS_STRIDE;
+                r = row[SYS_R];
+                eb = row[SYS_EB];
+                bx = row[SYS_BX];
+                by = row[SYS_BY];
+            }
+            const bool pass = sl < nsys && tile_box_contains(g, T, rng, r, sizeof(V) == 4 ? eb : 1e-9, bx, by);
             unsigned long long m = __ballot(pass);
-            ntile += __popcll(m);
+            ntile += (unsigned)__popcll(m);
+            if (m != 0 && !staged) {
+                stage_tile_wave<S, V>(fx + bp.node_off[s], fy + bp.node_off[s], g, T, sx[wave], sy[wave]);
+                staged = true;
+            }
             while (m) {
-                const int c = sbase + __ffsll((long long)m) - 1;
+                const int c = __ffsll((long long)m) - 1;
                 m &= m - 1;
-                const unsigned sys = (unsigned)(cbase + c);
+                const unsigned sys = (unsigned)(sb + c);
                 if constexpr (sizeof(V) == 4) {
-                    tri32_system<S>(g, T, sx, sy, chunk.f[c], ((unsigned long long)sys << 32),
-                                    ((unsigned long long)s << 44) | ((unsigned long long)sys << 31), mode, tau,
-                                    &bs.n_hits[s], hits + (size_t)s * hcap, hcap, bs.n_flags, flags, flag_cap,
-                                    nbbox);
+                    const double* row = rows + (size_t)sys * SYS_STRIDE;  // wave-uniform
+                    const float fr[6] = {(float)row[SYS_R],   (float)row[SYS_EB],  (float)row[SYS_BXH],
+                                         (float)row[SYS_BXL], (float)row[SYS_BYH], (float)row[SYS_BYL]};
+                    tri32_system<S, 64>(g, T, sx[wave], sy[wave], fr, ((unsigned long long)sys << 32),
+                                        ((unsigned long long)s << 44) | ((unsigned long long)sys << 31), mode,
+                                        (float)(tau * g.h * g.h),
+                                        &bs.n_hits[s], hits + (size_t)s * hcap, hcap, bs.n_flags, flags, flag_cap,
+                                        nbbox, lane);
                 } else {
-                    tri64_system<S>(g, T, sx, sy, chunk.r[c], chunk.bx[c], chunk.by[c],
-                                    ((unsigned long long)sys << 32), &bs.n_hits[s], hits + (size_t)s * hcap, hcap,
-                                    nbbox);
+                    tri64_system<S, 64>(g, T, sx[wave], sy[wave], bcast(r, c), bcast(bx, c), bcast(by, c),
+                                        ((unsigned long long)sys << 32), &bs.n_hits[s], hits + (size_t)s * hcap,
+                                        hcap, nbbox, lane);
                 }
             }
         }
     }
-    write_part(part, blockIdx.x, ntile, nbbox, sbb);
+    write_part_sum(part, blockIdx.x, ntile, nbbox, sp);
 }
 
 // ============================================================== positions and fallback
@@ -498,20 +506,20 @@ hipError_t launch_bmap(const BatchPlan& bp, int* fmap, int* tmap, hipStream_t s)
 }
 
 hipError_t launch_bfield32(const BatchPlan& bp, const int* fmap, long long n_items, const float* tab32, float* fx,
-                           float* fy, int npl, const KernelEvents* ev, hipStream_t s)
+                           float* fy, float* rr, int npl, const KernelEvents* ev, hipStream_t s)
 {
     const dim3 grid((unsigned)n_items), block(256);
     switch (npl) {
-    case 1: return launch_ev(ev, k_bfield32<1>, grid, block, s, bp, fmap, tab32, fx, fy);
-    case 4: return launch_ev(ev, k_bfield32<4>, grid, block, s, bp, fmap, tab32, fx, fy);
-    default: return launch_ev(ev, k_bfield32<2>, grid, block, s, bp, fmap, tab32, fx, fy);
+    case 1: return launch_ev(ev, k_bfield32<1>, grid, block, s, bp, fmap, tab32, fx, fy, rr);
+    case 4: return launch_ev(ev, k_bfield32<4>, grid, block, s, bp, fmap, tab32, fx, fy, rr);
+    default: return launch_ev(ev, k_bfield32<2>, grid, block, s, bp, fmap, tab32, fx, fy, rr);
     }
 }
 
 hipError_t launch_bfield64(const BatchPlan& bp, const int* fmap, long long n_items, const double* tab64, double* fx,
-                           double* fy, const KernelEvents* ev, hipStream_t s)
+                           double* fy, double* rr, const KernelEvents* ev, hipStream_t s)
 {
-    return launch_ev(ev, k_bfield64, dim3((unsigned)n_items), dim3(256), s, bp, fmap, tab64, fx, fy);
+    return launch_ev(ev, k_bfield64, dim3((unsigned)n_items), dim3(256), s, bp, fmap, tab64, fx, fy, rr);
 }
 
 template <class F>
@@ -526,20 +534,20 @@ static hipError_t with_bshape(int shape, F f)
 }
 
 hipError_t launch_btri(const BatchPlan& bp, const int* tmap, long long n_items, int nsys, const double* sysrow,
-                       const void* fx, const void* fy, bool fp32, const BatchState& bs, int mode, float tau, int hcap,
-                       unsigned long long* hits, unsigned long long* flags, long long flag_cap, unsigned* part,
-                       int shape, hipStream_t s)
+                       const void* fx, const void* fy, const void* rr, bool fp32, const BatchState& bs, int mode,
+                       double tau, int hcap, unsigned long long* hits, unsigned long long* flags, long long flag_cap,
+                       unsigned* part, int shape, hipStream_t s)
 {
+    const unsigned nb = (unsigned)((n_items + 3) / 4);
     return with_bshape(shape, [&](auto sh) {
         using S = decltype(sh);
         if (fp32)
-            k_btri<S, float><<<(unsigned)n_items, 256, 0, s>>>(bp, tmap, nsys, sysrow, (const float*)fx,
-                                                               (const float*)fy, bs, mode, tau, hcap, hits, flags,
-                                                               flag_cap, part);
+            k_btri<S, float><<<nb, 256, 0, s>>>(bp, tmap, n_items, nsys, sysrow, (const float*)fx, (const float*)fy,
+                                                (const float*)rr, bs, mode, tau, hcap, hits, flags, flag_cap, part);
         else
-            k_btri<S, double><<<(unsigned)n_items, 256, 0, s>>>(bp, tmap, nsys, sysrow, (const double*)fx,
-                                                                (const double*)fy, bs, mode, tau, hcap, hits, flags,
-                                                                flag_cap, part);
+            k_btri<S, double><<<nb, 256, 0, s>>>(bp, tmap, n_items, nsys, sysrow, (const double*)fx,
+                                                 (const double*)fy, (const double*)rr, bs, mode, tau, hcap, hits,
+                                                 flags, flag_cap, part);
         return hipGetLastError();
     });
 }

@@ -52,6 +52,8 @@ struct BatchPlan {
     const long long* fitem_off;   // [n+1] field work items, in plan order
     const long long* titem_off;   // [n+1] triangle-stage tiles, in plan order
     const long long* node_off;    // [n] offset of each sample's field (nodes)
+    const long long* rr_off;      // [n] offset of each sample's tile range partials (values)
+    int tx_shift;                 // log2 of the tile width in cells
 };
 
 // Per-sample counters and status of a batch chunk (device arrays).
@@ -136,13 +138,13 @@ hipError_t launch_bsys(const BatchPlan& bp, const ObsPtrs& obs, const double* bt
                        const double* by, double* sysrow, const BatchState& bs, hipStream_t s);
 hipError_t launch_bmap(const BatchPlan& bp, int* fmap, int* tmap, hipStream_t s);
 hipError_t launch_bfield32(const BatchPlan& bp, const int* fmap, long long n_items, const float* tab32, float* fx,
-                           float* fy, int npl, const KernelEvents* ev, hipStream_t s);
+                           float* fy, float* rr, int npl, const KernelEvents* ev, hipStream_t s);
 hipError_t launch_bfield64(const BatchPlan& bp, const int* fmap, long long n_items, const double* tab64, double* fx,
-                           double* fy, const KernelEvents* ev, hipStream_t s);
+                           double* fy, double* rr, const KernelEvents* ev, hipStream_t s);
 hipError_t launch_btri(const BatchPlan& bp, const int* tmap, long long n_items, int nsys, const double* sysrow,
-                       const void* fx, const void* fy, bool fp32, const BatchState& bs, int mode, float tau, int hcap,
-                       unsigned long long* hits, unsigned long long* flags, long long flag_cap, unsigned* part,
-                       int shape, hipStream_t s);
+                       const void* fx, const void* fy, const void* rr, bool fp32, const BatchState& bs, int mode,
+                       double tau, int hcap, unsigned long long* hits, unsigned long long* flags, long long flag_cap,
+                       unsigned* part, int shape, hipStream_t s);
 hipError_t launch_bfbpos(const BatchPlan& bp, int nsys, const double* tab64, const double* sysrow,
                          const BatchState& bs, int hcap, const unsigned long long* hits,
                          const unsigned long long* flags, long long flag_cap, unsigned long long* fb, double* pos,

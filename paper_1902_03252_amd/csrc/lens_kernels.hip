@@ -220,7 +220,7 @@ __global__ __launch_bounds__(256) void k_cull(const V* __restrict__ ax, const V*
         double rng[4] = {0.0, 0.0, 0.0, 0.0};
         if (act) {
             T = tile_of<S>(g, tiles_x, tile);
-            tile_range_wave<S, V>(ax, ay, rr, g, tiles_x, T, rng);
+            tile_range_wave<S, V>(rr, tiles_x, T, rng);
         }
         for (int sb = 0; sb < nsys; sb += 64) {
             const int s = sb + lane;

@@ -224,7 +224,6 @@ __device__ __forceinline__ void tile_partials(const V* sx, const V* sy, int i0, 
 
 // ---------------------------------------------------------------- triangles
 
-constexpr int SYS_CHUNK = 128;  // systems staged in LDS at a time
 
 enum : int { kMiss = 0, kHit = 1, kFlag = 2 };
 
@@ -302,43 +301,14 @@ __device__ __forceinline__ int decide32(const float* dx, const float* dy, float 
     return kFlag;
 }
 
-// Per-system data of one chunk of systems, staged in LDS by the tile kernels.
-struct SysChunk {
-    double bx[SYS_CHUNK], by[SYS_CHUNK], r[SYS_CHUNK], eb[SYS_CHUNK];
-    float f[SYS_CHUNK][6];  // r, E_B, bx_hi, bx_lo, by_hi, by_lo as float
-};
-
-__device__ __forceinline__ void load_chunk(SysChunk& c, const double* __restrict__ sysrow, int nsys, int base)
-{
-    const int t = threadIdx.x;
-    const int s = base + t;
-    if (t < SYS_CHUNK && s < nsys) {
-        const double* row = sysrow + (size_t)s * SYS_STRIDE;
-        const double bx = row[SYS_BX], by = row[SYS_BY], r = row[SYS_R], eb = row[SYS_EB];
-        c.bx[t] = bx;
-        c.by[t] = by;
-        c.r[t] = r;
-        c.eb[t] = eb;
-        c.f[t][0] = (float)r;
-        c.f[t][1] = (float)eb;
-        c.f[t][2] = (float)row[SYS_BXH];
-        c.f[t][3] = (float)row[SYS_BXL];
-        c.f[t][4] = (float)row[SYS_BYH];
-        c.f[t][5] = (float)row[SYS_BYL];
-    }
-}
-
 // ---------------------------------------------------------------- tiles
 
-// A tile of TX x TY cells with its one-node halo of (TX+1) x (TY+1) nodes,
-// processed by one workgroup of 256 threads.
+// A tile of TX x TY cells with its one-node halo of (TX+1) x (TY+1) nodes.
 template <int TX_, int TY_>
 struct TileShape {
     static constexpr int TX = TX_, TY = TY_;
     static constexpr int TNX = TX + 1, TNY = TY + 1;
-    static constexpr int LOADS = (TNX * TNY + 255) / 256;  // node loads per thread
-    static constexpr int ITERS = (TX * TY + 255) / 256;    // cells per thread
-    static_assert(TX * TY % 256 == 0, "a tile is a whole number of cells per thread");
+    static_assert(TX * TY % 256 == 0, "a tile is a whole number of cells per wave step");
 };
 
 // Tile geometry from a linear tile index.
@@ -357,146 +327,6 @@ __device__ __forceinline__ Tile tile_of(const GridDesc& g, int tiles_x, int tile
     return T;
 }
 
-// Issues every load of a tile's node values (with the halo) into registers;
-// nothing waits for them here.
-template <class S, typename V>
-__device__ __forceinline__ void load_tile(const V* __restrict__ ax, const V* __restrict__ ay, const GridDesc& g,
-                                          const Tile& T, V* vx, V* vy)
-{
-#pragma unroll
-    for (int k = 0; k < S::LOADS; k++) {
-        const int q = threadIdx.x + 256 * k;
-        const int li = q % S::TNX, lj = q / S::TNX;
-        const bool in = q < S::TNX * S::TNY && li <= T.ncx && lj <= T.ncy;
-        const size_t n = in ? (size_t)(T.cj0 + lj) * g.nx + (T.ci0 + li) : 0;
-        vx[k] = in ? ax[n] : V(0);
-        vy[k] = in ? ay[n] : V(0);
-    }
-}
-
-// Stores the registers of a tile to LDS and leaves the tile's deflection
-// range (min/max of each component over its nodes) in rng[0..3] for every
-// thread.  Contains the workgroup barrier that publishes the LDS tile.
-template <class S, typename V>
-__device__ __forceinline__ void stage_tile(const Tile& T, const V* vx, const V* vy, V (*sx)[S::TNX],
-                                           V (*sy)[S::TNX], V (*wred)[4], V* rng)
-{
-    V xmn = V(INFINITY), xmx = V(-INFINITY), ymn = V(INFINITY), ymx = V(-INFINITY);
-#pragma unroll
-    for (int k = 0; k < S::LOADS; k++) {
-        const int q = threadIdx.x + 256 * k;
-        const int li = q % S::TNX, lj = q / S::TNX;
-        if (q < S::TNX * S::TNY) {
-            sx[lj][li] = vx[k];
-            sy[lj][li] = vy[k];
-            if (li <= T.ncx && lj <= T.ncy) {
-                xmn = vx[k] < xmn ? vx[k] : xmn;
-                xmx = vx[k] > xmx ? vx[k] : xmx;
-                ymn = vy[k] < ymn ? vy[k] : ymn;
-                ymx = vy[k] > ymx ? vy[k] : ymx;
-            }
-        }
-    }
-    for (int m = 32; m >= 1; m >>= 1) {
-        const V a = __shfl_xor(xmn, m, 64), b = __shfl_xor(xmx, m, 64);
-        const V c = __shfl_xor(ymn, m, 64), d = __shfl_xor(ymx, m, 64);
-        xmn = a < xmn ? a : xmn;
-        xmx = b > xmx ? b : xmx;
-        ymn = c < ymn ? c : ymn;
-        ymx = d > ymx ? d : ymx;
-    }
-    if (lane_id() == 0) {
-        const int w = threadIdx.x >> 6;
-        wred[w][0] = xmn;
-        wred[w][1] = xmx;
-        wred[w][2] = ymn;
-        wred[w][3] = ymx;
-    }
-    __syncthreads();
-    rng[0] = wred[0][0];
-    rng[1] = wred[0][1];
-    rng[2] = wred[0][2];
-    rng[3] = wred[0][3];
-    for (int w = 1; w < 4; w++) {
-        rng[0] = wred[w][0] < rng[0] ? wred[w][0] : rng[0];
-        rng[1] = wred[w][1] > rng[1] ? wred[w][1] : rng[1];
-        rng[2] = wred[w][2] < rng[2] ? wred[w][2] : rng[2];
-        rng[3] = wred[w][3] > rng[3] ? wred[w][3] : rng[3];
-    }
-}
-
-// Deflection range of tile T (with its halo) for every lane of a wave, from
-// the field kernel's row partials plus the halo column read directly.
-template <class S, typename V>
-__device__ __forceinline__ void tile_range_wave(const V* __restrict__ ax, const V* __restrict__ ay,
-                                                const V* __restrict__ rr, const GridDesc& g, int tiles_x,
-                                                const Tile& T, double* rng)
-{
-    const int lane = lane_id();
-    const int col = T.ci0 / S::TX;
-    V mnx = V(INFINITY), mxx = V(-INFINITY), mny = V(INFINITY), mxy = V(-INFINITY);
-    if (lane <= T.ncy) {
-        const int j = T.cj0 + lane;
-        const V* q = rr + ((size_t)j * (tiles_x + 1) + col) * kRR;
-        mnx = q[0];
-        mxx = q[1];
-        mny = q[2];
-        mxy = q[3];
-        if (T.ncx == S::TX) {  // halo column: first node of the next column group
-            const V vx = q[kRR + 4], vy = q[kRR + 5];
-            mnx = fmin(mnx, vx);
-            mxx = fmax(mxx, vx);
-            mny = fmin(mny, vy);
-            mxy = fmax(mxy, vy);
-        }
-    }
-    for (int m = 32; m >= 1; m >>= 1) {
-        mnx = fmin(mnx, __shfl_xor(mnx, m, 64));
-        mxx = fmax(mxx, __shfl_xor(mxx, m, 64));
-        mny = fmin(mny, __shfl_xor(mny, m, 64));
-        mxy = fmax(mxy, __shfl_xor(mxy, m, 64));
-    }
-    rng[0] = mnx;
-    rng[1] = mxx;
-    rng[2] = mny;
-    rng[3] = mxy;
-}
-
-// Sums a wave-uniform count a and a per-lane count b over the workgroup and
-// writes them to the workgroup's statistics slot.  All threads must call it.
-__device__ __forceinline__ void write_part_sum(unsigned* part, size_t slot, unsigned a, unsigned b,
-                                               unsigned (*s)[2])
-{
-    for (int m = 32; m >= 1; m >>= 1) b += __shfl_xor(b, m, 64);
-    if (lane_id() == 0) {
-        s[threadIdx.x >> 6][0] = a;
-        s[threadIdx.x >> 6][1] = b;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned sa = 0, sb = 0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); w++) {
-            sa += s[w][0];
-            sb += s[w][1];
-        }
-        part[2 * slot + 0] = sa;
-        part[2 * slot + 1] = sb;
-    }
-}
-
-// Writes a workgroup's statistics to its own slot (no contended atomic).
-__device__ __forceinline__ void write_part(unsigned* part, size_t slot, unsigned ntile, unsigned nbbox,
-                                           unsigned* sbb)
-{
-    for (int m = 32; m >= 1; m >>= 1) nbbox += __shfl_xor(nbbox, m, 64);
-    if (lane_id() == 0) sbb[threadIdx.x >> 6] = nbbox;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        part[2 * slot + 0] = ntile;
-        part[2 * slot + 1] = sbb[0] + sbb[1] + sbb[2] + sbb[3];
-    }
-}
-
 // Whether the tile's source-plane box [theta_min - r alpha_max, theta_max -
 // r alpha_min] (per axis, widened by eb) contains the barycentre (bx, by);
 // the box contains every source-plane vertex of the tile.
@@ -513,20 +343,20 @@ __device__ __forceinline__ bool tile_box_contains(const GridDesc& g, const Tile&
 // certified FP32 decision for each, hits and undecided tests appended with
 // one atomic per wave.  fr = {r, E_B, bx_hi, bx_lo, by_hi, by_lo} as float;
 // an appended key is (hit_base | triangle id) or (flag_base | triangle id).
-template <class S>
+template <class S, int NT = 256>
 __device__ __forceinline__ void tri32_system(const GridDesc& g, const Tile& T, const float (*sx)[S::TNX],
                                              const float (*sy)[S::TNX], const float* fr,
                                              unsigned long long hit_base, unsigned long long flag_base, int mode,
                                              float tau, unsigned long long* hit_counter,
                                              unsigned long long* hit_keys, long long hit_cap,
                                              unsigned long long* flag_counter, unsigned long long* flag_keys,
-                                             long long flag_cap, unsigned& nbbox)
+                                             long long flag_cap, unsigned& nbbox, int tix = threadIdx.x)
 {
     const float r = fr[0], E = fr[1], bxh = fr[2], bxl = fr[3], byh = fr[4], byl = fr[5];
     const float h32 = (float)g.h;
-#pragma unroll
-    for (int it = 0; it < S::ITERS; it++) {
-        const int cidx = threadIdx.x + 256 * it;
+#pragma unroll 1
+    for (int it = 0; it < S::TX * S::TY / NT; it++) {
+        const int cidx = tix + NT * it;
         const int li = cidx % S::TX, lj = cidx / S::TX;
         const bool valid = li < T.ncx && lj < T.ncy;
         const int gi = T.ci0 + li, gj = T.cj0 + lj;
@@ -556,15 +386,16 @@ __device__ __forceinline__ void tri32_system(const GridDesc& g, const Tile& T, c
 
 // All triangles of a staged FP64 tile against one system (FP64 path): exact
 // bounding box, then exact orientation signs.
-template <class S>
+template <class S, int NT = 256>
 __device__ __forceinline__ void tri64_system(const GridDesc& g, const Tile& T, const double (*sx)[S::TNX],
                                              const double (*sy)[S::TNX], double r, double bx, double by,
                                              unsigned long long hit_base, unsigned long long* hit_counter,
-                                             unsigned long long* hit_keys, long long hit_cap, unsigned& nbbox)
+                                             unsigned long long* hit_keys, long long hit_cap, unsigned& nbbox,
+                                             int tix = threadIdx.x)
 {
 #pragma unroll 1
-    for (int it = 0; it < S::ITERS; it++) {
-        const int cidx = threadIdx.x + 256 * it;
+    for (int it = 0; it < S::TX * S::TY / NT; it++) {
+        const int cidx = tix + NT * it;
         const int li = cidx % S::TX, lj = cidx / S::TX;
         const bool valid = li < T.ncx && lj < T.ncy;
         const int gi = T.ci0 + li, gj = T.cj0 + lj;
