@@ -327,6 +327,86 @@ __device__ __forceinline__ Tile tile_of(const GridDesc& g, int tiles_x, int tile
     return T;
 }
 
+// Deflection range of tile T (with its halo) for every lane of a wave, from
+// the field kernel's row partials: lanes over the tile's node rows, then a
+// butterfly min/max.
+template <class S, typename V>
+__device__ __forceinline__ void tile_range_wave(const V* __restrict__ rr, int tiles_x, const Tile& T, double* rng)
+{
+    const int lane = lane_id();
+    const int col = T.ci0 / S::TX;
+    V mnx = V(INFINITY), mxx = V(-INFINITY), mny = V(INFINITY), mxy = V(-INFINITY);
+    if (lane <= T.ncy) {
+        const int j = T.cj0 + lane;
+        const V* q = rr + ((size_t)j * (tiles_x + 1) + col) * kRR;
+        mnx = q[0];
+        mxx = q[1];
+        mny = q[2];
+        mxy = q[3];
+        if (T.ncx == S::TX) {  // halo column: first node of the next column group
+            const V vx = q[kRR + 4], vy = q[kRR + 5];
+            mnx = fmin(mnx, vx);
+            mxx = fmax(mxx, vx);
+            mny = fmin(mny, vy);
+            mxy = fmax(mxy, vy);
+        }
+    }
+    for (int m = 32; m >= 1; m >>= 1) {
+        mnx = fmin(mnx, __shfl_xor(mnx, m, 64));
+        mxx = fmax(mxx, __shfl_xor(mxx, m, 64));
+        mny = fmin(mny, __shfl_xor(mny, m, 64));
+        mxy = fmax(mxy, __shfl_xor(mxy, m, 64));
+    }
+    rng[0] = mnx;
+    rng[1] = mxx;
+    rng[2] = mny;
+    rng[3] = mxy;
+}
+
+// Loads tile T's nodes (with the halo) into a wave-private LDS tile.
+template <class S, typename V>
+__device__ __forceinline__ void stage_tile_wave(const V* __restrict__ ax, const V* __restrict__ ay, const GridDesc& g,
+                                                const Tile& T, V (*sx)[S::TNX], V (*sy)[S::TNX])
+{
+    const int lane = lane_id();
+    constexpr int N = S::TNX * S::TNY;
+#pragma unroll
+    for (int k = 0; k < (N + 63) / 64; k++) {
+        const int q = lane + 64 * k;
+        const int li = q % S::TNX, lj = q / S::TNX;
+        if (q < N && li <= T.ncx && lj <= T.ncy) {
+            const size_t n = (size_t)(T.cj0 + lj) * g.nx + (T.ci0 + li);
+            sx[lj][li] = ax[n];
+            sy[lj][li] = ay[n];
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Sums a wave-uniform count a and a per-lane count b over the workgroup and
+// writes them to the workgroup's statistics slot.  All threads must call it.
+__device__ __forceinline__ void write_part_sum(unsigned* part, size_t slot, unsigned a, unsigned b,
+                                               unsigned (*s)[2])
+{
+    for (int m = 32; m >= 1; m >>= 1) b += __shfl_xor(b, m, 64);
+    if (lane_id() == 0) {
+        s[threadIdx.x >> 6][0] = a;
+        s[threadIdx.x >> 6][1] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned sa = 0, sb = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); w++) {
+            sa += s[w][0];
+            sb += s[w][1];
+        }
+        part[2 * slot + 0] = sa;
+        part[2 * slot + 1] = sb;
+    }
+}
+
 // Whether the tile's source-plane box [theta_min - r alpha_max, theta_max -
 // r alpha_min] (per axis, widened by eb) contains the barycentre (bx, by);
 // the box contains every source-plane vertex of the tile.
