@@ -798,7 +798,7 @@ extern "C" int lens_deflect_backward(lens_ctx* ctx, const lens_potentials* pot, 
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return LENS_ERR_DEVICE;
     const GridDesc g = grid_desc(grid);
-    int rc = ensure(ctx, B_VJP, (size_t)7 * pot->n * vjp_chunks(g) * 8);
+    int rc = ensure(ctx, B_VJP, vjp_scratch(pot->n, g));
     if (rc) return rc;
     int slot;
     KernelEvents kev;

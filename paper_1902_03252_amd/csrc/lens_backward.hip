@@ -22,6 +22,18 @@
 //     s:    dK = -K a/(s (s-a)), df = 1/(qs (qs+s))          (0 for s = inf)
 //     sigma_v: dK = 2 K/sigma_v (computed without the division)
 // The centre of a singular profile contributes nothing, as in the forward path.
+//
+// Summed over nodes, the seven products factor into per-potential constants
+// times seven node sums (Fg = F' (g . m), U = d1^2 - d2^2, V = 2 d1 d2,
+// X = g1 d1 - g2 d2, Y = g1 d2 + g2 d1):
+//     T1 = sum 2 Fg d1 + f g1      x_c:  -K (A T1 + B T2)
+//     T2 = sum 2 Fg d2 + f g2      y_c:  -K (B T1 + C T2)
+//     W1 = sum Fg U + f X          eps:  K (-cos 2Phi W1 - sin 2Phi W2)
+//     W2 = sum Fg V + f Y          Phi:  2 eps K (sin 2Phi W1 - cos 2Phi W2)
+//     F = sum f (g . m)            a:    K/(s-a) F + K Da
+//     Da = sum -(g . m)/(qa A_)    s:    -K a/(s (s-a)) F + K Ds
+//     Ds = sum (g . m)/(qs B_)     sigma_v: 2 K/sigma_v F
+// so the kernels accumulate the node sums and apply the constants once.
 #include "lens_path.hpp"
 
 namespace lens {
@@ -29,7 +41,7 @@ namespace lens {
 // Derivative constants of one potential, arcsec units.
 enum : int {
     D_XC = 0, D_YC, D_A, D_B, D_C, D_AE, D_BE, D_AP, D_BP, D_RA, D_A2, D_RS, D_S2, D_S2A2, D_SMA, D_K, D_KA, D_KS,
-    D_KSIG, D_SINF, D_OK, D_STRIDE = 24
+    D_KSIG, D_SINF, D_OK, D_CXH, D_CXL, D_CYH, D_CYL, D_STRIDE = 28
 };
 
 __device__ __forceinline__ void dconst(const PotPtrs& pot, int p, double* d)
@@ -65,9 +77,37 @@ __device__ __forceinline__ void dconst(const PotPtrs& pot, int p, double* d)
     d[D_OK] = ok ? 1.0 : 0.0;
 }
 
-__device__ __forceinline__ double bsqrt(double v) { return sqrt(v); }
-__device__ __forceinline__ float bsqrt(float v) { return __builtin_amdgcn_sqrtf(v); }
-__device__ __forceinline__ double brcp(double v) { return 1.0 / v; }
+// Square root and reciprocal square root of a positive argument.  FP64: the
+// hardware estimate of 1/sqrt(x) refined by two Goldschmidt iterations, then
+// one Newton correction of the root (Markstein, "IA-64 and elementary
+// functions", 2000); both results within a few ulp.  FP32: the hardware
+// instructions (1 ulp).
+__device__ __forceinline__ void sqrt_rsq(double x, double& s, double& is)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    s = fma(fma(-g, g, x), h, g);
+    is = h + h;
+}
+__device__ __forceinline__ void sqrt_rsq(float x, float& s, float& is)
+{
+    s = __builtin_amdgcn_sqrtf(x);
+    is = __builtin_amdgcn_rsqf(x);
+}
+// Reciprocal of a positive normal argument: the hardware estimate refined by
+// two Newton-Raphson steps (FP64); the hardware instruction (FP32, 1 ulp).
+__device__ __forceinline__ double brcp(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
 __device__ __forceinline__ float brcp(float v) { return __builtin_amdgcn_rcpf(v); }
 
 template <typename T>
@@ -101,117 +141,201 @@ __device__ __forceinline__ DConst<T> load_dconst(const double* d)
     return k;
 }
 
-// acc[0..6] += g . d alpha / d (x_c, y_c, eps, Phi, a, s, sigma_v) at offset d.
-template <typename T>
-__device__ __forceinline__ void vjp_term(const DConst<T>& k, T d1, T d2, T g1, T g2, T* acc)
+// sum[0..6] += the node sums (T1, T2, W1, W2, F, Da, Ds) of one node at offset
+// d with cotangent g, for a cut (CUT) or uncut profile.  Straight-line code so
+// that calls in one basic block interleave; for a singular profile (SING) the
+// centre runs with g = 0 and R^2 = 1, so that its products are exact zeros.
+template <typename T, bool CUT, bool SING>
+__device__ __forceinline__ void vjp_sums(const DConst<T>& k, T d1, T d2, T g1, T g2, T* sum)
 {
     const T m1 = k.A * d1 + k.B * d2, m2 = k.B * d1 + k.C * d2;
-    const T R2 = d1 * m1 + d2 * m2;
-    if (k.a == (T)0 && R2 == (T)0) return;
+    T R2 = d1 * m1 + d2 * m2;
+    if constexpr (SING) {
+        const bool c = R2 == (T)0;
+        R2 = c ? (T)1 : R2;
+        g1 = c ? (T)0 : g1;
+        g2 = c ? (T)0 : g2;
+    }
     // f and F' without cancellation: with A_ = qa + a, B_ = qs + s,
     //   qs - qa = (s^2 - a^2)/(qs + qa),  B_ - A_ = (qs - qa) + (s - a),
     //   f = (B_ - A_)/(A_ B_),
     //   F' = -[(qs - qa) B_^2 + qa (B_ - A_)(B_ + A_)] / (2 qa qs A_^2 B_^2).
-    const T qa = bsqrt(k.a2 + R2);
-    const T A_ = qa + k.a, iA = brcp(A_), iqa = brcp(qa);
-    T f, Fp, dfa = -iA * iqa, dfs = (T)0;
-    if (k.sinf) {
+    // The reciprocals 1/(A_ B_), 1/A_, 1/B_ and 1/(qs + qa) come from the one
+    // reciprocal of A_ B_ (qs + qa).
+    T qa, iqa;
+    sqrt_rsq(k.a2 + R2, qa, iqa);
+    const T A_ = qa + k.a;
+    const T gm = g1 * m1 + g2 * m2;
+    T f, Fp, dfa;
+    if constexpr (!CUT) {
+        const T iA = brcp(A_);
         f = iA;
         Fp = (T)(-0.5) * iA * iA * iqa;
+        dfa = -iA * iqa;
     } else {
-        const T qs = bsqrt(k.s2 + R2);
-        const T B_ = qs + k.s, iB = brcp(B_), iqs = brcp(qs);
-        const T dq = k.s2a2 * brcp(qs + qa);
+        T qs, iqs;
+        sqrt_rsq(k.s2 + R2, qs, iqs);
+        const T B_ = qs + k.s, S = qs + qa, AB = A_ * B_;
+        const T inv = brcp(AB * S), iAB = S * inv;
+        const T dq = k.s2a2 * (AB * inv);
         const T dB = dq + k.sma;
-        f = dB * iA * iB;
-        Fp = (T)(-0.5) * (dq * B_ * B_ + qa * dB * (B_ + A_)) * (iqa * iqs) * (iA * iA) * (iB * iB);
-        dfs = iB * iqs;
+        f = dB * iAB;
+        Fp = (T)(-0.5) * (dq * B_ * B_ + qa * dB * (B_ + A_)) * (iqa * iqs) * (iAB * iAB);
+        dfa = -(B_ * iAB) * iqa;
+        sum[6] += ((A_ * iAB) * iqs) * gm;
     }
-    const T gm = g1 * m1 + g2 * m2;
-    const T Kf = k.K * f, KFp = k.K * Fp;
-    acc[0] -= (T)2 * KFp * m1 * gm + Kf * (g1 * k.A + g2 * k.B);
-    acc[1] -= (T)2 * KFp * m2 * gm + Kf * (g1 * k.B + g2 * k.C);
-    const T e1 = k.Ae * d1 + k.Be * d2, e2 = k.Be * d1 - k.Ae * d2;
-    acc[2] += KFp * (d1 * e1 + d2 * e2) * gm + Kf * (g1 * e1 + g2 * e2);
-    const T p1 = k.Ap * d1 + k.Bp * d2, p2 = k.Bp * d1 - k.Ap * d2;
-    acc[3] += KFp * (d1 * p1 + d2 * p2) * gm + Kf * (g1 * p1 + g2 * p2);
-    acc[4] += (k.Ka * f + k.K * dfa) * gm;
-    acc[5] += (k.Ks * f + k.K * dfs) * gm;
-    acc[6] += k.Ksig * f * gm;
+    const T Fg = Fp * gm, Fg2 = Fg + Fg;
+    sum[0] += Fg2 * d1 + f * g1;
+    sum[1] += Fg2 * d2 + f * g2;
+    sum[2] += Fg * (d1 * d1 - d2 * d2) + f * (g1 * d1 - g2 * d2);
+    sum[3] += Fg2 * (d1 * d2) + f * (g1 * d2 + g2 * d1);
+    sum[4] += f * gm;
+    sum[5] += dfa * gm;
+}
+
+// sum[0..6] += the node sums of two nodes (one basic block).
+template <typename T, bool CUT, bool SING>
+__device__ __forceinline__ void vjp_sums2(const DConst<T>& k, T d1a, T d2a, T g1a, T g2a, T d1b, T d2b, T g1b,
+                                          T g2b, T* sum)
+{
+    vjp_sums<T, CUT, SING>(k, d1a, d2a, g1a, g2a, sum);
+    vjp_sums<T, CUT, SING>(k, d1b, d2b, g1b, g2b, sum);
+}
+
+// Dispatch on the profile kind (uniform over the wave).
+template <typename T>
+__device__ __forceinline__ void vjp_pair(const DConst<T>& k, T d1a, T d2a, T g1a, T g2a, T d1b, T d2b, T g1b,
+                                         T g2b, T* sum)
+{
+    if (k.sinf) {
+        if (k.a == (T)0)
+            vjp_sums2<T, false, true>(k, d1a, d2a, g1a, g2a, d1b, d2b, g1b, g2b, sum);
+        else
+            vjp_sums2<T, false, false>(k, d1a, d2a, g1a, g2a, d1b, d2b, g1b, g2b, sum);
+    } else {
+        if (k.a == (T)0)
+            vjp_sums2<T, true, true>(k, d1a, d2a, g1a, g2a, d1b, d2b, g1b, g2b, sum);
+        else
+            vjp_sums2<T, true, false>(k, d1a, d2a, g1a, g2a, d1b, d2b, g1b, g2b, sum);
+    }
+}
+
+// Product c of (x_c, y_c, eps, Phi, a, s, sigma_v) from the FP64 node sums.
+__device__ __forceinline__ double vjp_combine(const double* d, const double* sum, int c)
+{
+    const double K = d[D_K];
+    switch (c) {
+    case 0: return -K * (d[D_A] * sum[0] + d[D_B] * sum[1]);
+    case 1: return -K * (d[D_B] * sum[0] + d[D_C] * sum[1]);
+    case 2: return K * (d[D_AE] * sum[2] + d[D_BE] * sum[3]);
+    case 3: return K * (d[D_AP] * sum[2] + d[D_BP] * sum[3]);
+    case 4: return d[D_KA] * sum[4] + K * sum[5];
+    case 5: return d[D_SINF] != 0.0 ? 0.0 : d[D_KS] * sum[4] + K * sum[6];
+    default: return d[D_KSIG] * sum[4];
+    }
 }
 
 // ============================================================== field VJP
 
-constexpr int kVjpNpt = 16;   // nodes per thread
-constexpr int kVjpGroup = 2;  // potentials per workgroup
-constexpr int kVjpChunk = 256 * kVjpNpt;
+#ifndef LENS_VJP_ROWS
+#define LENS_VJP_ROWS 16
+#endif
+#ifndef LENS_VJP_GROUP
+#define LENS_VJP_GROUP 2
+#endif
+constexpr int kVjpRows = LENS_VJP_ROWS;   // grid rows per wave (nodes per thread)
+constexpr int kVjpGroup = LENS_VJP_GROUP; // potentials per workgroup
+constexpr int kVjpTileY = 4 * kVjpRows;
 
-// Workgroup (chunk, group): nodes [chunk*4096, +4096) of the row-major grid,
-// strided over the threads; potentials [group*2, +2).  Per potential every
-// thread sums its nodes' seven products in T, the workgroup reduces them in
-// FP64 in a fixed order and writes part[(k*P + p)*n_chunks + chunk].
-template <typename T>
-__global__ __launch_bounds__(256) void k_vjp(PotPtrs pot, GridDesc g, const double* __restrict__ gx,
-                                             const double* __restrict__ gy, int n_chunks,
-                                             double* __restrict__ part, int* __restrict__ status)
+// Derivative constants of every potential, plus (FP32 path) the node-unit
+// split of its centre as in the FP32 field: slot D_CX.. of row p.
+__global__ __launch_bounds__(64) void k_vjp_prep(PotPtrs pot, GridDesc g, double* __restrict__ dtab,
+                                                 int* __restrict__ status)
 {
-    __shared__ double sc[kVjpGroup][D_STRIDE];
-    __shared__ double red[4][8];
-    const int chunk = blockIdx.x % n_chunks, grp = blockIdx.x / n_chunks;
-    const int p0 = grp * kVjpGroup, npg = min(kVjpGroup, pot.n - p0);
-    const int t = threadIdx.x, lane = lane_id(), wave = t >> 6;
-    if (blockIdx.x == 0 && t == 0 && status) *status = kStatusOk;
-    if (t < npg) dconst(pot, p0 + t, sc[t]);
-    const long long n_nodes = (long long)g.nx * g.ny;
-    T g1[kVjpNpt], g2[kVjpNpt];
-    int ni[kVjpNpt], nj[kVjpNpt];
+    const int p = blockIdx.x * 64 + threadIdx.x;
+    if (p == 0 && status) *status = kStatusOk;
+    if (p >= pot.n) return;
+    double* d = dtab + (size_t)p * D_STRIDE;
+    dconst(pot, p, d);
+    const double cxn = (d[D_XC] - g.x0) / g.h, cyn = (d[D_YC] - g.y0) / g.h;
+    d[D_CXH] = (float)rint(cxn);
+    d[D_CXL] = (float)(cxn - rint(cxn));
+    d[D_CYH] = (float)rint(cyn);
+    d[D_CYL] = (float)(cyn - rint(cyn));
+}
+
+// Workgroup (tile, group): a 64 x 64 node tile of the grid, lane = column and
+// wave = a band of 16 rows, times the potentials [group*2, +2), whose
+// constants every lane reads from the same address.  Per potential every
+// thread accumulates its nodes' seven node sums in T; the workgroup reduces
+// them in FP64 in a fixed order, applies the potential's constants and writes
+// the seven products to part[(k*P + p)*n_tiles + tile].
+template <typename T>
+__global__ __launch_bounds__(256) void k_vjp(const double* __restrict__ dtab, int np, GridDesc g,
+                                             const double* __restrict__ gx, const double* __restrict__ gy,
+                                             int tiles_x, int n_tiles, double* __restrict__ part)
+{
+    __shared__ double red[kVjpGroup * 7][4];
+    const int tile = blockIdx.x % n_tiles, grp = blockIdx.x / n_tiles;
+    const int p0 = grp * kVjpGroup, npg = min(kVjpGroup, np - p0);
+    const int t = threadIdx.x, lane = lane_id();
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int i = (tile % tiles_x) * 64 + lane;
+    const int jb = (tile / tiles_x) * kVjpTileY + wave * kVjpRows;
+    const int nrow = min(kVjpRows, g.ny - jb);
+    const bool col = i < g.nx;
+    const int ic = col ? i : 0;
+    T acc[kVjpGroup][7];
 #pragma unroll
-    for (int u = 0; u < kVjpNpt; u++) {
-        const long long n = (long long)chunk * kVjpChunk + u * 256 + t;
-        const bool in = n < n_nodes;
-        const long long nn = in ? n : 0;
-        nj[u] = (int)(nn / g.nx);
-        ni[u] = (int)(nn - (long long)nj[u] * g.nx);
-        g1[u] = in ? (T)gx[nn] : (T)0;
-        g2[u] = in ? (T)gy[nn] : (T)0;
-    }
-    __syncthreads();
-    for (int q = 0; q < npg; q++) {
-        const double* d = sc[q];
-        const DConst<T> k = load_dconst<T>(d);
-        T acc[7] = {(T)0, (T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
-        if constexpr (sizeof(T) == 8) {
-            const double xc = d[D_XC], yc = d[D_YC];
+    for (int q = 0; q < kVjpGroup; q++)
 #pragma unroll
-            for (int u = 0; u < kVjpNpt; u++) {
-                if (g1[u] == (T)0 && g2[u] == (T)0) continue;  // nothing to add (and no 0 * inf)
-                const double d1 = (g.x0 + ni[u] * g.h) - xc, d2 = (g.y0 + nj[u] * g.h) - yc;
-                vjp_term<T>(k, d1, d2, g1[u], g2[u], acc);
+        for (int c = 0; c < 7; c++) acc[q][c] = (T)0;
+    const float ihf = (float)g.h;
+    for (int u = 0; u < nrow; u += 2) {
+        // rows j and j + 1 (a row past the band or the grid has g = 0)
+        const int j = jb + u;
+        const bool two = u + 1 < nrow;
+        const size_t n0 = (size_t)j * g.nx + ic, n1 = two ? n0 + g.nx : n0;
+        T ga1 = col ? (T)gx[n0] : (T)0, ga2 = col ? (T)gy[n0] : (T)0;
+        T gb1 = col ? (T)gx[n1] : (T)0, gb2 = col ? (T)gy[n1] : (T)0;
+        gb1 = two ? gb1 : (T)0;
+        gb2 = two ? gb2 : (T)0;
+#pragma unroll
+        for (int q = 0; q < kVjpGroup; q++) {
+            if (q >= npg) break;
+            const double* d = dtab + (size_t)(p0 + q) * D_STRIDE;
+            const DConst<T> k = load_dconst<T>(d);
+            T d1, d2a, d2b;
+            if constexpr (sizeof(T) == 8) {
+                d1 = (g.x0 + i * g.h) - d[D_XC];
+                d2a = (g.y0 + j * g.h) - d[D_YC];
+                d2b = (g.y0 + (j + 1) * g.h) - d[D_YC];
+            } else {
+                // offsets from the node-unit split of the centre, as in the FP32 field
+                d1 = (((float)i - (float)d[D_CXH]) - (float)d[D_CXL]) * ihf;
+                d2a = (((float)j - (float)d[D_CYH]) - (float)d[D_CYL]) * ihf;
+                d2b = (((float)(j + 1) - (float)d[D_CYH]) - (float)d[D_CYL]) * ihf;
             }
-        } else {
-            // offsets from the node-unit split of the centre, as in the FP32 field
-            const double cxn = (d[D_XC] - g.x0) / g.h, cyn = (d[D_YC] - g.y0) / g.h;
-            const float cxh = (float)rint(cxn), cyh = (float)rint(cyn);
-            const float cxl = (float)(cxn - rint(cxn)), cyl = (float)(cyn - rint(cyn));
-            const float h = (float)g.h;
-#pragma unroll
-            for (int u = 0; u < kVjpNpt; u++) {
-                if (g1[u] == (T)0 && g2[u] == (T)0) continue;
-                const float d1 = (((float)ni[u] - cxh) - cxl) * h, d2 = (((float)nj[u] - cyh) - cyl) * h;
-                vjp_term<T>(k, d1, d2, g1[u], g2[u], acc);
-            }
+            vjp_pair<T>(k, d1, d2a, ga1, ga2, d1, d2b, gb1, gb2, acc[q]);
         }
+    }
+#pragma unroll
+    for (int q = 0; q < kVjpGroup; q++)
 #pragma unroll
         for (int c = 0; c < 7; c++) {
-            const double v = wave_sum((double)acc[c]);
-            if (lane == 0) red[wave][c] = v;
+            const double v = wave_sum((double)acc[q][c]);
+            if (lane == 0) red[q * 7 + c][wave] = v;
         }
-        __syncthreads();
-        if (t < 7) {
-            const double v = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
-            part[((size_t)t * pot.n + p0 + q) * n_chunks + chunk] = v;
+    __syncthreads();
+    if (t < 7 * npg) {
+        const int q = t / 7, c = t - 7 * q;
+        double sum[7];
+#pragma unroll
+        for (int r = 0; r < 7; r++) {
+            const double* v = red[q * 7 + r];
+            sum[r] = (v[0] + v[1]) + (v[2] + v[3]);
         }
-        __syncthreads();
+        part[((size_t)c * np + p0 + q) * n_tiles + tile] = vjp_combine(dtab + (size_t)(p0 + q) * D_STRIDE, sum, c);
     }
 }
 
@@ -336,14 +460,13 @@ __global__ __launch_bounds__(256) void k_src_bwd(PotPtrs pot, ObsPtrs obs, const
     const DConst<double> k = load_dconst<double>(d);
     double acc[7] = {0, 0, 0, 0, 0, 0, 0};
     for (int j = lane; j < obs.n_img; j += 64)
-        vjp_term<double>(k, obs.x[j] - d[D_XC], obs.y[j] - d[D_YC], cot[2 * j], cot[2 * j + 1], acc);
+        vjp_pair<double>(k, obs.x[j] - d[D_XC], obs.y[j] - d[D_YC], cot[2 * j], cot[2 * j + 1], 0.0, 0.0, 0.0, 0.0,
+                         acc);
+#pragma unroll
+    for (int c = 0; c < 7; c++) acc[c] = wave_sum(acc[c]);
     const double scale = g_chi2 ? *g_chi2 : 1.0;
     const bool ok = st->status == kStatusOk;
-#pragma unroll
-    for (int c = 0; c < 7; c++) {
-        const double v = wave_sum(acc[c]);
-        if (lane == 0) grad[(size_t)c * pot.n + p] = ok ? scale * v : __builtin_nan("");
-    }
+    if (lane < 7) grad[(size_t)lane * pot.n + p] = ok ? scale * vjp_combine(d, acc, lane) : __builtin_nan("");
 }
 
 __global__ void k_status(int* status, int v)
@@ -353,20 +476,30 @@ __global__ void k_status(int* status, int v)
 
 // ============================================================== launchers
 
-int vjp_chunks(const GridDesc& g) { return (int)(((long long)g.nx * g.ny + kVjpChunk - 1) / kVjpChunk); }
+static int vjp_tiles_x(const GridDesc& g) { return (g.nx + 63) / 64; }
+
+int vjp_chunks(const GridDesc& g) { return vjp_tiles_x(g) * ((g.ny + kVjpTileY - 1) / kVjpTileY); }
+
+size_t vjp_scratch(int np, const GridDesc& g) { return ((size_t)7 * vjp_chunks(g) + D_STRIDE) * (size_t)np * 8; }
 
 hipError_t launch_vjp(const PotPtrs& pot, const GridDesc& g, bool fp32, const double* gx, const double* gy,
-                      double* part, double* grad, int* status, const KernelEvents* ev, hipStream_t s)
+                      double* scratch, double* grad, int* status, const KernelEvents* ev, hipStream_t s)
 {
     if (pot.n == 0) {
         if (status) k_status<<<1, 64, 0, s>>>(status, kStatusOk);
         return hipGetLastError();
     }
-    const int nc = vjp_chunks(g);
+    const int nc = vjp_chunks(g), tx = vjp_tiles_x(g);
+    double* dtab = scratch;
+    double* part = scratch + (size_t)D_STRIDE * pot.n;
+    k_vjp_prep<<<(unsigned)((pot.n + 63) / 64), 64, 0, s>>>(pot, g, dtab, status);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     const long long nb = (long long)nc * ((pot.n + kVjpGroup - 1) / kVjpGroup);
-    hipError_t e = fp32 ? launch_ev(ev, k_vjp<float>, dim3((unsigned)nb), dim3(256), s, pot, g, gx, gy, nc, part, status)
-                        : launch_ev(ev, k_vjp<double>, dim3((unsigned)nb), dim3(256), s, pot, g, gx, gy, nc, part,
-                                    status);
+    e = fp32 ? launch_ev(ev, k_vjp<float>, dim3((unsigned)nb), dim3(256), s, (const double*)dtab, pot.n, g, gx, gy,
+                         tx, nc, part)
+             : launch_ev(ev, k_vjp<double>, dim3((unsigned)nb), dim3(256), s, (const double*)dtab, pot.n, g, gx, gy,
+                         tx, nc, part);
     if (e != hipSuccess) return e;
     k_vjp_final<<<(unsigned)((7ll * pot.n + 3) / 4), 256, 0, s>>>(pot, part, nc, grad, status);
     return hipGetLastError();

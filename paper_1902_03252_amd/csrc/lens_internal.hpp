@@ -127,8 +127,9 @@ struct SrcState {
 };
 
 int vjp_chunks(const GridDesc& g);
+size_t vjp_scratch(int np, const GridDesc& g);  // bytes of device scratch of launch_vjp
 hipError_t launch_vjp(const PotPtrs& pot, const GridDesc& g, bool fp32, const double* gx, const double* gy,
-                      double* part, double* grad, int* status, const KernelEvents* ev, hipStream_t s);
+                      double* scratch, double* grad, int* status, const KernelEvents* ev, hipStream_t s);
 hipError_t launch_src(const PotPtrs& pot, const ObsPtrs& obs, double* beta, double* cot, double* csys,
                       SrcState* st, double* chi2, int* status, const double* g_chi2, double* grad, hipStream_t s);
 
