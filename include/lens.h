@@ -111,9 +111,11 @@ typedef struct {
     double fb_tau;        /* literal-mode factor (e.g. 1e-6); ignored in mode 0    */
     int32_t hit_capacity; /* rows of out->hits / out->img_xy, 1 .. 8192            */
     int32_t field_npl;    /* grid nodes per thread of the FP32 field kernel: 1, 2, 4 or
-                             8; 0 = chosen from the grid size                        */
+                             8 (batched: 1, 2, 4); 0 = the autotuned choice, else
+                             chosen from the grid size (batched: 2)               */
     int32_t tile;         /* cells per triangle-stage tile: 1 = 32x8, 2 = 64x16,
-                             3 = 64x8, 4 = 32x16; 0 = 32x8                           */
+                             3 = 64x8, 4 = 32x16; 0 = the autotuned choice, else
+                             32x8                                                 */
 } lens_chi2_opts;
 
 typedef struct {
@@ -193,6 +195,52 @@ typedef struct {
 int lens_image_chi2_batched(lens_ctx *ctx, const lens_potentials *all, int32_t n_samples,
                             const int32_t *pot_off, const lens_grid *grids, const lens_obs *obs,
                             const lens_chi2_opts *opts, lens_batch_out *out, hipStream_t stream);
+
+/* ---------------------------------------------------------------- autotuning
+ *
+ * A context keeps a table of the fastest triangle-stage tile shape
+ * (lens_chi2_opts.tile) and FP32 field nodes per thread (.field_npl) per
+ * bucket (precision, single or batched call, ceil(log2 of the grid side
+ * max(nx, ny)), ceil(log2 of the potential count P)); for a batch the side is
+ * the largest over the samples and P the rounded-up mean.  A call whose
+ * opts->tile or opts->field_npl is 0 takes the table's choice for its bucket
+ * when there is one, else the fixed default.  lens_create merges the JSON file
+ * named by the environment variable LENS_AUTOTUNE_CACHE, if it exists and
+ * parses (otherwise the table starts empty).  Entries carry the GPU
+ * architecture (e.g. gfx950); a file written on another one adds nothing. */
+
+/* Times every candidate on the caller's problem -- the nodes per thread 1, 2,
+ * 4, 8 (MIXED only) with tile shape 1, then the other tile shapes with the
+ * fastest of those -- each by one warm-up and `reps` (1..100) timed calls
+ * (median, HIP events on `stream`), records the fastest in the table and
+ * leaves `out` holding the result of one more call with it.  opts->tile and
+ * opts->field_npl are ignored; a candidate whose scratch bound is exceeded
+ * (LENS_ERR_CAPACITY) is skipped.  Synchronises `stream` (not capturable).
+ * tile, field_npl: host, may be NULL; receive the choice (field_npl 0 for
+ * FP64, where it has no effect). */
+int lens_autotune_chi2(lens_ctx *ctx, const lens_potentials *pot, const lens_grid *grid, const lens_obs *obs,
+                       const lens_chi2_opts *opts, lens_chi2_out *out, int32_t reps, int32_t *tile,
+                       int32_t *field_npl, hipStream_t stream);
+
+/* The same for lens_image_chi2_batched (nodes per thread 1, 2, 4). */
+int lens_autotune_chi2_batched(lens_ctx *ctx, const lens_potentials *all, int32_t n_samples,
+                               const int32_t *pot_off, const lens_grid *grids, const lens_obs *obs,
+                               const lens_chi2_opts *opts, lens_batch_out *out, int32_t reps, int32_t *tile,
+                               int32_t *field_npl, hipStream_t stream);
+
+/* The table's choice for the bucket of (prec, batched 0/1, grid side n_side,
+ * n_pot potentials): *tile, *field_npl (host), both 0 if the table has none. */
+int lens_autotune_lookup(lens_ctx *ctx, lens_precision prec, int32_t batched, int32_t n_side, int32_t n_pot,
+                         int32_t *tile, int32_t *field_npl);
+
+/* Writes the table as JSON (through a temporary file renamed into place);
+ * LENS_ERR_INVALID if it cannot be written. */
+int lens_autotune_save(lens_ctx *ctx, const char *path);
+
+/* Merges a JSON table written by lens_autotune_save (an entry replaces the
+ * one of its bucket).  LENS_ERR_INVALID for a missing or malformed file, which
+ * leaves the table unchanged. */
+int lens_autotune_load(lens_ctx *ctx, const char *path);
 
 /* ---------------------------------------------------------------- backward form
  *

@@ -14,6 +14,7 @@ from __future__ import annotations
 
 import ctypes as C
 import dataclasses
+import os
 
 import torch
 
@@ -209,11 +210,19 @@ def lens_image_chi2(params: torch.Tensor, grid, obs: Obs, prec: str = "mixed", f
     out = out or chi2_buffers(obs, hit_capacity, params.device)
     opts = L.LensChi2Opts(_PREC[prec], int(fb_mode), float(fb_tau), int(out.hits.shape[0]), int(field_npl),
                           int(tile))
-    co = L.LensChi2Out(out.chi2.data_ptr(), out.chi2_sys.data_ptr(), out.n_pred.data_ptr(), out.hits.data_ptr(),
-                       out.img_xy.data_ptr(), out.match.data_ptr(), out.stats.data_ptr())
     L.check(ctx._lib.lens_image_chi2(ctx.handle, C.byref(p), C.byref(_grid(grid)), C.byref(o), C.byref(opts),
-                                     C.byref(co), ctx.stream()), "lens_image_chi2")
+                                     C.byref(_chi2_out(out)), ctx.stream()), "lens_image_chi2")
     return out
+
+
+def _chi2_out(out: Chi2Result):
+    return L.LensChi2Out(out.chi2.data_ptr(), out.chi2_sys.data_ptr(), out.n_pred.data_ptr(), out.hits.data_ptr(),
+                         out.img_xy.data_ptr(), out.match.data_ptr(), out.stats.data_ptr())
+
+
+def _batch_out(out: "BatchResult"):
+    return L.LensBatchOut(out.chi2.data_ptr(), out.chi2_sys.data_ptr(), out.n_pred.data_ptr(),
+                          out.status.data_ptr(), out.stats.data_ptr())
 
 
 class BatchLayout:
@@ -257,12 +266,68 @@ def lens_image_chi2_batched(params: torch.Tensor, layout: BatchLayout, obs: Obs,
     p, o = _pots(params), _obs(obs)
     out = out or batch_buffers(layout.n, obs, params.device)
     opts = L.LensChi2Opts(_PREC[prec], int(fb_mode), float(fb_tau), int(hit_capacity), int(field_npl), int(tile))
-    bo = L.LensBatchOut(out.chi2.data_ptr(), out.chi2_sys.data_ptr(), out.n_pred.data_ptr(), out.status.data_ptr(),
-                        out.stats.data_ptr())
     L.check(ctx._lib.lens_image_chi2_batched(ctx.handle, C.byref(p), layout.n, layout.pot_off, layout.grids,
-                                             C.byref(o), C.byref(opts), C.byref(bo), ctx.stream()),
+                                             C.byref(o), C.byref(opts), C.byref(_batch_out(out)), ctx.stream()),
             "lens_image_chi2_batched")
     return out
+
+
+# ---------------------------------------------------------------- autotuning
+
+def autotune_chi2(params: torch.Tensor, grid, obs: Obs, prec: str = "mixed", fb_mode: int = 0,
+                  fb_tau: float = 1e-6, hit_capacity: int = 4096, out: Chi2Result | None = None,
+                  ctx: Context | None = None, reps: int = 5):
+    """Times the tile shapes / FP32 field nodes per thread on this problem and
+    records the fastest in the context's table (synchronises the stream).
+    Returns (tile, field_npl, out); out holds the result of the chosen configuration."""
+    ctx = ctx or context(params.device.index)
+    if prec not in ("fp64", "mixed"):
+        raise ValueError("prec must be 'fp64' or 'mixed'")
+    p, o = _pots(params), _obs(obs)
+    out = out or chi2_buffers(obs, hit_capacity, params.device)
+    opts = L.LensChi2Opts(_PREC[prec], int(fb_mode), float(fb_tau), int(out.hits.shape[0]), 0, 0)
+    t, n = C.c_int32(), C.c_int32()
+    L.check(ctx._lib.lens_autotune_chi2(ctx.handle, C.byref(p), C.byref(_grid(grid)), C.byref(o), C.byref(opts),
+                                        C.byref(_chi2_out(out)), int(reps), C.byref(t), C.byref(n), ctx.stream()),
+            "lens_autotune_chi2")
+    return t.value, n.value, out
+
+
+def autotune_chi2_batched(params: torch.Tensor, layout: BatchLayout, obs: Obs, prec: str = "mixed",
+                          fb_mode: int = 0, fb_tau: float = 1e-6, hit_capacity: int = 1024,
+                          out: BatchResult | None = None, ctx: Context | None = None, reps: int = 3):
+    """autotune_chi2 for the batched form; returns (tile, field_npl, out)."""
+    ctx = ctx or context(params.device.index)
+    if prec not in ("fp64", "mixed"):
+        raise ValueError("prec must be 'fp64' or 'mixed'")
+    p, o = _pots(params), _obs(obs)
+    out = out or batch_buffers(layout.n, obs, params.device)
+    opts = L.LensChi2Opts(_PREC[prec], int(fb_mode), float(fb_tau), int(hit_capacity), 0, 0)
+    t, n = C.c_int32(), C.c_int32()
+    L.check(ctx._lib.lens_autotune_chi2_batched(ctx.handle, C.byref(p), layout.n, layout.pot_off, layout.grids,
+                                                C.byref(o), C.byref(opts), C.byref(_batch_out(out)), int(reps),
+                                                C.byref(t), C.byref(n), ctx.stream()),
+            "lens_autotune_chi2_batched")
+    return t.value, n.value, out
+
+
+def autotune_lookup(prec: str, batched: bool, n_side: int, n_pot: int, ctx: Context | None = None):
+    """The context table's (tile, field_npl) for a bucket; (0, 0) if none."""
+    ctx = ctx or context()
+    t, n = C.c_int32(), C.c_int32()
+    L.check(ctx._lib.lens_autotune_lookup(ctx.handle, _PREC[prec], int(bool(batched)), int(n_side), int(n_pot),
+                                          C.byref(t), C.byref(n)), "lens_autotune_lookup")
+    return t.value, n.value
+
+
+def autotune_save(path: str, ctx: Context | None = None):
+    ctx = ctx or context()
+    L.check(ctx._lib.lens_autotune_save(ctx.handle, os.fsencode(path)), "lens_autotune_save")
+
+
+def autotune_load(path: str, ctx: Context | None = None):
+    ctx = ctx or context()
+    L.check(ctx._lib.lens_autotune_load(ctx.handle, os.fsencode(path)), "lens_autotune_load")
 
 
 # ---------------------------------------------------------------- backward form

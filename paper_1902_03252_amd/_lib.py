@@ -21,7 +21,8 @@ STAT_N = 8
 
 EXPORTS = ("lens_create", "lens_destroy", "lens_dls_dos", "lens_deflect", "lens_source_positions",
            "lens_image_chi2", "lens_image_chi2_batched", "lens_deflect_backward", "lens_src_chi2",
-           "lens_src_chi2_backward", "lens_set_timing", "lens_field_timing", "lens_strerror")
+           "lens_src_chi2_backward", "lens_autotune_chi2", "lens_autotune_chi2_batched", "lens_autotune_lookup",
+           "lens_autotune_save", "lens_autotune_load", "lens_set_timing", "lens_field_timing", "lens_strerror")
 
 
 class LensPotentials(C.Structure):
@@ -89,6 +90,20 @@ def load(path: str = LIB_PATH):
     lib.lens_src_chi2.restype = C.c_int
     lib.lens_src_chi2_backward.argtypes = [vp, C.POINTER(LensPotentials), C.POINTER(LensObs), vp, vp, vp, vp]
     lib.lens_src_chi2_backward.restype = C.c_int
+    pi32 = C.POINTER(i32)
+    lib.lens_autotune_chi2.argtypes = [vp, C.POINTER(LensPotentials), C.POINTER(LensGrid), C.POINTER(LensObs),
+                                       C.POINTER(LensChi2Opts), C.POINTER(LensChi2Out), i32, pi32, pi32, vp]
+    lib.lens_autotune_chi2.restype = C.c_int
+    lib.lens_autotune_chi2_batched.argtypes = [vp, C.POINTER(LensPotentials), i32, pi32, C.POINTER(LensGrid),
+                                               C.POINTER(LensObs), C.POINTER(LensChi2Opts), C.POINTER(LensBatchOut),
+                                               i32, pi32, pi32, vp]
+    lib.lens_autotune_chi2_batched.restype = C.c_int
+    lib.lens_autotune_lookup.argtypes = [vp, C.c_int, i32, i32, i32, pi32, pi32]
+    lib.lens_autotune_lookup.restype = C.c_int
+    lib.lens_autotune_save.argtypes = [vp, C.c_char_p]
+    lib.lens_autotune_save.restype = C.c_int
+    lib.lens_autotune_load.argtypes = [vp, C.c_char_p]
+    lib.lens_autotune_load.restype = C.c_int
     lib.lens_set_timing.argtypes = [vp, C.c_int]
     lib.lens_set_timing.restype = C.c_int
     lib.lens_field_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]

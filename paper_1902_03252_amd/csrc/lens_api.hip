@@ -4,6 +4,7 @@
 #include "lens.h"
 #include "lens_device.hpp"
 #include "lens_internal.hpp"
+#include "lens_tune.hpp"
 
 #include <algorithm>
 #include <climits>
@@ -66,7 +67,12 @@ struct lens_ctx {
     double total_ms;
     long long launches;
     std::vector<PlanEntry*>* plans;  // batch plans, one per distinct shape class
+    TuneTable* tune;                 // autotuned tile shape / nodes per thread per bucket
 };
+
+TuneTable* lens_ctx_tune(lens_ctx* ctx) { return ctx ? ctx->tune : nullptr; }
+int lens_ctx_device(lens_ctx* ctx) { return ctx->device; }
+int lens_ctx_timing(lens_ctx* ctx) { return ctx->timing; }
 
 namespace {
 
@@ -191,6 +197,17 @@ int field_npl(const GridDesc& g)
     return 1;
 }
 
+// Fills a zero tile shape / nodes per thread from the autotuned table entry of
+// the call's bucket, when there is one.
+void resolve_tuned(lens_ctx* ctx, int prec, int batched, long long side, long long np, int& shape, int& npl)
+{
+    if (shape && npl) return;
+    int t = 0, n = 0;
+    if (!tune_lookup(ctx->tune, prec, batched, tune_log2(side), tune_log2(np), &t, &n)) return;
+    if (!shape) shape = t;
+    if (!npl) npl = n;
+}
+
 // Folds every recorded (start, stop) pair into the totals.
 int fold_timing(lens_ctx* c)
 {
@@ -276,10 +293,18 @@ int lens_create(lens_ctx** ctx, int device)
     if (!c) return LENS_ERR_DEVICE;
     c->device = device;
     c->plans = new (std::nothrow) std::vector<PlanEntry*>();
-    if (!c->plans) {
+    c->tune = tune_new();
+    if (!c->plans || !c->tune) {
+        delete c->plans;
+        tune_delete(c->tune);
         free(c);
         return LENS_ERR_DEVICE;
     }
+    // a missing or malformed cache file leaves the table empty
+    const char* cache = getenv("LENS_AUTOTUNE_CACHE");
+    hipDeviceProp_t prop;
+    if (cache && *cache && hipGetDeviceProperties(&prop, device) == hipSuccess)
+        (void)tune_load(c->tune, cache, prop.gcnArchName);
     *ctx = c;
     return LENS_OK;
 }
@@ -301,6 +326,7 @@ void lens_destroy(lens_ctx* ctx)
             delete ctx->plans;
         }
     }
+    tune_delete(ctx->tune);
     free(ctx);
 }
 
@@ -421,8 +447,10 @@ int lens_image_chi2(lens_ctx* ctx, const lens_potentials* pot, const lens_grid* 
     const bool mixed = opts->prec == LENS_MIXED;
     const size_t nn = (size_t)g.nx * g.ny;
     int rc;
-    const int shape = opts->tile ? opts->tile : 1;
-    const int npl = opts->field_npl ? opts->field_npl : field_npl(g);
+    int shape = opts->tile, npl = opts->field_npl;
+    resolve_tuned(ctx, opts->prec, 0, std::max(g.nx, g.ny), np, shape, npl);
+    if (!shape) shape = 1;
+    if (!npl) npl = field_npl(g);
     int tile_x, tile_y, tiles_x;
     tile_dims(shape, tile_x, tile_y);
     const int tx_shift = tile_x == 64 ? 6 : 5;
@@ -700,8 +728,12 @@ extern "C" int lens_image_chi2_batched(lens_ctx* ctx, const lens_potentials* all
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return LENS_ERR_DEVICE;
     const bool mixed = opts->prec == LENS_MIXED;
-    const int npl = mixed ? (opts->field_npl ? opts->field_npl : 2) : 1;
-    const int shape = opts->tile ? opts->tile : 1;
+    int shape = opts->tile, npl = opts->field_npl;
+    int side = 1;
+    for (int i = 0; i < n_samples; i++) side = std::max(side, std::max(grids[i].nx, grids[i].ny));
+    resolve_tuned(ctx, opts->prec, 1, side, ((long long)all->n + n_samples - 1) / n_samples, shape, npl);
+    if (!shape) shape = 1;
+    npl = mixed ? (npl ? npl : 2) : 1;
     PlanEntry* plan = nullptr;
     int rc = batch_plan(ctx, n_samples, pot_off, grids, npl, shape, mixed, stream, &plan);
     if (rc) return rc;
