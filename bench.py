@@ -33,9 +33,10 @@ PEAK_FP64_TFLOPS = 78.6    # MI355X FP64 vector peak
 FLOPS_PER_EVAL = 34        # flops of one cored/cut pixel-potential evaluation, counted on the formula
                            # (+,-,x = 1, fma = 2, sqrt = 1, div = 1): translate 2, rotate 6, R^2 5,
                            # two square roots 4, f 5, lens-frame gradient 4, rotate back + sum 8
-FLOPS_PER_VJP = 107        # flops of one cored/cut (node, potential) term of the deflection VJP, counted on the
-                           # formula as above: offsets and R^2 9, square roots and reciprocals 5 + 9, f and F' 11,
-                           # df/da, df/ds 3, g.m, Kf, KF' 5, x/y rows 18, eps/Phi rows 34, a/s/sigma rows 13
+FLOPS_PER_VJP = 78         # flops of one cored/cut (node, potential) term of the deflection VJP in its factored
+                           # form (seven node sums, per-potential constants applied once), counted as above:
+                           # m and R^2 9, square roots 4, reciprocals 1/(A_ B_ S), 1/qa, 1/qs and f 13,
+                           # F' 11, df/da, df/ds 4, g.m and F'(g.m) 5, the seven sums 32
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_field32_cluster.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1902_03252_amd", "csrc", f)
                   for f in ("lens_kernels.hip", "lens_path.hpp", "lens_device.hpp")]
@@ -57,9 +58,10 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_per_launch():
+def traffic_per_launch(npl: int):
     """HBM bytes per launch of the field kernel from the committed rocprofv3 PMC
-    summary, or None when it was taken on a different kernel source."""
+    summary, or None when it was taken on a different kernel source or nodes
+    per thread."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
@@ -67,12 +69,25 @@ def traffic_per_launch():
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_sha256_16") != kernel_hash():
+    if kv.get("kernel_source_sha256_16") != kernel_hash() or kv.get("field_npl") != str(npl):
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def field_npl_used(lens, ctx, grid, n_pot: int) -> int:
+    """Nodes per thread of the FP32 field in an untuned-options mixed call: the
+    context's autotuned choice, else the library's default rule."""
+    _, npl = lens.autotune_lookup("mixed", False, max(grid.nx, grid.ny), n_pot, ctx=ctx)
+    if npl:
+        return npl
+    env = os.environ.get("LENS_FIELD_NPL")
+    if env in ("1", "2", "4", "8"):
+        return int(env)
+    nodes = grid.nx * grid.ny
+    return 4 if nodes >= 8 << 20 else 2 if nodes >= 1 << 20 else 1
 
 
 def time_steps(torch, fn, steps, warmup):
@@ -86,18 +101,34 @@ def time_steps(torch, fn, steps, warmup):
     return (time.perf_counter() - t0) / steps
 
 
+def autotune(args, lens, ctx, prec, batched, grid, n_pot, tune):
+    """Tunes a bucket the context's table does not hold yet (with --autotune);
+    returns the (tile, field_npl) the timed calls use, (0, 0) for the defaults."""
+    side = max(grid.nx, grid.ny)
+    if args.autotune and lens.autotune_lookup(prec, batched, side, n_pot, ctx=ctx) == (0, 0):
+        tune()
+    return lens.autotune_lookup(prec, batched, side, n_pot, ctx=ctx)
+
+
 def gpu_bench(args):
     import torch
     import paper_1902_03252_amd as lens
 
     ctx = lens.context(0)
+    if args.tune_cache and os.path.exists(args.tune_cache):
+        lens.autotune_load(args.tune_cache, ctx=ctx)
     prm, grid, obs_np = load_workload(2)
     p = torch.as_tensor(prm, dtype=torch.float64, device="cuda")
     obs = lens.Obs.from_numpy(obs_np)
     n_tri = grid.n_triangles
     res = {}
+    tuned = {}
     for prec in ("mixed", "fp64"):
         out = lens.chi2_buffers(obs, 4096, "cuda")
+        # records this bucket's fastest tile shape / nodes per thread in the context
+        tuned[f"cluster_{prec}"] = autotune(args, lens, ctx, prec, False, grid, prm.shape[1],
+                                            lambda: lens.autotune_chi2(p, grid, obs, prec=prec, out=out, ctx=ctx,
+                                                                       reps=5))
         step = lambda: lens.lens_image_chi2(p, grid, obs, prec=prec, out=out, ctx=ctx)
         # eager, with the field kernel bracketed by HIP events on the call's stream
         ctx.set_timing(True)
@@ -129,6 +160,9 @@ def gpu_bench(args):
     obs3 = lens.Obs.from_numpy(obs3_np)
     for prec in ("mixed", "fp64"):
         out = lens.chi2_buffers(obs3, 4096, "cuda")
+        tuned[f"large_{prec}"] = autotune(args, lens, ctx, prec, False, grid3, prm3.shape[1],
+                                          lambda: lens.autotune_chi2(p3, grid3, obs3, prec=prec, out=out, ctx=ctx,
+                                                                     reps=3))
         ctx.set_timing(True)
         ctx.field_timing(reset=True)
         dt = time_steps(torch, lambda: lens.lens_image_chi2(p3, grid3, obs3, prec=prec, out=out, ctx=ctx),
@@ -146,9 +180,11 @@ def gpu_bench(args):
                            flagged_tests=int(st[1]), fallback_rate=float(st[1]) / float(st[6]),
                            hits=int(st[0]))
     large["speedup_mixed_vs_fp64"] = large["fp64"]["ms_per_eval"] / large["mixed"]["ms_per_eval"]
-    batched = batched_bench(torch, lens, ctx, obs, obs_np, args) if args.batch > 0 else None
+    batched = batched_bench(torch, lens, ctx, obs, obs_np, args, tuned) if args.batch > 0 else None
     backward = backward_bench(torch, lens, ctx, obs, args) if args.backward else None
-    return prm, grid, obs_np, n_tri, res, large, batched, backward
+    if args.tune_cache:
+        lens.autotune_save(args.tune_cache, ctx=ctx)
+    return prm, grid, obs_np, n_tri, res, large, batched, backward, tuned
 
 
 def backward_bench(torch, lens, ctx, obs, args):
@@ -181,7 +217,7 @@ def backward_bench(torch, lens, ctx, obs, args):
     return out
 
 
-def batched_bench(torch, lens, ctx, obs, obs_np, args):
+def batched_bench(torch, lens, ctx, obs, obs_np, args, tuned):
     """A sampler's batch: n lens models with P ~ U{10..200} potentials and grid
     sides drawn from {256, 512, 1024, 2048} over +-80", evaluated by one batched
     call, captured into a HIP graph and replayed."""
@@ -196,6 +232,11 @@ def batched_bench(torch, lens, ctx, obs, obs_np, args):
     out_res = {}
     for prec in ("mixed", "fp64"):
         out = lens.batch_buffers(layout.n, obs, "cuda")
+        side = max(max(g.nx, g.ny) for g in grids)
+        tuned[f"batched_{prec}"] = autotune(args, lens, ctx, prec, True, S.Grid(0.0, 0.0, 1.0, side, side),
+                                            -(-params.shape[1] // len(grids)),
+                                            lambda: lens.autotune_chi2_batched(p, layout, obs, prec=prec, out=out,
+                                                                               ctx=ctx, reps=2))
         step = lambda: lens.lens_image_chi2_batched(p, layout, obs, prec=prec, out=out, ctx=ctx)
         ctx.set_timing(True)
         step()  # builds and caches the plan
@@ -256,6 +297,11 @@ def main():
     ap.add_argument("--batch", type=int, default=1024, help="samples of the batched leg (0 skips it)")
     ap.add_argument("--batch-steps", type=int, default=5, help="timed replays of the batched leg")
     ap.add_argument("--no-backward", dest="backward", action="store_false", help="skip the backward leg")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="time the default tile shape / nodes per thread instead of the autotuned ones")
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotune table (JSON) merged before tuning and written at the end; buckets it holds "
+                         "are not tuned again")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 256 MiB device-to-device 3 times (a known-size kernel that calibrates the "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
@@ -273,14 +319,16 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    prm, grid, obs_np, n_tri, res, large, batched, backward = gpu_bench(args)
+    prm, grid, obs_np, n_tri, res, large, batched, backward, tuned = gpu_bench(args)
     mixed, fp64 = res["mixed"], res["fp64"]
     step_s = mixed["graph_s"]
     evals = grid.nx * grid.ny * prm.shape[1]
     flops = FLOPS_PER_EVAL * evals
     kern_s = mixed["kern_ms"] / 1e3
     achieved = flops / kern_s / 1e12
-    traffic = traffic_per_launch()
+    import paper_1902_03252_amd as lens
+    npl = field_npl_used(lens, lens.context(0), grid, prm.shape[1])
+    traffic = traffic_per_launch(npl)
 
     cpu, want = (None, None) if args.no_cpu else cpu_baseline(prm, grid, obs_np, args.cpu_budget)
     parity = None
@@ -319,13 +367,14 @@ def main():
         "graph_replay_matches_eager": mixed["graph_matches_eager"] and fp64["graph_matches_eager"],
         "fallback": {"flagged_tests": int(st[1]), "tests": int(st[6]), "rate": float(st[1]) / float(st[6]),
                      "fallback_hits": int(st[5]), "hits": int(st[0])},
-        "roofline": {"bound": "alu", "kernel": "k_field32 (FP32 deflection field)",
+        "roofline": {"bound": "alu", "kernel": f"k_field32<{npl}> (FP32 deflection field)",
                      "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
                      "flops_per_launch": flops, "avg_launch_ms": mixed["kern_ms"], "launches_timed": mixed["launches"]},
         "large": large,
         "batched": batched,
         "backward": backward,
+        "autotuned": {k: {"tile": t, "field_npl": n} for k, (t, n) in tuned.items() if t} or None,
         "cpu_baseline": cpu,
         "parity": parity,
     }

@@ -209,10 +209,12 @@ int lens_image_chi2_batched(lens_ctx *ctx, const lens_potentials *all, int32_t n
  * parses (otherwise the table starts empty).  Entries carry the GPU
  * architecture (e.g. gfx950); a file written on another one adds nothing. */
 
-/* Times every candidate on the caller's problem -- the nodes per thread 1, 2,
- * 4, 8 (MIXED only) with tile shape 1, then the other tile shapes with the
- * fastest of those -- each by one warm-up and `reps` (1..100) timed calls
- * (median, HIP events on `stream`), records the fastest in the table and
+/* Times the candidates on the caller's problem -- the default configuration
+ * first, then the other nodes per thread 1, 2, 4, 8 (MIXED only) with tile
+ * shape 1, then the other tile shapes with the best of those -- each by one
+ * warm-up and `reps` (1..100) timed calls (median, HIP events on `stream`).  A
+ * candidate replaces the best so far only when it is more than 2 % faster
+ * (timing noise keeps the default).  Records the choice in the table and
  * leaves `out` holding the result of one more call with it.  opts->tile and
  * opts->field_npl are ignored; a candidate whose scratch bound is exceeded
  * (LENS_ERR_CAPACITY) is skipped.  Synchronises `stream` (not capturable).

@@ -280,6 +280,14 @@ ObsPtrs no_obs()
 
 }  // namespace
 
+int lens_default_field_npl(int nx, int ny)
+{
+    GridDesc g{};
+    g.nx = nx;
+    g.ny = ny;
+    return field_npl(g);
+}
+
 extern "C" {
 
 int lens_create(lens_ctx** ctx, int device)

@@ -323,11 +323,16 @@ int time_call(Call call, int reps, hipStream_t s, hipEvent_t a, hipEvent_t b, do
     return LENS_OK;
 }
 
-// Tries the nodes per thread (mixed only) with the default tile, then every
-// tile shape with the best nodes per thread; records and returns the fastest.
+// Tries the default configuration first, then the other nodes per thread
+// (mixed only) with the default tile, then the other tile shapes with the
+// best nodes per thread.  A candidate replaces the best so far only when it is
+// faster by more than kMargin, so timing noise leaves the default in place;
+// records and returns the choice.
+constexpr double kMargin = 0.02;
+
 template <typename Run>
-int tune(lens_ctx* ctx, int prec, int batched, int n_log2, int p_log2, int reps, hipStream_t s, Run run,
-         int32_t* tile_out, int32_t* npl_out)
+int tune(lens_ctx* ctx, int prec, int batched, int n_log2, int p_log2, int default_npl, int reps, hipStream_t s,
+         Run run, int32_t* tile_out, int32_t* npl_out)
 {
     if (reps < 1 || reps > 100) return LENS_ERR_INVALID;
     TuneTable* table = lens_ctx_tune(ctx);
@@ -340,7 +345,8 @@ int tune(lens_ctx* ctx, int prec, int batched, int n_log2, int p_log2, int reps,
     hipEvent_t a = nullptr, b = nullptr;
     int rc = LENS_OK;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) rc = LENS_ERR_DEVICE;
-    int best_tile = 1, best_npl = 0;
+    const bool mixed = prec == LENS_MIXED;
+    int best_tile = 1, best_npl = mixed ? default_npl : 0;
     double best = INFINITY;
     auto trial = [&](int tile, int npl) {
         if (rc) return;
@@ -351,20 +357,20 @@ int tune(lens_ctx* ctx, int prec, int batched, int n_log2, int p_log2, int reps,
             rc = r;
             return;
         }
-        if (ms < best) {
+        if (ms < best * (1.0 - kMargin)) {
             best = ms;
             best_tile = tile;
             best_npl = npl;
         }
     };
-    if (prec == LENS_MIXED) {
+    trial(best_tile, best_npl);
+    if (mixed) {
         const int npls[4] = {1, 2, 4, 8};
-        for (int k = 0; k < (batched ? 3 : 4); k++) trial(1, npls[k]);
-        const int npl = best_npl;
-        for (int tile = 2; tile <= 4; tile++) trial(tile, npl);
-    } else {
-        for (int tile = 1; tile <= 4; tile++) trial(tile, 0);
+        for (int k = 0; k < (batched ? 3 : 4); k++)
+            if (npls[k] != default_npl) trial(1, npls[k]);
     }
+    const int npl = best_npl;
+    for (int tile = 2; tile <= 4; tile++) trial(tile, npl);
     if (!rc && !std::isfinite(best)) rc = LENS_ERR_CAPACITY;
     if (!rc) {
         record(table, TuneEntry{prec, batched, n_log2, p_log2, best_tile, best_npl, best});
@@ -402,7 +408,8 @@ int lens_autotune_chi2(lens_ctx* ctx, const lens_potentials* pot, const lens_gri
             o.field_npl = npl;
             return lens_image_chi2(ctx, pot, grid, obs, &o, out, stream);
         };
-        return tune(ctx, opts->prec, 0, n_log2, p_log2, reps, stream, run, tile, field_npl);
+        return tune(ctx, opts->prec, 0, n_log2, p_log2, lens_default_field_npl(grid->nx, grid->ny), reps, stream, run,
+                    tile, field_npl);
     } catch (...) {
         return LENS_ERR_DEVICE;
     }
@@ -424,7 +431,7 @@ int lens_autotune_chi2_batched(lens_ctx* ctx, const lens_potentials* all, int32_
             o.field_npl = npl;
             return lens_image_chi2_batched(ctx, all, n_samples, pot_off, grids, obs, &o, out, stream);
         };
-        return tune(ctx, opts->prec, 1, tune_log2(side), tune_log2(mean_p), reps, stream, run, tile, field_npl);
+        return tune(ctx, opts->prec, 1, tune_log2(side), tune_log2(mean_p), 2, reps, stream, run, tile, field_npl);
     } catch (...) {
         return LENS_ERR_DEVICE;
     }

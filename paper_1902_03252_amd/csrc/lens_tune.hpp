@@ -31,3 +31,4 @@ int tune_load(TuneTable* t, const char* path, const char* arch);
 lens::TuneTable* lens_ctx_tune(lens_ctx* ctx);
 int lens_ctx_device(lens_ctx* ctx);
 int lens_ctx_timing(lens_ctx* ctx);  // whether field-kernel timing is on
+int lens_default_field_npl(int nx, int ny);  // FP32 field nodes per thread of an untuned single call
