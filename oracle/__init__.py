@@ -72,6 +72,9 @@ def _load():
         lib.orc_src_chi2.argtypes = [dp, i, i, ip, dp, dp, dp, dp]
         lib.orc_src_chi2_grad.argtypes = [dp, i, i, ip, dp, dp, dp, dp, dp]
         lib.orc_alpha_vjp.argtypes = [dp, i, d, d, d, i, i, dp, dp, dp, i, i]
+        u8p = C.POINTER(C.c_uint8)
+        lib.orc_dp_patches.argtypes = [dp, i, i, i, i, d, d, d, i, i, u8p]
+        lib.orc_criteria.argtypes = [dp, dp, i, i, d, d, d, u8p]
         _lib = lib
     return _lib
 
@@ -310,3 +313,32 @@ def alpha_vjp(prm, grid, gx, gy, nthreads: int | None = None, absolute: bool = F
     _load().orc_alpha_vjp(pp, n, grid.x0, grid.y0, grid.h, grid.nx, grid.ny, gxp, gyp, _d(g)[1],
                           nthreads or default_threads(), int(bool(absolute)))
     return g
+
+
+# ---------------------------------------------------------------- the paper's mixed-precision gradient
+
+PATCH_CLUSTER, PATCH_GALAXY = 400, 20   # Sec. 3.2 / Appendix A.3, pixels
+T12, T34 = 0.0092, 0.0104               # Sec. 3.3 thresholds for 0.03 arcsec pixels, arcsec
+
+
+def _u8(shape):
+    a = np.zeros(shape, dtype=np.uint8)
+    return a, a.ctypes.data_as(C.POINTER(C.c_uint8))
+
+
+def dp_patches(prm, grid, n_cluster: int, pc: int = PATCH_CLUSTER, pg: int = PATCH_GALAXY):
+    """uint8 [ny, nx]: 1 inside the double-precision block of some halo."""
+    prm, pp, n = _prm(prm)
+    m, mp = _u8((grid.ny, grid.nx))
+    _load().orc_dp_patches(pp, n, int(n_cluster), int(pc), int(pg), grid.x0, grid.y0, grid.h, grid.nx, grid.ny, mp)
+    return m
+
+
+def criteria(ax, ay, dx: float, t12: float = T12, t34: float = T34):
+    """uint8 [ny, nx]: 1 where the criteria of Sec. 3.3 ask for double precision."""
+    ax, axp = _d(ax)
+    ay, ayp = _d(ay)
+    ny, nx = ax.shape
+    f, fp = _u8((ny, nx))
+    _load().orc_criteria(axp, ayp, nx, ny, float(dx), float(t12), float(t34), fp)
+    return f

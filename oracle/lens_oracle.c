@@ -814,3 +814,62 @@ void orc_alpha_vjp(const double *prm, int np, double x0, double y0, double h, in
     }
     free(jobs);
 }
+
+/* ----------------------------------------------------------------------- */
+/* The paper's mixed-precision gradient (Sec. 3.2, Sec. 3.3, Appendix A.3) */
+/* ----------------------------------------------------------------------- */
+
+/* Double-precision patches (Sec. 3.2, Appendix A.3): a block of pc x pc pixels
+ * centred on each of the first n_cluster potentials (the cluster-scale halos)
+ * and of pg x pg pixels centred on every other potential (galaxy-scale halos).
+ * READING: the block centred on a halo spans node indices [k - p/2, k - p/2 + p)
+ * along each axis, k = the node nearest the centre, (x_c - x0)/h rounded with
+ * halves away from zero; blocks are clipped to the grid.  mask[j*nx + i] = 1
+ * inside any block, 0 elsewhere. */
+void orc_dp_patches(const double *prm, int np, int n_cluster, int pc, int pg, double x0, double y0, double h,
+                    int nx, int ny, uint8_t *mask)
+{
+    memset(mask, 0, (size_t)nx * ny);
+    for (int p = 0; p < np; p++) {
+        long size = p < n_cluster ? pc : pg;
+        long ki = lround((prm[p] - x0) / h), kj = lround((prm[np + p] - y0) / h);
+        long i0 = ki - size / 2, j0 = kj - size / 2;
+        for (long j = j0; j < j0 + size; j++) {
+            if (j < 0 || j >= ny) continue;
+            for (long i = i0; i < i0 + size; i++) {
+                if (i < 0 || i >= nx) continue;
+                mask[(size_t)j * nx + i] = 1;
+            }
+        }
+    }
+}
+
+/* The criteria of Sec. 3.3 on a gradient field (ax, ay) whose pixels have
+ * length dx along both axes:
+ *     d1 = ax(i, j) - ax(i-1, j),   d2 = ay(i, j) - ay(i, j-1),
+ *     d3 = ax(i, j) - ax(i, j-1),   d4 = ay(i, j) - ay(i-1, j),
+ * pixel (i, j) needs double precision when |dx - d1| < t12 or |dx - d2| < t12
+ * (the source-plane pixel length below t12, eq. Criterion_delta_1_2) or
+ * |d3| > t34 or |d4| > t34 (eq. Criterion_delta_3_4).  READING: a difference
+ * whose neighbour lies outside the image (i = 0 for d1 and d4, j = 0 for d2 and
+ * d3) is not evaluated.  flags[j*nx + i] = 1 for such pixels, else 0. */
+void orc_criteria(const double *ax, const double *ay, int nx, int ny, double dx, double t12, double t34,
+                  uint8_t *flags)
+{
+    for (int j = 0; j < ny; j++)
+        for (int i = 0; i < nx; i++) {
+            size_t n = (size_t)j * nx + i;
+            int need = 0;
+            if (i > 0) {
+                double d1 = ax[n] - ax[n - 1];
+                double d4 = ay[n] - ay[n - 1];
+                if (fabs(dx - d1) < t12 || fabs(d4) > t34) need = 1;
+            }
+            if (j > 0) {
+                double d2 = ay[n] - ay[n - nx];
+                double d3 = ax[n] - ax[n - nx];
+                if (fabs(dx - d2) < t12 || fabs(d3) > t34) need = 1;
+            }
+            flags[n] = (uint8_t)need;
+        }
+}

@@ -225,3 +225,42 @@ def batch_samples(n_samples: int = 1024, base: np.ndarray | None = None, seed_st
 def cotangent(n_nodes: int, seed_stream: int = 5) -> np.ndarray:
     """Seeded N(0,1) cotangent for the deflection-field backward pass, shape [2, n_nodes]."""
     return rng(5, seed_stream).normal(0.0, 1.0, (2, n_nodes))
+
+
+# --------------------------------------------------------------------------
+# the paper's benchmark lens (Sec. 4): SIE halos on an HST ACS-like image
+# --------------------------------------------------------------------------
+
+PAPER_PIXEL = 0.03  # arcsec per pixel (Sec. 3.2, Sec. 4)
+PAPER_SIDE = 6730   # pixels per side (Sec. 4)
+PAPER_GALAXIES = 700
+
+
+def paper_grid(n: int = PAPER_SIDE, h: float = PAPER_PIXEL, ny: int | None = None) -> Grid:
+    """n x ny nodes of spacing h centred on the origin (reading: one node per pixel)."""
+    ny = n if ny is None else ny
+    return Grid(-0.5 * (n - 1) * h, -0.5 * (ny - 1) * h, h, n, ny)
+
+
+def paper_sie_cluster(grid: Grid, n_galaxies: int = PAPER_GALAXIES, seed: int = 0) -> np.ndarray:
+    """Two cluster-scale SIE halos (sigma_v 1000 and 700 km/s, eps 0.05 and
+    0.04) followed by n_galaxies galaxy-scale SIE halos (sigma_v ~ U[10, 15]
+    km/s, eps ~ U[0, 0.15]), Sec. 4.  Readings (the paper gives no positions
+    or angles): the two halos at (-0.2, -0.1) and (0.25, 0.15) times the grid's
+    half widths, at position angles 0.5 and 2.0 rad; galaxies uniform over the
+    grid with phi ~ U[0, pi)."""
+    g = np.random.Generator(np.random.PCG64([SEED_BASE, 200 + seed]))
+    lx, ly = 0.5 * (grid.nx - 1) * grid.h, 0.5 * (grid.ny - 1) * grid.h
+    cx, cy = grid.x0 + lx, grid.y0 + ly
+    prm = _empty(2 + n_galaxies)
+    prm[:, 0] = (cx - 0.2 * lx, cy - 0.1 * ly, 0.05, 0.5, 0.0, np.inf, 1000.0)
+    prm[:, 1] = (cx + 0.25 * lx, cy + 0.15 * ly, 0.04, 2.0, 0.0, np.inf, 700.0)
+    n = n_galaxies
+    prm[0, 2:] = g.uniform(cx - lx, cx + lx, n)
+    prm[1, 2:] = g.uniform(cy - ly, cy + ly, n)
+    prm[2, 2:] = g.uniform(0.0, 0.15, n)
+    prm[3, 2:] = g.uniform(0.0, math.pi, n)
+    prm[4, 2:] = 0.0
+    prm[5, 2:] = np.inf
+    prm[6, 2:] = g.uniform(10.0, 15.0, n)
+    return prm

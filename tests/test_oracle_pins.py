@@ -458,3 +458,81 @@ def _small_cluster():
     xs = g.uniform(-20, 20, (6, 2))
     obs = dict(sys_off=np.array([0, 3, 6], np.int32), x=xs[:, 0], y=xs[:, 1], sigma=np.full(6, 0.1), dls=r)
     return prm, grid, obs
+
+
+# --------------------------------------------------------------- the paper's mixed-precision gradient
+
+def test_dp_patches_block_geometry():
+    """Blocks of Sec. 3.2 / Appendix A.3 by hand-counted integer geometry: an
+    interior block has p^2 pixels spanning [k - p/2, k - p/2 + p); halves round
+    away from zero; blocks clip at the grid edge; overlapping blocks count once;
+    only the first n_cluster halos get the large block.  Catches an off-by-one
+    in the span, a round-half-even centre, a missing clip or a swapped axis."""
+    g = S.Grid(0.0, 0.0, 0.5, 120, 90)
+    # (5.25 - 0)/0.5 = 10.5 -> 11; (7.0)/0.5 = 14
+    m = oracle.dp_patches(pot(x=5.25, y=7.0), g, 0, 400, 20)
+    rows, cols = np.nonzero(m)
+    assert m.sum() == 400
+    assert (cols.min(), cols.max(), rows.min(), rows.max()) == (1, 20, 4, 23)
+    # -1.25/0.5 = -2.5 -> -3: columns [-13, 7) clipped to [0, 7)
+    m = oracle.dp_patches(pot(x=-1.25, y=20.0), g, 0, 400, 20)
+    rows, cols = np.nonzero(m)
+    assert (cols.min(), cols.max(), rows.min(), rows.max()) == (0, 6, 30, 49) and m.sum() == 7 * 20
+    # two galaxy blocks at nodes (50, 40) and (60, 45): 400 + 400 - 10 * 15
+    two = np.concatenate([pot(x=25.0, y=20.0), pot(x=30.0, y=22.5)], axis=1)
+    assert oracle.dp_patches(two, g, 0, 400, 20).sum() == 650
+    # the first potential is cluster-scale: a 30 x 30 block (clipped at y = 89) plus a 20 x 20 one
+    m = oracle.dp_patches(two, g, 1, 30, 20)
+    big = (np.arange(35, 65), np.arange(25, 55))
+    assert m[np.ix_(big[1], big[0])].all()
+    assert m.sum() == 30 * 30 + 20 * 20 - len(range(50, 65)) * len(range(35, 55))
+
+
+def test_criteria_sis_axis_closed_form():
+    """Criteria of Sec. 3.3 on the oracle's own SIS field, along the row through
+    the centre, against their closed forms: with R = (i - ic) h and the
+    neighbour row one pixel below, d1 = d4 = 0, d2 = b0 h / sqrt(R^2 + h^2)
+    (the tangential stretch that vanishes on the Einstein ring) and
+    d3 = b0 (1 - R / sqrt(R^2 + h^2)).  Catches a swapped difference direction
+    (i+1 for i-1), d2 and d3 exchanged, a wrong threshold comparison (<= vs >,
+    |d| vs d) or an axis mix-up."""
+    h, b0 = 0.03, oracle.b0(1000.0)
+    ic, nx = 20, 1500
+    g = S.Grid(-ic * h, -h, h, nx, 3)  # centre at node (20, 1)
+    ax, ay = oracle.alpha_grid(pot(sig=1000.0), g, nthreads=2)
+    f = oracle.criteria(ax, ay, h)
+    R = (np.arange(ic + 2, nx) - ic) * h
+    q = np.sqrt(R * R + h * h)
+    d2 = b0 * h / q
+    d3 = b0 * (1.0 - R / q)
+    a = np.abs(h - d2) - oracle.T12
+    b = d3 - oracle.T34
+    want = (a < 0) | (b > 0)
+    clear = (np.abs(a) > 1e-9) & (np.abs(b) > 1e-9)
+    got = f[1, ic + 2:].astype(bool)
+    assert clear.sum() > 1000
+    np.testing.assert_array_equal(got[clear], want[clear])
+    # both bands are present: the core (d3) and the Einstein ring (d2, b0 = 28.8")
+    assert want[R < 1.0].all() and not want[(R > 2.0) & (R < 20.0)].any() and want[np.abs(R - b0) < 1.0].all()
+
+
+def test_criteria_edges_and_linear_fields():
+    """Fields whose differences are constant: a flag appears exactly where the
+    difference is evaluated, never on the first column (d1, d4) or first row
+    (d2, d3) of the image.  Catches a wrap-around neighbour or an evaluated edge."""
+    h = 0.03
+    i = np.arange(40)[None, :] * np.ones((30, 1))
+    j = np.arange(30)[:, None] * np.ones((1, 40))
+    zero = np.zeros((30, 40))
+    f = oracle.criteria((h - 0.001) * i, zero, h)          # |h - d1| = 0.001
+    np.testing.assert_array_equal(f, (i >= 1).astype(np.uint8))
+    f = oracle.criteria(zero, (h - 0.001) * j, h)          # |h - d2| = 0.001
+    np.testing.assert_array_equal(f, (j >= 1).astype(np.uint8))
+    f = oracle.criteria(0.02 * j, zero, h)                 # d3 = 0.02 > 0.0104
+    np.testing.assert_array_equal(f, (j >= 1).astype(np.uint8))
+    f = oracle.criteria(zero, -0.02 * i, h)                # |d4| = 0.02
+    np.testing.assert_array_equal(f, (i >= 1).astype(np.uint8))
+    f = oracle.criteria(0.005 * j, 0.005 * j, h)           # source pixels h long, |d3| < t34: nothing
+    assert f.sum() == 0
+    f = oracle.criteria(h * i, zero, h)                    # d1 = h: source pixel of length 0
+    np.testing.assert_array_equal(f, (i >= 1).astype(np.uint8))
