@@ -30,6 +30,10 @@ sys.path.insert(0, ROOT)
 METRIC = "image-plane χ² evals/sec and grid triangles/s, mixed vs FP64, 1 MI355X"
 PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector peak
 PEAK_FP64_TFLOPS = 78.6    # MI355X FP64 vector peak
+FLOPS_PER_SIE = 26         # flops of one SIE pixel-potential evaluation (Algorithm 1, cos/sin hoisted)
+# The paper's runtimes for its benchmark (Table 2): seconds, (double precision, mixed precision)
+PAPER_TABLE2_S = {"Xeon E5-2680 v3, 12 cores": (8.1, 7.40), "GTX 1080 Ti (+Xeon)": (6.8, 1.58),
+                  "P100 (+Xeon)": (0.71, 0.58), "V100 (+Xeon)": (0.46, 0.39)}
 FLOPS_PER_EVAL = 34        # flops of one cored/cut pixel-potential evaluation, counted on the formula
                            # (+,-,x = 1, fma = 2, sqrt = 1, div = 1): translate 2, rotate 6, R^2 5,
                            # two square roots 4, f 5, lens-frame gradient 4, rotate back + sum 8
@@ -181,10 +185,50 @@ def gpu_bench(args):
                            hits=int(st[0]))
     large["speedup_mixed_vs_fp64"] = large["fp64"]["ms_per_eval"] / large["mixed"]["ms_per_eval"]
     batched = batched_bench(torch, lens, ctx, obs, obs_np, args, tuned) if args.batch > 0 else None
+    paper = paper_bench(torch, lens, ctx, args) if args.paper else None
     backward = backward_bench(torch, lens, ctx, obs, args) if args.backward else None
     if args.tune_cache:
         lens.autotune_save(args.tune_cache, ctx=ctx)
-    return prm, grid, obs_np, n_tri, res, large, batched, backward, tuned
+    return prm, grid, obs_np, n_tri, res, large, batched, backward, tuned, paper
+
+
+def paper_bench(torch, lens, ctx, args):
+    """The paper's own benchmark (Sec. 4, Table 2): grad Psi at every pixel of a
+    6730^2 HST ACS image (0.03 arcsec pixels) for 2 cluster-scale + 700
+    galaxy-scale SIE halos: the paper's mixed-precision gradient (FP32, FP64
+    blocks of 400^2 / 20^2 pixels, FP64 where the criteria of Sec. 3.3 hold),
+    and the pure FP64 and FP32 gradients, beside the paper's runtimes."""
+    import synthlens as S
+    grid = S.paper_grid()
+    prm = S.paper_sie_cluster(grid)
+    p = torch.as_tensor(prm, dtype=torch.float64, device="cuda")
+    evals = float(grid.nx * grid.ny * prm.shape[1])
+    out = lens.mixed_buffers(grid, "cuda")
+    legs = {"mixed": lambda: lens.lens_deflect_mixed(p, grid, 2, out=out, ctx=ctx),
+            "fp64": lambda: lens.lens_deflect(p, grid, "fp64", ctx=ctx, check=False),
+            "fp32": lambda: lens.lens_deflect(p, grid, "fp32", ctx=ctx, check=False)}
+    res = {}
+    for name, step in legs.items():
+        ctx.set_timing(True)
+        ctx.field_timing(reset=True)
+        dt = time_steps(torch, step, 5, 2)
+        kms, nl = ctx.field_timing(reset=True)
+        ctx.set_timing(False)
+        res[name] = dict(ms=dt * 1e3, pixel_potential_evals_per_s=evals / dt,
+                         field_kernel_ms=kms / max(nl, 1))
+    st = out.stats.cpu().numpy()
+    assert st[3] == 0
+    n = grid.nx * grid.ny
+    res["mixed"].update(fp64_block_px=int(st[0]), fp64_criteria_px=int(st[1]), fp64_fraction=float(st[2]) / n)
+    res["fp32"]["field_tflops"] = FLOPS_PER_SIE * evals / (res["fp32"]["field_kernel_ms"] / 1e3) / 1e12
+    res["fp64"]["field_tflops"] = FLOPS_PER_SIE * evals / (res["fp64"]["field_kernel_ms"] / 1e3) / 1e12
+    res["paper_table2_s"] = {k: {"dp": v[0], "mixed": v[1]} for k, v in PAPER_TABLE2_S.items()}
+    v100_dp, v100_mixed = PAPER_TABLE2_S["V100 (+Xeon)"]
+    res["speedup_vs_v100"] = {"mixed": v100_mixed / (res["mixed"]["ms"] / 1e3),
+                              "fp64": v100_dp / (res["fp64"]["ms"] / 1e3)}
+    res["workload"] = (f"{grid.nx}^2 pixels of {grid.h} arcsec, 2 + {prm.shape[1] - 2} SIE halos, "
+                       f"{evals:.3e} pixel-potential evaluations (Sec. 4); other hardware's times are context")
+    return res
 
 
 def backward_bench(torch, lens, ctx, obs, args):
@@ -297,6 +341,8 @@ def main():
     ap.add_argument("--batch", type=int, default=1024, help="samples of the batched leg (0 skips it)")
     ap.add_argument("--batch-steps", type=int, default=5, help="timed replays of the batched leg")
     ap.add_argument("--no-backward", dest="backward", action="store_false", help="skip the backward leg")
+    ap.add_argument("--no-paper", dest="paper", action="store_false",
+                    help="skip the paper's own benchmark (6730^2 SIE gradient, mixed / FP64 / FP32)")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="time the default tile shape / nodes per thread instead of the autotuned ones")
     ap.add_argument("--tune-cache", default=None,
@@ -319,7 +365,7 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    prm, grid, obs_np, n_tri, res, large, batched, backward, tuned = gpu_bench(args)
+    prm, grid, obs_np, n_tri, res, large, batched, backward, tuned, paper = gpu_bench(args)
     mixed, fp64 = res["mixed"], res["fp64"]
     step_s = mixed["graph_s"]
     evals = grid.nx * grid.ny * prm.shape[1]
@@ -374,6 +420,7 @@ def main():
         "large": large,
         "batched": batched,
         "backward": backward,
+        "paper_benchmark": paper,
         "autotuned": {k: {"tile": t, "field_npl": n} for k, (t, n) in tuned.items() if t} or None,
         "cpu_baseline": cpu,
         "parity": parity,

@@ -153,6 +153,38 @@ int lens_dls_dos(lens_ctx *ctx, double zl, const double *zs, int32_t n, double o
 int lens_deflect(lens_ctx *ctx, const lens_potentials *pot, const lens_grid *grid,
                  lens_precision prec, void *ax, void *ay, int32_t *status, hipStream_t stream);
 
+/* Options of the paper's mixed-precision gradient (Sec. 3.2, 3.3, Appendix A.3). */
+typedef struct {
+    int32_t n_cluster;      /* the first n_cluster potentials are the cluster-scale halos      */
+    int32_t patch_cluster;  /* side of their double-precision pixel blocks (the paper: 400)    */
+    int32_t patch_galaxy;   /* side of the blocks of the other (galaxy-scale) halos (paper: 20) */
+    double t12;             /* criteria thresholds, arcsec: |dx - d1|, |dx - d2| < t12 ...      */
+    double t34;             /* ... or |d3|, |d4| > t34 (paper: 0.0092, 0.0104 for dx = 0.03")  */
+} lens_mixed_opts;
+
+/* The paper's mixed-precision gradient of an SIE lens (every potential with
+ * r_core = 0 and r_cut = +inf, the model its precision study covers; Sec. 3.2):
+ *  1. grad Psi in FP32 at every node (node offsets from an exact split of the
+ *     centre, alpha = K M d / R), except
+ *  2. FP64 inside a block of patch_cluster^2 nodes centred on each
+ *     cluster-scale halo and patch_galaxy^2 nodes on every other halo (node
+ *     indices [k - p/2, k - p/2 + p) per axis, k the node nearest the centre,
+ *     rounded half away from zero; clipped to the grid);
+ *  3. on that field, with dx = grid->dx, d1 = ax(i,j) - ax(i-1,j),
+ *     d2 = ay(i,j) - ay(i,j-1), d3 = ax(i,j) - ax(i,j-1), d4 = ay(i,j) - ay(i-1,j)
+ *     (differences whose neighbour lies outside the grid are not evaluated),
+ *     every other node with |dx - d1| < t12, |dx - d2| < t12, |d3| > t34 or
+ *     |d4| > t34 is recomputed in FP64 (Sec. 3.3).
+ * ax, ay: device double [ny*nx] (row-major, node (i,j) at j*nx + i).  mask:
+ * device uint8 [ny*nx] or NULL; receives 0 (FP32), 1 (FP64 block) or 2 (FP64
+ * by the criteria).  stats: device int64 [4]: block nodes, criteria nodes, all
+ * FP64 nodes, status (LENS_OK, or LENS_ERR_INVALID for a potential outside the
+ * SIE domain: outputs NaN, counts 0).  ny*nx < 2^32.  Host-side argument errors
+ * return LENS_ERR_INVALID. */
+int lens_deflect_mixed(lens_ctx *ctx, const lens_potentials *pot, const lens_grid *grid,
+                       const lens_mixed_opts *opts, double *ax, double *ay, uint8_t *mask, int64_t *stats,
+                       hipStream_t stream);
+
 /* Source positions of the observed images and barycentres of the systems
  * (Sec. 2.2.2): beta_ij = theta_ij - (D_LS/D_OS)_i grad Psi(theta_ij) in FP64,
  * barycentre = unweighted mean of the system's beta_ij.  beta_x, beta_y:

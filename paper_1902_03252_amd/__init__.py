@@ -155,6 +155,36 @@ def lens_deflect(params: torch.Tensor, grid, prec: str = "fp64", ctx: Context | 
     return ax, ay
 
 
+@dataclasses.dataclass
+class MixedResult:
+    ax: torch.Tensor     # [ny, nx] float64
+    ay: torch.Tensor     # [ny, nx] float64
+    mask: torch.Tensor   # [ny, nx] uint8: 0 FP32, 1 FP64 block, 2 FP64 by the criteria
+    stats: torch.Tensor  # [4] int64: block nodes, criteria nodes, FP64 nodes, status
+
+
+def mixed_buffers(grid, device) -> MixedResult:
+    z = lambda dt: torch.empty((grid.ny, grid.nx), dtype=dt, device=device)
+    return MixedResult(z(torch.float64), z(torch.float64), z(torch.uint8),
+                       torch.zeros(4, dtype=torch.int64, device=device))
+
+
+def lens_deflect_mixed(params: torch.Tensor, grid, n_cluster: int, patch_cluster: int = 400,
+                       patch_galaxy: int = 20, t12: float = 0.0092, t34: float = 0.0104,
+                       out: MixedResult | None = None, ctx: Context | None = None) -> MixedResult:
+    """The paper's mixed-precision gradient of an SIE lens (asynchronous):
+    FP32 everywhere, FP64 in blocks around the halos and where the criteria
+    of its Sec. 3.3 hold.  The first n_cluster potentials are the cluster-scale halos."""
+    ctx = ctx or context(params.device.index)
+    p = _pots(params)
+    out = out or mixed_buffers(grid, params.device)
+    opts = L.LensMixedOpts(int(n_cluster), int(patch_cluster), int(patch_galaxy), float(t12), float(t34))
+    L.check(ctx._lib.lens_deflect_mixed(ctx.handle, C.byref(p), C.byref(_grid(grid)), C.byref(opts),
+                                        L.ptr(out.ax), L.ptr(out.ay), L.ptr(out.mask), L.ptr(out.stats),
+                                        ctx.stream()), "lens_deflect_mixed")
+    return out
+
+
 def lens_source_positions(params: torch.Tensor, obs: Obs, ctx: Context | None = None, check: bool = True):
     """Source positions of the observed images [n_img, 2] and barycentres [n_sys, 2]."""
     ctx = ctx or context(params.device.index)

@@ -19,7 +19,7 @@ LENS_FP64, LENS_FP32, LENS_MIXED = 0, 1, 2
 STAT_HITS, STAT_FLAGGED, STAT_TILE_PASS, STAT_BBOX_PASS, STAT_STATUS, STAT_FB_HITS, STAT_TESTS = range(7)
 STAT_N = 8
 
-EXPORTS = ("lens_create", "lens_destroy", "lens_dls_dos", "lens_deflect", "lens_source_positions",
+EXPORTS = ("lens_create", "lens_destroy", "lens_dls_dos", "lens_deflect", "lens_deflect_mixed", "lens_source_positions",
            "lens_image_chi2", "lens_image_chi2_batched", "lens_deflect_backward", "lens_src_chi2",
            "lens_src_chi2_backward", "lens_autotune_chi2", "lens_autotune_chi2_batched", "lens_autotune_lookup",
            "lens_autotune_save", "lens_autotune_load", "lens_set_timing", "lens_field_timing", "lens_strerror")
@@ -37,6 +37,11 @@ class LensGrid(C.Structure):
 class LensObs(C.Structure):
     _fields_ = [("n_sys", C.c_int32), ("n_img", C.c_int32), ("sys_off", C.c_void_p), ("x", C.c_void_p),
                 ("y", C.c_void_p), ("sigma", C.c_void_p), ("dls_dos", C.c_void_p)]
+
+
+class LensMixedOpts(C.Structure):
+    _fields_ = [("n_cluster", C.c_int32), ("patch_cluster", C.c_int32), ("patch_galaxy", C.c_int32),
+                ("t12", C.c_double), ("t34", C.c_double)]
 
 
 class LensChi2Opts(C.Structure):
@@ -75,6 +80,9 @@ def load(path: str = LIB_PATH):
     lib.lens_dls_dos.restype = C.c_int
     lib.lens_deflect.argtypes = [vp, C.POINTER(LensPotentials), C.POINTER(LensGrid), C.c_int, vp, vp, vp, vp]
     lib.lens_deflect.restype = C.c_int
+    lib.lens_deflect_mixed.argtypes = [vp, C.POINTER(LensPotentials), C.POINTER(LensGrid), C.POINTER(LensMixedOpts),
+                                       vp, vp, vp, vp, vp]
+    lib.lens_deflect_mixed.restype = C.c_int
     lib.lens_source_positions.argtypes = [vp, C.POINTER(LensPotentials), C.POINTER(LensObs), vp, vp, vp, vp, vp, vp]
     lib.lens_source_positions.restype = C.c_int
     lib.lens_image_chi2.argtypes = [vp, C.POINTER(LensPotentials), C.POINTER(LensGrid), C.POINTER(LensObs),

@@ -18,7 +18,7 @@ using namespace lens;
 namespace {
 
 enum Buf { B_TAB64, B_TAB32, B_BTERM, B_FIELD, B_BX, B_BY, B_SYS, B_STATE, B_HITS, B_FLAGS, B_POS, B_CONTRIB,
-           B_PART, B_BCOUNT, B_VJP, B_SRC, B_SRCST, B_RR, B_PAIRS, B_NBUF };
+           B_PART, B_BCOUNT, B_VJP, B_SRC, B_SRCST, B_RR, B_PAIRS, B_MIX, B_MLIST, B_MMASK, B_NBUF };
 
 // Device work plan of one chunk of a batch (see lens_image_chi2_batched).
 struct PlanChunk {
@@ -408,6 +408,49 @@ int lens_deflect(lens_ctx* ctx, const lens_potentials* pot, const lens_grid* gri
     timing_end(ctx, slot);
     if (status && launch_export(nullptr, 0, st, nullptr, nullptr, status, stream) != hipSuccess)
         return LENS_ERR_DEVICE;
+    return LENS_OK;
+}
+
+int lens_deflect_mixed(lens_ctx* ctx, const lens_potentials* pot, const lens_grid* grid, const lens_mixed_opts* opts,
+                       double* ax, double* ay, uint8_t* mask, int64_t* stats, hipStream_t stream)
+{
+    if (!ctx || check_pot(pot) || check_grid(grid) || !opts || !ax || !ay || !stats) return LENS_ERR_INVALID;
+    if (opts->n_cluster < 0 || opts->n_cluster > pot->n || opts->patch_cluster < 0 || opts->patch_galaxy < 0 ||
+        opts->patch_cluster > (1 << 20) || opts->patch_galaxy > (1 << 20) || !(opts->t12 >= 0.0) ||
+        !is_fin(opts->t12) || !(opts->t34 >= 0.0) || !is_fin(opts->t34))
+        return LENS_ERR_INVALID;
+    const long long nn = (long long)grid->nx * grid->ny;
+    if (nn >= (1ll << 32)) return LENS_ERR_INVALID;  // DP list entries are 32-bit pixel indices
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return LENS_ERR_DEVICE;
+    const GridDesc g = grid_desc(grid);
+    const size_t np = pot->n > 0 ? pot->n : 1;
+    int rc;
+    if ((rc = ensure(ctx, B_TAB64, np * T64_STRIDE * 8)) || (rc = ensure(ctx, B_TAB32, np * T32_STRIDE * 4)) ||
+        (rc = ensure(ctx, B_BTERM, np * 3 * 8)) || (rc = ensure(ctx, B_MIX, sizeof(MixState))) ||
+        (rc = ensure(ctx, B_MLIST, (size_t)nn * 4)) || (!mask && (rc = ensure(ctx, B_MMASK, (size_t)nn))))
+        return rc;
+    MixedLaunch ml;
+    ml.tab64 = (double*)ctx->buf[B_TAB64];
+    ml.tab32 = (float*)ctx->buf[B_TAB32];
+    ml.bterm = (double*)ctx->buf[B_BTERM];
+    ml.st = (MixState*)ctx->buf[B_MIX];
+    ml.ax = ax;
+    ml.ay = ay;
+    ml.mask = mask ? mask : (unsigned char*)ctx->buf[B_MMASK];
+    ml.list = (unsigned*)ctx->buf[B_MLIST];
+    ml.stats = (long long*)stats;
+    ml.n_cluster = opts->n_cluster;
+    ml.pc = opts->patch_cluster;
+    ml.pg = opts->patch_galaxy;
+    ml.npl = std::min(field_npl(g), 4);
+    ml.t12 = opts->t12;
+    ml.t34 = opts->t34;
+    int slot;
+    KernelEvents kev;
+    if ((rc = timing_begin(ctx, &kev, &ml.ev, &slot))) return rc;
+    if (launch_mixed(pot_ptrs(pot), g, ml, stream) != hipSuccess) return LENS_ERR_DEVICE;
+    timing_end(ctx, slot);
     return LENS_OK;
 }
 

@@ -133,6 +133,31 @@ hipError_t launch_vjp(const PotPtrs& pot, const GridDesc& g, bool fp32, const do
 hipError_t launch_src(const PotPtrs& pot, const ObsPtrs& obs, double* beta, double* cot, double* csys,
                       SrcState* st, double* chi2, int* status, const double* g_chi2, double* grad, hipStream_t s);
 
+// Device state of the mixed-precision SIE gradient (reset by its first kernel).
+struct MixState {
+    unsigned n_list;   // DP list length
+    unsigned n_patch;  // list entries that are block pixels
+    int status;
+    int pad;
+};
+
+// Arguments of the mixed-precision SIE gradient.
+struct MixedLaunch {
+    double* tab64;
+    float* tab32;
+    double* bterm;
+    MixState* st;
+    double *ax, *ay;       // [ny*nx] output
+    unsigned char* mask;   // [ny*nx] 0 FP32, 1 DP block, 2 DP by the criteria
+    unsigned* list;        // [ny*nx] DP pixel list
+    long long* stats;      // [4] block pixels, criteria pixels, DP pixels, status
+    int n_cluster, pc, pg, npl;
+    double t12, t34;
+    const KernelEvents* ev;  // times the FP32 field kernel when not null
+};
+
+hipError_t launch_mixed(const PotPtrs& pot, const GridDesc& g, const MixedLaunch& ml, hipStream_t s);
+
 hipError_t launch_bhead(const BatchPlan& bp, const PotPtrs& pot, const ObsPtrs& obs, double* tab64, float* tab32,
                         double* bterm, double* bx, double* by, int np_chunk, hipStream_t s);
 hipError_t launch_bsys(const BatchPlan& bp, const ObsPtrs& obs, const double* bterm, const double* bx,
