@@ -13,6 +13,7 @@ paper is silent.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 
@@ -342,3 +343,56 @@ def criteria(ax, ay, dx: float, t12: float = T12, t34: float = T34):
     f, fp = _u8((ny, nx))
     _load().orc_criteria(axp, ayp, nx, ny, float(dx), float(t12), float(t34), fp)
     return f
+
+
+# ---------------------------------------------------------------- sampler steps
+#
+# The paper evaluates chi^2 inside a sampler over the lens parameters
+# (Sec. 2.2.1).  These are the textbook steps of two samplers, written out
+# plainly: Hamiltonian Monte Carlo (Duane, Kennedy, Pendleton & Roweth 1987;
+# the leapfrog form of Neal 2011, "MCMC using Hamiltonian dynamics", Sec. 5.3)
+# and random-walk Metropolis (Metropolis et al. 1953).  Random draws are
+# arguments.
+
+def hmc_step_generic(q0, step, n_leapfrog: int, momentum, u: float, energy):
+    """One HMC step in the coordinates z = q/step with unit masses.
+    energy(q) -> (U, dU/dq).  Returns (q, U, accepted)."""
+    q0 = np.asarray(q0, dtype=np.float64)
+    free = np.asarray(step) != 0
+    q = q0.copy()
+    p = np.where(free, momentum, 0.0)
+    u0, g = energy(q)
+    p = p - np.where(free, 0.5 * step * g, 0.0)                      # half kick
+    u1 = u0
+    for ell in range(1, n_leapfrog + 1):
+        q = np.where(free, q + step * p, q)                           # drift
+        u1, g = energy(q)
+        c = 1.0 if ell < n_leapfrog else 0.5
+        p = p - np.where(free, c * step * g, 0.0)                     # kick (half at the end)
+    h0 = u0 + 0.5 * float(np.sum(np.where(free, momentum, 0.0) ** 2))
+    h1 = u1 + 0.5 * float(np.sum(p ** 2))
+    accept = bool(np.isfinite(u0) and np.isfinite(h1) and math.log(u) < h0 - h1)
+    return (q, u1, True) if accept else (q0.copy(), u0, False)
+
+
+def _src_energy(obs):
+    def energy(q):
+        c = src_chi2(q, obs)
+        if not np.isfinite(c):
+            return float("nan"), np.full(q.shape, np.nan)
+        return 0.5 * c, 0.5 * src_chi2_grad(q, obs)
+    return energy
+
+
+def hmc_step(state, obs, step, n_leapfrog: int, momentum, u: float):
+    """HMC on the source-plane chi^2 (U = chi^2/2): returns (state, chi2, accepted)."""
+    q, u1, acc = hmc_step_generic(state, step, n_leapfrog, momentum, u, _src_energy(obs))
+    return q, 2.0 * u1, acc
+
+
+def mh_accept(chi2_new: float, chi2_cur: float, u: float, valid: bool) -> bool:
+    """Metropolis acceptance for the log-likelihood -chi^2/2; any valid proposal
+    replaces a state whose chi^2 is not finite."""
+    if not valid or not np.isfinite(chi2_new):
+        return False
+    return (not np.isfinite(chi2_cur)) or math.log(u) < -0.5 * (chi2_new - chi2_cur)

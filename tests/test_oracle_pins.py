@@ -536,3 +536,60 @@ def test_criteria_edges_and_linear_fields():
     assert f.sum() == 0
     f = oracle.criteria(h * i, zero, h)                    # d1 = h: source pixel of length 0
     np.testing.assert_array_equal(f, (i >= 1).astype(np.uint8))
+
+
+# --------------------------------------------------------------- sampler steps
+
+def test_hmc_leapfrog_matches_harmonic_map():
+    """For U = q^2 / (2 sigma^2) the leapfrog map in z = q/step with omega =
+    step/sigma is the linear map M = [[1 - w/2, 1], [-w (1 - w/4), 1 - w/2]],
+    w = omega^2 (kick-drift-kick with unit step); L steps are M^L (numpy matrix
+    power).  Catches a missing half kick, the kick/drift order, the step
+    scaling or the sign of the gradient."""
+    sigma, s, L = 1.7, 0.4, 7
+    w = (s / sigma) ** 2
+    M = np.array([[1 - w / 2, 1.0], [-w * (1 - w / 4), 1 - w / 2]])
+    energy = lambda q: (0.5 * float(np.sum(q * q)) / sigma ** 2, q / sigma ** 2)
+    q0, p0 = np.array([0.9, -2.1]), np.array([0.3, 1.2])
+    q, _, acc = oracle.hmc_step_generic(q0, np.full(2, s), L, p0, 1e-300, energy)
+    assert acc
+    ML = np.linalg.matrix_power(M, L)
+    for k in range(2):
+        z, _ = ML @ np.array([q0[k] / s, p0[k]])
+        assert q[k] == pytest.approx(z * s, rel=1e-12)
+    # a frozen coordinate (step 0) does not move
+    q, _, _ = oracle.hmc_step_generic(q0, np.array([s, 0.0]), L, p0, 1e-300, energy)
+    assert q[1] == q0[1]
+
+
+def test_hmc_reversible_and_samples_a_gaussian():
+    """Leapfrog is reversible (negated end momentum returns to the start), and
+    the chain's moments match N(0, sigma^2) (seeded; 5-sigma sampling bounds).
+    Catches a non-symmetric integrator or a wrong acceptance sign."""
+    sigma = 2.5
+    energy = lambda q: (0.5 * float(np.sum(q * q)) / sigma ** 2, q / sigma ** 2)
+    q0, p0, s, L = np.array([1.3]), np.array([0.7]), np.array([0.9]), 6
+    w = (s[0] / sigma) ** 2
+    M = np.linalg.matrix_power(np.array([[1 - w / 2, 1.0], [-w * (1 - w / 4), 1 - w / 2]]), L)
+    z1, p1 = M @ np.array([q0[0] / s[0], p0[0]])
+    back, _, _ = oracle.hmc_step_generic(np.array([z1 * s[0]]), s, L, np.array([-p1]), 1e-300, energy)
+    assert back[0] == pytest.approx(q0[0], rel=1e-12)
+    g = np.random.default_rng(11)
+    q, xs = np.zeros(1), []
+    for _ in range(20000):
+        q, _, _ = oracle.hmc_step_generic(q, np.array([1.1]), 5, g.normal(size=1), g.uniform(), energy)
+        xs.append(q[0])
+    xs = np.array(xs[1000:])
+    n_eff = len(xs) / 4  # conservative
+    assert abs(xs.mean()) < 5 * sigma / math.sqrt(n_eff)
+    assert abs(xs.var() / sigma ** 2 - 1) < 5 * math.sqrt(2 / n_eff)
+
+
+def test_metropolis_acceptance_rule():
+    """log-likelihood -chi^2/2: a chi^2 larger by 2 is accepted exactly when
+    u < 1/e; invalid proposals never; any valid proposal from an infinite chi^2."""
+    e = math.exp(-1.0)
+    assert oracle.mh_accept(12.0, 10.0, e * 0.999, True) and not oracle.mh_accept(12.0, 10.0, e * 1.001, True)
+    assert oracle.mh_accept(5.0, 10.0, 0.999999, True)
+    assert not oracle.mh_accept(5.0, 10.0, 0.5, False) and not oracle.mh_accept(math.inf, 10.0, 0.5, True)
+    assert oracle.mh_accept(1e9, math.inf, 0.999, True)
