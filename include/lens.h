@@ -228,6 +228,43 @@ int lens_image_chi2_batched(lens_ctx *ctx, const lens_potentials *all, int32_t n
                             const int32_t *pot_off, const lens_grid *grids, const lens_obs *obs,
                             const lens_chi2_opts *opts, lens_batch_out *out, hipStream_t stream);
 
+/* ---------------------------------------------------------------- sampler steps
+ *
+ * The paper evaluates chi^2 inside a sampler over the lens parameters
+ * (Sec. 2.2.1).  Two steps of such samplers run on the device.  A parameter
+ * table is a device double array [7][n] (rows x, y, eps, phi, r_core, r_cut,
+ * sigma_v, the layout of lens_potentials' arrays placed one after another);
+ * step: device double [7][n], a parameter with step 0 is held fixed.  The
+ * random numbers are inputs, so a step is a deterministic function of them.
+ * Both are stream-ordered and capturable (no host synchronisation). */
+
+/* One Hamiltonian Monte Carlo step on the source-plane chi^2 (lens_src_chi2):
+ * potential energy U = chi^2/2, coordinates z = q/step with unit masses,
+ * n_leapfrog (1..1000) leapfrog steps of size 1 in z (half momentum kicks at
+ * both ends), then acceptance when u < exp(H0 - H1), H = U + |p|^2/2 over the
+ * free parameters, and both chi^2 valid.  state: [7][n], replaced by the
+ * trajectory's end on acceptance.  momentum: device [7][n] N(0,1) draws; u:
+ * device [1] U(0,1) draw; chi2: device [1], receives the chi^2 of the
+ * resulting state; accepted: device int32 [1]. */
+int lens_hmc_step(lens_ctx *ctx, double *state, int32_t n, const lens_obs *obs, const double *step,
+                  int32_t n_leapfrog, const double *momentum, const double *u, double *chi2, int32_t *accepted,
+                  hipStream_t stream);
+
+/* One random-walk Metropolis step of n_chains independent chains on the
+ * image-plane chi^2 (log-likelihood -chi^2/2), n potentials each, every chain
+ * on `grid`: proposals = state + step * noise (multiply and add rounded
+ * separately; step [7][n] shared by the chains), evaluated by one
+ * lens_image_chi2_batched call with `opts`; chain b accepts when its proposal's
+ * status is OK, its chi^2 finite and log u_b < -(chi2_new - chi2_b)/2 (any
+ * valid proposal when chi2_b is not finite).  states: device [7][n_chains*n]
+ * (chain b owns columns [b*n, b*n + n)), updated; noise: device
+ * [7][n_chains*n] N(0,1); u: device [n_chains] U(0,1); chi2: device
+ * [n_chains], the current chains' chi^2 on input (e.g. from
+ * lens_image_chi2_batched), updated; accepted: device int32 [n_chains]. */
+int lens_mh_step_batched(lens_ctx *ctx, double *states, int32_t n_chains, int32_t n, const lens_grid *grid,
+                         const lens_obs *obs, const lens_chi2_opts *opts, const double *step, const double *noise,
+                         const double *u, double *chi2, int32_t *accepted, hipStream_t stream);
+
 /* ---------------------------------------------------------------- autotuning
  *
  * A context keeps a table of the fastest triangle-stage tile shape

@@ -302,6 +302,62 @@ def lens_image_chi2_batched(params: torch.Tensor, layout: BatchLayout, obs: Obs,
     return out
 
 
+# ---------------------------------------------------------------- sampler steps
+
+def _table(t: torch.Tensor, name: str) -> torch.Tensor:
+    _require_cuda(t, torch.float64, name)
+    if t.dim() != 2 or t.shape[0] != 7 or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous [7, n] float64 tensor")
+    return t
+
+
+def hmc_step(state: torch.Tensor, obs: Obs, step: torch.Tensor, n_leapfrog: int, momentum: torch.Tensor,
+             u: torch.Tensor, ctx: Context | None = None):
+    """One HMC step on the source-plane chi^2 (asynchronous).  state [7, n] is
+    updated in place on acceptance; momentum [7, n] N(0,1) and u [1] U(0,1) are
+    the step's random draws.  Returns (chi2 [1], accepted [1] int32) tensors."""
+    ctx = ctx or context(state.device.index)
+    _table(state, "state")
+    for name, t in (("step", step), ("momentum", momentum)):
+        _require_cuda(t, torch.float64, name)
+        if t.shape != state.shape or not t.is_contiguous():
+            raise ValueError(f"{name} must match state")
+    _require_cuda(u, torch.float64, "u")
+    chi2 = torch.empty(1, dtype=torch.float64, device=state.device)
+    acc = torch.empty(1, dtype=torch.int32, device=state.device)
+    L.check(ctx._lib.lens_hmc_step(ctx.handle, L.ptr(state), state.shape[1], C.byref(_obs(obs)), L.ptr(step),
+                                   int(n_leapfrog), L.ptr(momentum), L.ptr(u), L.ptr(chi2), L.ptr(acc),
+                                   ctx.stream()), "lens_hmc_step")
+    return chi2, acc
+
+
+def mh_step_batched(states: torch.Tensor, n_chains: int, grid, obs: Obs, step: torch.Tensor, noise: torch.Tensor,
+                    u: torch.Tensor, chi2: torch.Tensor, prec: str = "mixed", fb_mode: int = 0,
+                    fb_tau: float = 1e-6, hit_capacity: int = 1024, ctx: Context | None = None) -> torch.Tensor:
+    """One Metropolis step of n_chains chains on the image-plane chi^2
+    (asynchronous).  states [7, n_chains*n] and chi2 [n_chains] are updated in
+    place; noise [7, n_chains*n] N(0,1), u [n_chains] U(0,1).  Returns the
+    accepted flags [n_chains] int32."""
+    ctx = ctx or context(states.device.index)
+    _table(states, "states")
+    if states.shape[1] % n_chains:
+        raise ValueError("states must hold n_chains equal blocks of columns")
+    n = states.shape[1] // n_chains
+    _require_cuda(step, torch.float64, "step")
+    _require_cuda(noise, torch.float64, "noise")
+    _require_cuda(u, torch.float64, "u")
+    _require_cuda(chi2, torch.float64, "chi2")
+    if step.shape != (7, n) or noise.shape != states.shape or u.numel() != n_chains or chi2.numel() != n_chains:
+        raise ValueError("step [7, n], noise like states, u and chi2 [n_chains]")
+    acc = torch.empty(n_chains, dtype=torch.int32, device=states.device)
+    opts = L.LensChi2Opts(_PREC[prec], int(fb_mode), float(fb_tau), int(hit_capacity), 0, 0)
+    L.check(ctx._lib.lens_mh_step_batched(ctx.handle, L.ptr(states), int(n_chains), int(n), C.byref(_grid(grid)),
+                                          C.byref(_obs(obs)), C.byref(opts), L.ptr(step.contiguous()),
+                                          L.ptr(noise.contiguous()), L.ptr(u), L.ptr(chi2), L.ptr(acc),
+                                          ctx.stream()), "lens_mh_step_batched")
+    return acc
+
+
 # ---------------------------------------------------------------- autotuning
 
 def autotune_chi2(params: torch.Tensor, grid, obs: Obs, prec: str = "mixed", fb_mode: int = 0,

@@ -19,10 +19,11 @@ LENS_FP64, LENS_FP32, LENS_MIXED = 0, 1, 2
 STAT_HITS, STAT_FLAGGED, STAT_TILE_PASS, STAT_BBOX_PASS, STAT_STATUS, STAT_FB_HITS, STAT_TESTS = range(7)
 STAT_N = 8
 
-EXPORTS = ("lens_create", "lens_destroy", "lens_dls_dos", "lens_deflect", "lens_deflect_mixed", "lens_source_positions",
-           "lens_image_chi2", "lens_image_chi2_batched", "lens_deflect_backward", "lens_src_chi2",
-           "lens_src_chi2_backward", "lens_autotune_chi2", "lens_autotune_chi2_batched", "lens_autotune_lookup",
-           "lens_autotune_save", "lens_autotune_load", "lens_set_timing", "lens_field_timing", "lens_strerror")
+EXPORTS = ("lens_create", "lens_destroy", "lens_dls_dos", "lens_deflect", "lens_deflect_mixed",
+           "lens_source_positions", "lens_image_chi2", "lens_image_chi2_batched", "lens_deflect_backward",
+           "lens_src_chi2", "lens_src_chi2_backward", "lens_hmc_step", "lens_mh_step_batched",
+           "lens_autotune_chi2", "lens_autotune_chi2_batched", "lens_autotune_lookup", "lens_autotune_save",
+           "lens_autotune_load", "lens_set_timing", "lens_field_timing", "lens_strerror")
 
 
 class LensPotentials(C.Structure):
@@ -99,6 +100,11 @@ def load(path: str = LIB_PATH):
     lib.lens_src_chi2_backward.argtypes = [vp, C.POINTER(LensPotentials), C.POINTER(LensObs), vp, vp, vp, vp]
     lib.lens_src_chi2_backward.restype = C.c_int
     pi32 = C.POINTER(i32)
+    lib.lens_hmc_step.argtypes = [vp, vp, i32, C.POINTER(LensObs), vp, i32, vp, vp, vp, vp, vp]
+    lib.lens_hmc_step.restype = C.c_int
+    lib.lens_mh_step_batched.argtypes = [vp, vp, i32, i32, C.POINTER(LensGrid), C.POINTER(LensObs),
+                                         C.POINTER(LensChi2Opts), vp, vp, vp, vp, vp, vp]
+    lib.lens_mh_step_batched.restype = C.c_int
     lib.lens_autotune_chi2.argtypes = [vp, C.POINTER(LensPotentials), C.POINTER(LensGrid), C.POINTER(LensObs),
                                        C.POINTER(LensChi2Opts), C.POINTER(LensChi2Out), i32, pi32, pi32, vp]
     lib.lens_autotune_chi2.restype = C.c_int

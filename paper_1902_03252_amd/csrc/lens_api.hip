@@ -18,7 +18,7 @@ using namespace lens;
 namespace {
 
 enum Buf { B_TAB64, B_TAB32, B_BTERM, B_FIELD, B_BX, B_BY, B_SYS, B_STATE, B_HITS, B_FLAGS, B_POS, B_CONTRIB,
-           B_PART, B_BCOUNT, B_VJP, B_SRC, B_SRCST, B_RR, B_PAIRS, B_MIX, B_MLIST, B_MMASK, B_NBUF };
+           B_PART, B_BCOUNT, B_VJP, B_SRC, B_SRCST, B_RR, B_PAIRS, B_MIX, B_MLIST, B_MMASK, B_HMC, B_MHP, B_NBUF };
 
 // Device work plan of one chunk of a batch (see lens_image_chi2_batched).
 struct PlanChunk {
@@ -926,4 +926,97 @@ extern "C" int lens_src_chi2_backward(lens_ctx* ctx, const lens_potentials* pot,
 {
     if (!ctx || check_pot(pot) || check_obs(obs) || (pot->n > 0 && !grad)) return LENS_ERR_INVALID;
     return src_common(ctx, pot, obs, nullptr, status, g_chi2, grad, stream);
+}
+
+// ---------------------------------------------------------------- sampler steps
+
+namespace {
+
+lens_potentials table_pots(double* t, int n)
+{
+    lens_potentials p;
+    p.n = n;
+    p.x = t;
+    p.y = t + (size_t)n;
+    p.eps = t + 2 * (size_t)n;
+    p.phi = t + 3 * (size_t)n;
+    p.r_core = t + 4 * (size_t)n;
+    p.r_cut = t + 5 * (size_t)n;
+    p.sigma_v = t + 6 * (size_t)n;
+    return p;
+}
+
+}  // namespace
+
+extern "C" int lens_hmc_step(lens_ctx* ctx, double* state, int32_t n, const lens_obs* obs, const double* step,
+                             int32_t n_leapfrog, const double* momentum, const double* u, double* chi2,
+                             int32_t* accepted, hipStream_t stream)
+{
+    if (!ctx || !state || n < 1 || check_obs(obs) || !step || !momentum || !u || !chi2 || !accepted ||
+        n_leapfrog < 1 || n_leapfrog > 1000 || n > (1 << 24))
+        return LENS_ERR_INVALID;
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return LENS_ERR_DEVICE;
+    const int n7 = 7 * n;
+    int rc;
+    if ((rc = ensure(ctx, B_HMC, (size_t)3 * n7 * 8 + 64))) return rc;
+    double* q = (double*)ctx->buf[B_HMC];
+    double* pm = q + n7;
+    double* g = pm + n7;
+    double* chi2_pair = g + n7;                      // [2]
+    int* status_pair = (int*)(chi2_pair + 2);        // [2]
+    const lens_potentials qp = table_pots(q, n);
+    if (launch_hmc_begin(state, momentum, step, n7, q, pm, stream) != hipSuccess) return LENS_ERR_DEVICE;
+    if ((rc = src_common(ctx, &qp, obs, chi2_pair, status_pair, nullptr, g, stream))) return rc;
+    if (launch_hmc_kick(g, step, n7, 0.5, pm, stream) != hipSuccess) return LENS_ERR_DEVICE;
+    for (int l = 1; l <= n_leapfrog; l++) {
+        if (launch_hmc_drift(pm, step, n7, q, stream) != hipSuccess) return LENS_ERR_DEVICE;
+        if ((rc = src_common(ctx, &qp, obs, chi2_pair + 1, status_pair + 1, nullptr, g, stream))) return rc;
+        if (launch_hmc_kick(g, step, n7, l < n_leapfrog ? 1.0 : 0.5, pm, stream) != hipSuccess)
+            return LENS_ERR_DEVICE;
+    }
+    if (launch_hmc_accept(state, q, momentum, pm, step, n7, chi2_pair, status_pair, u, chi2, accepted, stream) !=
+        hipSuccess)
+        return LENS_ERR_DEVICE;
+    return LENS_OK;
+}
+
+extern "C" int lens_mh_step_batched(lens_ctx* ctx, double* states, int32_t n_chains, int32_t n,
+                                    const lens_grid* grid, const lens_obs* obs, const lens_chi2_opts* opts,
+                                    const double* step, const double* noise, const double* u, double* chi2,
+                                    int32_t* accepted, hipStream_t stream)
+{
+    if (!ctx || !states || n_chains < 1 || n_chains > (1 << 20) || n < 1 || check_grid(grid) || check_obs(obs) ||
+        !opts || !step || !noise || !u || !chi2 || !accepted)
+        return LENS_ERR_INVALID;
+    const long long bn = (long long)n_chains * n;
+    if (bn > (1ll << 28)) return LENS_ERR_INVALID;
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return LENS_ERR_DEVICE;
+    const size_t ns = obs->n_sys > 0 ? obs->n_sys : 1;
+    const size_t bytes = (size_t)7 * bn * 8 + (size_t)n_chains * (8 + 8 * ns + 4 * ns + 4) + 8 * LENS_STAT_N + 256;
+    int rc;
+    if ((rc = ensure(ctx, B_MHP, bytes))) return rc;
+    double* prop = (double*)ctx->buf[B_MHP];
+    double* chi2_new = prop + 7 * bn;
+    double* chi2_sys = chi2_new + n_chains;
+    int64_t* stats = (int64_t*)(chi2_sys + (size_t)n_chains * ns);
+    int32_t* n_pred = (int32_t*)(stats + LENS_STAT_N);
+    int32_t* status = n_pred + (size_t)n_chains * ns;
+    if (launch_mh_propose(states, step, noise, n, n_chains, prop, stream) != hipSuccess) return LENS_ERR_DEVICE;
+    std::vector<int32_t> pot_off((size_t)n_chains + 1);
+    for (int b = 0; b <= n_chains; b++) pot_off[b] = (int32_t)((long long)b * n);
+    std::vector<lens_grid> grids((size_t)n_chains, *grid);
+    const lens_potentials all = table_pots(prop, (int)bn);
+    lens_batch_out bo;
+    bo.chi2 = chi2_new;
+    bo.chi2_sys = chi2_sys;
+    bo.n_pred = n_pred;
+    bo.status = status;
+    bo.stats = stats;
+    if ((rc = lens_image_chi2_batched(ctx, &all, n_chains, pot_off.data(), grids.data(), obs, opts, &bo, stream)))
+        return rc;
+    if (launch_mh_accept(states, prop, n, n_chains, chi2_new, status, u, chi2, accepted, stream) != hipSuccess)
+        return LENS_ERR_DEVICE;
+    return LENS_OK;
 }

@@ -158,6 +158,18 @@ struct MixedLaunch {
 
 hipError_t launch_mixed(const PotPtrs& pot, const GridDesc& g, const MixedLaunch& ml, hipStream_t s);
 
+hipError_t launch_hmc_begin(const double* state, const double* momentum, const double* step, int n7, double* q,
+                            double* p, hipStream_t s);
+hipError_t launch_hmc_kick(const double* grad, const double* step, int n7, double c, double* p, hipStream_t s);
+hipError_t launch_hmc_drift(const double* p, const double* step, int n7, double* q, hipStream_t s);
+hipError_t launch_hmc_accept(double* state, const double* q, const double* momentum, const double* p,
+                             const double* step, int n7, const double* chi2_pair, const int* status_pair,
+                             const double* u, double* chi2, int* accepted, hipStream_t s);
+hipError_t launch_mh_propose(const double* state, const double* step, const double* noise, int n, int b,
+                             double* prop, hipStream_t s);
+hipError_t launch_mh_accept(double* state, const double* prop, int n, int b, const double* chi2_new,
+                            const int* status_new, const double* u, double* chi2, int* accepted, hipStream_t s);
+
 hipError_t launch_bhead(const BatchPlan& bp, const PotPtrs& pot, const ObsPtrs& obs, double* tab64, float* tab32,
                         double* bterm, double* bx, double* by, int np_chunk, hipStream_t s);
 hipError_t launch_bsys(const BatchPlan& bp, const ObsPtrs& obs, const double* bterm, const double* bx,
