@@ -186,10 +186,11 @@ def gpu_bench(args):
     large["speedup_mixed_vs_fp64"] = large["fp64"]["ms_per_eval"] / large["mixed"]["ms_per_eval"]
     batched = batched_bench(torch, lens, ctx, obs, obs_np, args, tuned) if args.batch > 0 else None
     paper = paper_bench(torch, lens, ctx, args) if args.paper else None
+    sampler = sampler_bench(torch, lens, ctx, args) if args.sampler else None
     backward = backward_bench(torch, lens, ctx, obs, args) if args.backward else None
     if args.tune_cache:
         lens.autotune_save(args.tune_cache, ctx=ctx)
-    return prm, grid, obs_np, n_tri, res, large, batched, backward, tuned, paper
+    return prm, grid, obs_np, n_tri, res, large, batched, backward, tuned, paper, sampler
 
 
 def paper_bench(torch, lens, ctx, args):
@@ -229,6 +230,66 @@ def paper_bench(torch, lens, ctx, args):
     res["workload"] = (f"{grid.nx}^2 pixels of {grid.h} arcsec, 2 + {prm.shape[1] - 2} SIE halos, "
                        f"{evals:.3e} pixel-potential evaluations (Sec. 4); other hardware's times are context")
     return res
+
+
+def sampler_bench(torch, lens, ctx, args):
+    """Sampler steps on the cluster model (50 potentials, 20 systems): HMC with
+    10 leapfrog steps on the source-plane chi^2 (free: the halo's centre,
+    eps, phi, core and sigma_v, every galaxy's sigma_v), graph-replayed; and one
+    random-walk Metropolis step of 256 chains on the 512^2 grid (one batched
+    mixed chi^2 of all proposals per step)."""
+    import synthlens as S
+    prm, _, obs_np = load_workload(2)
+    obs = lens.Obs.from_numpy(obs_np)
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    st = np.zeros_like(prm)
+    st[0, 0] = st[1, 0] = 2e-3
+    st[2, 0], st[3, 0], st[4, 0], st[6, 0] = 2e-4, 2e-3, 2e-3, 0.5
+    st[6, 1:] = 0.2
+    state, step = dev(prm), dev(st)
+    mom = torch.randn(prm.shape, dtype=torch.float64, device="cuda")
+    u = torch.rand(1, dtype=torch.float64, device="cuda")
+    L = 10
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        lens.hmc_step(state.clone(), obs, step, L, mom, u, ctx=ctx)
+    torch.cuda.current_stream().wait_stream(s)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        _, acc = lens.hmc_step(state, obs, step, L, mom, u, ctx=ctx)
+    n_acc = torch.zeros(1, dtype=torch.int64, device="cuda")
+
+    def hmc():
+        mom.normal_()
+        u.uniform_()
+        graph.replay()
+        n_acc.add_(acc)
+
+    dt = time_steps(torch, hmc, 50, 5)
+    hmc_res = dict(ms_per_step=dt * 1e3, leapfrog_steps_per_s=L / dt, acceptance=float(n_acc.item()) / 55,
+                   free_parameters=int((st != 0).sum()), n_leapfrog=L)
+    del graph
+    B, n = 256, prm.shape[1]
+    grid = S.WORKLOADS[5].grid
+    states = dev(np.tile(prm, (1, B)))
+    layout = lens.BatchLayout([b * n for b in range(B + 1)], [grid] * B)
+    chi2 = lens.lens_image_chi2_batched(states, layout, obs, ctx=ctx).chi2.clone()
+    mh_st = dev(st * 0.5)
+    noise = torch.empty_like(states)
+    uu = torch.empty(B, dtype=torch.float64, device="cuda")
+    accs = []
+
+    def mh():
+        noise.normal_()
+        uu.uniform_()
+        accs.append(lens.mh_step_batched(states, B, grid, obs, mh_st, noise, uu, chi2, ctx=ctx))
+
+    dt = time_steps(torch, mh, 5, 1)
+    rate = float(torch.stack(accs).double().mean().item())
+    mh_res = dict(chains=B, ms_per_step=dt * 1e3, chain_steps_per_s=B / dt, acceptance=rate,
+                  grid=f"{grid.nx}x{grid.ny}", precision="mixed")
+    return {"hmc_source_plane": hmc_res, "metropolis_image_plane": mh_res}
 
 
 def backward_bench(torch, lens, ctx, obs, args):
@@ -341,6 +402,7 @@ def main():
     ap.add_argument("--batch", type=int, default=1024, help="samples of the batched leg (0 skips it)")
     ap.add_argument("--batch-steps", type=int, default=5, help="timed replays of the batched leg")
     ap.add_argument("--no-backward", dest="backward", action="store_false", help="skip the backward leg")
+    ap.add_argument("--no-sampler", dest="sampler", action="store_false", help="skip the sampler-step leg")
     ap.add_argument("--no-paper", dest="paper", action="store_false",
                     help="skip the paper's own benchmark (6730^2 SIE gradient, mixed / FP64 / FP32)")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
@@ -365,7 +427,7 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    prm, grid, obs_np, n_tri, res, large, batched, backward, tuned, paper = gpu_bench(args)
+    prm, grid, obs_np, n_tri, res, large, batched, backward, tuned, paper, sampler = gpu_bench(args)
     mixed, fp64 = res["mixed"], res["fp64"]
     step_s = mixed["graph_s"]
     evals = grid.nx * grid.ny * prm.shape[1]
@@ -421,6 +483,7 @@ def main():
         "batched": batched,
         "backward": backward,
         "paper_benchmark": paper,
+        "sampler": sampler,
         "autotuned": {k: {"tile": t, "field_npl": n} for k, (t, n) in tuned.items() if t} or None,
         "cpu_baseline": cpu,
         "parity": parity,
