@@ -76,6 +76,8 @@ def _load():
         u8p = C.POINTER(C.c_uint8)
         lib.orc_dp_patches.argtypes = [dp, i, i, i, i, d, d, d, i, i, u8p]
         lib.orc_criteria.argtypes = [dp, dp, i, i, d, d, d, u8p]
+        lib.orc_nfw_alpha.argtypes = [dp, i, d, d, dp, dp]
+        lib.orc_nfw_alpha_grid.argtypes = [dp, i, d, d, d, i, i, dp, dp, i]
         _lib = lib
     return _lib
 
@@ -396,3 +398,27 @@ def mh_accept(chi2_new: float, chi2_cur: float, u: float, valid: bool) -> bool:
     if not valid or not np.isfinite(chi2_new):
         return False
     return (not np.isfinite(chi2_cur)) or math.log(u) < -0.5 * (chi2_new - chi2_cur)
+
+
+# ---------------------------------------------------------------- pseudo-elliptical NFW
+
+def _nfw(prm):
+    prm = np.ascontiguousarray(prm, dtype=np.float64)
+    if prm.ndim != 2 or prm.shape[0] != 6:
+        raise ValueError("NFW parameters must be [6, P]: x, y, eps, phi, r_s, kappa_s")
+    return prm, prm.ctypes.data_as(C.POINTER(C.c_double)), prm.shape[1]
+
+
+def nfw_alpha(prm, t1: float, t2: float):
+    prm, pp, n = _nfw(prm)
+    a1, a2 = C.c_double(), C.c_double()
+    _load().orc_nfw_alpha(pp, n, t1, t2, C.byref(a1), C.byref(a2))
+    return a1.value, a2.value
+
+
+def nfw_alpha_grid(prm, grid, nthreads: int | None = None):
+    prm, pp, n = _nfw(prm)
+    ax, ay = np.empty((grid.ny, grid.nx)), np.empty((grid.ny, grid.nx))
+    _load().orc_nfw_alpha_grid(pp, n, grid.x0, grid.y0, grid.h, grid.nx, grid.ny, _d(ax)[1], _d(ay)[1],
+                               nthreads or default_threads())
+    return ax, ay

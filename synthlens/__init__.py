@@ -264,3 +264,32 @@ def paper_sie_cluster(grid: Grid, n_galaxies: int = PAPER_GALAXIES, seed: int = 
     prm[5, 2:] = np.inf
     prm[6, 2:] = g.uniform(10.0, 15.0, n)
     return prm
+
+
+# --------------------------------------------------------------------------
+# pseudo-elliptical NFW halos (parameter table [6, P]: x, y, eps, phi, r_s, kappa_s)
+# --------------------------------------------------------------------------
+
+NFW_ROWS = ("x", "y", "eps", "phi", "r_s", "kappa_s")
+
+
+def nfw_cluster(grid: Grid, n_galaxies: int = PAPER_GALAXIES, seed: int = 0) -> np.ndarray:
+    """The benchmark cluster of paper_sie_cluster with NFW halos instead of
+    SIEs (reading; the paper only names the profile): two cluster-scale halos
+    at the same places (r_s 40" and 30", kappa_s 0.25 and 0.2, eps 0.05 and
+    0.04) and galaxy-scale halos with r_s ~ U[1, 4]", kappa_s ~ U[0.01, 0.05],
+    eps ~ U[0, 0.15], uniform over the grid."""
+    g = np.random.Generator(np.random.PCG64([SEED_BASE, 300 + seed]))
+    lx, ly = 0.5 * (grid.nx - 1) * grid.h, 0.5 * (grid.ny - 1) * grid.h
+    cx, cy = grid.x0 + lx, grid.y0 + ly
+    prm = np.zeros((6, 2 + n_galaxies))
+    prm[:, 0] = (cx - 0.2 * lx, cy - 0.1 * ly, 0.05, 0.5, 40.0, 0.25)
+    prm[:, 1] = (cx + 0.25 * lx, cy + 0.15 * ly, 0.04, 2.0, 30.0, 0.2)
+    n = n_galaxies
+    prm[0, 2:] = g.uniform(cx - lx, cx + lx, n)
+    prm[1, 2:] = g.uniform(cy - ly, cy + ly, n)
+    prm[2, 2:] = g.uniform(0.0, 0.15, n)
+    prm[3, 2:] = g.uniform(0.0, math.pi, n)
+    prm[4, 2:] = g.uniform(1.0, 4.0, n)
+    prm[5, 2:] = g.uniform(0.01, 0.05, n)
+    return prm

@@ -593,3 +593,73 @@ def test_metropolis_acceptance_rule():
     assert oracle.mh_accept(5.0, 10.0, 0.999999, True)
     assert not oracle.mh_accept(5.0, 10.0, 0.5, False) and not oracle.mh_accept(math.inf, 10.0, 0.5, True)
     assert oracle.mh_accept(1e9, math.inf, 0.999, True)
+
+
+# --------------------------------------------------------------- pseudo-elliptical NFW
+
+def nfw(x=0.0, y=0.0, eps=0.0, phi=0.0, rs=10.0, ks=0.2):
+    p = np.zeros((6, 1))
+    p[:, 0] = (x, y, eps, phi, rs, ks)
+    return p
+
+
+def test_nfw_deflection_is_the_enclosed_projected_density():
+    """The circular NFW deflection alpha(R) = R * (mean convergence inside R),
+    with the convergence obtained by integrating the 3D density
+    rho ~ 1 / (r (1 + r)^2) along the line of sight (scipy quadrature, no
+    closed form involved): alpha = (2 r_s / x) int_0^x x' k(x') dx',
+    k(x') = 2 kappa_s int_0^inf dz / (s (1 + s)^2), s = sqrt(x'^2 + z^2).
+    Catches a wrong F(x) branch, a missing log term or a wrong normalisation."""
+    rs, ks = 10.0, 0.2
+
+    def kappa(xp):
+        f = lambda z: 1.0 / (math.hypot(xp, z) * (1.0 + math.hypot(xp, z)) ** 2)
+        a = integrate.quad(f, 0.0, xp, limit=200, epsabs=0, epsrel=1e-12)[0]
+        b = integrate.quad(f, xp, np.inf, limit=200, epsabs=0, epsrel=1e-12)[0]
+        return 2.0 * ks * (a + b)
+
+    for x in (0.05, 0.5, 0.999, 1.0, 1.001, 2.0, 7.0):
+        inner = integrate.quad(lambda xp: xp * kappa(xp), 0.0, x, limit=200, epsabs=0, epsrel=1e-10)[0]
+        want = 2.0 * rs * inner / x
+        got, zero = oracle.nfw_alpha(nfw(rs=rs, ks=ks), x * rs, 0.0)
+        assert zero == 0.0
+        assert got == pytest.approx(want, rel=1e-7), x
+
+
+def test_nfw_limits_and_continuity():
+    """Series limits of g(x) = ln(x/2) + F(x): x -> 0, g ~ (x^2/2)(ln(2/x) - 1/2);
+    x -> inf, g ~ ln(x/2) + pi/(2x) - 1/x^2; and the three branches of F join
+    continuously at x = 1 (g(1) = 1 - ln 2)."""
+    rs, ks = 10.0, 0.2
+    a = lambda x: oracle.nfw_alpha(nfw(rs=rs, ks=ks), x * rs, 0.0)[0]
+    for x in (1e-3, 1e-4):
+        g = 0.5 * x * x * (math.log(2 / x) - 0.5)
+        assert a(x) == pytest.approx(4 * ks * rs * g / x, rel=3 * x * x * math.log(1 / x))
+    for x in (1e3, 1e4):
+        g = math.log(x / 2) + math.pi / (2 * x) - 1 / x ** 2
+        assert a(x) == pytest.approx(4 * ks * rs * g / x, rel=2 / x ** 3)
+    assert a(1.0) == pytest.approx(4 * ks * rs * (1 - math.log(2)), rel=1e-15)
+    assert abs(a(1 - 1e-9) - a(1.0)) < 1e-8 and abs(a(1 + 1e-9) - a(1.0)) < 1e-8
+
+
+def test_nfw_pseudo_elliptical_field_is_a_rotated_gradient():
+    """Rotating the point about the centre together with Phi rotates the
+    deflection (Algorithm 1's frame change), and the field is curl-free (a
+    gradient of the pseudo-elliptical potential): d a1/d t2 = d a2/d t1 by
+    central differences.  Catches a wrong rotation sign or eps on the wrong axis."""
+    p0 = nfw(x=1.5, y=-2.0, eps=0.3, phi=0.0, rs=8.0, ks=0.3)
+    phi = 0.7
+    p1 = p0.copy()
+    p1[3, 0] = phi
+    c, s = math.cos(phi), math.sin(phi)
+    for d in ((3.0, 1.0), (-0.4, 5.0), (12.0, -9.0)):
+        a0 = np.array(oracle.nfw_alpha(p0, 1.5 + d[0], -2.0 + d[1]))
+        r = (c * d[0] - s * d[1], s * d[0] + c * d[1])
+        a1 = np.array(oracle.nfw_alpha(p1, 1.5 + r[0], -2.0 + r[1]))
+        np.testing.assert_allclose(a1, [c * a0[0] - s * a0[1], s * a0[0] + c * a0[1]], rtol=1e-12, atol=1e-14)
+    p = nfw(x=0.0, y=0.0, eps=0.25, phi=0.4, rs=6.0, ks=0.25)
+    h = 1e-5
+    for t in ((2.0, 1.0), (-7.0, 3.0), (0.5, -0.3)):
+        d12 = (oracle.nfw_alpha(p, t[0], t[1] + h)[0] - oracle.nfw_alpha(p, t[0], t[1] - h)[0]) / (2 * h)
+        d21 = (oracle.nfw_alpha(p, t[0] + h, t[1])[1] - oracle.nfw_alpha(p, t[0] - h, t[1])[1]) / (2 * h)
+        assert d12 == pytest.approx(d21, rel=1e-6, abs=1e-9)
