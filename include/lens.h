@@ -153,6 +153,30 @@ int lens_dls_dos(lens_ctx *ctx, double zl, const double *zs, int32_t n, double o
 int lens_deflect(lens_ctx *ctx, const lens_potentials *pot, const lens_grid *grid,
                  lens_precision prec, void *ax, void *ay, int32_t *status, hipStream_t stream);
 
+/* Pseudo-elliptical NFW halos (structure of arrays, DEVICE pointers, double,
+ * length n): the second profile family the paper names (Sec. 5), in the frame
+ * construction of Algorithm 1 (Sec. 2.2.2). */
+typedef struct {
+    int32_t n;
+    const double *x, *y;     /* centre [arcsec]                                        */
+    const double *eps;       /* pseudo-ellipticity of the potential, 0 <= eps < 1      */
+    const double *phi;       /* position angle [rad]                                   */
+    const double *r_s;       /* scale radius [arcsec], > 0                             */
+    const double *kappa_s;   /* characteristic convergence rho_s r_s / Sigma_cr, >= 0  */
+} lens_nfw;
+
+/* Deflection gradient of NFW halos at every node: with m = M (theta - centre),
+ * R^2 = (theta - centre) . m as in Algorithm 1 and x = R / r_s,
+ *     alpha = sum over halos of 4 kappa_s g(x)/x^2 m,  g(x) = ln(x/2) + F(x),
+ *     F = arccosh(1/x)/sqrt(1 - x^2) (x < 1), 1 (x = 1), arccos(1/x)/sqrt(x^2 - 1) (x > 1)
+ * (Bartelmann 1996); a node at a centre gets 0 from that halo.  prec =
+ * LENS_FP64: ax, ay double [ny*nx]; LENS_FP32: float [ny*nx] (node offsets from
+ * an exact split of each centre, as the FP32 isothermal field).  status: device
+ * int32 [1] or NULL: LENS_OK, or LENS_ERR_INVALID for a halo outside the domain
+ * (outputs NaN). */
+int lens_deflect_nfw(lens_ctx *ctx, const lens_nfw *halos, const lens_grid *grid, lens_precision prec, void *ax,
+                     void *ay, int32_t *status, hipStream_t stream);
+
 /* Options of the paper's mixed-precision gradient (Sec. 3.2, 3.3, Appendix A.3). */
 typedef struct {
     int32_t n_cluster;      /* the first n_cluster potentials are the cluster-scale halos      */

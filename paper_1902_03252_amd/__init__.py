@@ -155,6 +155,31 @@ def lens_deflect(params: torch.Tensor, grid, prec: str = "fp64", ctx: Context | 
     return ax, ay
 
 
+def lens_deflect_nfw(halos: torch.Tensor, grid, prec: str = "fp64", ctx: Context | None = None,
+                     check: bool = True):
+    """Deflection of pseudo-elliptical NFW halos ([6, n] float64 table: x, y,
+    eps, phi, r_s, kappa_s) at every node: (ax, ay) [ny, nx], float64 for
+    'fp64', float32 for 'fp32'."""
+    ctx = ctx or context(halos.device.index)
+    if prec not in ("fp64", "fp32"):
+        raise ValueError("prec must be 'fp64' or 'fp32'")
+    _require_cuda(halos, torch.float64, "halos")
+    if halos.dim() != 2 or halos.shape[0] != 6:
+        raise ValueError("halos must be a [6, n] table")
+    n = halos.shape[1]
+    rows = [halos[k].data_ptr() if n else None for k in range(6)]
+    h = L.LensNfw(n, *rows)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    ax = torch.empty((grid.ny, grid.nx), dtype=dt, device=halos.device)
+    ay = torch.empty_like(ax)
+    status = torch.zeros(1, dtype=torch.int32, device=halos.device)
+    L.check(ctx._lib.lens_deflect_nfw(ctx.handle, C.byref(h), C.byref(_grid(grid)), _PREC[prec], L.ptr(ax),
+                                      L.ptr(ay), L.ptr(status), ctx.stream()), "lens_deflect_nfw")
+    if check and int(status.item()) != L.LENS_OK:
+        raise RuntimeError(f"lens_deflect_nfw: invalid halo parameters (status {int(status.item())})")
+    return ax, ay
+
+
 @dataclasses.dataclass
 class MixedResult:
     ax: torch.Tensor     # [ny, nx] float64

@@ -20,10 +20,10 @@ STAT_HITS, STAT_FLAGGED, STAT_TILE_PASS, STAT_BBOX_PASS, STAT_STATUS, STAT_FB_HI
 STAT_N = 8
 
 EXPORTS = ("lens_create", "lens_destroy", "lens_dls_dos", "lens_deflect", "lens_deflect_mixed",
-           "lens_source_positions", "lens_image_chi2", "lens_image_chi2_batched", "lens_deflect_backward",
-           "lens_src_chi2", "lens_src_chi2_backward", "lens_hmc_step", "lens_mh_step_batched",
-           "lens_autotune_chi2", "lens_autotune_chi2_batched", "lens_autotune_lookup", "lens_autotune_save",
-           "lens_autotune_load", "lens_set_timing", "lens_field_timing", "lens_strerror")
+           "lens_deflect_nfw", "lens_source_positions", "lens_image_chi2", "lens_image_chi2_batched",
+           "lens_deflect_backward", "lens_src_chi2", "lens_src_chi2_backward", "lens_hmc_step",
+           "lens_mh_step_batched", "lens_autotune_chi2", "lens_autotune_chi2_batched", "lens_autotune_lookup",
+           "lens_autotune_save", "lens_autotune_load", "lens_set_timing", "lens_field_timing", "lens_strerror")
 
 
 class LensPotentials(C.Structure):
@@ -38,6 +38,11 @@ class LensGrid(C.Structure):
 class LensObs(C.Structure):
     _fields_ = [("n_sys", C.c_int32), ("n_img", C.c_int32), ("sys_off", C.c_void_p), ("x", C.c_void_p),
                 ("y", C.c_void_p), ("sigma", C.c_void_p), ("dls_dos", C.c_void_p)]
+
+
+class LensNfw(C.Structure):
+    _fields_ = [("n", C.c_int32), ("x", C.c_void_p), ("y", C.c_void_p), ("eps", C.c_void_p), ("phi", C.c_void_p),
+                ("r_s", C.c_void_p), ("kappa_s", C.c_void_p)]
 
 
 class LensMixedOpts(C.Structure):
@@ -81,6 +86,8 @@ def load(path: str = LIB_PATH):
     lib.lens_dls_dos.restype = C.c_int
     lib.lens_deflect.argtypes = [vp, C.POINTER(LensPotentials), C.POINTER(LensGrid), C.c_int, vp, vp, vp, vp]
     lib.lens_deflect.restype = C.c_int
+    lib.lens_deflect_nfw.argtypes = [vp, C.POINTER(LensNfw), C.POINTER(LensGrid), C.c_int, vp, vp, vp, vp]
+    lib.lens_deflect_nfw.restype = C.c_int
     lib.lens_deflect_mixed.argtypes = [vp, C.POINTER(LensPotentials), C.POINTER(LensGrid), C.POINTER(LensMixedOpts),
                                        vp, vp, vp, vp, vp]
     lib.lens_deflect_mixed.restype = C.c_int

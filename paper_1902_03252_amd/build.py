@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "liblens.so")
-SOURCES = ["lens_kernels.hip", "lens_batched.hip", "lens_backward.hip", "lens_api.hip", "lens_tune.hip", "lens_mixed.hip", "lens_sampler.hip"]
+SOURCES = ["lens_kernels.hip", "lens_batched.hip", "lens_backward.hip", "lens_api.hip", "lens_tune.hip", "lens_mixed.hip", "lens_sampler.hip", "lens_nfw.hip"]
 ARCH = "gfx950"
 
 

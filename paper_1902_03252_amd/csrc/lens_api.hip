@@ -18,7 +18,7 @@ using namespace lens;
 namespace {
 
 enum Buf { B_TAB64, B_TAB32, B_BTERM, B_FIELD, B_BX, B_BY, B_SYS, B_STATE, B_HITS, B_FLAGS, B_POS, B_CONTRIB,
-           B_PART, B_BCOUNT, B_VJP, B_SRC, B_SRCST, B_RR, B_PAIRS, B_MIX, B_MLIST, B_MMASK, B_HMC, B_MHP, B_NBUF };
+           B_PART, B_BCOUNT, B_VJP, B_SRC, B_SRCST, B_RR, B_PAIRS, B_MIX, B_MLIST, B_MMASK, B_HMC, B_MHP, B_NFW, B_NBUF };
 
 // Device work plan of one chunk of a batch (see lens_image_chi2_batched).
 struct PlanChunk {
@@ -450,6 +450,35 @@ int lens_deflect_mixed(lens_ctx* ctx, const lens_potentials* pot, const lens_gri
     KernelEvents kev;
     if ((rc = timing_begin(ctx, &kev, &ml.ev, &slot))) return rc;
     if (launch_mixed(pot_ptrs(pot), g, ml, stream) != hipSuccess) return LENS_ERR_DEVICE;
+    timing_end(ctx, slot);
+    return LENS_OK;
+}
+
+int lens_deflect_nfw(lens_ctx* ctx, const lens_nfw* halos, const lens_grid* grid, lens_precision prec, void* ax,
+                     void* ay, int32_t* status, hipStream_t stream)
+{
+    if (!ctx || !halos || halos->n < 0 || check_grid(grid) || !ax || !ay) return LENS_ERR_INVALID;
+    if (halos->n > 0 && (!halos->x || !halos->y || !halos->eps || !halos->phi || !halos->r_s || !halos->kappa_s))
+        return LENS_ERR_INVALID;
+    if (prec != LENS_FP64 && prec != LENS_FP32) return LENS_ERR_INVALID;
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return LENS_ERR_DEVICE;
+    int rc;
+    if ((rc = ensure(ctx, B_NFW, nfw_scratch(halos->n)))) return rc;
+    NfwPtrs h;
+    h.n = halos->n;
+    h.x = halos->x;
+    h.y = halos->y;
+    h.eps = halos->eps;
+    h.phi = halos->phi;
+    h.r_s = halos->r_s;
+    h.kappa_s = halos->kappa_s;
+    int slot;
+    KernelEvents kev;
+    const KernelEvents* ev;
+    if ((rc = timing_begin(ctx, &kev, &ev, &slot))) return rc;
+    if (launch_nfw(h, grid_desc(grid), prec == LENS_FP32, ax, ay, status, ctx->buf[B_NFW], ev, stream) != hipSuccess)
+        return LENS_ERR_DEVICE;
     timing_end(ctx, slot);
     return LENS_OK;
 }

@@ -13,6 +13,12 @@ struct PotPtrs {
     const double *x, *y, *eps, *phi, *r_core, *r_cut, *sigma_v;
 };
 
+// Pseudo-elliptical NFW halos (structure of arrays, device pointers).
+struct NfwPtrs {
+    int n;
+    const double *x, *y, *eps, *phi, *r_s, *kappa_s;
+};
+
 struct GridDesc {
     double x0, y0, h;
     int nx, ny;
@@ -157,6 +163,10 @@ struct MixedLaunch {
 };
 
 hipError_t launch_mixed(const PotPtrs& pot, const GridDesc& g, const MixedLaunch& ml, hipStream_t s);
+
+size_t nfw_scratch(int np);  // bytes of device scratch of launch_nfw
+hipError_t launch_nfw(const NfwPtrs& h, const GridDesc& g, bool fp32, void* ax, void* ay, int* status,
+                      void* scratch, const KernelEvents* ev, hipStream_t s);
 
 hipError_t launch_hmc_begin(const double* state, const double* momentum, const double* step, int n7, double* q,
                             double* p, hipStream_t s);
