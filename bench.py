@@ -187,10 +187,11 @@ def gpu_bench(args):
     batched = batched_bench(torch, lens, ctx, obs, obs_np, args, tuned) if args.batch > 0 else None
     paper = paper_bench(torch, lens, ctx, args) if args.paper else None
     sampler = sampler_bench(torch, lens, ctx, args) if args.sampler else None
+    precision = precision_bench(torch, lens, ctx, args) if args.paper else None
     backward = backward_bench(torch, lens, ctx, obs, args) if args.backward else None
     if args.tune_cache:
         lens.autotune_save(args.tune_cache, ctx=ctx)
-    return prm, grid, obs_np, n_tri, res, large, batched, backward, tuned, paper, sampler
+    return prm, grid, obs_np, n_tri, res, large, batched, backward, tuned, paper, sampler, precision
 
 
 def paper_bench(torch, lens, ctx, args):
@@ -230,6 +231,53 @@ def paper_bench(torch, lens, ctx, args):
     res["workload"] = (f"{grid.nx}^2 pixels of {grid.h} arcsec, 2 + {prm.shape[1] - 2} SIE halos, "
                        f"{evals:.3e} pixel-potential evaluations (Sec. 4); other hardware's times are context")
     return res
+
+
+def sp_safe(torch, a32, a64, h):
+    """FP32 error against FP64 and the share of pixels where single precision
+    is accurate enough: |error_i| <= 7.5e-3" / M_i (a quarter pixel of 0.03"
+    over the magnification along axis i, Sec. 3.2), with M_i = dx / |dx - d_i|
+    from the FP64 field (d_1, d_2 the differences of Sec. 3.3)."""
+    ex = (a32[0].double() - a64[0]).abs()
+    ey = (a32[1].double() - a64[1]).abs()
+    d1 = torch.zeros_like(a64[0])
+    d2 = torch.zeros_like(a64[1])
+    d1[:, 1:] = a64[0][:, 1:] - a64[0][:, :-1]
+    d2[1:, :] = a64[1][1:, :] - a64[1][:-1, :]
+    ok = (ex <= 7.5e-3 * (h - d1).abs() / h) & (ey <= 7.5e-3 * (h - d2).abs() / h)
+    e = torch.maximum(ex, ey)
+    return dict(fp32_max_err_arcsec=float(e.max()), frac_within_2p3e_3=float((e <= 2.3e-3).double().mean()),
+                frac_sp_safe_with_magnification=float(ok.double().mean()))
+
+
+def precision_bench(torch, lens, ctx, args):
+    """The precision study the paper asks for beyond the SIE (Sec. 5): on the
+    benchmark image (6730^2 pixels of 0.03"), the FP32 field against the FP64
+    field for the SIE cluster (2 + 700 halos) and for the same cluster of
+    pseudo-elliptical NFW halos, with the FP32 / FP64 field times."""
+    import synthlens as S
+    grid = S.paper_grid()
+    out = {}
+    for name, prm, fn in (("sie", S.paper_sie_cluster(grid), lens.lens_deflect),
+                          ("nfw", S.nfw_cluster(grid), lens.lens_deflect_nfw)):
+        p = torch.as_tensor(prm, dtype=torch.float64, device="cuda")
+        res = {}
+        fields = {}
+        for prec in ("fp32", "fp64"):
+            ctx.set_timing(True)
+            ctx.field_timing(reset=True)
+            dt = time_steps(torch, lambda: fn(p, grid, prec, ctx=ctx, check=False), 3, 1)
+            kms, nl = ctx.field_timing(reset=True)
+            ctx.set_timing(False)
+            fields[prec] = fn(p, grid, prec, ctx=ctx)
+            res[f"{prec}_ms"] = dt * 1e3
+            res[f"{prec}_field_kernel_ms"] = kms / max(nl, 1)
+        res.update(sp_safe(torch, fields["fp32"], fields["fp64"], grid.h))
+        res["halos"] = int(prm.shape[1])
+        out[name] = res
+        del fields
+    out["workload"] = f"{grid.nx}^2 pixels of {grid.h} arcsec; SIE and NFW clusters of 2 + 700 halos"
+    return out
 
 
 def sampler_bench(torch, lens, ctx, args):
@@ -427,7 +475,7 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    prm, grid, obs_np, n_tri, res, large, batched, backward, tuned, paper, sampler = gpu_bench(args)
+    prm, grid, obs_np, n_tri, res, large, batched, backward, tuned, paper, sampler, precision = gpu_bench(args)
     mixed, fp64 = res["mixed"], res["fp64"]
     step_s = mixed["graph_s"]
     evals = grid.nx * grid.ny * prm.shape[1]
@@ -484,6 +532,7 @@ def main():
         "backward": backward,
         "paper_benchmark": paper,
         "sampler": sampler,
+        "precision_study": precision,
         "autotuned": {k: {"tile": t, "field_npl": n} for k, (t, n) in tuned.items() if t} or None,
         "cpu_baseline": cpu,
         "parity": parity,
