@@ -254,16 +254,22 @@ void timing_end(lens_ctx* c, int slot)
 
 // Constants, source positions, barycentres and error bound: the head of every
 // entry point (obs may have no systems and no images).
-int head(lens_ctx* c, const lens_potentials* pot, const GridDesc& g, const ObsPtrs& obs, double* bx, double* by,
-         hipStream_t s)
+int head_buffers(lens_ctx* c, int np, const ObsPtrs& obs)
 {
-    const int np = pot->n;
     int rc;
     if ((rc = ensure(c, B_TAB64, (size_t)np * T64_STRIDE * 8)) ||
         (rc = ensure(c, B_TAB32, (size_t)np * T32_STRIDE * 4)) || (rc = ensure(c, B_BTERM, (size_t)np * 3 * 8)) ||
         (rc = ensure(c, B_SYS, (size_t)(obs.n_sys > 0 ? obs.n_sys : 1) * SYS_STRIDE * 8)) ||
         (rc = ensure(c, B_STATE, sizeof(EvalState))))
         return rc;
+    return LENS_OK;
+}
+
+int head(lens_ctx* c, const lens_potentials* pot, const GridDesc& g, const ObsPtrs& obs, double* bx, double* by,
+         hipStream_t s)
+{
+    int rc;
+    if ((rc = head_buffers(c, pot->n, obs))) return rc;
     if (launch_head(pot_ptrs(pot), g, obs, (double*)c->buf[B_TAB64], (float*)c->buf[B_TAB32],
                     (double*)c->buf[B_BTERM], bx, by, (double*)c->buf[B_SYS], (EvalState*)c->buf[B_STATE],
                     s) != hipSuccess)
@@ -556,7 +562,16 @@ int lens_image_chi2(lens_ctx* ctx, const lens_potentials* pot, const lens_grid* 
     unsigned* part = (unsigned*)ctx->buf[B_PART];
     unsigned long long* pairs = (unsigned long long*)ctx->buf[B_PAIRS];
     unsigned* counts = (unsigned*)(pairs + (size_t)region * n_cull);
-    if ((rc = head(ctx, pot, g, o, (double*)ctx->buf[B_BX], (double*)ctx->buf[B_BY], stream))) return rc;
+    // the head's source-plane part runs inside the field launch when the grid allows
+    const bool fused = fused_head_fits(g, o, npl, mixed) != 0;
+    if (fused) {
+        if ((rc = head_buffers(ctx, np, o))) return rc;
+        if (launch_prep(pot_ptrs(pot), g, (double*)ctx->buf[B_TAB64], (float*)ctx->buf[B_TAB32],
+                        (double*)ctx->buf[B_BTERM], stream) != hipSuccess)
+            return LENS_ERR_DEVICE;
+    } else if ((rc = head(ctx, pot, g, o, (double*)ctx->buf[B_BX], (double*)ctx->buf[B_BY], stream))) {
+        return rc;
+    }
 
     const double* tab64 = (const double*)ctx->buf[B_TAB64];
     double* sysrow = (double*)ctx->buf[B_SYS];
@@ -574,9 +589,25 @@ int lens_image_chi2(lens_ctx* ctx, const lens_potentials* pot, const lens_grid* 
     void* field = ctx->buf[B_FIELD];
     const void* fx = field;
     const void* fy = (const char*)field + nn * vbytes;
-    if (mixed)
+    HeadArgs ha;
+    ha.pot = pot_ptrs(pot);
+    ha.g = g;
+    ha.obs = o;
+    ha.tab64 = tab64;
+    ha.bterm = (const double*)ctx->buf[B_BTERM];
+    ha.bx = (double*)ctx->buf[B_BX];
+    ha.by = (double*)ctx->buf[B_BY];
+    ha.sysrow = sysrow;
+    ha.st = st;
+    if (mixed && fused)
+        e = launch_field32h((const float*)ctx->buf[B_TAB32], np, g, (float*)field, (float*)field + nn, npl,
+                            (float*)rr, tx_shift, tiles_x, ha, ev, stream);
+    else if (mixed)
         e = launch_field32((const float*)ctx->buf[B_TAB32], np, g, (float*)field, (float*)field + nn, nullptr, npl,
                            (float*)rr, tx_shift, tiles_x, ev, stream);
+    else if (fused)
+        e = launch_field64h(tab64, np, g, (double*)field, (double*)field + nn, (double*)rr, tx_shift, tiles_x, ha,
+                            ev, stream);
     else
         e = launch_field64(tab64, np, g, (double*)field, (double*)field + nn, nullptr, (double*)rr, tx_shift,
                            tiles_x, ev, stream);

@@ -75,6 +75,25 @@ constexpr long long kFlagScratch = 1 << 20;
 constexpr int kMaxSystems = 1 << 19;      // systems fit the packed sort key
 constexpr int kBatchMax = 1024;           // batch: per-sample hit capacity, images and systems
 
+// Arguments of the head's source-plane part when it runs inside a field launch.
+struct HeadArgs {
+    PotPtrs pot;
+    GridDesc g;
+    ObsPtrs obs;
+    const double* tab64;  // prepared by launch_prep
+    const double* bterm;
+    double *bx, *by;      // [n_img] grad Psi, then beta
+    double* sysrow;
+    EvalState* st;
+};
+
+hipError_t launch_prep(const PotPtrs& pot, const GridDesc& g, double* tab64, float* tab32, double* bterm,
+                       hipStream_t s);
+int fused_head_fits(const GridDesc& g, const ObsPtrs& obs, int npl, bool fp32);
+hipError_t launch_field32h(const float* tab32, int np, const GridDesc& g, float* ax, float* ay, int npl, float* rr,
+                           int tx_shift, int tiles_x, const HeadArgs& h, const KernelEvents* ev, hipStream_t s);
+hipError_t launch_field64h(const double* tab64, int np, const GridDesc& g, double* ax, double* ay, double* rr,
+                           int tx_shift, int tiles_x, const HeadArgs& h, const KernelEvents* ev, hipStream_t s);
 hipError_t launch_head(const PotPtrs& pot, const GridDesc& g, const ObsPtrs& obs, double* tab64, float* tab32,
                        double* bterm, double* bx, double* by, double* sysrow, EvalState* st, hipStream_t s);
 hipError_t launch_field32(const float* tab32, int np, const GridDesc& g, float* ax, float* ay,

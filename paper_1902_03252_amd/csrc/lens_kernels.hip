@@ -38,33 +38,51 @@ namespace lens {
 //       E_B = r E_alpha + 4u Theta + 2u r (W + E_alpha) + 2^-25 h + 1e-9,
 //     W = sum_p w_p, Theta = max |theta - barycentre| over the grid; it sets
 //     the status from every domain check and zeroes the counters.
-__global__ __launch_bounds__(256) void k_head(PotPtrs pot, GridDesc g, ObsPtrs obs, double* __restrict__ tab64,
-                                              float* __restrict__ tab32, double* __restrict__ bterm,
-                                              double* __restrict__ beta_x, double* __restrict__ beta_y,
-                                              double* __restrict__ sysrow, EvalState* __restrict__ st)
+// Source-plane part of the head: grad Psi (FP64) at observed images j =
+// wave, wave + n_waves, ... (one wave per image, the potentials over the lanes
+// and a fixed butterfly sum), stored in beta_x/beta_y for head_finish.  TABLE:
+// the prepared table rows are read; otherwise each lane recomputes its rows
+// from the parameters.
+template <bool TABLE>
+__device__ __forceinline__ void head_images(const PotPtrs& pot, const double* __restrict__ tab64,
+                                            const ObsPtrs& obs, double* __restrict__ beta_x,
+                                            double* __restrict__ beta_y, int wave, int n_waves)
 {
-    __shared__ double sw[4], sj[4], sb[4];
-    __shared__ int last, sys_bad;
-    const int t = threadIdx.x;
     const int np = pot.n;
-    for (int p = blockIdx.x * 256 + t; p < np; p += gridDim.x * 256) prep_one(pot, g, p, p, tab64, tab32, bterm);
-    const int nwaves = gridDim.x * 4;
-    for (int j = blockIdx.x * 4 + (t >> 6); j < obs.n_img; j += nwaves) {
+    for (int j = wave; j < obs.n_img; j += n_waves) {
         const double t1 = obs.x[j], t2 = obs.y[j];
-        double s1 = 0.0, s2 = 0.0;
-        for (int p = lane_id(); p < np; p += 64) {
-            double row[T64_STRIDE], K, a1, a2;
-            row64(pot, p, row, K, a1, a2);
-            add_alpha64(row, t1, t2, s1, s2);
+        double a1, a2;
+        if constexpr (TABLE) {
+            alpha64_wave(tab64, np, t1, t2, a1, a2);
+        } else {
+            double s1 = 0.0, s2 = 0.0;
+            for (int p = lane_id(); p < np; p += 64) {
+                double row[T64_STRIDE], K, b1, b2;
+                row64(pot, p, row, K, b1, b2);
+                add_alpha64(row, t1, t2, s1, s2);
+            }
+            a1 = wave_sum(s1);
+            a2 = wave_sum(s2);
         }
-        const double a1 = wave_sum(s1), a2 = wave_sum(s2);
-        if (lane_id() == 0) {  // grad Psi for now; the last workgroup turns it into beta
+        if (lane_id() == 0) {  // grad Psi for now; head_finish turns it into beta
             beta_x[j] = a1;
             beta_y[j] = a2;
         }
     }
-    if (!last_workgroup(&st->head_ticket, &last)) return;
+}
 
+// The last workgroup's part of the head (256 threads): the FP32 error bound
+// E_alpha from the per-potential terms, beta_ij = theta_ij - r_i grad Psi,
+// barycentres and one row per system with its FP32 bound E_B, counters reset
+// and the status.
+__device__ __forceinline__ void head_finish(int np, const GridDesc& g, const ObsPtrs& obs,
+                                            const double* __restrict__ bterm, double* __restrict__ beta_x,
+                                            double* __restrict__ beta_y, double* __restrict__ sysrow,
+                                            EvalState* __restrict__ st)
+{
+    __shared__ double sw[4], sj[4], sb[4];
+    __shared__ int sys_bad;
+    const int t = threadIdx.x;
     double w = 0.0, jt = 0.0, bad = 0.0;
     for (int p = t; p < np; p += 256) {
         w += bterm[3 * p + 0];
@@ -133,6 +151,28 @@ __global__ __launch_bounds__(256) void k_head(PotPtrs pot, GridDesc g, ObsPtrs o
     }
 }
 
+__global__ __launch_bounds__(256) void k_head(PotPtrs pot, GridDesc g, ObsPtrs obs, double* __restrict__ tab64,
+                                              float* __restrict__ tab32, double* __restrict__ bterm,
+                                              double* __restrict__ beta_x, double* __restrict__ beta_y,
+                                              double* __restrict__ sysrow, EvalState* __restrict__ st)
+{
+    __shared__ int last;
+    for (int p = blockIdx.x * 256 + threadIdx.x; p < pot.n; p += gridDim.x * 256)
+        prep_one(pot, g, p, p, tab64, tab32, bterm);
+    head_images<false>(pot, nullptr, obs, beta_x, beta_y, blockIdx.x * 4 + (threadIdx.x >> 6), gridDim.x * 4);
+    if (!last_workgroup(&st->head_ticket, &last)) return;
+    head_finish(pot.n, g, obs, bterm, beta_x, beta_y, sysrow, st);
+}
+
+// Constants of every potential only (the fused field kernels do the rest of
+// the head).
+__global__ __launch_bounds__(256) void k_prep(PotPtrs pot, GridDesc g, double* __restrict__ tab64,
+                                              float* __restrict__ tab32, double* __restrict__ bterm)
+{
+    for (int p = blockIdx.x * 256 + threadIdx.x; p < pot.n; p += gridDim.x * 256)
+        prep_one(pot, g, p, p, tab64, tab32, bterm);
+}
+
 // ============================================================== deflection field
 
 // Each thread owns NPL consecutive nodes of one grid row; a workgroup of 256
@@ -141,14 +181,13 @@ __global__ __launch_bounds__(256) void k_head(PotPtrs pot, GridDesc g, ObsPtrs o
 // set, the kernel also writes the triangle stage's per-(row, tile column)
 // deflection ranges (tile width 1 << tx_shift cells).
 template <int NPL>
-__global__ __launch_bounds__(256) void k_field32(const float* __restrict__ tab32, int np, int nx, int ny,
-                                                 float* __restrict__ ax, float* __restrict__ ay,
-                                                 const EvalState* __restrict__ st, float* __restrict__ rr,
-                                                 int tx_shift, int tiles_x)
+__device__ __forceinline__ void field32_row(const float* __restrict__ tab32, int np, int nx, int j, int bx,
+                                            float* __restrict__ ax, float* __restrict__ ay,
+                                            const EvalState* __restrict__ st, float* __restrict__ rr,
+                                            int tx_shift, int tiles_x)
 {
-    const int j = blockIdx.y;
-    const int i0 = (blockIdx.x * 256 + threadIdx.x) * NPL;
-    if ((int)(blockIdx.x * 256 * NPL) >= nx) return;  // whole workgroup beyond the row
+    const int i0 = (bx * 256 + threadIdx.x) * NPL;
+    if (bx * 256 * NPL >= nx) return;  // whole workgroup beyond the row
     const float fj = (float)j;
     float fi[NPL], sx[NPL], sy[NPL];
 #pragma unroll
@@ -170,16 +209,24 @@ __global__ __launch_bounds__(256) void k_field32(const float* __restrict__ tab32
     }
 }
 
-// FP64 field: one node per thread, the same matrix form in arcsec; with rr
-// set, also the triangle stage's row partials (as k_field32).
-__global__ __launch_bounds__(256) void k_field64(const double* __restrict__ tab64, int np, GridDesc g,
-                                                 double* __restrict__ ax, double* __restrict__ ay,
-                                                 const EvalState* __restrict__ st, double* __restrict__ rr,
+template <int NPL>
+__global__ __launch_bounds__(256) void k_field32(const float* __restrict__ tab32, int np, int nx, int ny,
+                                                 float* __restrict__ ax, float* __restrict__ ay,
+                                                 const EvalState* __restrict__ st, float* __restrict__ rr,
                                                  int tx_shift, int tiles_x)
 {
-    const int j = blockIdx.y;
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if ((int)(blockIdx.x * 256) >= g.nx) return;
+    field32_row<NPL>(tab32, np, nx, blockIdx.y, blockIdx.x, ax, ay, st, rr, tx_shift, tiles_x);
+}
+
+// FP64 field: one node per thread, the same matrix form in arcsec; with rr
+// set, also the triangle stage's row partials (as k_field32).
+__device__ __forceinline__ void field64_row(const double* __restrict__ tab64, int np, const GridDesc& g, int j,
+                                            int bx, double* __restrict__ ax, double* __restrict__ ay,
+                                            const EvalState* __restrict__ st, double* __restrict__ rr, int tx_shift,
+                                            int tiles_x)
+{
+    const int i = bx * 256 + threadIdx.x;
+    if (bx * 256 >= g.nx) return;
     const double t1 = g.x0 + i * g.h, t2 = g.y0 + j * g.h;
     double s1 = 0.0, s2 = 0.0;
     for (int p = 0; p < np; p++) add_alpha64(tab64 + (size_t)p * T64_STRIDE, t1, t2, s1, s2);
@@ -189,6 +236,56 @@ __global__ __launch_bounds__(256) void k_field64(const double* __restrict__ tab6
     const size_t n = (size_t)j * g.nx + i;
     ax[n] = bad ? __builtin_nan("") : s1;
     ay[n] = bad ? __builtin_nan("") : s2;
+}
+
+__global__ __launch_bounds__(256) void k_field64(const double* __restrict__ tab64, int np, GridDesc g,
+                                                 double* __restrict__ ax, double* __restrict__ ay,
+                                                 const EvalState* __restrict__ st, double* __restrict__ rr,
+                                                 int tx_shift, int tiles_x)
+{
+    field64_row(tab64, np, g, blockIdx.y, blockIdx.x, ax, ay, st, rr, tx_shift, tiles_x);
+}
+
+// ---------------------------------------------------------------- head fused into the field launch
+
+// The head's source-plane part (after k_prep) run by the first `head_rows`
+// rows of workgroups of a field launch, which the hardware dispatches first:
+// one wave per observed image reads the prepared FP64 table; the last of these
+// workgroups runs head_finish.  The field workgroups do not depend on it (they
+// read only the FP32 / FP64 tables); the triangle stage after the launch does.
+__device__ __forceinline__ void fused_head(const HeadArgs& h, int head_rows)
+{
+    __shared__ int last;
+    const int nblk = head_rows * gridDim.x;
+    const int b = blockIdx.y * gridDim.x + blockIdx.x;
+    head_images<true>(h.pot, h.tab64, h.obs, h.bx, h.by, b * 4 + (threadIdx.x >> 6), nblk * 4);
+    if (!last_of(&h.st->head_ticket, (unsigned)nblk, &last)) return;
+    head_finish(h.pot.n, h.g, h.obs, h.bterm, h.bx, h.by, h.sysrow, h.st);
+}
+
+template <int NPL>
+__global__ __launch_bounds__(256) void k_field32h(const float* __restrict__ tab32, int np, int nx,
+                                                  float* __restrict__ ax, float* __restrict__ ay,
+                                                  float* __restrict__ rr, int tx_shift, int tiles_x, HeadArgs h,
+                                                  int head_rows)
+{
+    if ((int)blockIdx.y < head_rows) {
+        fused_head(h, head_rows);
+        return;
+    }
+    field32_row<NPL>(tab32, np, nx, blockIdx.y - head_rows, blockIdx.x, ax, ay, nullptr, rr, tx_shift, tiles_x);
+}
+
+__global__ __launch_bounds__(256) void k_field64h(const double* __restrict__ tab64, int np, GridDesc g,
+                                                  double* __restrict__ ax, double* __restrict__ ay,
+                                                  double* __restrict__ rr, int tx_shift, int tiles_x, HeadArgs h,
+                                                  int head_rows)
+{
+    if ((int)blockIdx.y < head_rows) {
+        fused_head(h, head_rows);
+        return;
+    }
+    field64_row(tab64, np, g, blockIdx.y - head_rows, blockIdx.x, ax, ay, nullptr, rr, tx_shift, tiles_x);
 }
 
 // ============================================================== triangle stage
@@ -754,6 +851,51 @@ hipError_t launch_field32(const float* tab32, int np, const GridDesc& g, float* 
     case 4: return launch_ev(ev, k_field32<4>, dim3(cdiv(g.nx, 1024), g.ny), dim3(256), s, tab32, np, g.nx, g.ny, ax, ay, st, rr, tx_shift, tiles_x);
     default: return launch_ev(ev, k_field32<8>, dim3(cdiv(g.nx, 2048), g.ny), dim3(256), s, tab32, np, g.nx, g.ny, ax, ay, st, rr, tx_shift, tiles_x);
     }
+}
+
+hipError_t launch_prep(const PotPtrs& pot, const GridDesc& g, double* tab64, float* tab32, double* bterm,
+                       hipStream_t s)
+{
+    if (pot.n == 0) return hipSuccess;
+    k_prep<<<clampu(cdiv(pot.n, 256), 1, 1024), 256, 0, s>>>(pot, g, tab64, tab32, bterm);
+    return hipGetLastError();
+}
+
+// Rows of head workgroups for a field launch `bx` workgroups wide: one wave
+// per observed image, at least one workgroup (head_finish always runs).
+static int head_rows_for(const ObsPtrs& obs, int bx)
+{
+    const long long blocks = obs.n_img > 0 ? cdiv(obs.n_img, 4) : 1;
+    return (int)((blocks + bx - 1) / bx);
+}
+
+int fused_head_fits(const GridDesc& g, const ObsPtrs& obs, int npl, bool fp32)
+{
+    const int bx = (int)cdiv(g.nx, fp32 ? 256 * npl : 256);
+    return g.ny + head_rows_for(obs, bx) <= 65535;
+}
+
+hipError_t launch_field32h(const float* tab32, int np, const GridDesc& g, float* ax, float* ay, int npl, float* rr,
+                           int tx_shift, int tiles_x, const HeadArgs& h, const KernelEvents* ev, hipStream_t s)
+{
+    const int bx = (int)cdiv(g.nx, 256 * npl);
+    const int hr = head_rows_for(h.obs, bx);
+    const dim3 grid((unsigned)bx, (unsigned)(g.ny + hr));
+    switch (npl) {
+    case 1: return launch_ev(ev, k_field32h<1>, grid, dim3(256), s, tab32, np, g.nx, ax, ay, rr, tx_shift, tiles_x, h, hr);
+    case 2: return launch_ev(ev, k_field32h<2>, grid, dim3(256), s, tab32, np, g.nx, ax, ay, rr, tx_shift, tiles_x, h, hr);
+    case 4: return launch_ev(ev, k_field32h<4>, grid, dim3(256), s, tab32, np, g.nx, ax, ay, rr, tx_shift, tiles_x, h, hr);
+    default: return launch_ev(ev, k_field32h<8>, grid, dim3(256), s, tab32, np, g.nx, ax, ay, rr, tx_shift, tiles_x, h, hr);
+    }
+}
+
+hipError_t launch_field64h(const double* tab64, int np, const GridDesc& g, double* ax, double* ay, double* rr,
+                           int tx_shift, int tiles_x, const HeadArgs& h, const KernelEvents* ev, hipStream_t s)
+{
+    const int bx = (int)cdiv(g.nx, 256);
+    const int hr = head_rows_for(h.obs, bx);
+    return launch_ev(ev, k_field64h, dim3((unsigned)bx, (unsigned)(g.ny + hr)), dim3(256), s, tab64, np, g, ax, ay,
+                     rr, tx_shift, tiles_x, h, hr);
 }
 
 hipError_t launch_field64(const double* tab64, int np, const GridDesc& g, double* ax, double* ay,

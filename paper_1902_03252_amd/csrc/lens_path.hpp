@@ -20,16 +20,21 @@ constexpr double kNodeSplitErr = 2.9802322387695312e-08;  // 2^-25 node units
 // publishes its global writes, then takes a ticket; the one that takes the
 // last ticket sees every other workgroup's writes and resets the ticket for
 // the next launch.
-__device__ __forceinline__ bool last_workgroup(unsigned* ticket, int* s_flag)
+__device__ __forceinline__ bool last_of(unsigned* ticket, unsigned count, int* s_flag)
 {
     __threadfence();
     __syncthreads();
-    if (threadIdx.x == 0) *s_flag = atomicAdd(ticket, 1u) == gridDim.x - 1;
+    if (threadIdx.x == 0) *s_flag = atomicAdd(ticket, 1u) == count - 1;
     __syncthreads();
     if (!*s_flag) return false;
     __threadfence();
     if (threadIdx.x == 0) *ticket = 0;
     return true;
+}
+
+__device__ __forceinline__ bool last_workgroup(unsigned* ticket, int* s_flag)
+{
+    return last_of(ticket, gridDim.x, s_flag);
 }
 
 // ============================================================== prep
