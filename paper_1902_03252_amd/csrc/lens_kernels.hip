@@ -1,20 +1,24 @@
 // HIP kernels of the image-plane chi^2 path for gfx950 (MI355X).
 //
 // One chi^2 evaluation (Rexroth et al. 2019, Sec. 2.2.1-2.2.2, Fig. 1):
-//   k_head   per-potential constants (FP64 and FP32 tables), domain checks,
-//            observed images -> source plane in FP64; the last workgroup
-//            forms the barycentres, the FP32 error bound and one row per
-//            system, and resets the counters
-//   k_field  deflection at every grid node (FP32 or FP64)          <- the time
-//   k_cull   one wave per tile of cells: the tile's deflection range (from the
-//            field kernel's row partials) bounds its source-plane vertices;
-//            every system whose barycentre the bound admits gives a (tile,
-//            system) pair
-//   k_pairs  persistent waves over 64-cell units of the pairs: triangle
-//            containment (FP32 certified signs or FP64 exact), each hit and
-//            each undecided test resolved at once in FP64 with its position
-//   k_tail   one workgroup: sort of the hits, matching of observed to
-//            predicted images, FP64 chi^2 in a fixed order
+//   k_prep    per-potential constants (FP64 and FP32 tables), domain terms
+//   k_field*h deflection at every grid node (FP32 or FP64) and the per-tile
+//             deflection ranges; its first rows of workgroups run the head:
+//             observed images -> source plane in FP64, then (last of them)
+//             the barycentres, the FP32 error bound, one row per system and
+//             the counters                                       <- the time
+//   k_cull    one wave per tile of cells: the tile's deflection range bounds
+//             its source-plane vertices; every system whose barycentre the
+//             bound admits gives a (tile, system) pair
+//   k_pairs   persistent waves over the pairs: triangle containment (FP32
+//             certified signs or FP64 exact); hits and undecided tests
+//             appended
+//   k_fbpos   FP64 re-test of the undecided tests, FP64 position of every hit
+//   k_tail    one workgroup: sort of the hits, matching of observed to
+//             predicted images, FP64 chi^2 in a fixed order
+// k_head (prep and head in one kernel) serves lens_deflect and
+// lens_source_positions, and the chi^2 path when the fused grid would exceed
+// 65535 rows of workgroups.
 #include "lens_path.hpp"
 
 namespace lens {
