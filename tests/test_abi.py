@@ -122,4 +122,45 @@ def test_host_validation_rejects_before_any_device_call(lib):
                             None) == L.LENS_ERR_INVALID
     assert lb.lens_src_chi2_backward(ctx, C.byref(pot2), C.byref(obs), None, None, None, None) == L.LENS_ERR_INVALID
     assert lb.lens_dls_dos(ctx, 0.3, buf, 1, 0.5, 0.7, buf, None) == L.LENS_ERR_INVALID  # not flat
+    # the paper's mixed-precision gradient
+    mo = L.LensMixedOpts(1, 400, 20, 0.0092, 0.0104)
+    assert lb.lens_deflect_mixed(ctx, C.byref(pot2), C.byref(grid), None, buf, buf, None, buf, None) == \
+        L.LENS_ERR_INVALID
+    assert lb.lens_deflect_mixed(ctx, C.byref(pot2), C.byref(grid), C.byref(mo), buf, buf, None, None, None) == \
+        L.LENS_ERR_INVALID  # no stats
+    for bad in (L.LensMixedOpts(5, 400, 20, 0.0092, 0.0104),       # more cluster halos than potentials
+                L.LensMixedOpts(-1, 400, 20, 0.0092, 0.0104),
+                L.LensMixedOpts(1, -4, 20, 0.0092, 0.0104),
+                L.LensMixedOpts(1, 400, 20, float("nan"), 0.0104),
+                L.LensMixedOpts(1, 400, 20, 0.0092, -1.0)):
+        assert lb.lens_deflect_mixed(ctx, C.byref(pot2), C.byref(grid), C.byref(bad), buf, buf, None, buf,
+                                     None) == L.LENS_ERR_INVALID
+    # NFW deflection
+    nfw = L.LensNfw(2, buf, buf, buf, buf, buf, buf)
+    assert lb.lens_deflect_nfw(ctx, None, C.byref(grid), 0, buf, buf, None, None) == L.LENS_ERR_INVALID
+    assert lb.lens_deflect_nfw(ctx, C.byref(L.LensNfw(2, buf, buf, buf, buf, None, buf)), C.byref(grid), 0, buf,
+                               buf, None, None) == L.LENS_ERR_INVALID
+    assert lb.lens_deflect_nfw(ctx, C.byref(L.LensNfw(-1, None, None, None, None, None, None)), C.byref(grid), 0,
+                               buf, buf, None, None) == L.LENS_ERR_INVALID
+    assert lb.lens_deflect_nfw(ctx, C.byref(nfw), C.byref(grid), 2, buf, buf, None, None) == L.LENS_ERR_INVALID
+    # sampler steps
+    assert lb.lens_hmc_step(ctx, buf, 0, C.byref(obs), buf, 5, buf, buf, buf, buf, None) == L.LENS_ERR_INVALID
+    assert lb.lens_hmc_step(ctx, buf, 3, C.byref(obs), buf, 0, buf, buf, buf, buf, None) == L.LENS_ERR_INVALID
+    assert lb.lens_hmc_step(ctx, buf, 3, C.byref(obs), buf, 1001, buf, buf, buf, buf, None) == L.LENS_ERR_INVALID
+    assert lb.lens_hmc_step(ctx, buf, 3, C.byref(obs), buf, 5, None, buf, buf, buf, None) == L.LENS_ERR_INVALID
+    assert lb.lens_mh_step_batched(ctx, buf, 0, 3, C.byref(grid), C.byref(obs), C.byref(opts), buf, buf, buf, buf,
+                                   buf, None) == L.LENS_ERR_INVALID
+    assert lb.lens_mh_step_batched(ctx, buf, 2, 3, C.byref(grid), C.byref(obs), C.byref(opts), buf, None, buf, buf,
+                                   buf, None) == L.LENS_ERR_INVALID
+    assert lb.lens_mh_step_batched(ctx, buf, 2, 3, C.byref(L.LensGrid(0, 0, -1.0, 16, 16)), C.byref(obs),
+                                   C.byref(opts), buf, buf, buf, buf, buf, None) == L.LENS_ERR_INVALID
+    # autotuning: argument checks that fail before the context is used
+    t, npl = C.c_int32(), C.c_int32()
+    assert lb.lens_autotune_chi2(ctx, C.byref(pot2), C.byref(grid), C.byref(obs), C.byref(opts), C.byref(out), 0,
+                                 None, None, None) == L.LENS_ERR_INVALID  # no repetitions
+    assert lb.lens_autotune_lookup(None, 2, 0, 16, 4, C.byref(t), C.byref(npl)) == L.LENS_ERR_INVALID
+    assert lb.lens_autotune_lookup(ctx, 2, 2, 16, 4, C.byref(t), C.byref(npl)) == L.LENS_ERR_INVALID
+    assert lb.lens_autotune_lookup(ctx, 2, 0, 0, 4, C.byref(t), C.byref(npl)) == L.LENS_ERR_INVALID
+    assert lb.lens_autotune_save(ctx, None) == L.LENS_ERR_INVALID
+    assert lb.lens_autotune_load(None, b"/nonexistent") == L.LENS_ERR_INVALID
     assert lb.lens_create(None, 0) == L.LENS_ERR_INVALID
