@@ -78,18 +78,16 @@ __device__ __forceinline__ void dconst(const PotPtrs& pot, int p, double* d)
 }
 
 // Square root and reciprocal square root of a positive argument.  FP64: the
-// hardware estimate of 1/sqrt(x) refined by two Goldschmidt iterations, then
-// one Newton correction of the root (Markstein, "IA-64 and elementary
-// functions", 2000); both results within a few ulp.  FP32: the hardware
-// instructions (1 ulp).
+// hardware estimate of 1/sqrt(x) (relative error below 2^-24 on gfx950,
+// measured) refined by one Goldschmidt iteration (error ~2^-47), then one
+// Newton correction of the root (Markstein, "IA-64 and elementary functions",
+// 2000): the root within a few ulp, the reciprocal within ~2^-46 relative.
+// FP32: the hardware instructions (1 ulp).
 __device__ __forceinline__ void sqrt_rsq(double x, double& s, double& is)
 {
     const double y = __builtin_amdgcn_rsq(x);
     double g = x * y, h = 0.5 * y;
-    double r = fma(-g, h, 0.5);
-    g = fma(g, r, g);
-    h = fma(h, r, h);
-    r = fma(-g, h, 0.5);
+    const double r = fma(-g, h, 0.5);
     g = fma(g, r, g);
     h = fma(h, r, h);
     s = fma(fma(-g, g, x), h, g);
@@ -100,12 +98,12 @@ __device__ __forceinline__ void sqrt_rsq(float x, float& s, float& is)
     s = __builtin_amdgcn_sqrtf(x);
     is = __builtin_amdgcn_rsqf(x);
 }
-// Reciprocal of a positive normal argument: the hardware estimate refined by
-// two Newton-Raphson steps (FP64); the hardware instruction (FP32, 1 ulp).
+// Reciprocal of a positive normal argument: the hardware estimate (2^-24)
+// refined by one Newton-Raphson step (~2^-48) in FP64; the hardware
+// instruction (FP32, 1 ulp).
 __device__ __forceinline__ double brcp(double x)
 {
-    double r = __builtin_amdgcn_rcp(x);
-    r = fma(r, fma(-x, r, 1.0), r);
+    const double r = __builtin_amdgcn_rcp(x);
     return fma(r, fma(-x, r, 1.0), r);
 }
 __device__ __forceinline__ float brcp(float v) { return __builtin_amdgcn_rcpf(v); }

@@ -201,15 +201,13 @@ __global__ __launch_bounds__(256) void k_mix_scan(const double* __restrict__ ax,
         if (bits & (1u << k)) list[pos++] = (unsigned)(c0 + k * 256 + t);
 }
 
-// 1/sqrt(x) in FP64 for a positive normal x: the hardware estimate refined by
-// two Newton-Raphson steps y <- y (3/2 - x y^2 / 2) (quadratic convergence: a
-// 2^-14 estimate is at the rounding level after the second step).
+// 1/sqrt(x) in FP64 for a positive normal x: the hardware estimate (relative
+// error below 2^-24 on gfx950, measured) refined by one Newton-Raphson step
+// y <- y (3/2 - x y^2 / 2), which squares the error: ~2^-47 relative.
 __device__ __forceinline__ double rsq64(double x)
 {
-    const double hx = 0.5 * x;
-    double y = __builtin_amdgcn_rsq(x);
-    y = fma(y, fma(-hx * y, y, 0.5), y);
-    return fma(y, fma(-hx * y, y, 0.5), y);
+    const double y = __builtin_amdgcn_rsq(x);
+    return fma(y, fma(-0.5 * x * y, y, 0.5), y);
 }
 
 // FP64 SIE contribution of table row t at (t1, t2): alpha += K m / R, m = M d,
