@@ -101,7 +101,7 @@ static __device__ void prep_one(const PotPtrs& pot, const GridDesc& g, int p, in
     u[T32_C] = (float)(C * h2);
     u[T32_A2] = (float)(a * a);
     u[T32_S2A2] = sinf ? 1e36f : (float)(s * s - a * a);  // uncut: s = 1e18 (see field32_pot)
-    u[T32_RA] = (float)a;
+    u[T32_RA] = a > 0.0 ? (float)a : 1e-20f;  // singular: A_ = R + 1e-20 (see field32_pot)
     u[T32_RS] = sinf ? 1e18f : (float)s;
     u[T32_K] = (float)(K / g.h);
     reinterpret_cast<int*>(u)[T32_KIND] = (a == 0.0 ? 2 : 0) + (sinf ? 1 : 0);
@@ -144,11 +144,14 @@ __device__ __forceinline__ int system_of(const int* __restrict__ sys_off, int ns
 // branch-free formula for all four radial-profile kinds:
 //     f = (B_ - A_) / (A_ B_),  A_ = sqrt(a^2 + R^2) + a,  B_ = sqrt(s^2 + R^2) + s.
 // An uncut profile is stored with s = 1e18 (s^2 - a^2 = 1e36): B_ = 2e18 in
-// FP32, B_ - A_ rounds to B_, and f = 1/A_ to a few ulps.  a^2 + R^2 is
-// clamped below at 1e-30 arcsec^2, which only matters at the centre of a
-// singular profile: there the offsets are exactly zero, so the contribution
-// is exactly zero (the centre convention); elsewhere the clamp is inactive or
-// inside the FP32 error bound (its Jacobian term).  Offsets from the centre
+// FP32, B_ - A_ rounds to B_, and f = 1/A_ to a few ulps.  A singular
+// profile (a = 0) is stored with a = 1e-20 arcsec in A_ only (a^2 stays 0), so
+// that A_ B_ > 0 everywhere: at the centre the offsets are exactly zero and
+// the contribution is exactly zero (the centre convention); elsewhere the
+// change of f, below 1e-20/R relative, lies inside the FP32 error bound (its
+// Jacobian term).  R^2 cannot round below zero unless it is itself at the
+// rounding level (eps near 1); the first root takes |a^2 + R^2| (a free
+// operand modifier) so that no NaN arises there.  Offsets from the centre
 // use the exact hi/lo split (see the FP32 table); hardware sqrt/rcp (1 ulp)
 // are accounted for in the error bound.
 template <int NPL>
@@ -165,8 +168,8 @@ __device__ __forceinline__ void field32_pot(const float* __restrict__ c, float f
         const float nxv = (fi[k] - cxh) - cxl;
         const float m1 = fmaf(A, nxv, bny);
         const float m2 = fmaf(B, nxv, cny);
-        const float qa2 = fmaxf(fmaf(nxv, m1, fmaf(nyv, m2, a2)), 1e-30f);  // a^2 + R^2
-        const float qa = __builtin_amdgcn_sqrtf(qa2) + ra;
+        const float qa2 = fmaf(nxv, m1, fmaf(nyv, m2, a2));  // a^2 + R^2
+        const float qa = __builtin_amdgcn_sqrtf(fabsf(qa2)) + ra;  // |.|: a source modifier
         const float qs = __builtin_amdgcn_sqrtf(qa2 + s2a2) + rs;
         const float kf = K * ((qs - qa) * __builtin_amdgcn_rcpf(qa * qs));
         sx[k] = fmaf(kf, m1, sx[k]);
