@@ -95,6 +95,30 @@ __device__ __forceinline__ float wave_min(float v)
 
 // ---------------------------------------------------------------- FP64 deflection
 
+// FP64 square root and reciprocal of positive normal arguments from the
+// hardware estimates (relative error below 2^-24 on gfx950, measured): the
+// root by one Goldschmidt iteration and one Newton correction, the reciprocal
+// by two Newton-Raphson steps (Markstein, "IA-64 and elementary functions",
+// 2000); both within about 1 ulp, at half the instructions of the
+// correctly rounded library sequences.  A zero argument gives NaN (callers
+// select the centre case out).
+__device__ __forceinline__ double sqrt_est64(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    return fma(fma(-g, g, x), h, g);
+}
+
+__device__ __forceinline__ double rcp_est64(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+
 // Adds the deflection of the potential in row `t` (FP64 table) at the point
 // (t1, t2) to (s1, s2).
 __device__ __forceinline__ void add_alpha64(const double* __restrict__ t, double t1, double t2,
@@ -106,13 +130,13 @@ __device__ __forceinline__ void add_alpha64(const double* __restrict__ t, double
     const double m2 = t[T64_B] * d1 + t[T64_C] * d2;
     const double R2 = d1 * m1 + d2 * m2;
     const double ra = t[T64_RA];
-    const double qa = sqrt(t[T64_A2] + R2) + ra;
+    const double qa = sqrt_est64(t[T64_A2] + R2) + ra;
     double f;
     if (t[T64_SINF] != 0.0) {
-        f = 1.0 / qa;
+        f = rcp_est64(qa);
     } else {
-        const double qs = sqrt(t[T64_S2] + R2) + t[T64_RS];
-        f = (qs - qa) / (qa * qs);
+        const double qs = sqrt_est64(t[T64_S2] + R2) + t[T64_RS];
+        f = (qs - qa) * rcp_est64(qa * qs);
     }
     if (ra == 0.0 && R2 == 0.0) f = 0.0;  // centre of a singular profile contributes 0
     const double kf = t[T64_K] * f;
