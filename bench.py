@@ -523,7 +523,8 @@ def main():
         "graph_replay_matches_eager": mixed["graph_matches_eager"] and fp64["graph_matches_eager"],
         "fallback": {"flagged_tests": int(st[1]), "tests": int(st[6]), "rate": float(st[1]) / float(st[6]),
                      "fallback_hits": int(st[5]), "hits": int(st[0])},
-        "roofline": {"bound": "alu", "kernel": f"k_field32<{npl}> (FP32 deflection field)",
+        "roofline": {"bound": "alu", "kernel": f"k_field32h<{npl}> (FP32 deflection field; its first workgroups "
+                                                  f"run the head's source-plane part)",
                      "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
                      "flops_per_launch": flops, "avg_launch_ms": mixed["kern_ms"], "launches_timed": mixed["launches"]},
