@@ -957,7 +957,7 @@ extern "C" int lens_deflect_backward(lens_ctx* ctx, const lens_potentials* pot, 
 namespace {
 
 int src_common(lens_ctx* ctx, const lens_potentials* pot, const lens_obs* obs, double* chi2, int32_t* status,
-               const double* g_chi2, double* grad, hipStream_t stream)
+               const double* g_chi2, double* grad, hipStream_t stream, const HmcUpdate* upd = nullptr)
 {
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return LENS_ERR_DEVICE;
@@ -967,7 +967,7 @@ int src_common(lens_ctx* ctx, const lens_potentials* pot, const lens_obs* obs, d
         return rc;
     double* beta = (double*)ctx->buf[B_SRC];
     if (launch_src(pot_ptrs(pot), obs_ptrs(obs), beta, beta + 2 * ni, beta + 4 * ni, (SrcState*)ctx->buf[B_SRCST],
-                   chi2, status, g_chi2, grad, stream) != hipSuccess)
+                   chi2, status, g_chi2, grad, upd, stream) != hipSuccess)
         return LENS_ERR_DEVICE;
     return LENS_OK;
 }
@@ -1027,13 +1027,14 @@ extern "C" int lens_hmc_step(lens_ctx* ctx, double* state, int32_t n, const lens
     int* status_pair = (int*)(chi2_pair + 2);        // [2]
     const lens_potentials qp = table_pots(q, n);
     if (launch_hmc_begin(state, momentum, step, n7, q, pm, stream) != hipSuccess) return LENS_ERR_DEVICE;
-    if ((rc = src_common(ctx, &qp, obs, chi2_pair, status_pair, nullptr, g, stream))) return rc;
-    if (launch_hmc_kick(g, step, n7, 0.5, pm, stream) != hipSuccess) return LENS_ERR_DEVICE;
+    // leapfrog: half kick and drift after the gradient at the start, full kick
+    // and drift after each inner gradient, half kick after the last one
+    HmcUpdate upd = {pm, q, step, 0.5, 1};
+    if ((rc = src_common(ctx, &qp, obs, chi2_pair, status_pair, nullptr, g, stream, &upd))) return rc;
     for (int l = 1; l <= n_leapfrog; l++) {
-        if (launch_hmc_drift(pm, step, n7, q, stream) != hipSuccess) return LENS_ERR_DEVICE;
-        if ((rc = src_common(ctx, &qp, obs, chi2_pair + 1, status_pair + 1, nullptr, g, stream))) return rc;
-        if (launch_hmc_kick(g, step, n7, l < n_leapfrog ? 1.0 : 0.5, pm, stream) != hipSuccess)
-            return LENS_ERR_DEVICE;
+        upd.kick = l < n_leapfrog ? 1.0 : 0.5;
+        upd.drift = l < n_leapfrog ? 1 : 0;
+        if ((rc = src_common(ctx, &qp, obs, chi2_pair + 1, status_pair + 1, nullptr, g, stream, &upd))) return rc;
     }
     if (launch_hmc_accept(state, q, momentum, pm, step, n7, chi2_pair, status_pair, u, chi2, accepted, stream) !=
         hipSuccess)

@@ -444,9 +444,10 @@ __global__ __launch_bounds__(256) void k_src_fwd(PotPtrs pot, ObsPtrs obs, doubl
 }
 
 // One wave per potential: d chi^2/d q = scale * sum_j G_j . d alpha_p(theta_j)/d q.
+// With has_upd, the HMC kick (and drift) of the entries it writes follow.
 __global__ __launch_bounds__(256) void k_src_bwd(PotPtrs pot, ObsPtrs obs, const double* __restrict__ cot,
                                                  const SrcState* __restrict__ st, const double* __restrict__ g_chi2,
-                                                 double* __restrict__ grad)
+                                                 double* __restrict__ grad, HmcUpdate upd, int has_upd)
 {
     __shared__ double sc[4][D_STRIDE];
     const int wave = threadIdx.x >> 6, lane = lane_id();
@@ -464,7 +465,14 @@ __global__ __launch_bounds__(256) void k_src_bwd(PotPtrs pot, ObsPtrs obs, const
     for (int c = 0; c < 7; c++) acc[c] = wave_sum(acc[c]);
     const double scale = g_chi2 ? *g_chi2 : 1.0;
     const bool ok = st->status == kStatusOk;
-    if (lane < 7) grad[(size_t)lane * pot.n + p] = ok ? scale * vjp_combine(d, acc, lane) : __builtin_nan("");
+    if (lane >= 7) return;
+    const size_t k7 = (size_t)lane * pot.n + p;
+    const double gv = ok ? scale * vjp_combine(d, acc, lane) : __builtin_nan("");
+    grad[k7] = gv;
+    if (has_upd && upd.step[k7] != 0.0) {
+        upd.p[k7] -= upd.kick * upd.step[k7] * (0.5 * gv);
+        if (upd.drift) upd.q[k7] += upd.step[k7] * upd.p[k7];
+    }
 }
 
 __global__ void k_status(int* status, int v)
@@ -504,7 +512,8 @@ hipError_t launch_vjp(const PotPtrs& pot, const GridDesc& g, bool fp32, const do
 }
 
 hipError_t launch_src(const PotPtrs& pot, const ObsPtrs& obs, double* beta, double* cot, double* csys,
-                      SrcState* st, double* chi2, int* status, const double* g_chi2, double* grad, hipStream_t s)
+                      SrcState* st, double* chi2, int* status, const double* g_chi2, double* grad,
+                      const HmcUpdate* upd, hipStream_t s)
 {
     long long nb = (obs.n_img + 3) / 4;
     if (nb < 1) nb = 1;
@@ -512,7 +521,9 @@ hipError_t launch_src(const PotPtrs& pot, const ObsPtrs& obs, double* beta, doub
     k_src_fwd<<<(unsigned)nb, 256, 0, s>>>(pot, obs, beta, cot, csys, st, chi2, status);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !grad || pot.n == 0) return e;
-    k_src_bwd<<<(unsigned)((pot.n + 3) / 4), 256, 0, s>>>(pot, obs, cot, st, g_chi2, grad);
+    const HmcUpdate none = {nullptr, nullptr, nullptr, 0.0, 0};
+    k_src_bwd<<<(unsigned)((pot.n + 3) / 4), 256, 0, s>>>(pot, obs, cot, st, g_chi2, grad, upd ? *upd : none,
+                                                          upd ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -155,8 +155,20 @@ int vjp_chunks(const GridDesc& g);
 size_t vjp_scratch(int np, const GridDesc& g);  // bytes of device scratch of launch_vjp
 hipError_t launch_vjp(const PotPtrs& pot, const GridDesc& g, bool fp32, const double* gx, const double* gy,
                       double* scratch, double* grad, int* status, const KernelEvents* ev, hipStream_t s);
+// HMC stages applied by the source-plane gradient kernel to the entries it
+// writes: p -= kick * step * grad / 2, then (drift) q += step * p, where
+// step != 0.
+struct HmcUpdate {
+    double* p;
+    double* q;
+    const double* step;
+    double kick;
+    int drift;
+};
+
 hipError_t launch_src(const PotPtrs& pot, const ObsPtrs& obs, double* beta, double* cot, double* csys,
-                      SrcState* st, double* chi2, int* status, const double* g_chi2, double* grad, hipStream_t s);
+                      SrcState* st, double* chi2, int* status, const double* g_chi2, double* grad,
+                      const HmcUpdate* upd, hipStream_t s);
 
 // Device state of the mixed-precision SIE gradient (reset by its first kernel).
 struct MixState {
@@ -189,8 +201,6 @@ hipError_t launch_nfw(const NfwPtrs& h, const GridDesc& g, bool fp32, void* ax, 
 
 hipError_t launch_hmc_begin(const double* state, const double* momentum, const double* step, int n7, double* q,
                             double* p, hipStream_t s);
-hipError_t launch_hmc_kick(const double* grad, const double* step, int n7, double c, double* p, hipStream_t s);
-hipError_t launch_hmc_drift(const double* p, const double* step, int n7, double* q, hipStream_t s);
 hipError_t launch_hmc_accept(double* state, const double* q, const double* momentum, const double* p,
                              const double* step, int n7, const double* chi2_pair, const int* status_pair,
                              const double* u, double* chi2, int* accepted, hipStream_t s);

@@ -2,8 +2,9 @@
 // paper's sampler (Sec. 2.2.1, whose chi^2 it evaluates) taken by
 //   - Hamiltonian Monte Carlo on the source-plane chi^2 (potential energy
 //     U = chi^2 / 2, unit masses in the coordinates z = q / step, leapfrog
-//     integration, Metropolis acceptance on the energy error), every leapfrog
-//     stage a device kernel between the source-plane chi^2 / gradient kernels;
+//     integration, Metropolis acceptance on the energy error): the momentum
+//     kicks and position drifts are applied by the source-plane gradient
+//     kernel to the entries it writes, so a leapfrog step is two kernels;
 //   - independent random-walk Metropolis chains on the image-plane chi^2
 //     (log-likelihood -chi^2 / 2), all chains' proposals evaluated by one
 //     batched chi^2 call.
@@ -25,25 +26,6 @@ __global__ __launch_bounds__(256) void k_hmc_begin(const double* __restrict__ st
     if (k >= n7) return;
     q[k] = state[k];
     p[k] = step[k] != 0.0 ? momentum[k] : 0.0;
-}
-
-// Momentum kick p -= c * step * dU/dq with dU/dq = grad chi^2 / 2 (c = 1/2 for
-// the half steps, 1 otherwise).
-__global__ __launch_bounds__(256) void k_hmc_kick(const double* __restrict__ grad, const double* __restrict__ step,
-                                                  int n7, double c, double* __restrict__ p)
-{
-    const int k = blockIdx.x * 256 + threadIdx.x;
-    if (k >= n7 || step[k] == 0.0) return;
-    p[k] -= c * step[k] * (0.5 * grad[k]);
-}
-
-// Position drift q += step * p.
-__global__ __launch_bounds__(256) void k_hmc_drift(const double* __restrict__ p, const double* __restrict__ step,
-                                                   int n7, double* __restrict__ q)
-{
-    const int k = blockIdx.x * 256 + threadIdx.x;
-    if (k >= n7 || step[k] == 0.0) return;
-    q[k] += step[k] * p[k];
 }
 
 // H = chi^2 / 2 + |p|^2 / 2 before (momentum input) and after (p) the
@@ -140,18 +122,6 @@ hipError_t launch_hmc_begin(const double* state, const double* momentum, const d
                             double* p, hipStream_t s)
 {
     k_hmc_begin<<<blocks_for(n7), 256, 0, s>>>(state, momentum, step, n7, q, p);
-    return hipGetLastError();
-}
-
-hipError_t launch_hmc_kick(const double* grad, const double* step, int n7, double c, double* p, hipStream_t s)
-{
-    k_hmc_kick<<<blocks_for(n7), 256, 0, s>>>(grad, step, n7, c, p);
-    return hipGetLastError();
-}
-
-hipError_t launch_hmc_drift(const double* p, const double* step, int n7, double* q, hipStream_t s)
-{
-    k_hmc_drift<<<blocks_for(n7), 256, 0, s>>>(p, step, n7, q);
     return hipGetLastError();
 }
 
