@@ -171,7 +171,7 @@ __global__ __launch_bounds__(256) void k_bfield32(BatchPlan bp, const int* __res
         sx[q] = 0.0f;
         sy[q] = 0.0f;
     }
-    field32_all<NPL>(tab, np, fj, fi, sx, sy);
+    field32_all_wg<NPL>(tab, np, fj, fi, sx, sy);
     const int tiles_x = (g.nx - 2) / (1 << bp.tx_shift) + 1;
     tile_partials<float, NPL>(sx, sy, i0, j, g.nx, bp.tx_shift, tiles_x, rr + bp.rr_off[s]);
     const size_t row = (size_t)bp.node_off[s] + (size_t)j * g.nx;
@@ -201,7 +201,7 @@ __global__ __launch_bounds__(256) void k_bfield64(BatchPlan bp, const int* __res
     const int np = bp.pot_off[s + 1] - bp.pot_off[s];
     const double t1 = g.x0 + i * g.h, t2 = g.y0 + j * g.h;
     double s1 = 0.0, s2 = 0.0;
-    for (int p = 0; p < np; p++) add_alpha64(tab + (size_t)p * T64_STRIDE, t1, t2, s1, s2);
+    alpha64_all_wg(tab, np, t1, t2, s1, s2);
     const int tiles_x = (g.nx - 2) / (1 << bp.tx_shift) + 1;
     tile_partials<double, 1>(&s1, &s2, i, j, g.nx, bp.tx_shift, tiles_x, rr + bp.rr_off[s]);
     if (i >= g.nx) return;

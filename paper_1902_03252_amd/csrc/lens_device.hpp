@@ -119,16 +119,27 @@ __device__ __forceinline__ double rcp_est64(double x)
     return fma(r, fma(-x, r, 1.0), r);
 }
 
+// The row part of a potential's FP64 deflection at ordinate t2: d2 = t2 - y_c
+// and the products B d2, C d2, common to every point of that ordinate.
+struct Row64 {
+    double d2, bd2, cd2;
+};
+
+__device__ __forceinline__ Row64 alpha64_rowc(const double* __restrict__ t, double t2)
+{
+    const double d2 = t2 - t[T64_YC];
+    return {d2, t[T64_B] * d2, t[T64_C] * d2};
+}
+
 // Adds the deflection of the potential in row `t` (FP64 table) at the point
-// (t1, t2) to (s1, s2).
-__device__ __forceinline__ void add_alpha64(const double* __restrict__ t, double t1, double t2,
-                                            double& s1, double& s2)
+// (t1, ordinate of rc) to (s1, s2), given the row part rc.
+__device__ __forceinline__ void add_alpha64(const double* __restrict__ t, double t1, const Row64& rc, double& s1,
+                                            double& s2)
 {
     const double d1 = t1 - t[T64_XC];
-    const double d2 = t2 - t[T64_YC];
-    const double m1 = t[T64_A] * d1 + t[T64_B] * d2;
-    const double m2 = t[T64_B] * d1 + t[T64_C] * d2;
-    const double R2 = d1 * m1 + d2 * m2;
+    const double m1 = fma(t[T64_A], d1, rc.bd2);
+    const double m2 = fma(t[T64_B], d1, rc.cd2);
+    const double R2 = fma(d1, m1, rc.d2 * m2);
     const double ra = t[T64_RA];
     const double qa = sqrt_est64(t[T64_A2] + R2) + ra;
     double f;
@@ -142,6 +153,31 @@ __device__ __forceinline__ void add_alpha64(const double* __restrict__ t, double
     const double kf = t[T64_K] * f;
     s1 += kf * m1;
     s2 += kf * m2;
+}
+
+// The same at the point (t1, t2).
+__device__ __forceinline__ void add_alpha64(const double* __restrict__ t, double t1, double t2, double& s1,
+                                            double& s2)
+{
+    add_alpha64(t, t1, alpha64_rowc(t, t2), s1, s2);
+}
+
+// Deflection at (t1, t2) of every potential of the FP64 table, for a
+// workgroup of 256 threads whose points share the ordinate t2 (all threads
+// call it): the row parts of up to 256 potentials at a time are computed once,
+// one potential per thread, into LDS.  Same arithmetic as add_alpha64 at
+// (t1, t2).
+__device__ __forceinline__ void alpha64_all_wg(const double* __restrict__ tab, int np, double t1, double t2,
+                                               double& s1, double& s2)
+{
+    __shared__ Row64 srow[256];
+    for (int p0 = 0; p0 < np; p0 += 256) {
+        const int pc = np - p0 < 256 ? np - p0 : 256;
+        if (p0 > 0) __syncthreads();  // the previous chunk has been read
+        if ((int)threadIdx.x < pc) srow[threadIdx.x] = alpha64_rowc(tab + (size_t)(p0 + threadIdx.x) * T64_STRIDE, t2);
+        __syncthreads();
+        for (int p = 0; p < pc; p++) add_alpha64(tab + (size_t)(p0 + p) * T64_STRIDE, t1, srow[p], s1, s2);
+    }
 }
 
 // grad Psi at one point with the potentials split over the 64 lanes of a

@@ -200,7 +200,7 @@ __device__ __forceinline__ void field32_row(const float* __restrict__ tab32, int
         sx[k] = 0.0f;
         sy[k] = 0.0f;
     }
-    field32_all<NPL>(tab32, np, fj, fi, sx, sy);
+    field32_all_wg<NPL>(tab32, np, fj, fi, sx, sy);
     if (rr) tile_partials<float, NPL>(sx, sy, i0, j, nx, tx_shift, tiles_x, rr);
     const bool bad = st != nullptr && st->status != kStatusOk;
     const size_t row = (size_t)j * nx;
@@ -230,10 +230,10 @@ __device__ __forceinline__ void field64_row(const double* __restrict__ tab64, in
                                             int tiles_x)
 {
     const int i = bx * 256 + threadIdx.x;
-    if (bx * 256 >= g.nx) return;
+    if (bx * 256 >= g.nx) return;  // whole workgroup beyond the row
     const double t1 = g.x0 + i * g.h, t2 = g.y0 + j * g.h;
     double s1 = 0.0, s2 = 0.0;
-    for (int p = 0; p < np; p++) add_alpha64(tab64 + (size_t)p * T64_STRIDE, t1, t2, s1, s2);
+    alpha64_all_wg(tab64, np, t1, t2, s1, s2);
     if (rr) tile_partials<double, 1>(&s1, &s2, i, j, g.nx, tx_shift, tiles_x, rr);
     if (i >= g.nx) return;
     const bool bad = st != nullptr && st->status != kStatusOk;
@@ -353,12 +353,105 @@ __global__ __launch_bounds__(256) void k_cull(const V* __restrict__ ax, const V*
     }
 }
 
+// Containment of one (tile, system) pair by one wave: the tile's cells are
+// strided over the lanes, up to four cells per lane per step, with every vertex
+// load of a step issued before any decision.  Mixed path: FP32 vertex offsets
+// and the certified sign test; FP64 path: exact containment on the FP64
+// field's vertices.  Certain hits and undecided tests are appended (system <<
+// 32 | triangle id) with one atomic per wave.  All 64 lanes call it together.
+template <class S, typename V>
+__device__ __forceinline__ void pair_test(const V* __restrict__ ax, const V* __restrict__ ay, const GridDesc& g,
+                                          const Tile& T, int sys, const double* __restrict__ sysrow,
+                                          EvalState* __restrict__ st, int mode, float tau,
+                                          unsigned long long* __restrict__ hit_keys, long long hit_cap,
+                                          unsigned long long* __restrict__ flag_keys, long long flag_cap,
+                                          unsigned& nbbox)
+{
+    constexpr int Q = S::TX * S::TY / 64;  // cells per lane for one pair
+    constexpr int QB = Q < 4 ? Q : 4;      // cells per lane per step
+    const int lane = lane_id();
+    const double* row = sysrow + (size_t)sys * SYS_STRIDE;
+    for (int q0 = 0; q0 < Q; q0 += QB) {
+        V va[QB][8];
+#pragma unroll
+        for (int b = 0; b < QB; b++) {
+            const int c = lane + 64 * (q0 + b), li = c % S::TX, lj = c / S::TX;
+            const bool valid = li < T.ncx && lj < T.ncy;
+            const size_t n00 = valid ? (size_t)(T.cj0 + lj) * g.nx + (T.ci0 + li) : 0;
+            const size_t n01 = n00 + g.nx;
+            va[b][0] = ax[n00];
+            va[b][1] = ax[n00 + 1];
+            va[b][2] = ax[n01];
+            va[b][3] = ax[n01 + 1];
+            va[b][4] = ay[n00];
+            va[b][5] = ay[n00 + 1];
+            va[b][6] = ay[n01];
+            va[b][7] = ay[n01 + 1];
+        }
+        unsigned bits = 0;  // 4 bits per cell: result of triangle 0, then triangle 1
+#pragma unroll
+        for (int b = 0; b < QB; b++) {
+            const int c = lane + 64 * (q0 + b), li = c % S::TX, lj = c / S::TX;
+            if (!(li < T.ncx && lj < T.ncy)) continue;
+            const int gi = T.ci0 + li, gj = T.cj0 + lj;
+            int res0 = kMiss, res1 = kMiss;
+            if constexpr (sizeof(V) == 4) {
+                const float r = (float)row[SYS_R], E = (float)row[SYS_EB];
+                const float bxh = (float)row[SYS_BXH], bxl = (float)row[SYS_BXL];
+                const float byh = (float)row[SYS_BYH], byl = (float)row[SYS_BYL];
+                const float h32 = (float)g.h;
+                const float ex0 = (((float)gi - bxh) - bxl) * h32;
+                const float ex1 = (((float)(gi + 1) - bxh) - bxl) * h32;
+                const float ey0 = (((float)gj - byh) - byl) * h32;
+                const float ey1 = (((float)(gj + 1) - byh) - byl) * h32;
+                const float d00x = fmaf(-r, va[b][0], ex0), d00y = fmaf(-r, va[b][4], ey0);
+                const float d10x = fmaf(-r, va[b][1], ex1), d10y = fmaf(-r, va[b][5], ey0);
+                const float d01x = fmaf(-r, va[b][2], ex0), d01y = fmaf(-r, va[b][6], ey1);
+                const float d11x = fmaf(-r, va[b][3], ex1), d11y = fmaf(-r, va[b][7], ey1);
+                const float tx[3] = {d00x, d10x, d01x}, ty[3] = {d00y, d10y, d01y};
+                const float ux[3] = {d11x, d01x, d10x}, uy[3] = {d11y, d01y, d10y};
+                res0 = decide32(tx, ty, E, mode, tau, nbbox);
+                res1 = decide32(ux, uy, E, mode, tau, nbbox);
+            } else {
+                const double r = row[SYS_R], bx = row[SYS_BX], by = row[SYS_BY];
+                const double t0x = g.x0 + gi * g.h, t1x = g.x0 + (gi + 1) * g.h;
+                const double t0y = g.y0 + gj * g.h, t1y = g.y0 + (gj + 1) * g.h;
+                const double b00x = t0x - r * va[b][0], b00y = t0y - r * va[b][4];
+                const double b10x = t1x - r * va[b][1], b10y = t0y - r * va[b][5];
+                const double b01x = t0x - r * va[b][2], b01y = t1y - r * va[b][6];
+                const double b11x = t1x - r * va[b][3], b11y = t1y - r * va[b][7];
+                const double vx0[3] = {b00x, b10x, b01x}, vy0[3] = {b00y, b10y, b01y};
+                const double vx1[3] = {b11x, b01x, b10x}, vy1[3] = {b11y, b01y, b10y};
+                if (!(bx < fmin(vx0[0], fmin(vx0[1], vx0[2])) || bx > fmax(vx0[0], fmax(vx0[1], vx0[2])) ||
+                      by < fmin(vy0[0], fmin(vy0[1], vy0[2])) || by > fmax(vy0[0], fmax(vy0[1], vy0[2])))) {
+                    nbbox++;
+                    res0 = contains_exact(vx0, vy0, bx, by) ? kHit : kMiss;
+                }
+                if (!(bx < fmin(vx1[0], fmin(vx1[1], vx1[2])) || bx > fmax(vx1[0], fmax(vx1[1], vx1[2])) ||
+                      by < fmin(vy1[0], fmin(vy1[1], vy1[2])) || by > fmax(vy1[0], fmax(vy1[1], vy1[2])))) {
+                    nbbox++;
+                    res1 = contains_exact(vx1, vy1, bx, by) ? kHit : kMiss;
+                }
+            }
+            bits |= (unsigned)(res0 | (res1 << 2)) << (4 * b);
+        }
+        if (__ballot(bits != 0) == 0) continue;  // the common case: no hit, nothing undecided
+        const unsigned long long base = (unsigned long long)(unsigned)sys << 32;
+#pragma unroll 1
+        for (int b = 0; b < QB; b++) {
+            const unsigned rb = (bits >> (4 * b)) & 15u;
+            const int c = lane + 64 * (q0 + b), li = c % S::TX, lj = c / S::TX;
+            const unsigned tid0 = (unsigned)(2 * ((T.cj0 + lj) * (g.nx - 1) + (T.ci0 + li)));
+            wave_append((rb & 3u) == kHit, base | tid0, &st->n_hits, hit_keys, hit_cap);
+            wave_append((rb >> 2) == kHit, base | (tid0 + 1), &st->n_hits, hit_keys, hit_cap);
+            wave_append((rb & 3u) == kFlag, base | tid0, &st->n_flags, flag_keys, flag_cap);
+            wave_append((rb >> 2) == kFlag, base | (tid0 + 1), &st->n_flags, flag_keys, flag_cap);
+        }
+    }
+}
+
 // Containment of the (tile, system) pairs, persistent waves, one pair at a
-// time: the pair's cells are strided over the lanes, up to four cells per lane
-// per step, with every vertex load of a step issued before any decision.
-// Mixed path: FP32 vertex offsets and the certified sign test; FP64 path:
-// exact containment on the FP64 field's vertices.  Certain hits and undecided
-// tests are appended (system << 32 | triangle id) with one atomic per wave.
+// time (pair_test).
 template <class S, typename V>
 __global__ __launch_bounds__(256) void k_pairs(const V* __restrict__ ax, const V* __restrict__ ay, GridDesc g,
                                                int tiles_x, const double* __restrict__ sysrow,
@@ -370,8 +463,6 @@ __global__ __launch_bounds__(256) void k_pairs(const V* __restrict__ ax, const V
                                                unsigned* __restrict__ part, int part_base)
 {
     __shared__ unsigned sp[4][2];
-    constexpr int Q = S::TX * S::TY / 64;  // cells per lane for one pair
-    constexpr int QB = Q < 4 ? Q : 4;      // cells per lane per step
     const int lane = lane_id(), t = threadIdx.x;
     // exclusive prefix of the culling counts in LDS: thread t owns counts
     // [4t, 4t+4) (n_cull <= 1024), wave scans, then the wave totals
@@ -417,85 +508,8 @@ __global__ __launch_bounds__(256) void k_pairs(const V* __restrict__ ax, const V
         const unsigned off = pidx - spre[lo];
         const unsigned long long pk = pairs[(size_t)cw * region + off];
         const int tile = (int)(pk >> 32), sys = (int)(pk & 0xffffffffu);
-        const Tile T = tile_of<S>(g, tiles_x, tile);
-        const double* row = sysrow + (size_t)sys * SYS_STRIDE;
-        for (int q0 = 0; q0 < Q; q0 += QB) {
-            V va[QB][8];
-#pragma unroll
-            for (int b = 0; b < QB; b++) {
-                const int c = lane + 64 * (q0 + b), li = c % S::TX, lj = c / S::TX;
-                const bool valid = li < T.ncx && lj < T.ncy;
-                const size_t n00 = valid ? (size_t)(T.cj0 + lj) * g.nx + (T.ci0 + li) : 0;
-                const size_t n01 = n00 + g.nx;
-                va[b][0] = ax[n00];
-                va[b][1] = ax[n00 + 1];
-                va[b][2] = ax[n01];
-                va[b][3] = ax[n01 + 1];
-                va[b][4] = ay[n00];
-                va[b][5] = ay[n00 + 1];
-                va[b][6] = ay[n01];
-                va[b][7] = ay[n01 + 1];
-            }
-            unsigned bits = 0;  // 4 bits per cell: result of triangle 0, then triangle 1
-#pragma unroll
-            for (int b = 0; b < QB; b++) {
-                const int c = lane + 64 * (q0 + b), li = c % S::TX, lj = c / S::TX;
-                if (!(li < T.ncx && lj < T.ncy)) continue;
-                const int gi = T.ci0 + li, gj = T.cj0 + lj;
-                int res0 = kMiss, res1 = kMiss;
-                if constexpr (sizeof(V) == 4) {
-                    const float r = (float)row[SYS_R], E = (float)row[SYS_EB];
-                    const float bxh = (float)row[SYS_BXH], bxl = (float)row[SYS_BXL];
-                    const float byh = (float)row[SYS_BYH], byl = (float)row[SYS_BYL];
-                    const float h32 = (float)g.h;
-                    const float ex0 = (((float)gi - bxh) - bxl) * h32;
-                    const float ex1 = (((float)(gi + 1) - bxh) - bxl) * h32;
-                    const float ey0 = (((float)gj - byh) - byl) * h32;
-                    const float ey1 = (((float)(gj + 1) - byh) - byl) * h32;
-                    const float d00x = fmaf(-r, va[b][0], ex0), d00y = fmaf(-r, va[b][4], ey0);
-                    const float d10x = fmaf(-r, va[b][1], ex1), d10y = fmaf(-r, va[b][5], ey0);
-                    const float d01x = fmaf(-r, va[b][2], ex0), d01y = fmaf(-r, va[b][6], ey1);
-                    const float d11x = fmaf(-r, va[b][3], ex1), d11y = fmaf(-r, va[b][7], ey1);
-                    const float tx[3] = {d00x, d10x, d01x}, ty[3] = {d00y, d10y, d01y};
-                    const float ux[3] = {d11x, d01x, d10x}, uy[3] = {d11y, d01y, d10y};
-                    res0 = decide32(tx, ty, E, mode, tau, nbbox);
-                    res1 = decide32(ux, uy, E, mode, tau, nbbox);
-                } else {
-                    const double r = row[SYS_R], bx = row[SYS_BX], by = row[SYS_BY];
-                    const double t0x = g.x0 + gi * g.h, t1x = g.x0 + (gi + 1) * g.h;
-                    const double t0y = g.y0 + gj * g.h, t1y = g.y0 + (gj + 1) * g.h;
-                    const double b00x = t0x - r * va[b][0], b00y = t0y - r * va[b][4];
-                    const double b10x = t1x - r * va[b][1], b10y = t0y - r * va[b][5];
-                    const double b01x = t0x - r * va[b][2], b01y = t1y - r * va[b][6];
-                    const double b11x = t1x - r * va[b][3], b11y = t1y - r * va[b][7];
-                    const double vx0[3] = {b00x, b10x, b01x}, vy0[3] = {b00y, b10y, b01y};
-                    const double vx1[3] = {b11x, b01x, b10x}, vy1[3] = {b11y, b01y, b10y};
-                    if (!(bx < fmin(vx0[0], fmin(vx0[1], vx0[2])) || bx > fmax(vx0[0], fmax(vx0[1], vx0[2])) ||
-                          by < fmin(vy0[0], fmin(vy0[1], vy0[2])) || by > fmax(vy0[0], fmax(vy0[1], vy0[2])))) {
-                        nbbox++;
-                        res0 = contains_exact(vx0, vy0, bx, by) ? kHit : kMiss;
-                    }
-                    if (!(bx < fmin(vx1[0], fmin(vx1[1], vx1[2])) || bx > fmax(vx1[0], fmax(vx1[1], vx1[2])) ||
-                          by < fmin(vy1[0], fmin(vy1[1], vy1[2])) || by > fmax(vy1[0], fmax(vy1[1], vy1[2])))) {
-                        nbbox++;
-                        res1 = contains_exact(vx1, vy1, bx, by) ? kHit : kMiss;
-                    }
-                }
-                bits |= (unsigned)(res0 | (res1 << 2)) << (4 * b);
-            }
-            if (__ballot(bits != 0) == 0) continue;  // the common case: no hit, nothing undecided
-            const unsigned long long base = (unsigned long long)(unsigned)sys << 32;
-#pragma unroll 1
-            for (int b = 0; b < QB; b++) {
-                const unsigned rb = (bits >> (4 * b)) & 15u;
-                const int c = lane + 64 * (q0 + b), li = c % S::TX, lj = c / S::TX;
-                const unsigned tid0 = (unsigned)(2 * ((T.cj0 + lj) * (g.nx - 1) + (T.ci0 + li)));
-                wave_append((rb & 3u) == kHit, base | tid0, &st->n_hits, hit_keys, hit_cap);
-                wave_append((rb >> 2) == kHit, base | (tid0 + 1), &st->n_hits, hit_keys, hit_cap);
-                wave_append((rb & 3u) == kFlag, base | tid0, &st->n_flags, flag_keys, flag_cap);
-                wave_append((rb >> 2) == kFlag, base | (tid0 + 1), &st->n_flags, flag_keys, flag_cap);
-            }
-        }
+        pair_test<S, V>(ax, ay, g, tile_of<S>(g, tiles_x, tile), sys, sysrow, st, mode, tau, hit_keys, hit_cap,
+                        flag_keys, flag_cap, nbbox);
     }
     write_part_sum(part, (size_t)part_base + blockIdx.x, 0u, nbbox, sp);
 }

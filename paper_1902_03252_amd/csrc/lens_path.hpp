@@ -154,15 +154,23 @@ __device__ __forceinline__ int system_of(const int* __restrict__ sys_off, int ns
 // operand modifier) so that no NaN arises there.  Offsets from the centre
 // use the exact hi/lo split (see the FP32 table); hardware sqrt/rcp (1 ulp)
 // are accounted for in the error bound.
+// The row part: nyv = (j - cy_hi) - cy_lo and the products B nyv, C nyv,
+// common to every node of row j.
+__device__ __forceinline__ float3 field32_rowc(const float* __restrict__ c, float fj)
+{
+    const float nyv = (fj - c[T32_CYH]) - c[T32_CYL];
+    return make_float3(nyv, c[T32_B] * nyv, c[T32_C] * nyv);
+}
+
+// The node part, given the row part rc of the same potential.
 template <int NPL>
-__device__ __forceinline__ void field32_pot(const float* __restrict__ c, float fj, const float* fi, float* sx,
+__device__ __forceinline__ void field32_pot(const float* __restrict__ c, float3 rc, const float* fi, float* sx,
                                             float* sy)
 {
-    const float cxh = c[T32_CXH], cxl = c[T32_CXL], cyh = c[T32_CYH], cyl = c[T32_CYL];
-    const float A = c[T32_A], B = c[T32_B], C = c[T32_C];
+    const float cxh = c[T32_CXH], cxl = c[T32_CXL];
+    const float A = c[T32_A], B = c[T32_B];
     const float a2 = c[T32_A2], s2a2 = c[T32_S2A2], ra = c[T32_RA], rs = c[T32_RS], K = c[T32_K];
-    const float nyv = (fj - cyh) - cyl;
-    const float bny = B * nyv, cny = C * nyv;
+    const float nyv = rc.x, bny = rc.y, cny = rc.z;
 #pragma unroll
     for (int k = 0; k < NPL; k++) {
         const float nxv = (fi[k] - cxh) - cxl;
@@ -177,12 +185,39 @@ __device__ __forceinline__ void field32_pot(const float* __restrict__ c, float f
     }
 }
 
+template <int NPL>
+__device__ __forceinline__ void field32_pot(const float* __restrict__ c, float fj, const float* fi, float* sx,
+                                            float* sy)
+{
+    field32_pot<NPL>(c, field32_rowc(c, fj), fi, sx, sy);
+}
+
 // Deflection of NPL nodes of one row by every potential of the FP32 table.
 template <int NPL>
 __device__ __forceinline__ void field32_all(const float* __restrict__ tab, int np, float fj, const float* fi,
                                             float* sx, float* sy)
 {
     for (int p = 0; p < np; p++) field32_pot<NPL>(tab + (size_t)p * T32_STRIDE, fj, fi, sx, sy);
+}
+
+// The same for a workgroup of 256 threads on one row (all threads call it,
+// with the same fj): the row parts of up to 256 potentials at a time are
+// computed once, one potential per thread, into LDS, so that the per-potential
+// work of every wave is the node part only (the row part is uniform over the
+// workgroup but costs a full vector instruction per wave).  Bit-identical to
+// field32_all.
+template <int NPL>
+__device__ __forceinline__ void field32_all_wg(const float* __restrict__ tab, int np, float fj, const float* fi,
+                                               float* sx, float* sy)
+{
+    __shared__ float3 srow[256];
+    for (int p0 = 0; p0 < np; p0 += 256) {
+        const int pc = np - p0 < 256 ? np - p0 : 256;
+        if (p0 > 0) __syncthreads();  // the previous chunk has been read
+        if ((int)threadIdx.x < pc) srow[threadIdx.x] = field32_rowc(tab + (size_t)(p0 + threadIdx.x) * T32_STRIDE, fj);
+        __syncthreads();
+        for (int p = 0; p < pc; p++) field32_pot<NPL>(tab + (size_t)(p0 + p) * T32_STRIDE, srow[p], fi, sx, sy);
+    }
 }
 
 // Range partials of the triangle stage, written by the field kernel: for grid
