@@ -78,7 +78,12 @@ __device__ __forceinline__ void head_images(const PotPtrs& pot, const double* __
 // The last workgroup's part of the head (256 threads): the FP32 error bound
 // E_alpha from the per-potential terms, beta_ij = theta_ij - r_i grad Psi,
 // barycentres and one row per system with its FP32 bound E_B, counters reset
-// and the status.
+// and the status.  Up to kHeadStage images the images are spread over the
+// threads (one round of independent loads) and staged in LDS for the
+// per-system sums; beyond, each system's thread walks its images.  Both forms
+// sum a system's images in image order.
+constexpr int kHeadStage = 512;
+
 __device__ __forceinline__ void head_finish(int np, const GridDesc& g, const ObsPtrs& obs,
                                             const double* __restrict__ bterm, double* __restrict__ beta_x,
                                             double* __restrict__ beta_y, double* __restrict__ sysrow,
@@ -86,13 +91,19 @@ __device__ __forceinline__ void head_finish(int np, const GridDesc& g, const Obs
 {
     __shared__ double sw[4], sj[4], sb[4];
     __shared__ int sys_bad;
+    __shared__ double sbx[kHeadStage], sby[kHeadStage];
+    __shared__ int soff[kHeadStage + 1];
     const int t = threadIdx.x;
+    const int nsys = obs.n_sys, nimg = obs.n_img;
+    const bool staged = nsys > 0 && nimg <= kHeadStage && nsys < kHeadStage;
     double w = 0.0, jt = 0.0, bad = 0.0;
     for (int p = t; p < np; p += 256) {
         w += bterm[3 * p + 0];
         jt += bterm[3 * p + 1];
         bad += bterm[3 * p + 2];
     }
+    if (staged)
+        for (int q = t; q <= nsys; q += 256) soff[q] = obs.sys_off[q];
     w = wave_sum(w);
     jt = wave_sum(jt);
     bad = wave_sum(bad);
@@ -101,26 +112,58 @@ __device__ __forceinline__ void head_finish(int np, const GridDesc& g, const Obs
         sj[t >> 6] = jt;
         sb[t >> 6] = bad;
     }
-    if (t == 0) sys_bad = obs.n_sys > 0 && (obs.sys_off[0] != 0 || obs.sys_off[obs.n_sys] != obs.n_img);
+    if (t == 0) sys_bad = nsys > 0 && (obs.sys_off[0] != 0 || obs.sys_off[nsys] != nimg);
     __syncthreads();
+    if (staged) {
+        // beta of every image, one thread each; an image whose system is out of
+        // order (invalid offsets) is left to the per-system check below
+        bool img_bad = false;
+        for (int j = t; j < nimg; j += 256) {
+            int lo = 0, hi = nsys - 1;  // the system owning image j
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (soff[mid] <= j) lo = mid; else hi = mid - 1;
+            }
+            const double r = obs.dls[lo];
+            const double b1 = obs.x[j] - r * beta_x[j], b2 = obs.y[j] - r * beta_y[j];
+            sbx[j] = b1;
+            sby[j] = b2;
+            const double sg = obs.sigma[j];
+            img_bad = img_bad || !(sg > 0.0 && isfinite(sg) && isfinite(obs.x[j]) && isfinite(obs.y[j]));
+        }
+        if (img_bad) atomicOr(&sys_bad, 1);
+        __syncthreads();
+        for (int j = t; j < nimg; j += 256) {
+            beta_x[j] = sbx[j];
+            beta_y[j] = sby[j];
+        }
+    }
     const double W = (sw[0] + sw[1]) + (sw[2] + sw[3]);
     const double Jsum = (sj[0] + sj[1]) + (sj[2] + sj[3]);
     const double Bsum = (sb[0] + sb[1]) + (sb[2] + sb[3]);
     const double e_alpha = kU32 * (64.0 + np) * W + Jsum + 1e-9;
     const double xlo = g.x0, xhi = g.x0 + (g.nx - 1) * g.h, ylo = g.y0, yhi = g.y0 + (g.ny - 1) * g.h;
-    for (int s = t; s < obs.n_sys; s += 256) {
-        const int j0 = obs.sys_off[s], j1 = obs.sys_off[s + 1];
-        bool ok = j0 <= j1 && j0 >= 0 && j1 <= obs.n_img;
+    for (int s = t; s < nsys; s += 256) {
+        const int j0 = staged ? soff[s] : obs.sys_off[s], j1 = staged ? soff[s + 1] : obs.sys_off[s + 1];
+        bool ok = j0 <= j1 && j0 >= 0 && j1 <= nimg;
         double bx = 0.0, by = 0.0;
         const double r = obs.dls[s];
         if (ok) {
             for (int j = j0; j < j1; j++) {
-                const double b1 = obs.x[j] - r * beta_x[j], b2 = obs.y[j] - r * beta_y[j];
-                beta_x[j] = b1;
-                beta_y[j] = b2;
+                double b1, b2;
+                if (staged) {
+                    b1 = sbx[j];
+                    b2 = sby[j];
+                } else {
+                    b1 = obs.x[j] - r * beta_x[j];
+                    b2 = obs.y[j] - r * beta_y[j];
+                    beta_x[j] = b1;
+                    beta_y[j] = b2;
+                    ok = ok && obs.sigma[j] > 0.0 && isfinite(obs.sigma[j]) && isfinite(obs.x[j]) &&
+                         isfinite(obs.y[j]);
+                }
                 bx += b1;
                 by += b2;
-                ok = ok && obs.sigma[j] > 0.0 && isfinite(obs.sigma[j]) && isfinite(obs.x[j]) && isfinite(obs.y[j]);
             }
             if (j1 > j0) {
                 bx /= (j1 - j0);
