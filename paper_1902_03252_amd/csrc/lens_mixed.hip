@@ -53,13 +53,12 @@ __global__ __launch_bounds__(256) void k_mix_prep(PotPtrs pot, GridDesc g, doubl
 // R^2 = d . m clamped below at 1e-30 (the centre, where m = 0, contributes 0),
 // alpha += (K/h) m / R.
 template <int NPL>
-__device__ __forceinline__ void sie32_pot(const float* __restrict__ c, float fj, const float* fi, float* sx,
+__device__ __forceinline__ void sie32_pot(const float* __restrict__ c, float3 rc, const float* fi, float* sx,
                                           float* sy)
 {
-    const float cxh = c[T32_CXH], cxl = c[T32_CXL], cyh = c[T32_CYH], cyl = c[T32_CYL];
-    const float A = c[T32_A], B = c[T32_B], C = c[T32_C], K = c[T32_K];
-    const float nyv = (fj - cyh) - cyl;
-    const float bny = B * nyv, cny = C * nyv;
+    const float cxh = c[T32_CXH], cxl = c[T32_CXL];
+    const float A = c[T32_A], B = c[T32_B], K = c[T32_K];
+    const float nyv = rc.x, bny = rc.y, cny = rc.z;  // the row part (pots_wg)
 #pragma unroll
     for (int k = 0; k < NPL; k++) {
         const float nxv = (fi[k] - cxh) - cxl;
@@ -92,8 +91,9 @@ __global__ __launch_bounds__(256) void k_mix_field32(const float* __restrict__ t
         sy[k] = 0.0f;
     }
     const bool bad = st->status != kStatusOk;
-    if (!bad)
-        for (int p = 0; p < np; p++) sie32_pot<NPL>(tab32 + (size_t)p * T32_STRIDE, fj, fi, sx, sy);
+    if (!bad)  // uniform over the launch
+        pots_wg<T32_STRIDE, T32_CYH, T32_CYL, T32_B, T32_C>(
+            tab32, np, fj, [&](const float* c, float3 rc) { sie32_pot<NPL>(c, rc, fi, sx, sy); });
     const size_t row = (size_t)j * nx;
 #pragma unroll
     for (int k = 0; k < NPL; k++) {

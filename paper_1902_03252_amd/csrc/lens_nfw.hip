@@ -122,22 +122,22 @@ __global__ __launch_bounds__(256) void k_nfw32(const float* __restrict__ t32, in
 #pragma unroll
     for (int k = 0; k < NPL; k++) sx[k] = sy[k] = 0.0f;
     const float fj = (float)j;
-    for (int p = 0; p < np && !bad; p++) {
-        const float* c = t32 + (size_t)p * N32_STRIDE;
-        const float nyv = (fj - c[N32_CYH]) - c[N32_CYL];
-        const float A = c[N32_A], B = c[N32_B], C = c[N32_C], irs2 = c[N32_IRS2], K = c[N32_K];
+    if (!bad)  // uniform over the launch
+        pots_wg<N32_STRIDE, N32_CYH, N32_CYL, N32_B, N32_C>(t32, np, fj, [&](const float* c, float3 rc) {
+            const float A = c[N32_A], B = c[N32_B], irs2 = c[N32_IRS2], K = c[N32_K];
+            const float nyv = rc.x, bny = rc.y, cny = rc.z;  // the row part
 #pragma unroll
-        for (int k = 0; k < NPL; k++) {
-            const float nxv = ((float)(i0 + k) - c[N32_CXH]) - c[N32_CXL];
-            const float m1 = fmaf(A, nxv, B * nyv), m2 = fmaf(B, nxv, C * nyv);
-            const float R2 = fmaf(nxv, m1, nyv * m2);
-            if (R2 > 0.0f) {
-                const float kg = K * nfw_gx2(R2 * irs2);
-                sx[k] = fmaf(kg, m1, sx[k]);
-                sy[k] = fmaf(kg, m2, sy[k]);
+            for (int k = 0; k < NPL; k++) {
+                const float nxv = ((float)(i0 + k) - c[N32_CXH]) - c[N32_CXL];
+                const float m1 = fmaf(A, nxv, bny), m2 = fmaf(B, nxv, cny);
+                const float R2 = fmaf(nxv, m1, nyv * m2);
+                if (R2 > 0.0f) {
+                    const float kg = K * nfw_gx2(R2 * irs2);
+                    sx[k] = fmaf(kg, m1, sx[k]);
+                    sy[k] = fmaf(kg, m2, sy[k]);
+                }
             }
-        }
-    }
+        });
     const size_t row = (size_t)j * nx;
 #pragma unroll
     for (int k = 0; k < NPL; k++)

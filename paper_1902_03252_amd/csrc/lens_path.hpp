@@ -200,24 +200,39 @@ __device__ __forceinline__ void field32_all(const float* __restrict__ tab, int n
     for (int p = 0; p < np; p++) field32_pot<NPL>(tab + (size_t)p * T32_STRIDE, fj, fi, sx, sy);
 }
 
-// The same for a workgroup of 256 threads on one row (all threads call it,
-// with the same fj): the row parts of up to 256 potentials at a time are
-// computed once, one potential per thread, into LDS, so that the per-potential
-// work of every wave is the node part only (the row part is uniform over the
-// workgroup but costs a full vector instruction per wave).  Bit-identical to
-// field32_all.
-template <int NPL>
-__device__ __forceinline__ void field32_all_wg(const float* __restrict__ tab, int np, float fj, const float* fi,
-                                               float* sx, float* sy)
+// Runs f(c, rc) for every row c of an FP32 table of np rows (STRIDE floats
+// each), in order, with rc = (n_y, B n_y, C n_y), n_y = (j - c[IYH]) - c[IYL]:
+// the row part of a potential, common to every node of grid row j.  For a
+// workgroup of 256 threads on one row (all threads call it, with the same
+// fj): the row parts of up to 256 potentials at a time are computed once, one
+// potential per thread, into LDS, so that the per-potential work of every
+// wave is the node part only (the row part is uniform over the workgroup but,
+// with no scalar FP32 ALU, costs a full vector instruction per wave).
+template <int STRIDE, int IYH, int IYL, int IB, int IC, class F>
+__device__ __forceinline__ void pots_wg(const float* __restrict__ tab, int np, float fj, F&& f)
 {
     __shared__ float3 srow[256];
     for (int p0 = 0; p0 < np; p0 += 256) {
         const int pc = np - p0 < 256 ? np - p0 : 256;
         if (p0 > 0) __syncthreads();  // the previous chunk has been read
-        if ((int)threadIdx.x < pc) srow[threadIdx.x] = field32_rowc(tab + (size_t)(p0 + threadIdx.x) * T32_STRIDE, fj);
+        if ((int)threadIdx.x < pc) {
+            const float* c = tab + (size_t)(p0 + threadIdx.x) * STRIDE;
+            const float nyv = (fj - c[IYH]) - c[IYL];
+            srow[threadIdx.x] = make_float3(nyv, c[IB] * nyv, c[IC] * nyv);
+        }
         __syncthreads();
-        for (int p = 0; p < pc; p++) field32_pot<NPL>(tab + (size_t)(p0 + p) * T32_STRIDE, srow[p], fi, sx, sy);
+        for (int p = 0; p < pc; p++) f(tab + (size_t)(p0 + p) * STRIDE, srow[p]);
     }
+}
+
+// field32_all for a workgroup of 256 threads on one row (pots_wg);
+// bit-identical to field32_all.
+template <int NPL>
+__device__ __forceinline__ void field32_all_wg(const float* __restrict__ tab, int np, float fj, const float* fi,
+                                               float* sx, float* sy)
+{
+    pots_wg<T32_STRIDE, T32_CYH, T32_CYL, T32_B, T32_C>(
+        tab, np, fj, [&](const float* c, float3 rc) { field32_pot<NPL>(c, rc, fi, sx, sy); });
 }
 
 // Range partials of the triangle stage, written by the field kernel: for grid
