@@ -182,6 +182,35 @@ def test_chi2_tile_shapes_and_nodes_per_thread(lens, tile, npl):
         compare_chi2(got, want, 1e-9 if prec == "fp64" else 1e-5, 1e-9 if prec == "fp64" else 1e-6)
 
 
+def _many_images_obs(n_sys, n_img, seed):
+    """n_img observed images in n_sys systems (at least one each), positions
+    uniform over the cluster field, distance ratios in [0.4, 1]."""
+    g = np.random.default_rng(seed)
+    sizes = 1 + g.multinomial(n_img - n_sys, np.full(n_sys, 1.0 / n_sys))
+    sys_off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
+    return dict(sys_off=sys_off, x=g.uniform(-60, 60, n_img), y=g.uniform(-60, 60, n_img),
+                sigma=np.full(n_img, 0.3), dls=g.uniform(0.4, 1.0, n_sys))
+
+
+@pytest.mark.parametrize("n_sys,n_img", [(120, 512), (512, 512), (150, 700)])
+def test_many_images_both_head_forms(lens, n_sys, n_img):
+    """Source positions and chi^2 with many observed images: up to 512 images
+    (and fewer than 512 systems) the head spreads the images over its threads,
+    beyond it walks each system's images; both against the oracle."""
+    prm, grid, _ = load_inputs(2)
+    grid = S.Grid(grid.x0, grid.y0, grid.h * (grid.nx - 1) / 200, 201, 201)
+    obs = _many_images_obs(n_sys, n_img, seed=n_sys + n_img)
+    beta, bar = lens.lens_source_positions(dev(prm), obs_of(obs))
+    bx, by, cx, cy = oracle.source_positions(prm, obs["sys_off"], obs["x"], obs["y"], obs["dls"])
+    np.testing.assert_allclose(beta.cpu().numpy(), np.stack([bx, by], 1), rtol=0, atol=1e-10)
+    np.testing.assert_allclose(bar.cpu().numpy(), np.stack([cx, cy], 1), rtol=0, atol=1e-10)
+    want = oracle.image_chi2(prm, grid, obs)
+    for prec in ("fp64", "mixed"):
+        got = run_chi2(lens, prm, grid, obs, prec, hit_capacity=8192)
+        print(f"  {n_sys} systems, {n_img} images, {prec}: hits {got['stats'][0]}", flush=True)
+        compare_chi2(got, want, 1e-9 if prec == "fp64" else 1e-5, 1e-9 if prec == "fp64" else 1e-6)
+
+
 def test_chi2_identity_lens_exact_images(lens):
     """No potentials: each system has one predicted image at its barycentre."""
     g = np.random.default_rng(11)
