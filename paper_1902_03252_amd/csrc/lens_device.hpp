@@ -132,7 +132,13 @@ __device__ __forceinline__ Row64 alpha64_rowc(const double* __restrict__ t, doub
 }
 
 // Adds the deflection of the potential in row `t` (FP64 table) at the point
-// (t1, ordinate of rc) to (s1, s2), given the row part rc.
+// (t1, ordinate of rc) to (s1, s2), given the row part rc.  The first root
+// takes max(|a^2 + R^2|, 1e-300): at the centre of a singular profile (a = 0,
+// R^2 = 0, m = 0 exactly) f is then finite (~1e150) and the contribution f m
+// exactly zero, the centre convention, without a test; |.| keeps a
+// rounding-level negative R^2 (eps near 1) from a NaN.  Everywhere else the
+// clamp is inactive (a^2 + R^2 >= 1e-300 unless the point lies within 1e-150"
+// of a singular centre without coinciding with it).
 __device__ __forceinline__ void add_alpha64(const double* __restrict__ t, double t1, const Row64& rc, double& s1,
                                             double& s2)
 {
@@ -140,16 +146,14 @@ __device__ __forceinline__ void add_alpha64(const double* __restrict__ t, double
     const double m1 = fma(t[T64_A], d1, rc.bd2);
     const double m2 = fma(t[T64_B], d1, rc.cd2);
     const double R2 = fma(d1, m1, rc.d2 * m2);
-    const double ra = t[T64_RA];
-    const double qa = sqrt_est64(t[T64_A2] + R2) + ra;
+    const double qa = sqrt_est64(fmax(fabs(t[T64_A2] + R2), 1e-300)) + t[T64_RA];
     double f;
-    if (t[T64_SINF] != 0.0) {
+    if (__double_as_longlong(t[T64_SINF]) != 0) {  // uncut (a scalar test of the stored 1.0 / +0.0)
         f = rcp_est64(qa);
     } else {
         const double qs = sqrt_est64(t[T64_S2] + R2) + t[T64_RS];
         f = (qs - qa) * rcp_est64(qa * qs);
     }
-    if (ra == 0.0 && R2 == 0.0) f = 0.0;  // centre of a singular profile contributes 0
     const double kf = t[T64_K] * f;
     s1 += kf * m1;
     s2 += kf * m2;
