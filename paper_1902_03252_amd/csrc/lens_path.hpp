@@ -153,16 +153,8 @@ __device__ __forceinline__ int system_of(const int* __restrict__ sys_off, int ns
 // rounding level (eps near 1); the first root takes |a^2 + R^2| (a free
 // operand modifier) so that no NaN arises there.  Offsets from the centre
 // use the exact hi/lo split (see the FP32 table); hardware sqrt/rcp (1 ulp)
-// are accounted for in the error bound.
-// The row part: nyv = (j - cy_hi) - cy_lo and the products B nyv, C nyv,
-// common to every node of row j.
-__device__ __forceinline__ float3 field32_rowc(const float* __restrict__ c, float fj)
-{
-    const float nyv = (fj - c[T32_CYH]) - c[T32_CYL];
-    return make_float3(nyv, c[T32_B] * nyv, c[T32_C] * nyv);
-}
-
-// The node part, given the row part rc of the same potential.
+// are accounted for in the error bound.  This is the node part, given the
+// row part rc = (n_y, B n_y, C n_y) of the same potential (see pots_wg).
 template <int NPL>
 __device__ __forceinline__ void field32_pot(const float* __restrict__ c, float3 rc, const float* fi, float* sx,
                                             float* sy)
@@ -183,21 +175,6 @@ __device__ __forceinline__ void field32_pot(const float* __restrict__ c, float3 
         sx[k] = fmaf(kf, m1, sx[k]);
         sy[k] = fmaf(kf, m2, sy[k]);
     }
-}
-
-template <int NPL>
-__device__ __forceinline__ void field32_pot(const float* __restrict__ c, float fj, const float* fi, float* sx,
-                                            float* sy)
-{
-    field32_pot<NPL>(c, field32_rowc(c, fj), fi, sx, sy);
-}
-
-// Deflection of NPL nodes of one row by every potential of the FP32 table.
-template <int NPL>
-__device__ __forceinline__ void field32_all(const float* __restrict__ tab, int np, float fj, const float* fi,
-                                            float* sx, float* sy)
-{
-    for (int p = 0; p < np; p++) field32_pot<NPL>(tab + (size_t)p * T32_STRIDE, fj, fi, sx, sy);
 }
 
 // Runs f(c, rc) for every row c of an FP32 table of np rows (STRIDE floats
@@ -225,8 +202,8 @@ __device__ __forceinline__ void pots_wg(const float* __restrict__ tab, int np, f
     }
 }
 
-// field32_all for a workgroup of 256 threads on one row (pots_wg);
-// bit-identical to field32_all.
+// Deflection of NPL nodes of one row by every potential of the FP32 table,
+// for a workgroup of 256 threads on that row (pots_wg).
 template <int NPL>
 __device__ __forceinline__ void field32_all_wg(const float* __restrict__ tab, int np, float fj, const float* fi,
                                                float* sx, float* sy)
