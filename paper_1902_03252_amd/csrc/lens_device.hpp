@@ -96,27 +96,28 @@ __device__ __forceinline__ float wave_min(float v)
 // ---------------------------------------------------------------- FP64 deflection
 
 // FP64 square root and reciprocal of positive normal arguments from the
-// hardware estimates (relative error below 2^-24 on gfx950, measured): the
-// root by one Goldschmidt iteration and one Newton correction, the reciprocal
-// by two Newton-Raphson steps (Markstein, "IA-64 and elementary functions",
-// 2000); both within about 1 ulp, at half the instructions of the
+// hardware estimates (relative error below 2^-24 on gfx950, measured).  The
+// root: one Goldschmidt iteration (g ~ sqrt(x) within ~2^-47) and one Newton
+// correction g + (x - g^2) h with the unrefined h ~ 1/(2 sqrt(x)), whose own
+// 2^-24 error enters only multiplied by the 2^-47 residual (Markstein,
+// "IA-64 and elementary functions", 2000).  The reciprocal: r (1 + e + e^2)
+// with e = 1 - x r, the second-order Newton-Raphson step, error ~e^3 plus
+// rounding.  Both within about 1 ulp, at half the instructions of the
 // correctly rounded library sequences.  A zero argument gives NaN (callers
-// select the centre case out).
+// keep it positive).
 __device__ __forceinline__ double sqrt_est64(double x)
 {
     const double y = __builtin_amdgcn_rsq(x);
-    double g = x * y, h = 0.5 * y;
-    const double r = fma(-g, h, 0.5);
-    g = fma(g, r, g);
-    h = fma(h, r, h);
-    return fma(fma(-g, g, x), h, g);
+    const double g = x * y, h = 0.5 * y;
+    const double g1 = fma(g, fma(-g, h, 0.5), g);
+    return fma(fma(-g1, g1, x), h, g1);
 }
 
 __device__ __forceinline__ double rcp_est64(double x)
 {
-    double r = __builtin_amdgcn_rcp(x);
-    r = fma(r, fma(-x, r, 1.0), r);
-    return fma(r, fma(-x, r, 1.0), r);
+    const double r = __builtin_amdgcn_rcp(x);
+    const double e = fma(-x, r, 1.0);
+    return fma(r, fma(e, e, e), r);
 }
 
 // The row part of a potential's FP64 deflection at ordinate t2: d2 = t2 - y_c
