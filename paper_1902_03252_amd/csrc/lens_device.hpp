@@ -46,6 +46,7 @@ enum : int {
     T32_RA, T32_RS,                          // a, s (arcsec)
     T32_K,                                   // K / h
     T32_KIND,                                // int bits: 0: a>0,s<inf  1: a>0,s=inf  2: a=0,s<inf  3: a=0,s=inf
+    T32_KINV, T32_RSK,                       // 1 / (K / h), s / (K / h) (the FP32 values)
     T32_STRIDE = 16
 };
 

@@ -53,7 +53,7 @@ __global__ __launch_bounds__(256) void k_mix_prep(PotPtrs pot, GridDesc g, doubl
 // R^2 = d . m clamped below at 1e-30 (the centre, where m = 0, contributes 0),
 // alpha += (K/h) m / R.
 template <int NPL>
-__device__ __forceinline__ void sie32_pot(const float* __restrict__ c, float3 rc, const float* fi, float* sx,
+__device__ __forceinline__ void sie32_pot(const float* __restrict__ c, float4 rc, const float* fi, float* sx,
                                           float* sy)
 {
     const float cxh = c[T32_CXH], cxl = c[T32_CXL];
@@ -92,8 +92,8 @@ __global__ __launch_bounds__(256) void k_mix_field32(const float* __restrict__ t
     }
     const bool bad = st->status != kStatusOk;
     if (!bad)  // uniform over the launch
-        pots_wg<T32_STRIDE, T32_CYH, T32_CYL, T32_B, T32_C>(
-            tab32, np, fj, [&](const float* c, float3 rc) { sie32_pot<NPL>(c, rc, fi, sx, sy); });
+        pots_wg<T32_STRIDE, T32_CYH, T32_CYL, T32_B, T32_C, -1>(
+            tab32, np, fj, [&](const float* c, float4 rc) { sie32_pot<NPL>(c, rc, fi, sx, sy); });
     const size_t row = (size_t)j * nx;
 #pragma unroll
     for (int k = 0; k < NPL; k++) {

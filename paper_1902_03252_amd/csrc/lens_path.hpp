@@ -96,16 +96,25 @@ static __device__ void prep_one(const PotPtrs& pot, const GridDesc& g, int p, in
     u[T32_CXL] = (float)cxl;
     u[T32_CYH] = (float)cyh;
     u[T32_CYL] = (float)cyl;
-    u[T32_A] = (float)(A * h2);
-    u[T32_B] = (float)(B * h2);
-    u[T32_C] = (float)(C * h2);
+    // a potential with K/h below 1e-15 (sigma_v = 0, or a deflection below
+    // 1e-14", far under the bound's 1e-9" floor) is stored with M = 0 and K = 0,
+    // so that its finite f multiplies m = 0 (field32_pot divides by K; 1/K <=
+    // 1e15 keeps s/K, B_/K and A_ B_/K finite for the uncut s = 1e18)
+    const float k32 = (float)(K / g.h);
+    const bool kz = !(k32 >= 1e-15f);
+    u[T32_A] = kz ? 0.0f : (float)(A * h2);
+    u[T32_B] = kz ? 0.0f : (float)(B * h2);
+    u[T32_C] = kz ? 0.0f : (float)(C * h2);
     u[T32_A2] = (float)(a * a);
     u[T32_S2A2] = sinf ? 1e36f : (float)(s * s - a * a);  // uncut: s = 1e18 (see field32_pot)
     u[T32_RA] = a > 0.0 ? (float)a : 1e-20f;  // singular: A_ = R + 1e-20 (see field32_pot)
     u[T32_RS] = sinf ? 1e18f : (float)s;
-    u[T32_K] = (float)(K / g.h);
+    u[T32_K] = kz ? 0.0f : k32;
     reinterpret_cast<int*>(u)[T32_KIND] = (a == 0.0 ? 2 : 0) + (sinf ? 1 : 0);
-    for (int k = T32_KIND + 1; k < T32_STRIDE; k++) u[k] = 0.0f;
+    const float kinv = kz ? 1.0f : (float)(1.0 / (double)k32);
+    u[T32_KINV] = kinv;
+    u[T32_RSK] = (float)((double)u[T32_RS] * (double)kinv);
+    for (int k = T32_RSK + 1; k < T32_STRIDE; k++) u[k] = 0.0f;
 
     const double w = K * a2 / sqrt(a1);
     const double rho = sqrt(a1) * g.h * sqrt(cxl * cxl + cyl * cyl);
@@ -153,16 +162,21 @@ __device__ __forceinline__ int system_of(const int* __restrict__ sys_off, int ns
 // rounding level (eps near 1); the first root takes |a^2 + R^2| (a free
 // operand modifier) so that no NaN arises there.  Offsets from the centre
 // use the exact hi/lo split (see the FP32 table); hardware sqrt/rcp (1 ulp)
-// are accounted for in the error bound.  This is the node part, given the
-// row part rc = (n_y, B n_y, C n_y) of the same potential (see pots_wg).
+// are accounted for in the error bound.  K f = K (B_ - A_) / (A_ B_) is
+// evaluated as (K b - A_) / (A_ b) with b = B_ / K = sqrt(s^2 + R^2) / K +
+// s / K (one fused multiply-add; 1/K and s/K are stored): one instruction
+// fewer than scaling by K after the division, and the error of K b - A_ is
+// that of B_ - A_ plus about 1 ulp of B_, which the bound's per-potential
+// budget covers.  This is the node part, given the row part rc = (n_y,
+// B n_y, C n_y, s / K) of the same potential (see pots_wg).
 template <int NPL>
-__device__ __forceinline__ void field32_pot(const float* __restrict__ c, float3 rc, const float* fi, float* sx,
+__device__ __forceinline__ void field32_pot(const float* __restrict__ c, float4 rc, const float* fi, float* sx,
                                             float* sy)
 {
     const float cxh = c[T32_CXH], cxl = c[T32_CXL];
     const float A = c[T32_A], B = c[T32_B];
-    const float a2 = c[T32_A2], s2a2 = c[T32_S2A2], ra = c[T32_RA], rs = c[T32_RS], K = c[T32_K];
-    const float nyv = rc.x, bny = rc.y, cny = rc.z;
+    const float a2 = c[T32_A2], s2a2 = c[T32_S2A2], ra = c[T32_RA], K = c[T32_K], kinv = c[T32_KINV];
+    const float nyv = rc.x, bny = rc.y, cny = rc.z, rsk = rc.w;
 #pragma unroll
     for (int k = 0; k < NPL; k++) {
         const float nxv = (fi[k] - cxh) - cxl;
@@ -170,32 +184,34 @@ __device__ __forceinline__ void field32_pot(const float* __restrict__ c, float3 
         const float m2 = fmaf(B, nxv, cny);
         const float qa2 = fmaf(nxv, m1, fmaf(nyv, m2, a2));  // a^2 + R^2
         const float qa = __builtin_amdgcn_sqrtf(fabsf(qa2)) + ra;  // |.|: a source modifier
-        const float qs = __builtin_amdgcn_sqrtf(qa2 + s2a2) + rs;
-        const float kf = K * ((qs - qa) * __builtin_amdgcn_rcpf(qa * qs));
+        const float qsk = fmaf(__builtin_amdgcn_sqrtf(qa2 + s2a2), kinv, rsk);  // B_ / K
+        const float kf = fmaf(qsk, K, -qa) * __builtin_amdgcn_rcpf(qa * qsk);
         sx[k] = fmaf(kf, m1, sx[k]);
         sy[k] = fmaf(kf, m2, sy[k]);
     }
 }
 
 // Runs f(c, rc) for every row c of an FP32 table of np rows (STRIDE floats
-// each), in order, with rc = (n_y, B n_y, C n_y), n_y = (j - c[IYH]) - c[IYL]:
-// the row part of a potential, common to every node of grid row j.  For a
-// workgroup of 256 threads on one row (all threads call it, with the same
-// fj): the row parts of up to 256 potentials at a time are computed once, one
-// potential per thread, into LDS, so that the per-potential work of every
-// wave is the node part only (the row part is uniform over the workgroup but,
-// with no scalar FP32 ALU, costs a full vector instruction per wave).
-template <int STRIDE, int IYH, int IYL, int IB, int IC, class F>
+// each), in order, with rc = (n_y, B n_y, C n_y, c[IW]), n_y = (j - c[IYH]) -
+// c[IYL]: the row part of a potential, common to every node of grid row j,
+// and one more constant of the potential (IW < 0: 0) that the caller wants
+// in a vector register.  For a workgroup of 256 threads on one row (all
+// threads call it, with the same fj): the row parts of up to 256 potentials
+// at a time are computed once, one potential per thread, into LDS, so that
+// the per-potential work of every wave is the node part only (the row part is
+// uniform over the workgroup but, with no scalar FP32 ALU, costs a full
+// vector instruction per wave).
+template <int STRIDE, int IYH, int IYL, int IB, int IC, int IW, class F>
 __device__ __forceinline__ void pots_wg(const float* __restrict__ tab, int np, float fj, F&& f)
 {
-    __shared__ float3 srow[256];
+    __shared__ float4 srow[256];
     for (int p0 = 0; p0 < np; p0 += 256) {
         const int pc = np - p0 < 256 ? np - p0 : 256;
         if (p0 > 0) __syncthreads();  // the previous chunk has been read
         if ((int)threadIdx.x < pc) {
             const float* c = tab + (size_t)(p0 + threadIdx.x) * STRIDE;
             const float nyv = (fj - c[IYH]) - c[IYL];
-            srow[threadIdx.x] = make_float3(nyv, c[IB] * nyv, c[IC] * nyv);
+            srow[threadIdx.x] = make_float4(nyv, c[IB] * nyv, c[IC] * nyv, IW >= 0 ? c[IW >= 0 ? IW : 0] : 0.0f);
         }
         __syncthreads();
         for (int p = 0; p < pc; p++) f(tab + (size_t)(p0 + p) * STRIDE, srow[p]);
@@ -203,13 +219,15 @@ __device__ __forceinline__ void pots_wg(const float* __restrict__ tab, int np, f
 }
 
 // Deflection of NPL nodes of one row by every potential of the FP32 table,
-// for a workgroup of 256 threads on that row (pots_wg).
+// for a workgroup of 256 threads on that row (pots_wg; s / K rides along with
+// the row part, as field32_pot's fused multiply-add can take only one scalar
+// operand).
 template <int NPL>
 __device__ __forceinline__ void field32_all_wg(const float* __restrict__ tab, int np, float fj, const float* fi,
                                                float* sx, float* sy)
 {
-    pots_wg<T32_STRIDE, T32_CYH, T32_CYL, T32_B, T32_C>(
-        tab, np, fj, [&](const float* c, float3 rc) { field32_pot<NPL>(c, rc, fi, sx, sy); });
+    pots_wg<T32_STRIDE, T32_CYH, T32_CYL, T32_B, T32_C, T32_RSK>(
+        tab, np, fj, [&](const float* c, float4 rc) { field32_pot<NPL>(c, rc, fi, sx, sy); });
 }
 
 // Range partials of the triangle stage, written by the field kernel: for grid
