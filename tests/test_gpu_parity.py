@@ -92,6 +92,31 @@ def test_deflect_singular_and_uncut_kinds(lens):
     assert err.max() <= fp32_alpha_bound(prm, grid)
 
 
+def test_deflect_zero_and_small_dispersion(lens):
+    """Potentials with sigma_v = 0, 1e-9 and 1e-4 km/s (cut and uncut, cored and
+    singular) beside ordinary ones: the FP32 table stores the first two with
+    K = 0 and divides by K for the others; both precisions against the oracle,
+    and the chi^2 with them against the oracle's."""
+    prm = S.sie_potentials(10, seed=5)
+    prm[4, :4] = [0.3, 0.0, 0.2, 0.0]
+    prm[5, :4] = [40.0, 25.0, np.inf, np.inf]
+    prm[6, :6] = [0.0, 0.0, 1e-9, 1e-9, 1e-4, 1e-4]
+    prm[5, 4] = np.inf
+    grid = S.Grid(-50.3, -49.1, 0.35, 289, 283)
+    ax_o, ay_o = oracle.alpha_grid(prm, grid)
+    ax, ay = lens.lens_deflect(dev(prm), grid, "fp64")
+    np.testing.assert_allclose(ax.cpu().numpy(), ax_o, rtol=0, atol=1e-10)
+    np.testing.assert_allclose(ay.cpu().numpy(), ay_o, rtol=0, atol=1e-10)
+    ax, ay = lens.lens_deflect(dev(prm), grid, "fp32")
+    err = np.maximum(np.abs(ax.cpu().numpy() - ax_o), np.abs(ay.cpu().numpy() - ay_o))
+    assert np.isfinite(err).all() and err.max() <= fp32_alpha_bound(prm, grid)
+    _, _, obs = load_inputs(2)
+    want = oracle.image_chi2(prm, grid, obs)
+    for prec in ("fp64", "mixed"):
+        got = run_chi2(lens, prm, grid, obs, prec)
+        compare_chi2(got, want, 1e-9 if prec == "fp64" else 1e-5, 1e-9 if prec == "fp64" else 1e-6)
+
+
 def test_deflect_invalid_parameters_reported(lens):
     prm = S.config1_potentials()
     for k, v in [(2, 1.0), (2, -0.1), (4, -1.0), (5, 0.1), (6, -5.0), (0, np.nan)]:
