@@ -617,7 +617,7 @@ int lens_image_chi2(lens_ctx* ctx, const lens_potentials* pot, const lens_grid* 
     unsigned long long* flags = (unsigned long long*)ctx->buf[B_FLAGS];
     const long long flag_cap = mixed ? kFlagScratch : 0;
     const float tau = (float)(opts->fb_tau * g.h * g.h);
-    e = launch_cull(mixed, fx, fy, rr, g, o.n_sys, sysrow, pairs, region, counts, part, shape, stream);
+    e = launch_cull(mixed, rr, g, o.n_sys, sysrow, pairs, region, counts, part, shape, stream);
     if (e == hipSuccess)
         e = launch_pairs(mixed, fx, fy, g, sysrow, st, opts->fb_mode, tau, pairs, region, counts, n_cull, hits,
                          kHitScratch, flags, flag_cap, part, n_cull, shape, stream);

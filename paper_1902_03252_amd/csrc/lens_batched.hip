@@ -348,7 +348,7 @@ __global__ __launch_bounds__(256) void k_bfbpos(BatchPlan bp, int nsys, const do
 // triangle id), chi2_i in image order (+inf without a predicted image) and
 // chi^2 in a fixed order (Sec. 2.2.1).  Needs hcap <= 1024 and at most 1024
 // images and systems (checked on the host).
-__global__ __launch_bounds__(256) void k_btail(BatchPlan bp, ObsPtrs obs, BatchState bs, int hcap,
+__global__ __launch_bounds__(256) void k_btail(ObsPtrs obs, BatchState bs, int hcap,
                                                long long flag_cap, const unsigned long long* __restrict__ hits,
                                                const unsigned long long* __restrict__ fb,
                                                const double* __restrict__ pos, const double* __restrict__ fb_pos,
@@ -566,7 +566,7 @@ hipError_t launch_btail(const BatchPlan& bp, const ObsPtrs& obs, const BatchStat
                         const double* fb_pos, double* chi2, double* chi2_sys, int* n_pred, int* status,
                         unsigned long long* agg, const unsigned* part, long long n_parts, hipStream_t s)
 {
-    k_btail<<<bp.n, 256, 0, s>>>(bp, obs, bs, hcap, flag_cap, hits, fb, pos, fb_pos, chi2, chi2_sys, n_pred, status,
+    k_btail<<<bp.n, 256, 0, s>>>(obs, bs, hcap, flag_cap, hits, fb, pos, fb_pos, chi2, chi2_sys, n_pred, status,
                                  agg, part, n_parts);
     return hipGetLastError();
 }

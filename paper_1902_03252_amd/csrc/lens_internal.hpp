@@ -108,7 +108,7 @@ constexpr int kMaxCull = 1024;             // culling workgroups (4 tiles per ro
 void tile_dims(int shape, int& tx, int& ty);
 long long tri_tiles(const GridDesc& g, int shape, int* tiles_x);
 void cull_shape(const GridDesc& g, int shape, int* n_cull, int* tpw);
-hipError_t launch_cull(bool fp32, const void* ax, const void* ay, const void* rr, const GridDesc& g, int nsys,
+hipError_t launch_cull(bool fp32, const void* rr, const GridDesc& g, int nsys,
                        const double* sysrow, unsigned long long* pairs, long long region, unsigned* counts,
                        unsigned* part, int shape, hipStream_t s);
 hipError_t launch_pairs(bool fp32, const void* ax, const void* ay, const GridDesc& g, const double* sysrow,

@@ -257,7 +257,7 @@ __device__ __forceinline__ void field32_row(const float* __restrict__ tab32, int
 }
 
 template <int NPL>
-__global__ __launch_bounds__(256) void k_field32(const float* __restrict__ tab32, int np, int nx, int ny,
+__global__ __launch_bounds__(256) void k_field32(const float* __restrict__ tab32, int np, int nx,
                                                  float* __restrict__ ax, float* __restrict__ ay,
                                                  const EvalState* __restrict__ st, float* __restrict__ rr,
                                                  int tx_shift, int tiles_x)
@@ -347,8 +347,7 @@ __global__ __launch_bounds__(256) void k_field64h(const double* __restrict__ tab
 // writes its count to counts[blockIdx.x]: no atomic is shared between
 // workgroups.
 template <class S, typename V>
-__global__ __launch_bounds__(256) void k_cull(const V* __restrict__ ax, const V* __restrict__ ay,
-                                              const V* __restrict__ rr, GridDesc g, int tiles_x, int n_tiles,
+__global__ __launch_bounds__(256) void k_cull(const V* __restrict__ rr, GridDesc g, int tiles_x, int n_tiles,
                                               int tpw, int nsys, const double* __restrict__ sysrow,
                                               unsigned long long* __restrict__ pairs, long long region,
                                               unsigned* __restrict__ counts, unsigned* __restrict__ part)
@@ -907,10 +906,10 @@ hipError_t launch_field32(const float* tab32, int np, const GridDesc& g, float* 
                           const KernelEvents* ev, hipStream_t s)
 {
     switch (npl) {
-    case 1: return launch_ev(ev, k_field32<1>, dim3(cdiv(g.nx, 256), g.ny), dim3(256), s, tab32, np, g.nx, g.ny, ax, ay, st, rr, tx_shift, tiles_x);
-    case 2: return launch_ev(ev, k_field32<2>, dim3(cdiv(g.nx, 512), g.ny), dim3(256), s, tab32, np, g.nx, g.ny, ax, ay, st, rr, tx_shift, tiles_x);
-    case 4: return launch_ev(ev, k_field32<4>, dim3(cdiv(g.nx, 1024), g.ny), dim3(256), s, tab32, np, g.nx, g.ny, ax, ay, st, rr, tx_shift, tiles_x);
-    default: return launch_ev(ev, k_field32<8>, dim3(cdiv(g.nx, 2048), g.ny), dim3(256), s, tab32, np, g.nx, g.ny, ax, ay, st, rr, tx_shift, tiles_x);
+    case 1: return launch_ev(ev, k_field32<1>, dim3(cdiv(g.nx, 256), g.ny), dim3(256), s, tab32, np, g.nx, ax, ay, st, rr, tx_shift, tiles_x);
+    case 2: return launch_ev(ev, k_field32<2>, dim3(cdiv(g.nx, 512), g.ny), dim3(256), s, tab32, np, g.nx, ax, ay, st, rr, tx_shift, tiles_x);
+    case 4: return launch_ev(ev, k_field32<4>, dim3(cdiv(g.nx, 1024), g.ny), dim3(256), s, tab32, np, g.nx, ax, ay, st, rr, tx_shift, tiles_x);
+    default: return launch_ev(ev, k_field32<8>, dim3(cdiv(g.nx, 2048), g.ny), dim3(256), s, tab32, np, g.nx, ax, ay, st, rr, tx_shift, tiles_x);
     }
 }
 
@@ -1015,7 +1014,7 @@ void cull_shape(const GridDesc& g, int shape, int* n_cull, int* tpw)
     *tpw = k;
 }
 
-hipError_t launch_cull(bool fp32, const void* ax, const void* ay, const void* rr, const GridDesc& g, int nsys,
+hipError_t launch_cull(bool fp32, const void* rr, const GridDesc& g, int nsys,
                        const double* sysrow, unsigned long long* pairs, long long region, unsigned* counts,
                        unsigned* part, int shape, hipStream_t s)
 {
@@ -1025,11 +1024,11 @@ hipError_t launch_cull(bool fp32, const void* ax, const void* ay, const void* rr
         const int n_tiles = (int)tri_tiles(g, shape, &tiles_x);
         cull_shape(g, shape, &nb, &tpw);
         if (fp32)
-            k_cull<S, float><<<nb, 256, 0, s>>>((const float*)ax, (const float*)ay, (const float*)rr, g, tiles_x,
-                                                n_tiles, tpw, nsys, sysrow, pairs, region, counts, part);
+            k_cull<S, float><<<nb, 256, 0, s>>>((const float*)rr, g, tiles_x, n_tiles, tpw, nsys, sysrow, pairs,
+                                                region, counts, part);
         else
-            k_cull<S, double><<<nb, 256, 0, s>>>((const double*)ax, (const double*)ay, (const double*)rr, g,
-                                                 tiles_x, n_tiles, tpw, nsys, sysrow, pairs, region, counts, part);
+            k_cull<S, double><<<nb, 256, 0, s>>>((const double*)rr, g, tiles_x, n_tiles, tpw, nsys, sysrow, pairs,
+                                                 region, counts, part);
         return hipGetLastError();
     });
 }

@@ -73,7 +73,7 @@ __device__ __forceinline__ bool row64(const PotPtrs& pot, int p, double* t, doub
 // Constants of parameter column p written to table row q; the FP64 row is
 // also copied to row_copy and the three bound terms returned in terms when
 // these are not null.
-static __device__ void prep_one(const PotPtrs& pot, const GridDesc& g, int p, int q, double* __restrict__ tab64,
+inline __device__ void prep_one(const PotPtrs& pot, const GridDesc& g, int p, int q, double* __restrict__ tab64,
                                 float* __restrict__ tab32, double* __restrict__ bterm,
                                 double* row_copy = nullptr, double* terms = nullptr)
 {
