@@ -168,13 +168,14 @@ __device__ __forceinline__ void add_alpha64(const double* __restrict__ t, double
     add_alpha64(t, t1, alpha64_rowc(t, t2), s1, s2);
 }
 
-// Deflection at (t1, t2) of every potential of the FP64 table, for a
-// workgroup of 256 threads whose points share the ordinate t2 (all threads
+// Deflection at (t1[k], t2), k < N, of every potential of the FP64 table, for
+// a workgroup of 256 threads whose points share the ordinate t2 (all threads
 // call it): the row parts of up to 256 potentials at a time are computed once,
-// one potential per thread, into LDS.  Same arithmetic as add_alpha64 at
-// (t1, t2).
-__device__ __forceinline__ void alpha64_all_wg(const double* __restrict__ tab, int np, double t1, double t2,
-                                               double& s1, double& s2)
+// one potential per thread, into LDS.  Same arithmetic as add_alpha64 at each
+// point.
+template <int N>
+__device__ __forceinline__ void alpha64_all_wg(const double* __restrict__ tab, int np, const double* t1, double t2,
+                                               double* s1, double* s2)
 {
     __shared__ Row64 srow[256];
     for (int p0 = 0; p0 < np; p0 += 256) {
@@ -182,8 +183,18 @@ __device__ __forceinline__ void alpha64_all_wg(const double* __restrict__ tab, i
         if (p0 > 0) __syncthreads();  // the previous chunk has been read
         if ((int)threadIdx.x < pc) srow[threadIdx.x] = alpha64_rowc(tab + (size_t)(p0 + threadIdx.x) * T64_STRIDE, t2);
         __syncthreads();
-        for (int p = 0; p < pc; p++) add_alpha64(tab + (size_t)(p0 + p) * T64_STRIDE, t1, srow[p], s1, s2);
+        for (int p = 0; p < pc; p++) {
+            const Row64 rc = srow[p];
+#pragma unroll
+            for (int k = 0; k < N; k++) add_alpha64(tab + (size_t)(p0 + p) * T64_STRIDE, t1[k], rc, s1[k], s2[k]);
+        }
     }
+}
+
+__device__ __forceinline__ void alpha64_all_wg(const double* __restrict__ tab, int np, double t1, double t2,
+                                               double& s1, double& s2)
+{
+    alpha64_all_wg<1>(tab, np, &t1, t2, &s1, &s2);
 }
 
 // grad Psi at one point with the potentials split over the 64 lanes of a

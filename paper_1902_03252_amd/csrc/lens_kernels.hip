@@ -265,24 +265,37 @@ __global__ __launch_bounds__(256) void k_field32(const float* __restrict__ tab32
     field32_row<NPL>(tab32, np, nx, blockIdx.y, blockIdx.x, ax, ay, st, rr, tx_shift, tiles_x);
 }
 
-// FP64 field: one node per thread, the same matrix form in arcsec; with rr
-// set, also the triangle stage's row partials (as k_field32).
+constexpr int kNpl64 = 2;  // FP64 field nodes per thread
+
+// FP64 field: kNpl64 consecutive nodes of one row per thread (a workgroup
+// covers 256 * kNpl64 nodes), the same matrix form in arcsec; with rr set,
+// also the triangle stage's row partials (as k_field32).
 __device__ __forceinline__ void field64_row(const double* __restrict__ tab64, int np, const GridDesc& g, int j,
                                             int bx, double* __restrict__ ax, double* __restrict__ ay,
                                             const EvalState* __restrict__ st, double* __restrict__ rr, int tx_shift,
                                             int tiles_x)
 {
-    const int i = bx * 256 + threadIdx.x;
-    if (bx * 256 >= g.nx) return;  // whole workgroup beyond the row
-    const double t1 = g.x0 + i * g.h, t2 = g.y0 + j * g.h;
-    double s1 = 0.0, s2 = 0.0;
-    alpha64_all_wg(tab64, np, t1, t2, s1, s2);
-    if (rr) tile_partials<double, 1>(&s1, &s2, i, j, g.nx, tx_shift, tiles_x, rr);
-    if (i >= g.nx) return;
+    const int i0 = (bx * 256 + (int)threadIdx.x) * kNpl64;
+    if (bx * 256 * kNpl64 >= g.nx) return;  // whole workgroup beyond the row
+    const double t2 = g.y0 + j * g.h;
+    double t1[kNpl64], s1[kNpl64], s2[kNpl64];
+#pragma unroll
+    for (int k = 0; k < kNpl64; k++) {
+        t1[k] = g.x0 + (i0 + k) * g.h;
+        s1[k] = 0.0;
+        s2[k] = 0.0;
+    }
+    alpha64_all_wg<kNpl64>(tab64, np, t1, t2, s1, s2);
+    if (rr) tile_partials<double, kNpl64>(s1, s2, i0, j, g.nx, tx_shift, tiles_x, rr);
     const bool bad = st != nullptr && st->status != kStatusOk;
-    const size_t n = (size_t)j * g.nx + i;
-    ax[n] = bad ? __builtin_nan("") : s1;
-    ay[n] = bad ? __builtin_nan("") : s2;
+    const size_t row = (size_t)j * g.nx;
+#pragma unroll
+    for (int k = 0; k < kNpl64; k++) {
+        if (i0 + k < g.nx) {
+            ax[row + i0 + k] = bad ? __builtin_nan("") : s1[k];
+            ay[row + i0 + k] = bad ? __builtin_nan("") : s2[k];
+        }
+    }
 }
 
 __global__ __launch_bounds__(256) void k_field64(const double* __restrict__ tab64, int np, GridDesc g,
@@ -931,7 +944,7 @@ static int head_rows_for(const ObsPtrs& obs, int bx)
 
 int fused_head_fits(const GridDesc& g, const ObsPtrs& obs, int npl, bool fp32)
 {
-    const int bx = (int)cdiv(g.nx, fp32 ? 256 * npl : 256);
+    const int bx = (int)cdiv(g.nx, fp32 ? 256 * npl : 256 * kNpl64);
     return g.ny + head_rows_for(obs, bx) <= 65535;
 }
 
@@ -952,7 +965,7 @@ hipError_t launch_field32h(const float* tab32, int np, const GridDesc& g, float*
 hipError_t launch_field64h(const double* tab64, int np, const GridDesc& g, double* ax, double* ay, double* rr,
                            int tx_shift, int tiles_x, const HeadArgs& h, const KernelEvents* ev, hipStream_t s)
 {
-    const int bx = (int)cdiv(g.nx, 256);
+    const int bx = (int)cdiv(g.nx, 256 * kNpl64);
     const int hr = head_rows_for(h.obs, bx);
     return launch_ev(ev, k_field64h, dim3((unsigned)bx, (unsigned)(g.ny + hr)), dim3(256), s, tab64, np, g, ax, ay,
                      rr, tx_shift, tiles_x, h, hr);
@@ -962,7 +975,7 @@ hipError_t launch_field64(const double* tab64, int np, const GridDesc& g, double
                           const EvalState* st, double* rr, int tx_shift, int tiles_x, const KernelEvents* ev,
                           hipStream_t s)
 {
-    return launch_ev(ev, k_field64, dim3(cdiv(g.nx, 256), g.ny), dim3(256), s, tab64, np, g, ax, ay, st, rr,
+    return launch_ev(ev, k_field64, dim3(cdiv(g.nx, 256 * kNpl64), g.ny), dim3(256), s, tab64, np, g, ax, ay, st, rr,
                      tx_shift, tiles_x);
 }
 
