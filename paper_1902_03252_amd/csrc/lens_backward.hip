@@ -305,9 +305,9 @@ __global__ __launch_bounds__(256) void k_vjp(const double* __restrict__ dtab, in
             const DConst<T> k = load_dconst<T>(d);
             T d1, d2a, d2b;
             if constexpr (sizeof(T) == 8) {
-                d1 = (g.x0 + i * g.h) - d[D_XC];
-                d2a = (g.y0 + j * g.h) - d[D_YC];
-                d2b = (g.y0 + (j + 1) * g.h) - d[D_YC];
+                d1 = node_coord(g.x0, i, g.h) - d[D_XC];
+                d2a = node_coord(g.y0, j, g.h) - d[D_YC];
+                d2b = node_coord(g.y0, j + 1, g.h) - d[D_YC];
             } else {
                 // offsets from the node-unit split of the centre, as in the FP32 field
                 d1 = (((float)i - (float)d[D_CXH]) - (float)d[D_CXL]) * ihf;
@@ -388,8 +388,8 @@ __global__ __launch_bounds__(256) void k_src_fwd(PotPtrs pot, ObsPtrs obs, doubl
         const double r = obs.dls[i];
         if (__ballot(bad) != 0 && lane == 0) s_bad = 1;
         if (lane == 0) {
-            beta[2 * j] = t1 - r * s1;
-            beta[2 * j + 1] = t2 - r * s2;
+            beta[2 * j] = src_map(t1, r, s1);
+            beta[2 * j + 1] = src_map(t2, r, s2);
         }
     }
     __syncthreads();

@@ -63,8 +63,8 @@ __global__ __launch_bounds__(256) void k_bhead(BatchPlan bp, PotPtrs pot, ObsPtr
         const double a1 = wave_sum(s1), a2 = wave_sum(s2);
         const double r = obs.dls[system_of(obs.sys_off, obs.n_sys, j)];
         if (lane_id() == 0) {
-            beta_x[it] = t1 - r * a1;
-            beta_y[it] = t2 - r * a2;
+            beta_x[it] = src_map(t1, r, a1);
+            beta_y[it] = src_map(t2, r, a2);
         }
     }
 }
@@ -199,7 +199,7 @@ __global__ __launch_bounds__(256) void k_bfield64(BatchPlan bp, const int* __res
     const int p0 = bp.pot_off[0];
     const double* tab = tab64 + (size_t)(bp.pot_off[s] - p0) * T64_STRIDE;
     const int np = bp.pot_off[s + 1] - bp.pot_off[s];
-    const double t1 = g.x0 + i * g.h, t2 = g.y0 + j * g.h;
+    const double t1 = node_coord(g.x0, i, g.h), t2 = node_coord(g.y0, j, g.h);
     double s1 = 0.0, s2 = 0.0;
     alpha64_all_wg(tab, np, t1, t2, s1, s2);
     const int tiles_x = (g.nx - 2) / (1 << bp.tx_shift) + 1;

@@ -94,6 +94,25 @@ __device__ __forceinline__ float wave_min(float v)
     return v;
 }
 
+// FP64 coordinate of grid node i on one axis, x0 + i h, with the product and
+// the sum rounded separately (no fused multiply-add): every FP64 node
+// position of the library is formed this way, so that FP64 offsets
+// theta - theta_c are the same numbers wherever they are computed, also at a
+// node that coincides (or nearly coincides) with a potential's centre.
+__device__ __forceinline__ double node_coord(double x0, double i, double h)
+{
+#pragma clang fp contract(off)
+    return x0 + i * h;
+}
+
+// FP64 source-plane coordinate theta - r alpha (the lens equation of
+// Sec. 2.2.2), product and difference rounded separately like node_coord.
+__device__ __forceinline__ double src_map(double t, double r, double a)
+{
+#pragma clang fp contract(off)
+    return t - r * a;
+}
+
 // ---------------------------------------------------------------- FP64 deflection
 
 // FP64 square root and reciprocal of positive normal arguments from the

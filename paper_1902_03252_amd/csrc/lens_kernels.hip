@@ -125,7 +125,7 @@ __device__ __forceinline__ void head_finish(int np, const GridDesc& g, const Obs
                 if (soff[mid] <= j) lo = mid; else hi = mid - 1;
             }
             const double r = obs.dls[lo];
-            const double b1 = obs.x[j] - r * beta_x[j], b2 = obs.y[j] - r * beta_y[j];
+            const double b1 = src_map(obs.x[j], r, beta_x[j]), b2 = src_map(obs.y[j], r, beta_y[j]);
             sbx[j] = b1;
             sby[j] = b2;
             const double sg = obs.sigma[j];
@@ -155,8 +155,8 @@ __device__ __forceinline__ void head_finish(int np, const GridDesc& g, const Obs
                     b1 = sbx[j];
                     b2 = sby[j];
                 } else {
-                    b1 = obs.x[j] - r * beta_x[j];
-                    b2 = obs.y[j] - r * beta_y[j];
+                    b1 = src_map(obs.x[j], r, beta_x[j]);
+                    b2 = src_map(obs.y[j], r, beta_y[j]);
                     beta_x[j] = b1;
                     beta_y[j] = b2;
                     ok = ok && obs.sigma[j] > 0.0 && isfinite(obs.sigma[j]) && isfinite(obs.x[j]) &&
@@ -277,11 +277,11 @@ __device__ __forceinline__ void field64_row(const double* __restrict__ tab64, in
 {
     const int i0 = (bx * 256 + (int)threadIdx.x) * kNpl64;
     if (bx * 256 * kNpl64 >= g.nx) return;  // whole workgroup beyond the row
-    const double t2 = g.y0 + j * g.h;
+    const double t2 = node_coord(g.y0, j, g.h);
     double t1[kNpl64], s1[kNpl64], s2[kNpl64];
 #pragma unroll
     for (int k = 0; k < kNpl64; k++) {
-        t1[k] = g.x0 + (i0 + k) * g.h;
+        t1[k] = node_coord(g.x0, i0 + k, g.h);
         s1[k] = 0.0;
         s2[k] = 0.0;
     }
@@ -469,12 +469,12 @@ __device__ __forceinline__ void pair_test(const V* __restrict__ ax, const V* __r
                 res1 = decide32(ux, uy, E, mode, tau, nbbox);
             } else {
                 const double r = row[SYS_R], bx = row[SYS_BX], by = row[SYS_BY];
-                const double t0x = g.x0 + gi * g.h, t1x = g.x0 + (gi + 1) * g.h;
-                const double t0y = g.y0 + gj * g.h, t1y = g.y0 + (gj + 1) * g.h;
-                const double b00x = t0x - r * va[b][0], b00y = t0y - r * va[b][4];
-                const double b10x = t1x - r * va[b][1], b10y = t0y - r * va[b][5];
-                const double b01x = t0x - r * va[b][2], b01y = t1y - r * va[b][6];
-                const double b11x = t1x - r * va[b][3], b11y = t1y - r * va[b][7];
+                const double t0x = node_coord(g.x0, gi, g.h), t1x = node_coord(g.x0, gi + 1, g.h);
+                const double t0y = node_coord(g.y0, gj, g.h), t1y = node_coord(g.y0, gj + 1, g.h);
+                const double b00x = src_map(t0x, r, va[b][0]), b00y = src_map(t0y, r, va[b][4]);
+                const double b10x = src_map(t1x, r, va[b][1]), b10y = src_map(t0y, r, va[b][5]);
+                const double b01x = src_map(t0x, r, va[b][2]), b01y = src_map(t1y, r, va[b][6]);
+                const double b11x = src_map(t1x, r, va[b][3]), b11y = src_map(t1y, r, va[b][7]);
                 const double vx0[3] = {b00x, b10x, b01x}, vy0[3] = {b00y, b10y, b01y};
                 const double vx1[3] = {b11x, b01x, b10x}, vy1[3] = {b11y, b01y, b10y};
                 if (!(bx < fmin(vx0[0], fmin(vx0[1], vx0[2])) || bx > fmax(vx0[0], fmax(vx0[1], vx0[2])) ||
@@ -654,7 +654,7 @@ __global__ __launch_bounds__(1024) void k_tail(ObsPtrs obs, EvalState* __restric
             soy[t] = obs.y[t];
             ssg[t] = obs.sigma[t];
         }
-        if (t <= nsys) soff[t] = obs.sys_off[t];
+        for (int q = t; q <= nsys; q += 1024) soff[q] = obs.sys_off[q];  // nsys + 1 <= 1025 entries
         if (t < nsys) {
             sfirst[t] = 0;
             send[t] = 0;

@@ -237,7 +237,7 @@ __global__ __launch_bounds__(256) void k_mix_dp(const double* __restrict__ tab64
     for (unsigned e = lo + blockIdx.x * 256 + threadIdx.x; e < hi; e += gridDim.x * 256) {
         const unsigned n = list[e];
         const int j = (int)(n / (unsigned)g.nx), i = (int)(n - (unsigned)j * (unsigned)g.nx);
-        const double t1 = g.x0 + i * g.h, t2 = g.y0 + j * g.h;
+        const double t1 = node_coord(g.x0, i, g.h), t2 = node_coord(g.y0, j, g.h);
         double s1 = 0.0, s2 = 0.0;
 #pragma unroll 4
         for (int p = 0; p < np; p++) sie64_add(tab64 + (size_t)p * T64_STRIDE, t1, t2, s1, s2);

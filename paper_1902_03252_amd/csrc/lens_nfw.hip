@@ -156,7 +156,7 @@ __global__ __launch_bounds__(256) void k_nfw64(const double* __restrict__ t64, i
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= g.nx) return;
     const bool bad = *st != kStatusOk;
-    const double t1 = g.x0 + i * g.h, t2 = g.y0 + j * g.h;
+    const double t1 = node_coord(g.x0, i, g.h), t2 = node_coord(g.y0, j, g.h);
     double s1 = 0.0, s2 = 0.0;
     for (int p = 0; p < np && !bad; p++) {
         const double* c = t64 + (size_t)p * N64_STRIDE;

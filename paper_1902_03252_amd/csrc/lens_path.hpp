@@ -88,8 +88,14 @@ inline __device__ void prep_one(const PotPtrs& pot, const GridDesc& g, int p, in
     const bool sinf = row[T64_SINF] != 0.0;
     const double cxn = (xc - g.x0) / g.h, cyn = (yc - g.y0) / g.h;
     ok = ok && fabs(cxn) < 4194304.0 && fabs(cyn) < 4194304.0;  // |centre| < 2^22 nodes
-    const double cxh = rint(cxn), cyh = rint(cyn);
-    const double cxl = cxn - cxh, cyl = cyn - cyh;
+    const double cxh = ok ? rint(cxn) : 0.0, cyh = ok ? rint(cyn) : 0.0;
+    // The fraction is taken from the FP64 offset of the nearest node itself,
+    // formed as every FP64 node offset is (node_coord, then the difference):
+    // at that node the FP32 offset (i - c_hi) - c_lo = -c_lo is then that FP64
+    // offset up to one FP32 rounding, a relative error even when the centre
+    // lies on (or within rounding of) the node.
+    const double cxl = -(node_coord(g.x0, cxh, g.h) - xc) / g.h;
+    const double cyl = -(node_coord(g.y0, cyh, g.h) - yc) / g.h;
     const double h2 = g.h * g.h;
     float* u = tab32 + (size_t)q * T32_STRIDE;
     u[T32_CXH] = (float)cxh;
@@ -116,20 +122,39 @@ inline __device__ void prep_one(const PotPtrs& pot, const GridDesc& g, int p, in
     u[T32_RSK] = (float)((double)u[T32_RS] * (double)kinv);
     for (int k = T32_RSK + 1; k < T32_STRIDE; k++) u[k] = 0.0f;
 
+    // Offset error term j_p.  Every node other than the nearest one lies at
+    // least half a node from the centre on one axis, so R >= sqrt(1 - eps) h
+    // max(rn, 1/2) there (R^2 >= (1 - eps) |d|^2), and its offset differs from
+    // the FP64 node offset by at most derr (FP32 rounding of the fraction, the
+    // FP64 reference's own rounding of the node positions and of theta -
+    // theta_c); J bounds the Jacobian of grad Psi_p at that radius.  At the
+    // nearest node the difference is relative (one FP32 rounding of c_lo,
+    // above): |Jacobian| |Delta d| <= (2 K (1 + eps) / ((1 - eps) R)) u |d| <=
+    // 2 u K (1 + eps) / (1 - eps)^1.5, whatever the distance.
     const double w = K * a2 / sqrt(a1);
-    const double rho = sqrt(a1) * g.h * sqrt(cxl * cxl + cyl * cyl);
-    const double den = a1 * (sqrt(a * a + rho * rho) + a);
-    const double J = den > 0.0 ? 2.0 * K * a2 / den : INFINITY;
-    // absolute offset error: FP32 rounding of the centre fraction, plus the FP64
-    // reference's own rounding of theta - theta_c
+    const double rn = sqrt(cxl * cxl + cyl * cyl);
+    const double rho = sqrt(a1) * g.h * fmax(rn, 0.5);
+    const double J = 2.0 * K * a2 / (a1 * (sqrt(a * a + rho * rho) + a));
     const double span = fabs(g.x0) + fabs(g.y0) + (double)(g.nx + g.ny) * g.h + fabs(xc) + fabs(yc);
-    const double derr = g.h * kNodeSplitErr + 4.5e-16 * span;
+    // (two nodes' roundings of x0 + i h and theta - theta_c, each <= 2^-53 (2 |x0| + 3 n h + |x_c|)
+    // per axis, below 1e-15 span)
+    const double derr = g.h * kNodeSplitErr + 1e-15 * span;
+    // That relative argument needs the FP32 evaluation at the nearest node to
+    // be accurate itself: for a (nearly) singular profile whose centre lies
+    // within 1e-10" of a node without coinciding with it, the 1e-20" stand-in
+    // core and the FP32 range of R^2 are not negligible there, and the term
+    // 2 w_p (any deflection direction) is taken instead: the bound then admits
+    // little, and the mixed path defers to the FP64 fallback or reports
+    // capacity.  A centre exactly on a node is exact in both precisions (zero
+    // offsets, zero contribution).
+    const bool near_singular = rn > 0.0 && g.h * rn < 1e-10 && a < 1e-10;
+    const double jt = J * derr + 2.0 * kU32 * K * a2 / (a1 * sqrt(a1)) + (near_singular ? 2.0 * w : 0.0);
     bterm[3 * q + 0] = ok ? w : 0.0;
-    bterm[3 * q + 1] = ok ? J * derr : 0.0;
+    bterm[3 * q + 1] = ok ? jt : 0.0;
     bterm[3 * q + 2] = ok ? 0.0 : 1.0;
     if (terms) {
         terms[0] = ok ? w : 0.0;
-        terms[1] = ok ? J * derr : 0.0;
+        terms[1] = ok ? jt : 0.0;
         terms[2] = ok ? 0.0 : 1.0;
     }
 }
@@ -466,8 +491,8 @@ __device__ __forceinline__ void write_part_sum(unsigned* part, size_t slot, unsi
 __device__ __forceinline__ bool tile_box_contains(const GridDesc& g, const Tile& T, const double* rng, double r,
                                                   double eb, double bx, double by)
 {
-    const double tx0 = g.x0 + T.ci0 * g.h, tx1 = g.x0 + (T.ci0 + T.ncx) * g.h;
-    const double ty0 = g.y0 + T.cj0 * g.h, ty1 = g.y0 + (T.cj0 + T.ncy) * g.h;
+    const double tx0 = node_coord(g.x0, T.ci0, g.h), tx1 = node_coord(g.x0, T.ci0 + T.ncx, g.h);
+    const double ty0 = node_coord(g.y0, T.cj0, g.h), ty1 = node_coord(g.y0, T.cj0 + T.ncy, g.h);
     return bx >= tx0 - r * rng[1] - eb && bx <= tx1 - r * rng[0] + eb && by >= ty0 - r * rng[3] - eb &&
            by <= ty1 - r * rng[2] + eb;
 }
@@ -534,12 +559,12 @@ __device__ __forceinline__ void tri64_system(const GridDesc& g, const Tile& T, c
         const int gi = T.ci0 + li, gj = T.cj0 + lj;
         bool h0 = false, h1 = false;
         if (valid) {
-            const double t0x = g.x0 + gi * g.h, t1x = g.x0 + (gi + 1) * g.h;
-            const double t0y = g.y0 + gj * g.h, t1y = g.y0 + (gj + 1) * g.h;
-            const double b00x = t0x - r * sx[lj][li], b00y = t0y - r * sy[lj][li];
-            const double b10x = t1x - r * sx[lj][li + 1], b10y = t0y - r * sy[lj][li + 1];
-            const double b01x = t0x - r * sx[lj + 1][li], b01y = t1y - r * sy[lj + 1][li];
-            const double b11x = t1x - r * sx[lj + 1][li + 1], b11y = t1y - r * sy[lj + 1][li + 1];
+            const double t0x = node_coord(g.x0, gi, g.h), t1x = node_coord(g.x0, gi + 1, g.h);
+            const double t0y = node_coord(g.y0, gj, g.h), t1y = node_coord(g.y0, gj + 1, g.h);
+            const double b00x = src_map(t0x, r, sx[lj][li]), b00y = src_map(t0y, r, sy[lj][li]);
+            const double b10x = src_map(t1x, r, sx[lj][li + 1]), b10y = src_map(t0y, r, sy[lj][li + 1]);
+            const double b01x = src_map(t0x, r, sx[lj + 1][li]), b01y = src_map(t1y, r, sy[lj + 1][li]);
+            const double b11x = src_map(t1x, r, sx[lj + 1][li + 1]), b11y = src_map(t1y, r, sy[lj + 1][li + 1]);
             const double vx0[3] = {b00x, b10x, b01x}, vy0[3] = {b00y, b10y, b01y};
             const double vx1[3] = {b11x, b01x, b10x}, vy1[3] = {b11y, b01y, b10y};
             const double lo0 = fmin(vx0[0], fmin(vx0[1], vx0[2])), hi0 = fmax(vx0[0], fmax(vx0[1], vx0[2]));
@@ -574,8 +599,8 @@ __device__ __forceinline__ void vertices64(const double* __restrict__ tab64, int
     double s[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
     for (int v = 0; v < 3; v++) {
-        tx[v] = g.x0 + ni[v] * g.h;
-        ty[v] = g.y0 + nj[v] * g.h;
+        tx[v] = node_coord(g.x0, ni[v], g.h);
+        ty[v] = node_coord(g.y0, nj[v], g.h);
     }
     for (int p = lane_id(); p < np; p += 64) {
         const double* t = tab64 + (size_t)p * T64_STRIDE;
@@ -584,8 +609,8 @@ __device__ __forceinline__ void vertices64(const double* __restrict__ tab64, int
     }
 #pragma unroll
     for (int v = 0; v < 3; v++) {
-        vx[v] = tx[v] - r * wave_sum(s[2 * v]);
-        vy[v] = ty[v] - r * wave_sum(s[2 * v + 1]);
+        vx[v] = src_map(tx[v], r, wave_sum(s[2 * v]));
+        vy[v] = src_map(ty[v], r, wave_sum(s[2 * v + 1]));
     }
 }
 

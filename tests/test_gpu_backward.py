@@ -81,7 +81,6 @@ def test_deflect_vjp_all_profile_kinds_ragged_grid(lens, prec):
     want, mag = oracle_vjp("kinds", prm, grid, gx, gy)
     got = lens.lens_deflect_backward(dev(prm), grid, dev(gx), dev(gy), prec).cpu().numpy()
     check_vjp(got, want, mag, prec, "kinds")
-    assert (got[5, 2:4] == 0).all() or True  # r_cut = inf rows: checked against the oracle's zeros above
     np.testing.assert_array_equal(got[5][np.isinf(prm[5])], 0.0)
 
 
