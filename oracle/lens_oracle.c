@@ -10,12 +10,14 @@
  * smoke check and the CPU-baseline leg of the benchmark load it.
  *
  * Every function follows the paper's steps in the paper's order and notation:
- *   - deflection: Algorithm 1 (translate, rotate by -Phi, pseudo-elliptical
- *     radius R, gradient in the lens frame, rotate back by +Phi, sum over
- *     potentials), with the singular isothermal radial profile generalised to
- *     the cored and cut isothermal (dPIE) profile that the paper names as the
- *     next model in Sec. 5.  With r_core = 0 and r_cut = inf the code below is
- *     Algorithm 1 itself.
+ *   - deflection: the pseudo-elliptical potential of Sec. 2.2.2 (the
+ *     potential's own frame, the coordinates theta_{i,eps} = sqrt(1 -/+ eps)
+ *     theta_i with their polar form (R, phi), the deflection components
+ *     |alpha(R)| sqrt(1 -/+ eps) (cos phi, sin phi), the frame turned back,
+ *     superposition over potentials), with the singular isothermal radial
+ *     profile generalised to the cored and cut isothermal (dPIE) profile that
+ *     the paper names as the next model in Sec. 5.  With r_core = 0 and
+ *     r_cut = inf it is the SIE gradient that Algorithm 1 computes.
  *   - lens equation in the form of Sec. 2.2.2 (beta = theta - (D_LS/D_OS) grad Psi,
  *     the distance ratio computed once per source).
  *   - chi^2 re-lensing of Sec. 2.2.1 / 2.2.2 and Fig. 1: observed images to the
@@ -110,41 +112,72 @@ static double orc_profile_K(double sigma_v, double a, double s)
     return isfinite(s) ? b0 * s / (s - a) : b0;
 }
 
+/* Turns the vector (x, y) by the angle whose cosine and sine are (c, s):
+ * (c x - s y, s x + c y).  A potential's own frame has its first axis along
+ * the semi-major axis, at angle Phi counter-clockwise from theta_1 (Sec. 2.2.2);
+ * sky -> own frame is the turn by -Phi, own frame -> sky the turn by +Phi. */
+static void orc_turn(double c, double s, double x, double y, double *ox, double *oy)
+{
+    *ox = c * x - s * y;
+    *oy = s * x + c * y;
+}
+
 /* grad Psi_eps at one point theta = (t1, t2), summed over np potentials given
  * as structure of arrays prm[7][np] (rows x, y, eps, phi, r_core, r_cut,
- * sigma_v).  Steps are those of Algorithm 1, in its order. */
+ * sigma_v).  For each potential, from the equations of Sec. 2.2.2: the offset
+ * from its centre in its own frame; the pseudo-elliptical coordinates
+ * theta_{1,eps} = sqrt(a_1) theta_1, theta_{2,eps} = sqrt(a_2) theta_2
+ * (a_{1,2} = 1 -/+ eps) and their polar form (R, phi); the deflection of the
+ * circular profile at R, |alpha(R)|, split into the pseudo-elliptical
+ * components |alpha(R)| sqrt(a_1) cos(phi) and |alpha(R)| sqrt(a_2) sin(phi);
+ * that vector turned back to the sky frame; the contributions of all
+ * potentials added (superposition).  For the SIS profile this is the SIE
+ * gradient ((1 - eps) b0 theta_1 / R, (1 + eps) b0 theta_2 / R) of the same
+ * section. */
 void orc_alpha(const double *prm, int np, double t1, double t2, double *a1, double *a2)
 {
     const double *xc = prm, *yc = prm + np, *eps = prm + 2 * np, *phi = prm + 3 * np;
     const double *rc = prm + 4 * np, *rcut = prm + 5 * np, *sig = prm + 6 * np;
     double sum1 = 0.0, sum2 = 0.0;
     for (int i = 0; i < np; i++) {
-        double dt1 = t1 - xc[i];                              /* translate          */
-        double dt2 = t2 - yc[i];
-        double dt1r = dt1 * cos(phi[i]) + dt2 * sin(phi[i]);   /* rotate by -Phi     */
-        double dt2r = dt2 * cos(phi[i]) - dt1 * sin(phi[i]);
-        double R2 = dt1r * dt1r * (1.0 - eps[i]) + dt2r * dt2r * (1.0 + eps[i]);
-        double Kf = orc_profile_K(sig[i], rc[i], rcut[i]) * orc_profile_f(R2, rc[i], rcut[i]);
-        double g1 = (1.0 - eps[i]) * Kf * dt1r;                /* lens-frame gradient */
-        double g2 = (1.0 + eps[i]) * Kf * dt2r;
-        double g1r = g1 * cos(-phi[i]) + g2 * sin(-phi[i]);     /* rotate back by +Phi */
-        double g2r = g2 * cos(-phi[i]) - g1 * sin(-phi[i]);
-        sum1 += g1r;                                           /* superposition       */
-        sum2 += g2r;
+        double c = cos(phi[i]), s = sin(phi[i]);
+        double u, v;                          /* offset in the potential's frame */
+        orc_turn(c, -s, t1 - xc[i], t2 - yc[i], &u, &v);
+        double sq1 = sqrt(1.0 - eps[i]), sq2 = sqrt(1.0 + eps[i]);
+        double e1 = sq1 * u, e2 = sq2 * v;   /* theta_{1,eps}, theta_{2,eps} */
+        double R2 = e1 * e1 + e2 * e2;
+        double f = orc_profile_f(R2, rc[i], rcut[i]);
+        if (f == 0.0) continue;               /* centre of a singular profile */
+        double R = sqrt(R2), ang = atan2(e2, e1);
+        double mag = orc_profile_K(sig[i], rc[i], rcut[i]) * R * f;   /* |alpha(R)| */
+        double g1, g2;
+        orc_turn(c, s, mag * sq1 * cos(ang), mag * sq2 * sin(ang), &g1, &g2);
+        sum1 += g1;
+        sum2 += g2;
     }
     *a1 = sum1;
     *a2 = sum2;
 }
 
-/* The same steps in complex arithmetic, used only for complex-step
+/* The same equations in complex arithmetic, used only for complex-step
  * derivatives (Squire & Trapp 1998): every operation is analytic away from
- * R = 0, so Im(f(x + i h)) / h = f'(x) to rounding for tiny h. */
+ * R = 0, so Im(f(x + i h)) / h = f'(x) to rounding for tiny h.  The polar
+ * angle enters through cos(phi) = theta_{1,eps} / R, sin(phi) =
+ * theta_{2,eps} / R (analytic, unlike atan2), with R cancelled against the
+ * profile's |alpha(R)| = K R f(R). */
 static double complex orc_profile_f_c(double complex R2, double complex a, double complex s, int s_inf)
 {
     if (creal(a) == 0.0 && cimag(a) == 0.0 && creal(R2) == 0.0 && cimag(R2) == 0.0) return 0.0;
     double complex f = 1.0 / (csqrt(a * a + R2) + a);
     if (!s_inf) f -= 1.0 / (csqrt(s * s + R2) + s);
     return f;
+}
+
+static void orc_turn_c(double complex c, double complex s, double complex x, double complex y,
+                       double complex *ox, double complex *oy)
+{
+    *ox = c * x - s * y;
+    *oy = s * x + c * y;
 }
 
 /* Deflection of a single potential with complex parameters p[7] at complex
@@ -154,17 +187,21 @@ static void orc_alpha1_c(const double complex *p, double complex t1, double comp
 {
     double complex xc = p[0], yc = p[1], eps = p[2], phi = p[3], rc = p[4], rcut = p[5], sig = p[6];
     int s_inf = !isfinite(creal(rcut));
-    double complex dt1 = t1 - xc, dt2 = t2 - yc;
-    double complex dt1r = dt1 * ccos(phi) + dt2 * csin(phi);
-    double complex dt2r = dt2 * ccos(phi) - dt1 * csin(phi);
-    double complex R2 = dt1r * dt1r * (1.0 - eps) + dt2r * dt2r * (1.0 + eps);
+    double complex c = ccos(phi), s = csin(phi), u, v;
+    orc_turn_c(c, -s, t1 - xc, t2 - yc, &u, &v);
+    double complex sq1 = csqrt(1.0 - eps), sq2 = csqrt(1.0 + eps);
+    double complex e1 = sq1 * u, e2 = sq2 * v;
+    double complex R2 = e1 * e1 + e2 * e2;
+    double complex f = orc_profile_f_c(R2, rc, rcut, s_inf);
+    if (f == 0.0) { *a1 = 0.0; *a2 = 0.0; return; }
     double complex ratio = sig / ORC_C_KMS;
     double complex b0 = 4.0 * ORC_PI * ratio * ratio * ORC_ARCSEC_PER_RAD;
     double complex K = s_inf ? b0 : b0 * rcut / (rcut - rc);
-    double complex Kf = K * orc_profile_f_c(R2, rc, rcut, s_inf);
-    double complex g1 = (1.0 - eps) * Kf * dt1r, g2 = (1.0 + eps) * Kf * dt2r;
-    *a1 = g1 * ccos(-phi) + g2 * csin(-phi);
-    *a2 = g2 * ccos(-phi) - g1 * csin(-phi);
+    /* |alpha(R)| cos(phi) = (K R f) (theta_{1,eps} / R) = K f theta_{1,eps}, and
+     * likewise for sin(phi): the same quantity, analytic also at R = 0 (the
+     * centre of a cored profile) */
+    double complex Kf = K * f;
+    orc_turn_c(c, s, Kf * sq1 * e1, Kf * sq2 * e2, a1, a2);
 }
 
 /* Complex deflection summed over all potentials; parameter (kq, pq) of the

@@ -395,6 +395,85 @@ def test_complex_step_identities():
             np.testing.assert_allclose(cs, fd, rtol=1e-6, atol=1e-8)
 
 
+def _exact_src_chi2(sys_off, bx, by, sig):
+    """sum_i sum_j |beta_ij - mean_j beta_ij|^2 / sigma_ij^2 in exact rational
+    arithmetic (every float converted exactly)."""
+    tot = Fraction(0)
+    for i in range(len(sys_off) - 1):
+        j0, j1 = int(sys_off[i]), int(sys_off[i + 1])
+        if j1 == j0:
+            continue
+        X = [Fraction(float(v)) for v in bx[j0:j1]]
+        Y = [Fraction(float(v)) for v in by[j0:j1]]
+        mx, my = sum(X) / len(X), sum(Y) / len(Y)
+        for k in range(j1 - j0):
+            s2 = Fraction(float(sig[j0 + k])) ** 2
+            tot += ((X[k] - mx) ** 2 + (Y[k] - my) ** 2) / s2
+    return tot
+
+
+def test_src_chi2_identity_lens_is_the_exact_scatter():
+    """With no potential the lens equation gives beta = theta, so the source-plane
+    chi^2 (reading of the smooth companion of the image-plane chi^2) is the
+    sigma-weighted scatter of each system's observed images about their unweighted
+    mean, computed here in exact rational arithmetic.  Catches sigma instead of
+    sigma^2, a weighted or wrongly delimited mean, a dropped component, a
+    missing system or a wrong normalisation."""
+    g = np.random.default_rng(31)
+    sizes = [1, 2, 3, 5, 4]
+    sys_off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
+    n = int(sys_off[-1])
+    obs = dict(sys_off=sys_off, x=g.uniform(-30, 30, n), y=g.uniform(-30, 30, n),
+               sigma=g.choice([0.05, 0.1, 0.25, 0.7], n), dls=g.uniform(0.4, 0.9, len(sizes)))
+    want = _exact_src_chi2(sys_off, obs["x"], obs["y"], obs["sigma"])
+    got = oracle.src_chi2(np.zeros((7, 0)), obs)
+    assert abs(Fraction(got) - want) <= Fraction(1, 10 ** 12) * want
+    # a single-image system contributes nothing; moving one image moves only its system's term
+    obs2 = dict(obs, x=obs["x"].copy())
+    obs2["x"][0] += 3.0
+    assert oracle.src_chi2(np.zeros((7, 0)), obs2) == pytest.approx(got, rel=1e-14)
+
+
+def test_src_chi2_vanishes_on_exact_images_of_a_singular_isothermal_sphere():
+    """A singular isothermal sphere at theta_c maps its two images theta_c + u(|b| +/- r b0)
+    (u the unit vector of the source offset b; the closed form of Sec. 2.1 with the
+    distance ratio r) onto one source, so their source-plane chi^2 is zero up to
+    rounding; a wrong sign or a misplaced distance ratio in the lens equation
+    separates them by ~2 r b0."""
+    xc, yc, sig = 1.5, -0.75, 600.0
+    b0 = 4 * math.pi * (sig / C_KMS) ** 2 * 180 * 3600 / math.pi
+    prm = pot(x=xc, y=yc, sig=sig)
+    xs, ys, sys_off, dls = [], [], [0], []
+    for (bx, by, r) in [(0.8, 0.3, 0.7), (-1.2, 2.0, 0.9), (0.05, -0.4, 0.55)]:
+        bl = math.hypot(bx, by)
+        ux, uy = bx / bl, by / bl
+        for t in (bl + r * b0, bl - r * b0):
+            xs.append(xc + ux * t)
+            ys.append(yc + uy * t)
+        sys_off.append(len(xs))
+        dls.append(r)
+    obs = dict(sys_off=np.array(sys_off, np.int32), x=np.array(xs), y=np.array(ys), sigma=np.full(len(xs), 0.1),
+               dls=np.array(dls))
+    assert oracle.src_chi2(prm, obs) <= 1e-18
+    bad = dict(obs, dls=obs["dls"] * 1.01)
+    assert oracle.src_chi2(prm, bad) > 1.0
+
+
+def test_nfw_grid_indexing_matches_pointwise_deflection():
+    """The NFW field at node (i, j) of a grid with nx != ny, x0 != y0, is the
+    pointwise deflection at (x0 + i h, y0 + j h), stored at row j, column i
+    (catches a transposed or mis-strided layout, or swapped axes)."""
+    prm = np.stack([nfw(x=1.3, y=-2.1, eps=0.2, phi=0.7, rs=6.0, ks=0.3)[:, 0],
+                    nfw(x=-4.0, y=3.5, eps=0.1, phi=2.0, rs=3.0, ks=0.1)[:, 0]], axis=1)
+    grid = S.Grid(-7.3, -5.1, 0.61, 23, 17)
+    ax, ay = oracle.nfw_alpha_grid(prm, grid)
+    assert ax.shape == (17, 23)
+    for j in range(grid.ny):
+        for i in range(grid.nx):
+            a = oracle.nfw_alpha(prm, grid.x0 + i * grid.h, grid.y0 + j * grid.h)
+            assert ax[j, i] == a[0] and ay[j, i] == a[1], (i, j)
+
+
 def test_src_chi2_gradient_against_finite_differences():
     """Complex-step gradient of the source-plane chi^2 vs central differences with
     h = 1e-6 relative (1e-6 absolute for parameters equal to zero)."""
