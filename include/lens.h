@@ -235,6 +235,13 @@ typedef struct {
     int32_t *status;    /* [n_samples]          LENS_OK / LENS_ERR_INVALID / _CAPACITY      */
     int64_t *stats;     /* [LENS_STAT_N] totals over the batch; stats[4] is 1 if any sample
                            is not OK, stats[7] the number of such samples                 */
+    /* Optional triangle hits of every sample (all three NULL, or all three set):   */
+    int32_t *n_hits;    /* [n_samples]          hits of each sample (0 if not OK)         */
+    int32_t *hits;      /* [n_samples * 2 * hit_capacity] sample s: (system, triangle id)
+                           pairs in rows [s * hit_capacity, s * hit_capacity + n_hits[s]),
+                           sorted as lens_image_chi2's                                   */
+    double *img_xy;     /* [n_samples * 2 * hit_capacity] predicted image positions (x, y)
+                           of those hits                                                  */
 } lens_batch_out;
 
 /* Batched image-plane chi^2: n_samples lens models -- the proposals of a

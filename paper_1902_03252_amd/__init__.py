@@ -276,8 +276,10 @@ def _chi2_out(out: Chi2Result):
 
 
 def _batch_out(out: "BatchResult"):
+    hits = out.hits is not None
     return L.LensBatchOut(out.chi2.data_ptr(), out.chi2_sys.data_ptr(), out.n_pred.data_ptr(),
-                          out.status.data_ptr(), out.stats.data_ptr())
+                          out.status.data_ptr(), out.stats.data_ptr(), out.n_hits.data_ptr() if hits else None,
+                          out.hits.data_ptr() if hits else None, out.img_xy.data_ptr() if hits else None)
 
 
 class BatchLayout:
@@ -301,12 +303,29 @@ class BatchResult:
     n_pred: torch.Tensor    # [n, S] int32
     status: torch.Tensor    # [n] int32
     stats: torch.Tensor     # [8] int64, totals over the batch
+    n_hits: torch.Tensor | None = None  # [n] int32 (with hits)
+    hits: torch.Tensor | None = None    # [n, hit_capacity, 2] int32 (system, triangle id), sorted
+    img_xy: torch.Tensor | None = None  # [n, hit_capacity, 2] float64 predicted image positions
+
+    def sample_hits(self, s: int) -> dict:
+        """Host copy of sample s's hits (requires buffers made with hits=True)."""
+        k = int(self.n_hits[s])
+        h = self.hits[s, :k].cpu().numpy()
+        xy = self.img_xy[s, :k].cpu().numpy()
+        return dict(hit_sys=h[:, 0].copy(), hit_tid=h[:, 1].copy(), hit_x=xy[:, 0].copy(), hit_y=xy[:, 1].copy())
 
 
-def batch_buffers(n: int, obs: Obs, device) -> BatchResult:
+def batch_buffers(n: int, obs: Obs, device, hits: bool = False, hit_capacity: int = 1024) -> BatchResult:
+    """Output buffers of a batched call; with hits=True also the per-sample hit
+    lists (the call must then use the same hit_capacity)."""
     z = lambda *s, dt=torch.float64: torch.zeros(*s, dtype=dt, device=device)
-    return BatchResult(z(n), z(n, obs.n_sys), z(n, obs.n_sys, dt=torch.int32), z(n, dt=torch.int32),
-                       z(STAT_N, dt=torch.int64))
+    r = BatchResult(z(n), z(n, obs.n_sys), z(n, obs.n_sys, dt=torch.int32), z(n, dt=torch.int32),
+                    z(STAT_N, dt=torch.int64))
+    if hits:
+        r.n_hits = z(n, dt=torch.int32)
+        r.hits = z(n, hit_capacity, 2, dt=torch.int32)
+        r.img_xy = z(n, hit_capacity, 2)
+    return r
 
 
 def lens_image_chi2_batched(params: torch.Tensor, layout: BatchLayout, obs: Obs, prec: str = "mixed",
@@ -320,6 +339,8 @@ def lens_image_chi2_batched(params: torch.Tensor, layout: BatchLayout, obs: Obs,
         raise ValueError("prec must be 'fp64' or 'mixed'")
     p, o = _pots(params), _obs(obs)
     out = out or batch_buffers(layout.n, obs, params.device)
+    if out.hits is not None and tuple(out.hits.shape) != (layout.n, int(hit_capacity), 2):
+        raise ValueError("the hit buffers must be [n_samples, hit_capacity, 2]")
     opts = L.LensChi2Opts(_PREC[prec], int(fb_mode), float(fb_tau), int(hit_capacity), int(field_npl), int(tile))
     L.check(ctx._lib.lens_image_chi2_batched(ctx.handle, C.byref(p), layout.n, layout.pot_off, layout.grids,
                                              C.byref(o), C.byref(opts), C.byref(_batch_out(out)), ctx.stream()),

@@ -62,7 +62,7 @@ class LensChi2Out(C.Structure):
 
 class LensBatchOut(C.Structure):
     _fields_ = [("chi2", C.c_void_p), ("chi2_sys", C.c_void_p), ("n_pred", C.c_void_p), ("status", C.c_void_p),
-                ("stats", C.c_void_p)]
+                ("stats", C.c_void_p), ("n_hits", C.c_void_p), ("hits", C.c_void_p), ("img_xy", C.c_void_p)]
 
 
 _lib = None

@@ -824,6 +824,8 @@ extern "C" int lens_image_chi2_batched(lens_ctx* ctx, const lens_potentials* all
     if (!ctx || check_pot(all) || n_samples < 1 || !pot_off || !grids || check_obs(obs) || !opts || !out)
         return LENS_ERR_INVALID;
     if (!out->chi2 || !out->chi2_sys || !out->n_pred || !out->status || !out->stats) return LENS_ERR_INVALID;
+    const bool want_hits = out->n_hits || out->hits || out->img_xy;
+    if (want_hits && !(out->n_hits && out->hits && out->img_xy)) return LENS_ERR_INVALID;
     if (obs->n_img > kBatchMax || obs->n_sys > kBatchMax) return LENS_ERR_INVALID;
     if (opts->prec != LENS_FP64 && opts->prec != LENS_MIXED) return LENS_ERR_INVALID;
     if (opts->hit_capacity < 1 || opts->hit_capacity > kBatchMax) return LENS_ERR_INVALID;
@@ -924,7 +926,10 @@ extern "C" int lens_image_chi2_batched(lens_ctx* ctx, const lens_potentials* all
         if (e == hipSuccess)
             e = launch_btail(bp, o, bs, hcap, flag_cap, hits, fb, pos, fb_pos, out->chi2 + ch.s0,
                              out->chi2_sys + (size_t)ch.s0 * o.n_sys, out->n_pred + (size_t)ch.s0 * o.n_sys,
-                             out->status + ch.s0, agg, part, (ch.n_tiles + 3) / 4, stream);
+                             out->status + ch.s0, agg, part, (ch.n_tiles + 3) / 4,
+                             want_hits ? out->n_hits + ch.s0 : nullptr,
+                             want_hits ? out->hits + (size_t)ch.s0 * 2 * hcap : nullptr,
+                             want_hits ? out->img_xy + (size_t)ch.s0 * 2 * hcap : nullptr, stream);
         if (e != hipSuccess) return LENS_ERR_DEVICE;
     }
     return launch_bstats(agg, n_tests, (long long*)out->stats, stream) == hipSuccess ? LENS_OK : LENS_ERR_DEVICE;
@@ -1070,7 +1075,7 @@ extern "C" int lens_mh_step_batched(lens_ctx* ctx, double* states, int32_t n_cha
     for (int b = 0; b <= n_chains; b++) pot_off[b] = (int32_t)((long long)b * n);
     std::vector<lens_grid> grids((size_t)n_chains, *grid);
     const lens_potentials all = table_pots(prop, (int)bn);
-    lens_batch_out bo;
+    lens_batch_out bo = {};
     bo.chi2 = chi2_new;
     bo.chi2_sys = chi2_sys;
     bo.n_pred = n_pred;

@@ -355,7 +355,9 @@ __global__ __launch_bounds__(256) void k_btail(ObsPtrs obs, BatchState bs, int h
                                                double* __restrict__ chi2, double* __restrict__ chi2_sys,
                                                int* __restrict__ n_pred, int* __restrict__ status,
                                                unsigned long long* __restrict__ agg,
-                                               const unsigned* __restrict__ part, long long n_parts)
+                                               const unsigned* __restrict__ part, long long n_parts,
+                                               int* __restrict__ out_nh, int* __restrict__ out_hits,
+                                               double* __restrict__ out_xy)
 {
     constexpr int NT = 256, CAP = 2 * kTailStage;
     {  // chunk statistics (tile passes, bbox passes), one slice of the tiles per workgroup
@@ -400,7 +402,10 @@ __global__ __launch_bounds__(256) void k_btail(ObsPtrs obs, BatchState bs, int h
             cs_out[i] = __builtin_nan("");
             np_out[i] = 0;
         }
-        if (t == 0) chi2[s] = __builtin_nan("");
+        if (t == 0) {
+            chi2[s] = __builtin_nan("");
+            if (out_nh) out_nh[s] = 0;
+        }
         return;
     }
     const int n = (int)(nc + nfb), ncert = (int)nc;
@@ -439,7 +444,16 @@ __global__ __launch_bounds__(256) void k_btail(ObsPtrs obs, BatchState bs, int h
         const int sy = (int)(key[q] >> 44);
         if (q == 0 || (int)(key[q - 1] >> 44) != sy) sfirst[sy] = q;
         if (q == n - 1 || (int)(key[q + 1] >> 44) != sy) send[sy] = q + 1;
+        if (out_hits) {  // the sorted hits and their positions, as the single evaluation writes them
+            const size_t o = (size_t)s * hcap + q;
+            const int idx = (int)(key[q] & 0xfff);
+            out_hits[2 * o] = sy;
+            out_hits[2 * o + 1] = (int)((key[q] >> 12) & 0x7fffffffull);
+            out_xy[2 * o] = upx[idx];
+            out_xy[2 * o + 1] = upy[idx];
+        }
     }
+    if (out_nh && t == 0) out_nh[s] = n;
     __syncthreads();
     for (int j = t; j < nimg; j += NT) {
         const int i = system_of(obs.sys_off, nsys, j);
@@ -564,10 +578,11 @@ hipError_t launch_bfbpos(const BatchPlan& bp, int nsys, const double* tab64, con
 hipError_t launch_btail(const BatchPlan& bp, const ObsPtrs& obs, const BatchState& bs, int hcap, long long flag_cap,
                         const unsigned long long* hits, const unsigned long long* fb, const double* pos,
                         const double* fb_pos, double* chi2, double* chi2_sys, int* n_pred, int* status,
-                        unsigned long long* agg, const unsigned* part, long long n_parts, hipStream_t s)
+                        unsigned long long* agg, const unsigned* part, long long n_parts, int* out_nh,
+                        int* out_hits, double* out_xy, hipStream_t s)
 {
     k_btail<<<bp.n, 256, 0, s>>>(obs, bs, hcap, flag_cap, hits, fb, pos, fb_pos, chi2, chi2_sys, n_pred, status,
-                                 agg, part, n_parts);
+                                 agg, part, n_parts, out_nh, out_hits, out_xy);
     return hipGetLastError();
 }
 

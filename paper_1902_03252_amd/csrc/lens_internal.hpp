@@ -229,7 +229,8 @@ hipError_t launch_bfbpos(const BatchPlan& bp, int nsys, const double* tab64, con
 hipError_t launch_btail(const BatchPlan& bp, const ObsPtrs& obs, const BatchState& bs, int hcap, long long flag_cap,
                         const unsigned long long* hits, const unsigned long long* fb, const double* pos,
                         const double* fb_pos, double* chi2, double* chi2_sys, int* n_pred, int* status,
-                        unsigned long long* agg, const unsigned* part, long long n_parts, hipStream_t s);
+                        unsigned long long* agg, const unsigned* part, long long n_parts, int* out_nh,
+                        int* out_hits, double* out_xy, hipStream_t s);
 hipError_t launch_bstats(const unsigned long long* agg, long long n_tests, long long* stats, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s);
 hipError_t launch_dls(double zl, const double* zs, int n, double om, double ol, double* out, hipStream_t s);

@@ -53,14 +53,30 @@ def batch(n=12, seed_stream=40):
     return params, pot_off, grids
 
 
-def run_batched(lens, params, pot_off, grids, obs, prec, ctx=None, **kw):
+def run_batched(lens, params, pot_off, grids, obs, prec, ctx=None, hits=False, **kw):
     layout = lens.BatchLayout(pot_off, grids)
-    res = lens.lens_image_chi2_batched(dev(params), layout, lens.Obs.from_numpy(obs), prec=prec, ctx=ctx, **kw)
+    o = lens.Obs.from_numpy(obs)
+    out = lens.batch_buffers(layout.n, o, "cuda", hits=hits, hit_capacity=kw.get("hit_capacity", 1024))
+    res = lens.lens_image_chi2_batched(dev(params), layout, o, prec=prec, ctx=ctx, out=out, **kw)
     torch.cuda.synchronize()
-    return {k: getattr(res, k).cpu().numpy() for k in ("chi2", "chi2_sys", "n_pred", "status", "stats")}
+    got = {k: getattr(res, k).cpu().numpy() for k in ("chi2", "chi2_sys", "n_pred", "status", "stats")}
+    if hits:
+        got["hits"] = [res.sample_hits(s) for s in range(layout.n)]
+    return got
 
 
-def check_sample(got, s, want, rtol):
+POS_TOL = {"fp64": 1e-9, "mixed": 1e-5}
+
+
+def check_sample(got, s, want, rtol, prec=None):
+    """Per-sample counts and chi^2; with the hit lists, also the sorted hit set
+    (bit-exact) and the predicted positions (1e-9" FP64, 1e-5" mixed)."""
+    if "hits" in got:
+        h = got["hits"][s]
+        np.testing.assert_array_equal(h["hit_sys"], want["hit_sys"])
+        np.testing.assert_array_equal(h["hit_tid"], want["hit_tid"])
+        np.testing.assert_allclose(h["hit_x"], want["hit_x"], rtol=0, atol=POS_TOL[prec])
+        np.testing.assert_allclose(h["hit_y"], want["hit_y"], rtol=0, atol=POS_TOL[prec])
     np.testing.assert_array_equal(got["n_pred"][s], want["n_pred"])
     fin = np.isfinite(want["chi2_sys"])
     np.testing.assert_array_equal(np.isfinite(got["chi2_sys"][s]), fin)
@@ -76,14 +92,14 @@ def test_batched_matches_oracle_and_single(lens, prec):
     _, _, obs = load_inputs(2)
     params, pot_off, grids = batch()
     print(f"batched {prec}: P={np.diff(pot_off).tolist()} sides={[g.nx for g in grids]}", flush=True)
-    got = run_batched(lens, params, pot_off, grids, obs, prec)
+    got = run_batched(lens, params, pot_off, grids, obs, prec, hits=True)
     assert (got["status"] == 0).all()
     o = lens.Obs.from_numpy(obs)
     hits = 0
     for s, prm in enumerate(split(params, pot_off)):
         want = oracle_of(("b", s), prm, grids[s], obs)
         hits += len(want["hit_sys"])
-        check_sample(got, s, want, RTOL[prec])
+        check_sample(got, s, want, RTOL[prec], prec)
         single = lens.lens_image_chi2(dev(prm), grids[s], o, prec=prec)
         torch.cuda.synchronize()
         one = single.host()
@@ -192,3 +208,33 @@ def test_batched_graph_replay_matches_eager(lens):
             for k in ("chi2", "chi2_sys", "n_pred", "status", "stats"):
                 np.testing.assert_array_equal(getattr(out, k).cpu().numpy(), eager[k], err_msg=f"{prec} {rep} {k}")
         del graph
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_batched_full_workload_sampled_against_oracle(lens, prec):
+    """The benchmark's 1024-sample batch (P 10..200, sides 256..2048, 1.49e9 nodes:
+    one chunk in mixed precision, two in FP64) with the hit lists; compared with the
+    oracle on sampled members: the largest grids with the most potentials, the last
+    samples of the batch (the highest node offsets of the chunk's field planes) and
+    a 256^2 sample -- hit sets bit-exact, positions and chi^2 within the bars."""
+    _, _, obs = load_inputs(2)
+    params, pot_off, grids = S.batch_samples(1024)
+    got = run_batched(lens, params, pot_off, grids, obs, prec, hits=True)
+    assert (got["status"] == 0).all()
+    counts = np.diff(pot_off)
+    sides = np.array([g.nx for g in grids])
+    big = [int(s) for s in np.argsort(-(sides.astype(np.int64) ** 2 * counts), kind="stable")
+           if sides[s] == 2048 and counts[s] >= 190][:6]
+    last = [1023, 1022, 1021, 1020, 1019]
+    small = [int(np.flatnonzero(sides == 256)[-1])]
+    pick = sorted(set(big + last + small))
+    assert len(pick) >= 12
+    blocks = split(params, pot_off)
+    for s in pick:
+        key = ("full", s)
+        if key not in _ORACLE:
+            _ORACLE[key] = oracle.image_chi2(blocks[s], grids[s], obs, nthreads=min(16, os.cpu_count() or 1))
+        want = _ORACLE[key]
+        print(f"  {prec} sample {s}: side {sides[s]} P {counts[s]} hits {len(want['hit_sys'])}", flush=True)
+        check_sample(got, s, want, RTOL[prec], prec)

@@ -35,19 +35,24 @@ def dev(a, dt=None):
 
 def fp32_alpha_bound(prm, grid):
     """The library's stated FP32 deflection bound (per component):
-    u (64 + P) sum_p w_p + sum_p j_p + 1e-9, with w_p = K (1+eps)/sqrt(1-eps)."""
+    u (64 + P) sum_p w_p + sum_p j_p + 1e-9, with w_p = K (1+eps)/sqrt(1-eps) and
+    j_p = J_p derr + 2u K (1+eps)/(1-eps)^1.5 (+ 2 w_p for a nearly singular
+    profile within 1e-10" of a node without being on it), J_p the Jacobian bound
+    at half a node or at the nearest node's distance, whichever is larger."""
     eps, a, s, sig = prm[2], prm[4], prm[5], prm[6]
     b0 = 4 * math.pi * (sig / 299792.458) ** 2 * 206264.80624709636
     K = np.where(np.isinf(s), b0, b0 * s / np.where(np.isinf(s), 1.0, s - a))
     w = K * (1 + eps) / np.sqrt(1 - eps)
-    cx = (prm[0] - grid.x0) / grid.h
-    cy = (prm[1] - grid.y0) / grid.h
-    fx, fy = cx - np.rint(cx), cy - np.rint(cy)
-    rho = np.sqrt(1 - eps) * grid.h * np.hypot(fx, fy)
-    den = (1 - eps) * (np.sqrt(a * a + rho * rho) + a)
-    J = 2 * K * (1 + eps) / den
+    cx = np.rint((prm[0] - grid.x0) / grid.h)
+    cy = np.rint((prm[1] - grid.y0) / grid.h)
+    fx = -((grid.x0 + cx * grid.h) - prm[0]) / grid.h
+    fy = -((grid.y0 + cy * grid.h) - prm[1]) / grid.h
+    rn = np.hypot(fx, fy)
+    rho = np.sqrt(1 - eps) * grid.h * np.maximum(rn, 0.5)
+    J = 2 * K * (1 + eps) / ((1 - eps) * (np.sqrt(a * a + rho * rho) + a))
     span = abs(grid.x0) + abs(grid.y0) + (grid.nx + grid.ny) * grid.h + abs(prm[0]) + abs(prm[1])
-    j = J * (grid.h * 2.0 ** -25 + 4.5e-16 * span)
+    near = (rn > 0) & (grid.h * rn < 1e-10) & (a < 1e-10)
+    j = J * (grid.h * 2.0 ** -25 + 1e-15 * span) + 2 * U32 * K * (1 + eps) / (1 - eps) ** 1.5 + np.where(near, 2 * w, 0.0)
     return U32 * (64 + prm.shape[1]) * w.sum() + j.sum() + 1e-9
 
 
@@ -279,16 +284,189 @@ def test_chi2_capacity_and_invalid_status(lens):
     assert got["status"] == 0
 
 
-def test_chi2_literal_threshold_mode(lens):
-    """Literal fallback threshold tau * h^2: runs, reports its fallback count; the hit set
-    is compared with the oracle and mismatches (if any) are reported, not asserted."""
-    prm, grid, obs = load_inputs(2)
-    got = run_chi2(lens, prm, grid, obs, "mixed", fb_mode=1, fb_tau=1e-6)
-    want = oracle.image_chi2(prm, grid, obs)
-    a = set(zip(got["hit_sys"], got["hit_tid"]))
-    b = set(zip(want["hit_sys"], want["hit_tid"]))
-    print(f"literal mode: flagged {got['stats'][1]}, hit-set mismatches {len(a ^ b)}", flush=True)
+def sys_vertex_bound(prm, grid, bar_x, bar_y, dls):
+    """The library's stated FP32 bound E_B on each component of a source-plane
+    vertex offset B - barycentre, per system:
+    r E_alpha + 4u Theta + 2u r (W + E_alpha) + 2^-25 h + 1e-9 (times 1 + 1e-6)."""
+    e_alpha = fp32_alpha_bound(prm, grid)
+    eps, a, s, sig = prm[2], prm[4], prm[5], prm[6]
+    b0 = 4 * math.pi * (sig / 299792.458) ** 2 * 206264.80624709636
+    K = np.where(np.isinf(s), b0, b0 * s / np.where(np.isinf(s), 1.0, s - a))
+    W = float((K * (1 + eps) / np.sqrt(1 - eps)).sum())
+    xlo, xhi = grid.x0, grid.x0 + (grid.nx - 1) * grid.h
+    ylo, yhi = grid.y0, grid.y0 + (grid.ny - 1) * grid.h
+    theta = np.maximum(np.maximum(abs(xlo - bar_x), abs(xhi - bar_x)), np.maximum(abs(ylo - bar_y), abs(yhi - bar_y)))
+    eb = dls * e_alpha + 4 * U32 * theta + 2 * U32 * dls * (W + e_alpha) + grid.h * 2.0 ** -25 + 1e-9
+    return eb * (1 + 1e-6)
+
+
+def triangle_margin(prm, grid, sys, tid, bar_x, bar_y, dls, eb):
+    """min_k (|c_k| - T_k) of one (system, triangle) test: c_k = d_k x d_k+1 from the
+    oracle's FP64 vertices (d = B - barycentre), T_k the bound on how far FP32
+    vertices within eb of these (and FP32 products) can move c_k.  A test can be
+    decided differently from the exact one by FP32 arithmetic only if this is <= 0."""
+    nx = grid.nx
+    cell, k = divmod(int(tid), 2)
+    j, i = divmod(cell, nx - 1)
+    nodes = [(i, j), (i + 1, j), (i, j + 1)] if k == 0 else [(i + 1, j + 1), (i, j + 1), (i + 1, j)]
+    th = np.array([(grid.x0 + a * grid.h, grid.y0 + b * grid.h) for a, b in nodes])
+    al = oracle.alpha_points(prm, th)
+    r = dls[sys]
+    d = th - r * al - np.array([bar_x[sys], bar_y[sys]])
+    E = eb[sys]
+    m = np.inf
+    for q in range(3):
+        u, v = d[q], d[(q + 1) % 3]
+        c = u[0] * v[1] - u[1] * v[0]
+        T = E * (abs(u).sum() + abs(v).sum()) + 2 * E * E + 2 * U32 * (abs(u[0] * v[1]) + abs(u[1] * v[0]))
+        m = min(m, abs(c) - 1.01 * T)
+    return m
+
+
+def _literal_check(lens, prm, grid, obs, want):
+    """Literal fallback rule |c| < tau h^2 (tau = 1e-6): the FP32 sign is taken
+    whenever |c| >= tau h^2, which does not guarantee the exact decision.  Every
+    hit-set difference from the oracle must be a test that FP32 arithmetic within
+    the stated vertex bound can legitimately get wrong (triangle_margin <= 0)."""
+    got = run_chi2(lens, prm, grid, obs, "mixed", fb_mode=1, fb_tau=1e-6, hit_capacity=8192)
     assert got["status"] == 0
+    a = set(zip(got["hit_sys"].tolist(), got["hit_tid"].tolist()))
+    b = set(zip(want["hit_sys"].tolist(), want["hit_tid"].tolist()))
+    diff = sorted(a ^ b)
+    st = got["stats"]
+    print(f"literal mode {grid.nx}x{grid.ny}: flagged {st[1]} of {st[6]} tests ({st[1] / max(st[6], 1):.2e}), "
+          f"fallback hits {st[5]}, hits {st[0]} (oracle {len(b)}), hit-set mismatches {len(diff)}", flush=True)
+    if diff:
+        eb = sys_vertex_bound(prm, grid, want["bar_x"], want["bar_y"], obs["dls"])
+        for sys, tid in diff:
+            m = triangle_margin(prm, grid, sys, tid, want["bar_x"], want["bar_y"], obs["dls"], eb)
+            print(f"  mismatch system {sys} triangle {tid}: margin {m:.3e}", flush=True)
+            assert m <= 0.0, (sys, tid, m)
+    return got, diff
+
+
+def test_chi2_literal_threshold_mode(lens):
+    prm, grid, obs = load_inputs(2)
+    _literal_check(lens, prm, grid, obs, oracle.image_chi2(prm, grid, obs))
+
+
+@pytest.mark.slow
+def test_chi2_literal_threshold_mode_large(lens):
+    """The literal rule on the 4096^2 / 200-potential / 100-system workload, against
+    the complete oracle run."""
+    prm, grid, obs = load_inputs(3)
+    _literal_check(lens, prm, grid, obs, _oracle_large())
+
+
+# ----------------------------------------------------------------- exact ties and edge cases
+
+def _tie_obs():
+    """Single-image systems on a grid whose nodes are exact binary fractions
+    (x0 = -8, h = 1/8): the barycentre (= the observed image, identity lens) lies
+    exactly on a node, on a horizontal / vertical edge, on a cell's anti-diagonal
+    (its midpoint and a quarter point), or 1e-12 arcsec off an edge or the
+    anti-diagonal, on either side."""
+    h, x0 = 0.125, -8.0
+    pts = []
+    for (i, j) in [(40, 70), (64, 64), (100, 3)]:
+        X, Y = x0 + i * h, x0 + j * h
+        pts += [(X, Y),                                  # node
+                (X + 0.5 * h, Y), (X, Y + 0.5 * h),      # horizontal / vertical edge
+                (X + 0.5 * h, Y + 0.5 * h),              # anti-diagonal midpoint
+                (X + 0.25 * h, Y + 0.75 * h),            # anti-diagonal, quarter point
+                (X + 0.5 * h, Y + 1e-12), (X + 0.5 * h, Y - 1e-12),
+                (X + 1e-12, Y + 0.5 * h), (X - 1e-12, Y + 0.5 * h),
+                (X + 0.5 * h + 1e-12, Y + 0.5 * h), (X + 0.5 * h - 1e-12, Y + 0.5 * h)]
+    pts = np.array(pts)
+    n = len(pts)
+    return S.Grid(x0, x0, h, 129, 129), dict(sys_off=np.arange(n + 1, dtype=np.int32), x=pts[:, 0],
+                                             y=pts[:, 1], sigma=np.full(n, 0.1), dls=np.full(n, 0.8))
+
+
+def test_chi2_exact_ties_identity_lens(lens):
+    """Barycentres exactly on nodes, edges and anti-diagonals are in no triangle
+    (strict inequalities decided exactly), and 1e-12 arcsec off an edge they are
+    in exactly one; both precisions equal the oracle, and in the mixed path those
+    tests are the ones sent to the FP64 fallback."""
+    grid, obs = _tie_obs()
+    prm = np.zeros((7, 0))
+    want = oracle.image_chi2(prm, grid, obs)
+    n_off = len(obs["x"]) // 11 * 6
+    assert int((want["n_pred"] == 1).sum()) == n_off and int((want["n_pred"] == 0).sum()) == len(obs["x"]) - n_off
+    for prec in ("fp64", "mixed"):
+        got = run_chi2(lens, prm, grid, obs, prec)
+        st = got["stats"]
+        print(f"ties {prec}: hits {st[0]} flagged {st[1]} fallback hits {st[5]}", flush=True)
+        compare_chi2(got, want, 1e-9, 1e-9)
+        if prec == "mixed":
+            assert st[1] > 0 and st[5] == n_off  # every hit was decided in FP64
+
+
+@pytest.mark.parametrize("n_sys", [1023, 1024, 1025])
+def test_chi2_systems_at_the_tail_staging_limit(lens, n_sys):
+    """1024 systems is the largest count the tail stages in LDS: the last system's
+    offsets, n_pred and chi^2 against the oracle at, below and above it."""
+    g = np.random.default_rng(n_sys)
+    grid = S.Grid(-40.0, -40.0, 0.5, 161, 161)
+    n_img = 1024 if n_sys <= 1024 else 1030
+    sizes = np.ones(n_sys, np.int64)
+    sizes[g.choice(n_sys, n_img - n_sys, replace=False)] += 1
+    sys_off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
+    obs = dict(sys_off=sys_off, x=g.uniform(-35, 35, n_img), y=g.uniform(-35, 35, n_img),
+               sigma=np.full(n_img, 0.3), dls=g.uniform(0.5, 1.0, n_sys))
+    for prm in (np.zeros((7, 0)), S.sie_potentials(2, seed=n_sys, half_width=30.0)):
+        want = oracle.image_chi2(prm, grid, obs)
+        for prec in ("fp64", "mixed"):
+            got = run_chi2(lens, prm, grid, obs, prec, hit_capacity=8192)
+            print(f"  {n_sys} systems P={prm.shape[1]} {prec}: hits {got['stats'][0]}", flush=True)
+            compare_chi2(got, want, 1e-9 if prec == "fp64" else 1e-5, 1e-9 if prec == "fp64" else 1e-6)
+
+
+def _singular_case(where):
+    """A singular isothermal lens (the SIE of Algorithm 1: r_core = 0, r_cut = inf)
+    on a 257^2 grid over +-40" whose nodes are exact binary fractions, with its
+    centre on the node at the origin, a hair off it, or at an ordinary position;
+    a second, singular and cut galaxy-scale potential on another node."""
+    off = {"on": (0.0, 0.0), "1e-9 node": (1e-9 * 0.3125, -0.7e-9 * 0.3125), "ordinary": (0.1, -0.07)}[where]
+    prm = np.array([[off[0], 2.5], [off[1], -1.25], [0.2, 0.1], [0.5, 1.0], [0.0, 0.0], [np.inf, 20.0],
+                    [800.0, 150.0]])
+    grid = S.Grid(-40.0, -40.0, 0.3125, 257, 257)
+    g = np.random.default_rng(7)
+    xs = g.uniform(-20, 20, (7, 2))
+    obs = dict(sys_off=np.array([0, 2, 3, 5, 7], np.int32), x=xs[:, 0], y=xs[:, 1], sigma=np.full(7, 0.1),
+               dls=np.array([0.6, 0.7, 0.8, 0.9]))
+    return prm, grid, obs
+
+
+@pytest.mark.parametrize("where", ["on", "1e-9 node", "ordinary"])
+def test_chi2_singular_centre_on_a_node(lens, where):
+    """The FP32 bound stays finite for a singular centre on (or next to) a lattice
+    node; both paths against the oracle, the mixed path without a capacity status."""
+    prm, grid, obs = _singular_case(where)
+    want = oracle.image_chi2(prm, grid, obs)
+    for prec in ("fp64", "mixed"):
+        got = run_chi2(lens, prm, grid, obs, prec)
+        st = got["stats"]
+        print(f"singular centre {where} {prec}: status {got['status']} hits {st[0]} flagged {st[1]}", flush=True)
+        compare_chi2(got, want, 1e-9 if prec == "fp64" else 1e-5, 1e-9 if prec == "fp64" else 1e-6)
+        if prec == "mixed":
+            assert st[1] < 1000  # the bound admits few undecided tests
+
+
+def test_deflect_singular_centre_on_a_node_within_bound(lens):
+    """FP32 deflections of the same lenses within the stated bound, at every node
+    including the one at (or next to) the centre."""
+    for where in ("on", "1e-9 node", "ordinary"):
+        prm, grid, _ = _singular_case(where)
+        ax_o, ay_o = oracle.alpha_grid(prm, grid)
+        ax, ay = lens.lens_deflect(dev(prm), grid, "fp64")
+        np.testing.assert_allclose(ax.cpu().numpy(), ax_o, rtol=0, atol=1e-10)
+        np.testing.assert_allclose(ay.cpu().numpy(), ay_o, rtol=0, atol=1e-10)
+        ax, ay = lens.lens_deflect(dev(prm), grid, "fp32")
+        err = np.maximum(np.abs(ax.cpu().numpy() - ax_o), np.abs(ay.cpu().numpy() - ay_o))
+        bound = fp32_alpha_bound(prm, grid)
+        print(f"  {where}: fp32 |err| max {err.max():.3e} bound {bound:.3e}", flush=True)
+        assert err.max() <= bound
 
 
 def test_chi2_deterministic(lens):
