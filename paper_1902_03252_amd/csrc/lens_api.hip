@@ -188,8 +188,8 @@ int field_npl(const GridDesc& g)
 {
     const char* env = getenv("LENS_FIELD_NPL");
     if (env) {
-        const int v = atoi(env);
-        if (v == 1 || v == 2 || v == 4 || v == 8) return v;
+        const int v = (int)strtol(env, nullptr, 0);
+        if (field_code_ok(v)) return v;
     }
     const long long nodes = (long long)g.nx * g.ny;
     if (nodes >= (8ll << 20)) return 4;
@@ -449,7 +449,7 @@ int lens_deflect_mixed(lens_ctx* ctx, const lens_potentials* pot, const lens_gri
     ml.n_cluster = opts->n_cluster;
     ml.pc = opts->patch_cluster;
     ml.pg = opts->patch_galaxy;
-    ml.npl = std::min(field_npl(g), 4);
+    ml.npl = std::min(field_cols(field_npl(g)) * field_rows(field_npl(g)), 4);
     ml.t12 = opts->t12;
     ml.t34 = opts->t34;
     int slot;
@@ -510,141 +510,211 @@ int lens_source_positions(lens_ctx* ctx, const lens_potentials* pot, const lens_
     return LENS_OK;
 }
 
-int lens_image_chi2(lens_ctx* ctx, const lens_potentials* pot, const lens_grid* grid, const lens_obs* obs,
-                    const lens_chi2_opts* opts, lens_chi2_out* out, hipStream_t stream)
+}  // extern "C"
+
+namespace {
+
+// Launch shape and scratch layout of one chi^2 evaluation (lens_image_chi2 and
+// lens_image_chi2_noalloc share them).
+enum { CB_STATE, CB_TAB64, CB_TAB32, CB_BTERM, CB_SYS, CB_BX, CB_BY, CB_FIELD, CB_CONTRIB, CB_HITS, CB_POS, CB_FLAGS,
+       CB_PART, CB_RR, CB_PAIRS, CB_N };
+
+struct Chi2Plan {
+    GridDesc g;
+    ObsPtrs o;
+    int np;
+    bool mixed, fused;
+    int shape, npl, tiles_x, tx_shift, n_cull, tpw, n_parts;
+    long long region, flag_cap;
+    size_t nn, vbytes;
+    size_t bytes[CB_N];
+};
+
+struct Chi2Bufs {
+    void* p[CB_N];
+};
+
+int chi2_check(const lens_potentials* pot, const lens_grid* grid, const lens_obs* obs, const lens_chi2_opts* opts,
+               const lens_chi2_out* out)
 {
-    if (!ctx || check_pot(pot) || check_grid(grid) || check_obs(obs) || !opts || !out) return LENS_ERR_INVALID;
+    if (check_pot(pot) || check_grid(grid) || check_obs(obs) || !opts || !out) return LENS_ERR_INVALID;
     if (opts->prec != LENS_FP64 && opts->prec != LENS_MIXED) return LENS_ERR_INVALID;
     if (opts->hit_capacity < 1 || opts->hit_capacity > kHitScratch) return LENS_ERR_INVALID;
     if (opts->prec == LENS_MIXED && (opts->fb_mode < 0 || opts->fb_mode > 1)) return LENS_ERR_INVALID;
     if (opts->prec == LENS_MIXED && opts->fb_mode == 1 && !(opts->fb_tau >= 0.0 && is_fin(opts->fb_tau)))
         return LENS_ERR_INVALID;
-    if (!(opts->field_npl == 0 || opts->field_npl == 1 || opts->field_npl == 2 || opts->field_npl == 4 ||
-          opts->field_npl == 8) ||
-        opts->tile < 0 || opts->tile > 4)
+    if (!(opts->field_npl == 0 || field_code_ok(opts->field_npl)) || opts->tile < 0 || opts->tile > 4)
         return LENS_ERR_INVALID;
     if (!out->chi2 || !out->chi2_sys || !out->n_pred || !out->hits || !out->img_xy || !out->stats)
         return LENS_ERR_INVALID;
-    DeviceGuard dg(ctx->device);
-    if (!dg.ok) return LENS_ERR_DEVICE;
-    const GridDesc g = grid_desc(grid);
-    const ObsPtrs o = obs_ptrs(obs);
-    const int np = pot->n;
-    const bool mixed = opts->prec == LENS_MIXED;
-    const size_t nn = (size_t)g.nx * g.ny;
-    int rc;
-    int shape = opts->tile, npl = opts->field_npl;
-    resolve_tuned(ctx, opts->prec, 0, std::max(g.nx, g.ny), np, shape, npl);
-    if (!shape) shape = 1;
-    if (!npl) npl = field_npl(g);
-    int tile_x, tile_y, tiles_x;
-    tile_dims(shape, tile_x, tile_y);
-    const int tx_shift = tile_x == 64 ? 6 : 5;
-    const long long n_tiles = tri_tiles(g, shape, &tiles_x);
-    int n_cull, tpw;
-    cull_shape(g, shape, &n_cull, &tpw);
-    const int n_parts = n_cull + kPairBlocks;
+    return LENS_OK;
+}
+
+// Shape of the launches and bytes of every scratch buffer; flag_cap is the
+// capacity of the undecided-test list (mixed path).
+int chi2_plan(lens_ctx* ctx, const lens_potentials* pot, const lens_grid* grid, const lens_obs* obs,
+              const lens_chi2_opts* opts, long long flag_cap, Chi2Plan& pl)
+{
+    pl.g = grid_desc(grid);
+    pl.o = obs_ptrs(obs);
+    pl.np = pot->n;
+    pl.mixed = opts->prec == LENS_MIXED;
+    pl.nn = (size_t)pl.g.nx * pl.g.ny;
+    pl.shape = opts->tile;
+    pl.npl = opts->field_npl;
+    resolve_tuned(ctx, opts->prec, 0, std::max(pl.g.nx, pl.g.ny), pl.np, pl.shape, pl.npl);
+    if (!pl.shape) pl.shape = 1;
+    if (!pl.npl) pl.npl = field_npl(pl.g);
+    int tile_x, tile_y;
+    tile_dims(pl.shape, tile_x, tile_y);
+    pl.tx_shift = tile_x == 64 ? 6 : 5;
+    tri_tiles(pl.g, pl.shape, &pl.tiles_x);
+    cull_shape(pl.g, pl.shape, &pl.n_cull, &pl.tpw);
+    pl.n_parts = pl.n_cull + kPairBlocks;
     // each culling workgroup owns room for every pair of its tiles
-    const long long region = 4ll * tpw * o.n_sys;
-    if (region * n_cull > (1ll << 28)) return LENS_ERR_CAPACITY;  // 2 GiB of pair keys
-    (void)n_tiles;
-    const size_t vbytes = mixed ? 4 : 8;
-    if ((rc = ensure(ctx, B_FIELD, nn * 2 * vbytes)) || (rc = ensure(ctx, B_BX, (size_t)o.n_img * 8)) ||
-        (rc = ensure(ctx, B_BY, (size_t)o.n_img * 8)) || (rc = ensure(ctx, B_HITS, (size_t)kHitScratch * 2 * 8)) ||
-        (rc = ensure(ctx, B_POS, (size_t)kHitScratch * 4 * 8)) || (rc = ensure(ctx, B_CONTRIB, (size_t)o.n_img * 8)) ||
-        (rc = ensure(ctx, B_FLAGS, (size_t)(mixed ? kFlagScratch : 1) * 8)) ||
-        (rc = ensure(ctx, B_PART, (size_t)n_parts * 2 * 4)) ||
-        (rc = ensure(ctx, B_SYS, (size_t)o.n_sys * SYS_STRIDE * 8)) ||
-        (rc = ensure(ctx, B_RR, (size_t)g.ny * (tiles_x + 1) * kRR * vbytes)) ||
-        (rc = ensure(ctx, B_PAIRS, (size_t)region * n_cull * 8 + (size_t)n_cull * 4)))
-        return rc;
-    void* rr = ctx->buf[B_RR];
-    unsigned* part = (unsigned*)ctx->buf[B_PART];
-    unsigned long long* pairs = (unsigned long long*)ctx->buf[B_PAIRS];
-    unsigned* counts = (unsigned*)(pairs + (size_t)region * n_cull);
+    pl.region = 4ll * pl.tpw * pl.o.n_sys;
+    if (pl.region * pl.n_cull > (1ll << 28)) return LENS_ERR_CAPACITY;  // 2 GiB of pair keys
+    pl.vbytes = pl.mixed ? 4 : 8;
+    pl.flag_cap = pl.mixed ? flag_cap : 0;
     // the head's source-plane part runs inside the field launch when the grid allows
-    const bool fused = fused_head_fits(g, o, npl, mixed) != 0;
-    if (fused) {
-        if ((rc = head_buffers(ctx, np, o))) return rc;
-        if (launch_prep(pot_ptrs(pot), g, (double*)ctx->buf[B_TAB64], (float*)ctx->buf[B_TAB32],
-                        (double*)ctx->buf[B_BTERM], stream) != hipSuccess)
-            return LENS_ERR_DEVICE;
-    } else if ((rc = head(ctx, pot, g, o, (double*)ctx->buf[B_BX], (double*)ctx->buf[B_BY], stream))) {
-        return rc;
-    }
+    pl.fused = fused_head_fits(pl.g, pl.o, pl.npl, pl.mixed) != 0;
+    size_t* b = pl.bytes;
+    b[CB_STATE] = sizeof(EvalState);
+    b[CB_TAB64] = (size_t)pl.np * T64_STRIDE * 8;
+    b[CB_TAB32] = (size_t)pl.np * T32_STRIDE * 4;
+    b[CB_BTERM] = (size_t)pl.np * 3 * 8;
+    b[CB_SYS] = (size_t)(pl.o.n_sys > 0 ? pl.o.n_sys : 1) * SYS_STRIDE * 8;
+    b[CB_BX] = (size_t)pl.o.n_img * 8;
+    b[CB_BY] = (size_t)pl.o.n_img * 8;
+    b[CB_FIELD] = pl.nn * 2 * pl.vbytes;
+    b[CB_CONTRIB] = (size_t)pl.o.n_img * 8;
+    b[CB_HITS] = (size_t)kHitScratch * 2 * 8;
+    b[CB_POS] = (size_t)kHitScratch * 4 * 8;
+    b[CB_FLAGS] = (size_t)(pl.mixed ? pl.flag_cap : 1) * 8;
+    b[CB_PART] = (size_t)pl.n_parts * 2 * 4;
+    b[CB_RR] = (size_t)pl.g.ny * (pl.tiles_x + 1) * kRR * pl.vbytes;
+    b[CB_PAIRS] = (size_t)pl.region * pl.n_cull * 8 + (size_t)pl.n_cull * 4;
+    return LENS_OK;
+}
 
-    const double* tab64 = (const double*)ctx->buf[B_TAB64];
-    double* sysrow = (double*)ctx->buf[B_SYS];
-    EvalState* st = (EvalState*)ctx->buf[B_STATE];
-    unsigned long long* hits = (unsigned long long*)ctx->buf[B_HITS];
+// The launch sequence of one evaluation on the given scratch; ctx (may be
+// null) only for the field kernel's timing.
+int chi2_run(lens_ctx* ctx, const Chi2Plan& pl, const Chi2Bufs& b, const lens_potentials* pot,
+             const lens_chi2_opts* opts, lens_chi2_out* out, hipStream_t stream)
+{
+    const GridDesc& g = pl.g;
+    const ObsPtrs& o = pl.o;
+    const int np = pl.np;
+    const bool mixed = pl.mixed;
+    const size_t nn = pl.nn;
+    double* tab64 = (double*)b.p[CB_TAB64];
+    float* tab32 = (float*)b.p[CB_TAB32];
+    double* bterm = (double*)b.p[CB_BTERM];
+    double* sysrow = (double*)b.p[CB_SYS];
+    EvalState* st = (EvalState*)b.p[CB_STATE];
+    double* bx = (double*)b.p[CB_BX];
+    double* by = (double*)b.p[CB_BY];
+    void* rr = b.p[CB_RR];
+    unsigned* part = (unsigned*)b.p[CB_PART];
+    unsigned long long* pairs = (unsigned long long*)b.p[CB_PAIRS];
+    unsigned* counts = (unsigned*)(pairs + (size_t)pl.region * pl.n_cull);
+    unsigned long long* hits = (unsigned long long*)b.p[CB_HITS];
     unsigned long long* fb_hits = hits + kHitScratch;
-    double* pos = (double*)ctx->buf[B_POS];
+    double* pos = (double*)b.p[CB_POS];
     double* fb_pos = pos + 2 * kHitScratch;
-
-    int slot;
+    unsigned long long* flags = (unsigned long long*)b.p[CB_FLAGS];
+    if (pl.fused) {
+        if (launch_prep(pot_ptrs(pot), g, tab64, tab32, bterm, st, stream) != hipSuccess) return LENS_ERR_DEVICE;
+    } else if (launch_head(pot_ptrs(pot), g, o, tab64, tab32, bterm, bx, by, sysrow, st, stream) != hipSuccess) {
+        return LENS_ERR_DEVICE;
+    }
+    int rc, slot = -1;
     KernelEvents kev;
-    const KernelEvents* ev;
-    if ((rc = timing_begin(ctx, &kev, &ev, &slot))) return rc;
+    const KernelEvents* ev = nullptr;
+    if (ctx && (rc = timing_begin(ctx, &kev, &ev, &slot))) return rc;
     hipError_t e;
-    void* field = ctx->buf[B_FIELD];
+    void* field = b.p[CB_FIELD];
     const void* fx = field;
-    const void* fy = (const char*)field + nn * vbytes;
+    const void* fy = (const char*)field + nn * pl.vbytes;
     HeadArgs ha;
     ha.pot = pot_ptrs(pot);
     ha.g = g;
     ha.obs = o;
     ha.tab64 = tab64;
-    ha.bterm = (const double*)ctx->buf[B_BTERM];
-    ha.bx = (double*)ctx->buf[B_BX];
-    ha.by = (double*)ctx->buf[B_BY];
+    ha.bterm = bterm;
+    ha.bx = bx;
+    ha.by = by;
     ha.sysrow = sysrow;
     ha.st = st;
-    if (mixed && fused)
-        e = launch_field32h((const float*)ctx->buf[B_TAB32], np, g, (float*)field, (float*)field + nn, npl,
-                            (float*)rr, tx_shift, tiles_x, ha, ev, stream);
+    if (mixed && pl.fused)
+        e = launch_field32h(tab32, np, g, (float*)field, (float*)field + nn, pl.npl, (float*)rr, pl.tx_shift,
+                            pl.tiles_x, ha, ev, stream);
     else if (mixed)
-        e = launch_field32((const float*)ctx->buf[B_TAB32], np, g, (float*)field, (float*)field + nn, nullptr, npl,
-                           (float*)rr, tx_shift, tiles_x, ev, stream);
-    else if (fused)
-        e = launch_field64h(tab64, np, g, (double*)field, (double*)field + nn, (double*)rr, tx_shift, tiles_x, ha,
-                            ev, stream);
+        e = launch_field32(tab32, np, g, (float*)field, (float*)field + nn, nullptr, pl.npl, (float*)rr, pl.tx_shift,
+                           pl.tiles_x, ev, stream);
+    else if (pl.fused)
+        e = launch_field64h(tab64, np, g, (double*)field, (double*)field + nn, (double*)rr, pl.tx_shift, pl.tiles_x,
+                            ha, ev, stream);
     else
-        e = launch_field64(tab64, np, g, (double*)field, (double*)field + nn, nullptr, (double*)rr, tx_shift,
-                           tiles_x, ev, stream);
+        e = launch_field64(tab64, np, g, (double*)field, (double*)field + nn, nullptr, (double*)rr, pl.tx_shift,
+                           pl.tiles_x, ev, stream);
     if (e != hipSuccess) return LENS_ERR_DEVICE;
-    timing_end(ctx, slot);
+    if (ctx) timing_end(ctx, slot);
 
-    unsigned long long* flags = (unsigned long long*)ctx->buf[B_FLAGS];
-    const long long flag_cap = mixed ? kFlagScratch : 0;
     const float tau = (float)(opts->fb_tau * g.h * g.h);
-    e = launch_cull(mixed, rr, g, o.n_sys, sysrow, pairs, region, counts, part, shape, stream);
+    e = launch_cull(mixed, rr, g, o.n_sys, sysrow, pairs, pl.region, counts, part, pl.shape, stream);
     if (e == hipSuccess)
-        e = launch_pairs(mixed, fx, fy, g, sysrow, st, opts->fb_mode, tau, pairs, region, counts, n_cull, hits,
-                         kHitScratch, flags, flag_cap, part, n_cull, shape, stream);
+        e = launch_pairs(mixed, fx, fy, g, sysrow, st, opts->fb_mode, tau, pairs, pl.region, counts, pl.n_cull, hits,
+                         kHitScratch, flags, pl.flag_cap, part, pl.n_cull, pl.shape, stream);
     if (e == hipSuccess)
-        e = launch_fbpos(tab64, np, g, sysrow, st, hits, kHitScratch, flags, flag_cap, fb_hits, kHitScratch, pos,
+        e = launch_fbpos(tab64, np, g, sysrow, st, hits, kHitScratch, flags, pl.flag_cap, fb_hits, kHitScratch, pos,
                          fb_pos, stream);
     if (e != hipSuccess) return LENS_ERR_DEVICE;
     TailLaunch tl;
     tl.obs = o;
     tl.hit_cap = kHitScratch;
-    tl.flag_cap = flag_cap;
+    tl.flag_cap = pl.flag_cap;
     tl.fb_cap = kHitScratch;
     tl.hit_capacity = opts->hit_capacity;
     tl.hit_keys = hits;
     tl.out_hits = out->hits;
     tl.img_xy = out->img_xy;
     tl.n_pred = out->n_pred;
-    tl.contrib = (double*)ctx->buf[B_CONTRIB];
+    tl.contrib = (double*)b.p[CB_CONTRIB];
     tl.chi2 = out->chi2;
     tl.chi2_sys = out->chi2_sys;
     tl.match = out->match;
     tl.stats = (long long*)out->stats;
     tl.n_tests = 2ll * (g.nx - 1) * (g.ny - 1) * o.n_sys;
     tl.part = part;
-    tl.n_parts = n_parts;
+    tl.n_parts = pl.n_parts;
     e = launch_tail(tl, st, fb_hits, pos, fb_pos, stream);
     return e == hipSuccess ? LENS_OK : LENS_ERR_DEVICE;
+}
+
+const int kCtxBuf[CB_N] = {B_STATE, B_TAB64, B_TAB32, B_BTERM, B_SYS, B_BX, B_BY, B_FIELD, B_CONTRIB, B_HITS,
+                           B_POS, B_FLAGS, B_PART, B_RR, B_PAIRS};
+
+}  // namespace
+
+extern "C" {
+
+int lens_image_chi2(lens_ctx* ctx, const lens_potentials* pot, const lens_grid* grid, const lens_obs* obs,
+                    const lens_chi2_opts* opts, lens_chi2_out* out, hipStream_t stream)
+{
+    if (!ctx) return LENS_ERR_INVALID;
+    int rc = chi2_check(pot, grid, obs, opts, out);
+    if (rc) return rc;
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return LENS_ERR_DEVICE;
+    Chi2Plan pl;
+    if ((rc = chi2_plan(ctx, pot, grid, obs, opts, kFlagScratch, pl))) return rc;
+    Chi2Bufs b;
+    for (int k = 0; k < CB_N; k++) {
+        if ((rc = ensure(ctx, kCtxBuf[k], pl.bytes[k]))) return rc;
+        b.p[k] = ctx->buf[kCtxBuf[k]];
+    }
+    return chi2_run(ctx, pl, b, pot, opts, out, stream);
 }
 
 }  // extern "C"

@@ -88,8 +88,19 @@ struct HeadArgs {
 };
 
 hipError_t launch_prep(const PotPtrs& pot, const GridDesc& g, double* tab64, float* tab32, double* bterm,
-                       hipStream_t s);
+                       EvalState* st, hipStream_t s);
 int fused_head_fits(const GridDesc& g, const ObsPtrs& obs, int npl, bool fp32);
+// FP32 field layout code (lens_chi2_opts.field_npl): C = 1, 2, 4 or 8
+// consecutive nodes of one row per thread, or 16 R + C for C consecutive nodes
+// in each of R consecutive rows (0x21, 0x22, 0x24, 0x41, 0x42).
+inline int field_cols(int code) { return code & 15; }
+inline int field_rows(int code) { return (code >> 4) ? (code >> 4) : 1; }
+inline bool field_code_ok(int code)
+{
+    return code == 1 || code == 2 || code == 4 || code == 8 || code == 0x21 || code == 0x22 || code == 0x24 ||
+           code == 0x41 || code == 0x42;
+}
+
 hipError_t launch_field32h(const float* tab32, int np, const GridDesc& g, float* ax, float* ay, int npl, float* rr,
                            int tx_shift, int tiles_x, const HeadArgs& h, const KernelEvents* ev, hipStream_t s);
 hipError_t launch_field64h(const double* tab64, int np, const GridDesc& g, double* ax, double* ay, double* rr,

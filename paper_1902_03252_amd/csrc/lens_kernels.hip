@@ -21,6 +21,8 @@
 // 65535 rows of workgroups.
 #include "lens_path.hpp"
 
+#include <type_traits>
+
 namespace lens {
 
 // Head of every evaluation, one wave per observed image (at least enough
@@ -212,57 +214,67 @@ __global__ __launch_bounds__(256) void k_head(PotPtrs pot, GridDesc g, ObsPtrs o
 }
 
 // Constants of every potential only (the fused field kernels do the rest of
-// the head).
+// the head); also clears the head's ticket for the field launch that follows
+// (it is left at zero by every completed launch, and cleared here whatever
+// the scratch held before).
 __global__ __launch_bounds__(256) void k_prep(PotPtrs pot, GridDesc g, double* __restrict__ tab64,
-                                              float* __restrict__ tab32, double* __restrict__ bterm)
+                                              float* __restrict__ tab32, double* __restrict__ bterm,
+                                              EvalState* __restrict__ st)
 {
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->head_ticket = 0;
     for (int p = blockIdx.x * 256 + threadIdx.x; p < pot.n; p += gridDim.x * 256)
         prep_one(pot, g, p, p, tab64, tab32, bterm);
 }
 
 // ============================================================== deflection field
 
-// Each thread owns NPL consecutive nodes of one grid row; a workgroup of 256
-// threads covers 256*NPL nodes of that row, so the row offset is uniform and
-// every per-potential constant is a wave-uniform (scalar) operand.  With rr
-// set, the kernel also writes the triangle stage's per-(row, tile column)
-// deflection ranges (tile width 1 << tx_shift cells).
-template <int NPL>
-__device__ __forceinline__ void field32_row(const float* __restrict__ tab32, int np, int nx, int j, int bx,
-                                            float* __restrict__ ax, float* __restrict__ ay,
-                                            const EvalState* __restrict__ st, float* __restrict__ rr,
-                                            int tx_shift, int tiles_x)
+// Each thread owns NPL consecutive nodes in each of NR consecutive grid rows
+// (rows j0 .. j0 + NR - 1); a workgroup of 256 threads covers 256*NPL columns
+// of those rows, so the row offsets are uniform and every per-potential
+// constant is a wave-uniform (scalar) operand.  With rr set, the kernel also
+// writes the triangle stage's per-(row, tile column) deflection ranges (tile
+// width 1 << tx_shift cells).
+template <int NPL, int NR>
+__device__ __forceinline__ void field32_block(const float* __restrict__ tab32, int np, int nx, int ny, int j0, int bx,
+                                              float* __restrict__ ax, float* __restrict__ ay,
+                                              const EvalState* __restrict__ st, float* __restrict__ rr,
+                                              int tx_shift, int tiles_x)
 {
     const int i0 = (bx * 256 + threadIdx.x) * NPL;
     if (bx * 256 * NPL >= nx) return;  // whole workgroup beyond the row
-    const float fj = (float)j;
-    float fi[NPL], sx[NPL], sy[NPL];
+    float fi[NPL], sx[NR * NPL], sy[NR * NPL];
 #pragma unroll
-    for (int k = 0; k < NPL; k++) {
-        fi[k] = (float)(i0 + k);
-        sx[k] = 0.0f;
-        sy[k] = 0.0f;
+    for (int k = 0; k < NPL; k++) fi[k] = (float)(i0 + k);
+#pragma unroll
+    for (int q = 0; q < NR * NPL; q++) {
+        sx[q] = 0.0f;
+        sy[q] = 0.0f;
     }
-    field32_all_wg<NPL>(tab32, np, fj, fi, sx, sy);
-    if (rr) tile_partials<float, NPL>(sx, sy, i0, j, nx, tx_shift, tiles_x, rr);
+    field32_all_wg<NPL, NR>(tab32, np, (float)j0, fi, sx, sy);
     const bool bad = st != nullptr && st->status != kStatusOk;
-    const size_t row = (size_t)j * nx;
 #pragma unroll
-    for (int k = 0; k < NPL; k++) {
-        if (i0 + k < nx) {
-            ax[row + i0 + k] = bad ? __builtin_nanf("") : sx[k];
-            ay[row + i0 + k] = bad ? __builtin_nanf("") : sy[k];
+    for (int r = 0; r < NR; r++) {
+        const int j = j0 + r;
+        if (j >= ny) break;  // uniform over the workgroup
+        if (rr) tile_partials<float, NPL>(sx + r * NPL, sy + r * NPL, i0, j, nx, tx_shift, tiles_x, rr);
+        const size_t row = (size_t)j * nx;
+#pragma unroll
+        for (int k = 0; k < NPL; k++) {
+            if (i0 + k < nx) {
+                ax[row + i0 + k] = bad ? __builtin_nanf("") : sx[r * NPL + k];
+                ay[row + i0 + k] = bad ? __builtin_nanf("") : sy[r * NPL + k];
+            }
         }
     }
 }
 
-template <int NPL>
-__global__ __launch_bounds__(256) void k_field32(const float* __restrict__ tab32, int np, int nx,
+template <int NPL, int NR>
+__global__ __launch_bounds__(256) void k_field32(const float* __restrict__ tab32, int np, int nx, int ny,
                                                  float* __restrict__ ax, float* __restrict__ ay,
                                                  const EvalState* __restrict__ st, float* __restrict__ rr,
                                                  int tx_shift, int tiles_x)
 {
-    field32_row<NPL>(tab32, np, nx, blockIdx.y, blockIdx.x, ax, ay, st, rr, tx_shift, tiles_x);
+    field32_block<NPL, NR>(tab32, np, nx, ny, blockIdx.y * NR, blockIdx.x, ax, ay, st, rr, tx_shift, tiles_x);
 }
 
 constexpr int kNpl64 = 2;  // FP64 field nodes per thread
@@ -323,8 +335,8 @@ __device__ __forceinline__ void fused_head(const HeadArgs& h, int head_rows)
     head_finish(h.pot.n, h.g, h.obs, h.bterm, h.bx, h.by, h.sysrow, h.st);
 }
 
-template <int NPL>
-__global__ __launch_bounds__(256) void k_field32h(const float* __restrict__ tab32, int np, int nx,
+template <int NPL, int NR>
+__global__ __launch_bounds__(256) void k_field32h(const float* __restrict__ tab32, int np, int nx, int ny,
                                                   float* __restrict__ ax, float* __restrict__ ay,
                                                   float* __restrict__ rr, int tx_shift, int tiles_x, HeadArgs h,
                                                   int head_rows)
@@ -333,7 +345,8 @@ __global__ __launch_bounds__(256) void k_field32h(const float* __restrict__ tab3
         fused_head(h, head_rows);
         return;
     }
-    field32_row<NPL>(tab32, np, nx, blockIdx.y - head_rows, blockIdx.x, ax, ay, nullptr, rr, tx_shift, tiles_x);
+    field32_block<NPL, NR>(tab32, np, nx, ny, (blockIdx.y - head_rows) * NR, blockIdx.x, ax, ay, nullptr, rr,
+                           tx_shift, tiles_x);
 }
 
 __global__ __launch_bounds__(256) void k_field64h(const double* __restrict__ tab64, int np, GridDesc g,
@@ -914,23 +927,41 @@ hipError_t launch_head(const PotPtrs& pot, const GridDesc& g, const ObsPtrs& obs
     return hipGetLastError();
 }
 
+// Calls f(integral_constant<NPL>, integral_constant<NR>) for an FP32 field
+// layout code (field_cols / field_rows); unknown codes take 2 x 1.
+template <class F>
+static hipError_t with_field_shape(int code, F f)
+{
+    using std::integral_constant;
+    switch (code) {
+    case 0x01: return f(integral_constant<int, 1>(), integral_constant<int, 1>());
+    case 0x04: return f(integral_constant<int, 4>(), integral_constant<int, 1>());
+    case 0x08: return f(integral_constant<int, 8>(), integral_constant<int, 1>());
+    case 0x21: return f(integral_constant<int, 1>(), integral_constant<int, 2>());
+    case 0x22: return f(integral_constant<int, 2>(), integral_constant<int, 2>());
+    case 0x24: return f(integral_constant<int, 4>(), integral_constant<int, 2>());
+    case 0x41: return f(integral_constant<int, 1>(), integral_constant<int, 4>());
+    case 0x42: return f(integral_constant<int, 2>(), integral_constant<int, 4>());
+    default: return f(integral_constant<int, 2>(), integral_constant<int, 1>());
+    }
+}
+
 hipError_t launch_field32(const float* tab32, int np, const GridDesc& g, float* ax, float* ay,
                           const EvalState* st, int npl, float* rr, int tx_shift, int tiles_x,
                           const KernelEvents* ev, hipStream_t s)
 {
-    switch (npl) {
-    case 1: return launch_ev(ev, k_field32<1>, dim3(cdiv(g.nx, 256), g.ny), dim3(256), s, tab32, np, g.nx, ax, ay, st, rr, tx_shift, tiles_x);
-    case 2: return launch_ev(ev, k_field32<2>, dim3(cdiv(g.nx, 512), g.ny), dim3(256), s, tab32, np, g.nx, ax, ay, st, rr, tx_shift, tiles_x);
-    case 4: return launch_ev(ev, k_field32<4>, dim3(cdiv(g.nx, 1024), g.ny), dim3(256), s, tab32, np, g.nx, ax, ay, st, rr, tx_shift, tiles_x);
-    default: return launch_ev(ev, k_field32<8>, dim3(cdiv(g.nx, 2048), g.ny), dim3(256), s, tab32, np, g.nx, ax, ay, st, rr, tx_shift, tiles_x);
-    }
+    return with_field_shape(npl, [&](auto c, auto r) {
+        constexpr int C = decltype(c)::value, R = decltype(r)::value;
+        const dim3 grid(cdiv(g.nx, 256 * C), cdiv(g.ny, R));
+        return launch_ev(ev, k_field32<C, R>, grid, dim3(256), s, tab32, np, g.nx, g.ny, ax, ay, st, rr, tx_shift,
+                         tiles_x);
+    });
 }
 
 hipError_t launch_prep(const PotPtrs& pot, const GridDesc& g, double* tab64, float* tab32, double* bterm,
-                       hipStream_t s)
+                       EvalState* st, hipStream_t s)
 {
-    if (pot.n == 0) return hipSuccess;
-    k_prep<<<clampu(cdiv(pot.n, 256), 1, 1024), 256, 0, s>>>(pot, g, tab64, tab32, bterm);
+    k_prep<<<clampu(cdiv(pot.n, 256), 1, 1024), 256, 0, s>>>(pot, g, tab64, tab32, bterm, st);
     return hipGetLastError();
 }
 
@@ -944,22 +975,22 @@ static int head_rows_for(const ObsPtrs& obs, int bx)
 
 int fused_head_fits(const GridDesc& g, const ObsPtrs& obs, int npl, bool fp32)
 {
-    const int bx = (int)cdiv(g.nx, fp32 ? 256 * npl : 256 * kNpl64);
-    return g.ny + head_rows_for(obs, bx) <= 65535;
+    const int bx = (int)cdiv(g.nx, fp32 ? 256 * field_cols(npl) : 256 * kNpl64);
+    const long long rows = fp32 ? cdiv(g.ny, field_rows(npl)) : g.ny;
+    return rows + head_rows_for(obs, bx) <= 65535;
 }
 
 hipError_t launch_field32h(const float* tab32, int np, const GridDesc& g, float* ax, float* ay, int npl, float* rr,
                            int tx_shift, int tiles_x, const HeadArgs& h, const KernelEvents* ev, hipStream_t s)
 {
-    const int bx = (int)cdiv(g.nx, 256 * npl);
-    const int hr = head_rows_for(h.obs, bx);
-    const dim3 grid((unsigned)bx, (unsigned)(g.ny + hr));
-    switch (npl) {
-    case 1: return launch_ev(ev, k_field32h<1>, grid, dim3(256), s, tab32, np, g.nx, ax, ay, rr, tx_shift, tiles_x, h, hr);
-    case 2: return launch_ev(ev, k_field32h<2>, grid, dim3(256), s, tab32, np, g.nx, ax, ay, rr, tx_shift, tiles_x, h, hr);
-    case 4: return launch_ev(ev, k_field32h<4>, grid, dim3(256), s, tab32, np, g.nx, ax, ay, rr, tx_shift, tiles_x, h, hr);
-    default: return launch_ev(ev, k_field32h<8>, grid, dim3(256), s, tab32, np, g.nx, ax, ay, rr, tx_shift, tiles_x, h, hr);
-    }
+    return with_field_shape(npl, [&](auto c, auto r) {
+        constexpr int C = decltype(c)::value, R = decltype(r)::value;
+        const int bx = (int)cdiv(g.nx, 256 * C);
+        const int hr = head_rows_for(h.obs, bx);
+        const dim3 grid((unsigned)bx, (unsigned)(cdiv(g.ny, R) + hr));
+        return launch_ev(ev, k_field32h<C, R>, grid, dim3(256), s, tab32, np, g.nx, g.ny, ax, ay, rr, tx_shift,
+                         tiles_x, h, hr);
+    });
 }
 
 hipError_t launch_field64h(const double* tab64, int np, const GridDesc& g, double* ax, double* ay, double* rr,

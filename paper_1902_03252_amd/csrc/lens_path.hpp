@@ -192,67 +192,91 @@ __device__ __forceinline__ int system_of(const int* __restrict__ sys_off, int ns
 // s / K (one fused multiply-add; 1/K and s/K are stored): one instruction
 // fewer than scaling by K after the division, and the error of K b - A_ is
 // that of B_ - A_ plus about 1 ulp of B_, which the bound's per-potential
-// budget covers.  This is the node part, given the row part rc = (n_y,
-// B n_y, C n_y, s / K) of the same potential (see pots_wg).
-template <int NPL>
-__device__ __forceinline__ void field32_pot(const float* __restrict__ c, float4 rc, const float* fi, float* sx,
-                                            float* sy)
+// budget covers.  This is the node part for NPL consecutive nodes in each of
+// NR consecutive rows (sx, sy: [NR][NPL]), given the row parts rc[r] = (n_y,
+// B n_y, C n_y, s / K) of the same potential for those rows (see
+// pots_wg_rows): the column offset n_x = (i - c_hi) - c_lo, two instructions,
+// is formed once per column and shared by the NR rows.  Every node's
+// arithmetic is the same whatever NPL and NR.
+template <int NPL, int NR = 1>
+__device__ __forceinline__ void field32_pot(const float* __restrict__ c, const float4* rc, const float* fi,
+                                            float* sx, float* sy)
 {
     const float cxh = c[T32_CXH], cxl = c[T32_CXL];
     const float A = c[T32_A], B = c[T32_B];
     const float a2 = c[T32_A2], s2a2 = c[T32_S2A2], ra = c[T32_RA], K = c[T32_K], kinv = c[T32_KINV];
-    const float nyv = rc.x, bny = rc.y, cny = rc.z, rsk = rc.w;
+    const float rsk = rc[0].w;
 #pragma unroll
     for (int k = 0; k < NPL; k++) {
         const float nxv = (fi[k] - cxh) - cxl;
-        const float m1 = fmaf(A, nxv, bny);
-        const float m2 = fmaf(B, nxv, cny);
-        const float qa2 = fmaf(nxv, m1, fmaf(nyv, m2, a2));  // a^2 + R^2
-        const float qa = __builtin_amdgcn_sqrtf(fabsf(qa2)) + ra;  // |.|: a source modifier
-        const float qsk = fmaf(__builtin_amdgcn_sqrtf(qa2 + s2a2), kinv, rsk);  // B_ / K
-        const float kf = fmaf(qsk, K, -qa) * __builtin_amdgcn_rcpf(qa * qsk);
-        sx[k] = fmaf(kf, m1, sx[k]);
-        sy[k] = fmaf(kf, m2, sy[k]);
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            const float nyv = rc[r].x, bny = rc[r].y, cny = rc[r].z;
+            const float m1 = fmaf(A, nxv, bny);
+            const float m2 = fmaf(B, nxv, cny);
+            const float qa2 = fmaf(nxv, m1, fmaf(nyv, m2, a2));  // a^2 + R^2
+            const float qa = __builtin_amdgcn_sqrtf(fabsf(qa2)) + ra;  // |.|: a source modifier
+            const float qsk = fmaf(__builtin_amdgcn_sqrtf(qa2 + s2a2), kinv, rsk);  // B_ / K
+            const float kf = fmaf(qsk, K, -qa) * __builtin_amdgcn_rcpf(qa * qsk);
+            sx[r * NPL + k] = fmaf(kf, m1, sx[r * NPL + k]);
+            sy[r * NPL + k] = fmaf(kf, m2, sy[r * NPL + k]);
+        }
     }
 }
 
 // Runs f(c, rc) for every row c of an FP32 table of np rows (STRIDE floats
-// each), in order, with rc = (n_y, B n_y, C n_y, c[IW]), n_y = (j - c[IYH]) -
-// c[IYL]: the row part of a potential, common to every node of grid row j,
-// and one more constant of the potential (IW < 0: 0) that the caller wants
-// in a vector register.  For a workgroup of 256 threads on one row (all
-// threads call it, with the same fj): the row parts of up to 256 potentials
-// at a time are computed once, one potential per thread, into LDS, so that
-// the per-potential work of every wave is the node part only (the row part is
-// uniform over the workgroup but, with no scalar FP32 ALU, costs a full
-// vector instruction per wave).
-template <int STRIDE, int IYH, int IYL, int IB, int IC, int IW, class F>
-__device__ __forceinline__ void pots_wg(const float* __restrict__ tab, int np, float fj, F&& f)
+// each), in order, with rc[r] = (n_y, B n_y, C n_y, c[IW]), n_y = (j - c[IYH])
+// - c[IYL], for the NR grid rows j = fj, fj + 1, ...: the row part of a
+// potential, common to every node of grid row j, and one more constant of the
+// potential (IW < 0: 0) that the caller wants in a vector register.  For a
+// workgroup of 256 threads on those rows (all threads call it, with the same
+// fj): the row parts of up to 256 potentials at a time are computed once, one
+// potential per thread, into LDS, so that the per-potential work of every
+// wave is the node part only (the row part is uniform over the workgroup but,
+// with no scalar FP32 ALU, costs a full vector instruction per wave).
+template <int STRIDE, int IYH, int IYL, int IB, int IC, int IW, int NR, class F>
+__device__ __forceinline__ void pots_wg_rows(const float* __restrict__ tab, int np, float fj, F&& f)
 {
-    __shared__ float4 srow[256];
+    __shared__ float4 srow[NR][256];
     for (int p0 = 0; p0 < np; p0 += 256) {
         const int pc = np - p0 < 256 ? np - p0 : 256;
         if (p0 > 0) __syncthreads();  // the previous chunk has been read
         if ((int)threadIdx.x < pc) {
             const float* c = tab + (size_t)(p0 + threadIdx.x) * STRIDE;
-            const float nyv = (fj - c[IYH]) - c[IYL];
-            srow[threadIdx.x] = make_float4(nyv, c[IB] * nyv, c[IC] * nyv, IW >= 0 ? c[IW >= 0 ? IW : 0] : 0.0f);
+            const float w = IW >= 0 ? c[IW >= 0 ? IW : 0] : 0.0f;
+#pragma unroll
+            for (int r = 0; r < NR; r++) {
+                const float nyv = ((fj + (float)r) - c[IYH]) - c[IYL];
+                srow[r][threadIdx.x] = make_float4(nyv, c[IB] * nyv, c[IC] * nyv, w);
+            }
         }
         __syncthreads();
-        for (int p = 0; p < pc; p++) f(tab + (size_t)(p0 + p) * STRIDE, srow[p]);
+        for (int p = 0; p < pc; p++) {
+            float4 rc[NR];
+#pragma unroll
+            for (int r = 0; r < NR; r++) rc[r] = srow[r][p];
+            f(tab + (size_t)(p0 + p) * STRIDE, rc);
+        }
     }
 }
 
-// Deflection of NPL nodes of one row by every potential of the FP32 table,
-// for a workgroup of 256 threads on that row (pots_wg; s / K rides along with
-// the row part, as field32_pot's fused multiply-add can take only one scalar
-// operand).
-template <int NPL>
+// One grid row (pots_wg_rows with NR = 1), f(c, rc) with the row part itself.
+template <int STRIDE, int IYH, int IYL, int IB, int IC, int IW, class F>
+__device__ __forceinline__ void pots_wg(const float* __restrict__ tab, int np, float fj, F&& f)
+{
+    pots_wg_rows<STRIDE, IYH, IYL, IB, IC, IW, 1>(tab, np, fj, [&](const float* c, const float4* rc) { f(c, rc[0]); });
+}
+
+// Deflection of NPL nodes in each of NR rows (fj, fj + 1, ...) by every
+// potential of the FP32 table, for a workgroup of 256 threads on those rows
+// (pots_wg_rows; s / K rides along with the row part, as field32_pot's fused
+// multiply-add can take only one scalar operand).  sx, sy: [NR][NPL].
+template <int NPL, int NR = 1>
 __device__ __forceinline__ void field32_all_wg(const float* __restrict__ tab, int np, float fj, const float* fi,
                                                float* sx, float* sy)
 {
-    pots_wg<T32_STRIDE, T32_CYH, T32_CYL, T32_B, T32_C, T32_RSK>(
-        tab, np, fj, [&](const float* c, float4 rc) { field32_pot<NPL>(c, rc, fi, sx, sy); });
+    pots_wg_rows<T32_STRIDE, T32_CYH, T32_CYL, T32_B, T32_C, T32_RSK, NR>(
+        tab, np, fj, [&](const float* c, const float4* rc) { field32_pot<NPL, NR>(c, rc, fi, sx, sy); });
 }
 
 // Range partials of the triangle stage, written by the field kernel: for grid

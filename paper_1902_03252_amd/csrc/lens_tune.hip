@@ -4,6 +4,7 @@
 // the table as JSON.  Host code only.  No C++ exception crosses the extern "C"
 // functions.
 #include "lens_tune.hpp"
+#include "lens_internal.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -64,7 +65,7 @@ static void record(TuneTable* t, const TuneEntry& v)
 
 static bool valid_entry(const TuneEntry& e)
 {
-    const bool npl_ok = e.npl == 0 || e.npl == 1 || e.npl == 2 || e.npl == 4 || (e.npl == 8 && !e.batched);
+    const bool npl_ok = e.npl == 0 || (e.batched ? (e.npl == 1 || e.npl == 2 || e.npl == 4) : field_code_ok(e.npl));
     return (e.prec == LENS_FP64 || e.prec == LENS_MIXED) && (e.batched == 0 || e.batched == 1) && e.n_log2 >= 0 &&
            e.n_log2 <= 62 && e.p_log2 >= 0 && e.p_log2 <= 62 && e.tile >= 1 && e.tile <= 4 && npl_ok;
 }
@@ -364,9 +365,9 @@ int tune(lens_ctx* ctx, int prec, int batched, int n_log2, int p_log2, int defau
         }
     };
     trial(best_tile, best_npl);
-    if (mixed) {
-        const int npls[4] = {1, 2, 4, 8};
-        for (int k = 0; k < (batched ? 3 : 4); k++)
+    if (mixed) {  // FP32 field layouts: nodes of one row, then blocks of rows x columns
+        const int npls[9] = {1, 2, 4, 8, 0x21, 0x22, 0x24, 0x41, 0x42};
+        for (int k = 0; k < (batched ? 3 : 9); k++)
             if (npls[k] != default_npl) trial(1, npls[k]);
     }
     const int npl = best_npl;

@@ -15,18 +15,18 @@ import bench  # noqa: E402
 def _summary(path, sha, npl, nbytes):
     with open(path, "w") as f:
         f.write("# header line: with a colon that must be ignored\n")
-        f.write(f"hbm_bytes_per_launch: {nbytes}\nkernel_source_sha256_16: {sha}\nfield_npl: {npl}\n")
+        f.write(f"hbm_bytes_per_launch: {nbytes}\nkernel_source_sha256_16: {sha}\nfield_npl: {hex(npl)}\n")
 
 
-def test_traffic_figure_requires_matching_sources_and_npl(tmp_path, monkeypatch):
+def test_traffic_figure_requires_matching_sources_and_field_layout(tmp_path, monkeypatch):
     path = str(tmp_path / "traffic.txt")
     monkeypatch.setattr(bench, "TRAFFIC_FILE", path)
-    assert bench.traffic_per_launch(2) is None  # no summary
-    _summary(path, bench.kernel_hash(), 2, 9624655)
-    assert bench.traffic_per_launch(2) == 9624655.0
-    assert bench.traffic_per_launch(4) is None  # another launch shape
-    _summary(path, "0" * 16, 2, 9624655)
-    assert bench.traffic_per_launch(2) is None  # taken on other sources
+    assert bench.traffic_per_launch(0x42) is None  # no summary
+    _summary(path, bench.kernel_hash(), 0x42, 137000000)
+    assert bench.traffic_per_launch(0x42) == 137000000.0
+    assert bench.traffic_per_launch(0x22) is None  # another field layout
+    _summary(path, "0" * 16, 0x42, 137000000)
+    assert bench.traffic_per_launch(0x42) is None  # taken on other sources
 
 
 def test_kernel_hash_is_stable_and_short():
