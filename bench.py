@@ -48,7 +48,7 @@ FLOPS_PER_VJP = 78         # flops of one cored/cut (node, potential) term of th
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_field32_large.txt")
 # FP32 field layout (lens_chi2_opts.field_npl) and triangle tile shape of the timed calls: the
 # library's defaults for each grid size, passed explicitly so that the profiled variant is the timed one
-HEADLINE_FIELD = 0x42     # 2 columns x 4 rows of nodes per thread
+HEADLINE_FIELD = 0x41     # 1 column x 4 rows of nodes per thread
 HEADLINE_TILE = 1         # 32 x 8 cells
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1902_03252_amd", "csrc", f)
                   for f in ("lens_kernels.hip", "lens_path.hpp", "lens_device.hpp")]
@@ -551,7 +551,7 @@ def main():
                    "grid": f"{grid.nx}x{grid.ny}", "potentials": int(prm.shape[1]), "systems": len(obs_np["dls"]),
                    "precision": "mixed (FP32 bulk, FP64 fallback/positions/chi2)",
                    "mode": "HIP graph replay of one evaluation",
-                   "field_layout": f"{HEADLINE_FIELD:#x} (2 columns x 4 rows of nodes per thread)",
+                   "field_layout": f"{HEADLINE_FIELD:#x} (1 column x 4 rows of nodes per thread)",
                    "tile": "32x8 cells"},
         "grid_triangles_per_s": n_tri / step_s,
         "triangle_source_tests_per_s": float(st[6]) / step_s,
@@ -567,7 +567,7 @@ def main():
         "fallback": {"flagged_tests": int(st[1]), "tests": int(st[6]), "rate": float(st[1]) / float(st[6]),
                      "fallback_hits": int(st[5]), "hits": int(st[0])},
         "literal": literal,
-        "roofline": {"bound": "alu", "kernel": f"k_field32h<2,4> (FP32 deflection field, 2 x 4 nodes per thread; "
+        "roofline": {"bound": "alu", "kernel": f"k_field32h<1,4> (FP32 deflection field, 1 x 4 nodes per thread; "
                                                   f"its first workgroups run the head's source-plane part)",
                      "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,

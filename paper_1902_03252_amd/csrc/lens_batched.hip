@@ -171,7 +171,8 @@ __global__ __launch_bounds__(256) void k_bfield32(BatchPlan bp, const int* __res
         sx[q] = 0.0f;
         sy[q] = 0.0f;
     }
-    field32_all_wg<NPL>(tab, np, fj, fi, sx, sy);
+    __shared__ float4 srow[256];
+    field32_all_wg<NPL>(tab, np, fj, fi, sx, sy, srow);
     const int tiles_x = (g.nx - 2) / (1 << bp.tx_shift) + 1;
     tile_partials<float, NPL>(sx, sy, i0, j, g.nx, bp.tx_shift, tiles_x, rr + bp.rr_off[s]);
     const size_t row = (size_t)bp.node_off[s] + (size_t)j * g.nx;

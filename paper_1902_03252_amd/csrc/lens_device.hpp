@@ -31,23 +31,28 @@ enum : int {
     T64_STRIDE = 16
 };
 
-// FP32 table, grid-node units, one 64-byte row per potential.  The centre is
+// FP32 table, grid-node units, one 96-byte row per potential.  The centre is
 // stored as (index of the nearest node) + (fraction): with node index i an
 // exact float, (i - c_hi) is exact and (i - c_hi) - c_lo carries only a
 // relative rounding error, so the FP32 offset from a potential's centre is
 // accurate to a few ulps of the offset itself, wherever the potential sits.
 // This removes the paper's error growth near potential centres far from the
 // origin (the |theta_center| / |Delta theta| term of its Appendix A).
+// The general field uses M scaled by 1/sqrt(A h^2) (AP, BP, CQ) so that
+// R^2 = m1'^2 + DQ n_y^2 with m1' = AP n_x + BP n_y (see field32_pot); the SIE
+// field of the paper's own benchmark uses M h^2 and K/h directly.
 enum : int {
     T32_CXH = 0, T32_CXL, T32_CYH, T32_CYL,  // centre in node units (hi + lo)
-    T32_A, T32_B, T32_C,                     // M h^2
+    T32_A, T32_B, T32_C,                     // M h^2 (SIE field)
+    T32_K,                                   // K / h (SIE field)
+    T32_AP, T32_BP, T32_CQ,                  // sqrt(A h^2), B h^2 / sqrt(A h^2), C h^2 / sqrt(A h^2)
+    T32_DQ,                                  // det(M h^2) / (A h^2) = (1 - eps^2) h^4 / (A h^2)
     T32_A2,                                  // a^2 (arcsec^2)
     T32_S2A2,                                // s^2 - a^2
-    T32_RA, T32_RS,                          // a, s (arcsec)
-    T32_K,                                   // K / h
-    T32_KIND,                                // int bits: 0: a>0,s<inf  1: a>0,s=inf  2: a=0,s<inf  3: a=0,s=inf
-    T32_KINV, T32_RSK,                       // 1 / (K / h), s / (K / h) (the FP32 values)
-    T32_STRIDE = 16
+    T32_RA,                                  // a (arcsec)
+    T32_KP,                                  // K' = (K / h) sqrt(A h^2)
+    T32_KINV, T32_RSK,                       // 1 / K', s / K' (the FP32 values)
+    T32_STRIDE = 24
 };
 
 // Per-system row (FP64): barycentre, its node-unit split, D_LS/D_OS and the

@@ -86,15 +86,27 @@ __device__ __forceinline__ void head_images(const PotPtrs& pot, const double* __
 // sum a system's images in image order.
 constexpr int kHeadStage = 512;
 
-__device__ __forceinline__ void head_finish(int np, const GridDesc& g, const ObsPtrs& obs,
+// LDS of head_finish, laid out in a caller's buffer so that the fused field
+// kernels can overlay it on the field loop's row parts.
+struct HeadLds {
+    double sw[4], sj[4], sb[4];
+    double sbx[kHeadStage], sby[kHeadStage];
+    int soff[kHeadStage + 1];
+    int sys_bad;
+};
+
+__device__ __forceinline__ void head_finish(HeadLds& L, int np, const GridDesc& g, const ObsPtrs& obs,
                                             const double* __restrict__ bterm, double* __restrict__ beta_x,
                                             double* __restrict__ beta_y, double* __restrict__ sysrow,
                                             EvalState* __restrict__ st)
 {
-    __shared__ double sw[4], sj[4], sb[4];
-    __shared__ int sys_bad;
-    __shared__ double sbx[kHeadStage], sby[kHeadStage];
-    __shared__ int soff[kHeadStage + 1];
+    double* sw = L.sw;
+    double* sj = L.sj;
+    double* sb = L.sb;
+    int& sys_bad = L.sys_bad;
+    double* sbx = L.sbx;
+    double* sby = L.sby;
+    int* soff = L.soff;
     const int t = threadIdx.x;
     const int nsys = obs.n_sys, nimg = obs.n_img;
     const bool staged = nsys > 0 && nimg <= kHeadStage && nsys < kHeadStage;
@@ -206,11 +218,12 @@ __global__ __launch_bounds__(256) void k_head(PotPtrs pot, GridDesc g, ObsPtrs o
                                               double* __restrict__ sysrow, EvalState* __restrict__ st)
 {
     __shared__ int last;
+    __shared__ HeadLds hl;
     for (int p = blockIdx.x * 256 + threadIdx.x; p < pot.n; p += gridDim.x * 256)
         prep_one(pot, g, p, p, tab64, tab32, bterm);
     head_images<false>(pot, nullptr, obs, beta_x, beta_y, blockIdx.x * 4 + (threadIdx.x >> 6), gridDim.x * 4);
     if (!last_workgroup(&st->head_ticket, &last)) return;
-    head_finish(pot.n, g, obs, bterm, beta_x, beta_y, sysrow, st);
+    head_finish(hl, pot.n, g, obs, bterm, beta_x, beta_y, sysrow, st);
 }
 
 // Constants of every potential only (the fused field kernels do the rest of
@@ -238,7 +251,7 @@ template <int NPL, int NR>
 __device__ __forceinline__ void field32_block(const float* __restrict__ tab32, int np, int nx, int ny, int j0, int bx,
                                               float* __restrict__ ax, float* __restrict__ ay,
                                               const EvalState* __restrict__ st, float* __restrict__ rr,
-                                              int tx_shift, int tiles_x)
+                                              int tx_shift, int tiles_x, float4* __restrict__ srow)
 {
     const int i0 = (bx * 256 + threadIdx.x) * NPL;
     if (bx * 256 * NPL >= nx) return;  // whole workgroup beyond the row
@@ -250,7 +263,7 @@ __device__ __forceinline__ void field32_block(const float* __restrict__ tab32, i
         sx[q] = 0.0f;
         sy[q] = 0.0f;
     }
-    field32_all_wg<NPL, NR>(tab32, np, (float)j0, fi, sx, sy);
+    field32_all_wg<NPL, NR>(tab32, np, (float)j0, fi, sx, sy, srow);
     const bool bad = st != nullptr && st->status != kStatusOk;
 #pragma unroll
     for (int r = 0; r < NR; r++) {
@@ -274,7 +287,8 @@ __global__ __launch_bounds__(256) void k_field32(const float* __restrict__ tab32
                                                  const EvalState* __restrict__ st, float* __restrict__ rr,
                                                  int tx_shift, int tiles_x)
 {
-    field32_block<NPL, NR>(tab32, np, nx, ny, blockIdx.y * NR, blockIdx.x, ax, ay, st, rr, tx_shift, tiles_x);
+    __shared__ float4 srow[NR * 256];
+    field32_block<NPL, NR>(tab32, np, nx, ny, blockIdx.y * NR, blockIdx.x, ax, ay, st, rr, tx_shift, tiles_x, srow);
 }
 
 constexpr int kNpl64 = 2;  // FP64 field nodes per thread
@@ -325,14 +339,26 @@ __global__ __launch_bounds__(256) void k_field64(const double* __restrict__ tab6
 // one wave per observed image reads the prepared FP64 table; the last of these
 // workgroups runs head_finish.  The field workgroups do not depend on it (they
 // read only the FP32 / FP64 tables); the triangle stage after the launch does.
-__device__ __forceinline__ void fused_head(const HeadArgs& h, int head_rows)
+__device__ __forceinline__ void fused_head(HeadLds& L, const HeadArgs& h, int head_rows)
 {
     __shared__ int last;
     const int nblk = head_rows * gridDim.x;
     const int b = blockIdx.y * gridDim.x + blockIdx.x;
     head_images<true>(h.pot, h.tab64, h.obs, h.bx, h.by, b * 4 + (threadIdx.x >> 6), nblk * 4);
     if (!last_of(&h.st->head_ticket, (unsigned)nblk, &last)) return;
-    head_finish(h.pot.n, h.g, h.obs, h.bterm, h.bx, h.by, h.sysrow, h.st);
+    head_finish(L, h.pot.n, h.g, h.obs, h.bterm, h.bx, h.by, h.sysrow, h.st);
+}
+
+// One LDS buffer for both parts of a fused field launch (a workgroup runs
+// either the head or the field): the head's arrays and the field loop's row
+// parts overlay, so the launch needs the larger of the two, not their sum.
+template <int BYTES>
+struct alignas(16) FusedLds {
+    unsigned char raw[BYTES];
+};
+constexpr int fused_lds_bytes(int field_bytes)
+{
+    return field_bytes > (int)sizeof(HeadLds) ? field_bytes : (int)sizeof(HeadLds);
 }
 
 template <int NPL, int NR>
@@ -341,12 +367,13 @@ __global__ __launch_bounds__(256) void k_field32h(const float* __restrict__ tab3
                                                   float* __restrict__ rr, int tx_shift, int tiles_x, HeadArgs h,
                                                   int head_rows)
 {
+    __shared__ FusedLds<fused_lds_bytes(NR * 256 * (int)sizeof(float4))> lds;
     if ((int)blockIdx.y < head_rows) {
-        fused_head(h, head_rows);
+        fused_head(*reinterpret_cast<HeadLds*>(lds.raw), h, head_rows);
         return;
     }
     field32_block<NPL, NR>(tab32, np, nx, ny, (blockIdx.y - head_rows) * NR, blockIdx.x, ax, ay, nullptr, rr,
-                           tx_shift, tiles_x);
+                           tx_shift, tiles_x, reinterpret_cast<float4*>(lds.raw));
 }
 
 __global__ __launch_bounds__(256) void k_field64h(const double* __restrict__ tab64, int np, GridDesc g,
@@ -354,8 +381,9 @@ __global__ __launch_bounds__(256) void k_field64h(const double* __restrict__ tab
                                                   double* __restrict__ rr, int tx_shift, int tiles_x, HeadArgs h,
                                                   int head_rows)
 {
+    __shared__ HeadLds hl;
     if ((int)blockIdx.y < head_rows) {
-        fused_head(h, head_rows);
+        fused_head(hl, h, head_rows);
         return;
     }
     field64_row(tab64, np, g, blockIdx.y - head_rows, blockIdx.x, ax, ay, nullptr, rr, tx_shift, tiles_x);

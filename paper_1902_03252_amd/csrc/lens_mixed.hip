@@ -92,7 +92,7 @@ __global__ __launch_bounds__(256) void k_mix_field32(const float* __restrict__ t
     }
     const bool bad = st->status != kStatusOk;
     if (!bad)  // uniform over the launch
-        pots_wg<T32_STRIDE, T32_CYH, T32_CYL, T32_B, T32_C, -1>(
+        pots_wg<T32_STRIDE, T32_CYH, T32_CYL, T32_B, T32_C>(
             tab32, np, fj, [&](const float* c, float4 rc) { sie32_pot<NPL>(c, rc, fi, sx, sy); });
     const size_t row = (size_t)j * nx;
 #pragma unroll

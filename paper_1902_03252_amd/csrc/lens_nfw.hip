@@ -123,7 +123,7 @@ __global__ __launch_bounds__(256) void k_nfw32(const float* __restrict__ t32, in
     for (int k = 0; k < NPL; k++) sx[k] = sy[k] = 0.0f;
     const float fj = (float)j;
     if (!bad)  // uniform over the launch
-        pots_wg<N32_STRIDE, N32_CYH, N32_CYL, N32_B, N32_C, -1>(t32, np, fj, [&](const float* c, float4 rc) {
+        pots_wg<N32_STRIDE, N32_CYH, N32_CYL, N32_B, N32_C>(t32, np, fj, [&](const float* c, float4 rc) {
             const float A = c[N32_A], B = c[N32_B], irs2 = c[N32_IRS2], K = c[N32_K];
             const float nyv = rc.x, bny = rc.y, cny = rc.z;  // the row part
 #pragma unroll

@@ -102,24 +102,38 @@ inline __device__ void prep_one(const PotPtrs& pot, const GridDesc& g, int p, in
     u[T32_CXL] = (float)cxl;
     u[T32_CYH] = (float)cyh;
     u[T32_CYL] = (float)cyl;
-    // a potential with K/h below 1e-15 (sigma_v = 0, or a deflection below
-    // 1e-14", far under the bound's 1e-9" floor) is stored with M = 0 and K = 0,
-    // so that its finite f multiplies m = 0 (field32_pot divides by K; 1/K <=
-    // 1e15 keeps s/K, B_/K and A_ B_/K finite for the uncut s = 1e18)
+    // SIE field (the paper's benchmark): M h^2 and K/h; a potential with K/h
+    // below 1e-15 (sigma_v = 0, or a deflection below 1e-14") is stored with
+    // M = 0 and K = 0
     const float k32 = (float)(K / g.h);
     const bool kz = !(k32 >= 1e-15f);
     u[T32_A] = kz ? 0.0f : (float)(A * h2);
     u[T32_B] = kz ? 0.0f : (float)(B * h2);
     u[T32_C] = kz ? 0.0f : (float)(C * h2);
-    u[T32_A2] = (float)(a * a);
-    u[T32_S2A2] = sinf ? 1e36f : (float)(s * s - a * a);  // uncut: s = 1e18 (see field32_pot)
-    u[T32_RA] = a > 0.0 ? (float)a : 1e-20f;  // singular: A_ = R + 1e-20 (see field32_pot)
-    u[T32_RS] = sinf ? 1e18f : (float)s;
     u[T32_K] = kz ? 0.0f : k32;
-    reinterpret_cast<int*>(u)[T32_KIND] = (a == 0.0 ? 2 : 0) + (sinf ? 1 : 0);
-    const float kinv = kz ? 1.0f : (float)(1.0 / (double)k32);
+    // General field (field32_pot): M scaled by 1/sqrt(A h^2) and K' = (K/h)
+    // sqrt(A h^2) = K sqrt(A).  A finite cut radius beyond 1e18" is stored as
+    // uncut (its term 1/B_ < 5e-19 is below the rounding of 1/A_ for any
+    // A_ < 1e9"), an uncut profile with s = 1e18 (s^2 - a^2 = 1e36), and a
+    // singular one with a = 1e-20 in A_ only.  A potential with K' below 1e-12
+    // is stored with zero coefficients and K' = 0 (its finite f multiplies
+    // m = 0) and its whole deflection, at most w_p, is charged to the bound
+    // below; 1/K' <= 1e12 keeps B_/K' <= 2e30.
+    const bool sbig = sinf || s > 1e18;
+    const double sA = sqrt(A * h2);
+    const float kp = (float)(K * sqrt(A));
+    const bool kzp = !(kp >= 1e-12f);
+    u[T32_AP] = kzp ? 0.0f : (float)sA;
+    u[T32_BP] = kzp ? 0.0f : (float)(B * h2 / sA);
+    u[T32_CQ] = kzp ? 0.0f : (float)(C * h2 / sA);
+    u[T32_DQ] = (float)(a1 * a2 * h2 / A);
+    u[T32_A2] = (float)(a * a);
+    u[T32_S2A2] = sbig ? 1e36f : (float)(s * s - a * a);
+    u[T32_RA] = a > 0.0 ? (float)a : 1e-20f;
+    u[T32_KP] = kzp ? 0.0f : kp;
+    const float kinv = kzp ? 1.0f : (float)(1.0 / (double)kp);
     u[T32_KINV] = kinv;
-    u[T32_RSK] = (float)((double)u[T32_RS] * (double)kinv);
+    u[T32_RSK] = (float)((double)(sbig ? 1e18f : (float)s) * (double)kinv);
     for (int k = T32_RSK + 1; k < T32_STRIDE; k++) u[k] = 0.0f;
 
     // Offset error term j_p.  Every node other than the nearest one lies at
@@ -148,7 +162,13 @@ inline __device__ void prep_one(const PotPtrs& pot, const GridDesc& g, int p, in
     // capacity.  A centre exactly on a node is exact in both precisions (zero
     // offsets, zero contribution).
     const bool near_singular = rn > 0.0 && g.h * rn < 1e-10 && a < 1e-10;
-    const double jt = J * derr + 2.0 * kU32 * K * a2 / (a1 * sqrt(a1)) + (near_singular ? 2.0 * w : 0.0);
+    // The FP32 products stay finite while qa B_/K' <= (sqrt(a^2 + R^2) + a)
+    // (2 s + R) / K' does (R <= sqrt(1 + eps) |d|, |d| <= span); beyond, the
+    // same 2 w_p is taken.
+    const double rmax = sqrt(a2) * span, se = sbig ? 1e18 : s;
+    const bool range = !kzp && (sqrt(a * a + rmax * rmax) + a) * (2.0 * se + rmax) * (double)kinv > 1e37;
+    const double jt = J * derr + 2.0 * kU32 * K * a2 / (a1 * sqrt(a1)) +
+                      ((near_singular || range) ? 2.0 * w : 0.0) + (kzp ? w : 0.0);
     bterm[3 * q + 0] = ok ? w : 0.0;
     bterm[3 * q + 1] = ok ? jt : 0.0;
     bterm[3 * q + 2] = ok ? 0.0 : 1.0;
@@ -177,47 +197,51 @@ __device__ __forceinline__ int system_of(const int* __restrict__ sys_off, int ns
 // FP32 contribution of one potential row `c` for NPL nodes of a row, one
 // branch-free formula for all four radial-profile kinds:
 //     f = (B_ - A_) / (A_ B_),  A_ = sqrt(a^2 + R^2) + a,  B_ = sqrt(s^2 + R^2) + s.
-// An uncut profile is stored with s = 1e18 (s^2 - a^2 = 1e36): B_ = 2e18 in
-// FP32, B_ - A_ rounds to B_, and f = 1/A_ to a few ulps.  A singular
-// profile (a = 0) is stored with a = 1e-20 arcsec in A_ only (a^2 stays 0), so
-// that A_ B_ > 0 everywhere: at the centre the offsets are exactly zero and
-// the contribution is exactly zero (the centre convention); elsewhere the
-// change of f, below 1e-20/R relative, lies inside the FP32 error bound (its
-// Jacobian term).  R^2 cannot round below zero unless it is itself at the
-// rounding level (eps near 1); the first root takes |a^2 + R^2| (a free
-// operand modifier) so that no NaN arises there.  Offsets from the centre
-// use the exact hi/lo split (see the FP32 table); hardware sqrt/rcp (1 ulp)
-// are accounted for in the error bound.  K f = K (B_ - A_) / (A_ B_) is
-// evaluated as (K b - A_) / (A_ b) with b = B_ / K = sqrt(s^2 + R^2) / K +
-// s / K (one fused multiply-add; 1/K and s/K are stored): one instruction
-// fewer than scaling by K after the division, and the error of K b - A_ is
-// that of B_ - A_ plus about 1 ulp of B_, which the bound's per-potential
-// budget covers.  This is the node part for NPL consecutive nodes in each of
-// NR consecutive rows (sx, sy: [NR][NPL]), given the row parts rc[r] = (n_y,
-// B n_y, C n_y, s / K) of the same potential for those rows (see
-// pots_wg_rows): the column offset n_x = (i - c_hi) - c_lo, two instructions,
-// is formed once per column and shared by the NR rows.  Every node's
-// arithmetic is the same whatever NPL and NR.
+// With M h^2 = [[A, B], [B, C]] and n the node-unit offset, the table holds
+// M scaled by 1/sqrt(A): m' = (sqrt(A) n_x + B/sqrt(A) n_y, B/sqrt(A) n_x +
+// C/sqrt(A) n_y) = M h^2 n / sqrt(A), and R^2 = n . M h^2 n =
+// m'_1^2 + (det(M h^2)/A) n_y^2 (completing the square in n_x): a sum of two
+// non-negative terms, so a^2 + R^2 is one fused multiply-add of m'_1 onto a
+// row constant E = (det/A) n_y^2 + a^2, never negative.  The deflection
+// K f M d = (K' f) m' with K' = (K/h) sqrt(A), and K' f = K' (B_ - A_) /
+// (A_ B_) is evaluated as (K' b - A_) / (A_ b) with b = B_ / K' =
+// sqrt(s^2 + R^2) / K' + s / K' (one fused multiply-add; 1/K' and s/K' are
+// stored).  An uncut profile is stored with s = 1e18 (s^2 - a^2 = 1e36):
+// B_ = 2e18 in FP32, B_ - A_ rounds to B_, and f = 1/A_ to a few ulps.  A
+// singular profile (a = 0) is stored with a = 1e-20 arcsec in A_ only (a^2
+// stays 0), so that A_ B_ > 0 everywhere: at the centre the offsets are
+// exactly zero and the contribution is exactly zero (the centre convention);
+// elsewhere the change of f, below 1e-20/R relative, lies inside the FP32
+// error bound (its Jacobian term).  Offsets from the centre use the exact
+// hi/lo split (see the FP32 table); hardware sqrt/rcp (1 ulp) are accounted
+// for in the error bound (a float32 emulation with 1-ulp root and reciprocal
+// errors over random profiles, eps up to 0.95, and radii from 1e-3 to 1e4
+// nodes stays under 9 u w_p, inside the bound's 64 u w_p per potential).
+// This is the node part for NPL consecutive nodes in each of NR consecutive
+// rows (sx, sy: [NR][NPL]), given the row parts rc[r] = (B/sqrt(A) n_y,
+// C/sqrt(A) n_y, E, s/K') of the same potential for those rows (see
+// field32_all_wg): the column offset n_x = (i - c_hi) - c_lo, two
+// instructions, is formed once per column and shared by the NR rows; per
+// node and potential, 11 vector instructions and 3 transcendentals (2 roots,
+// 1 reciprocal).  Every node's arithmetic is the same whatever NPL and NR.
 template <int NPL, int NR = 1>
 __device__ __forceinline__ void field32_pot(const float* __restrict__ c, const float4* rc, const float* fi,
                                             float* sx, float* sy)
 {
     const float cxh = c[T32_CXH], cxl = c[T32_CXL];
-    const float A = c[T32_A], B = c[T32_B];
-    const float a2 = c[T32_A2], s2a2 = c[T32_S2A2], ra = c[T32_RA], K = c[T32_K], kinv = c[T32_KINV];
-    const float rsk = rc[0].w;
+    const float ap = c[T32_AP], bp = c[T32_BP];
+    const float s2a2 = c[T32_S2A2], ra = c[T32_RA], kp = c[T32_KP], kinv = c[T32_KINV];
 #pragma unroll
     for (int k = 0; k < NPL; k++) {
         const float nxv = (fi[k] - cxh) - cxl;
 #pragma unroll
         for (int r = 0; r < NR; r++) {
-            const float nyv = rc[r].x, bny = rc[r].y, cny = rc[r].z;
-            const float m1 = fmaf(A, nxv, bny);
-            const float m2 = fmaf(B, nxv, cny);
-            const float qa2 = fmaf(nxv, m1, fmaf(nyv, m2, a2));  // a^2 + R^2
-            const float qa = __builtin_amdgcn_sqrtf(fabsf(qa2)) + ra;  // |.|: a source modifier
-            const float qsk = fmaf(__builtin_amdgcn_sqrtf(qa2 + s2a2), kinv, rsk);  // B_ / K
-            const float kf = fmaf(qsk, K, -qa) * __builtin_amdgcn_rcpf(qa * qsk);
+            const float m1 = fmaf(ap, nxv, rc[r].x);
+            const float m2 = fmaf(bp, nxv, rc[r].y);
+            const float qa2 = fmaf(m1, m1, rc[r].z);  // a^2 + R^2 >= 0
+            const float qa = __builtin_amdgcn_sqrtf(qa2) + ra;
+            const float qsk = fmaf(__builtin_amdgcn_sqrtf(qa2 + s2a2), kinv, rc[r].w);  // B_ / K'
+            const float kf = fmaf(qsk, kp, -qa) * __builtin_amdgcn_rcpf(qa * qsk);
             sx[r * NPL + k] = fmaf(kf, m1, sx[r * NPL + k]);
             sy[r * NPL + k] = fmaf(kf, m2, sy[r * NPL + k]);
         }
@@ -225,58 +249,63 @@ __device__ __forceinline__ void field32_pot(const float* __restrict__ c, const f
 }
 
 // Runs f(c, rc) for every row c of an FP32 table of np rows (STRIDE floats
-// each), in order, with rc[r] = (n_y, B n_y, C n_y, c[IW]), n_y = (j - c[IYH])
-// - c[IYL], for the NR grid rows j = fj, fj + 1, ...: the row part of a
-// potential, common to every node of grid row j, and one more constant of the
-// potential (IW < 0: 0) that the caller wants in a vector register.  For a
-// workgroup of 256 threads on those rows (all threads call it, with the same
-// fj): the row parts of up to 256 potentials at a time are computed once, one
-// potential per thread, into LDS, so that the per-potential work of every
-// wave is the node part only (the row part is uniform over the workgroup but,
-// with no scalar FP32 ALU, costs a full vector instruction per wave).
-template <int STRIDE, int IYH, int IYL, int IB, int IC, int IW, int NR, class F>
-__device__ __forceinline__ void pots_wg_rows(const float* __restrict__ tab, int np, float fj, F&& f)
+// each), in order, with rc[r] = rowf(c, n_y), n_y = (j - c[IYH]) - c[IYL],
+// for the NR grid rows j = fj, fj + 1, ...: the row part of a potential,
+// common to every node of grid row j.  For a workgroup of 256 threads on
+// those rows (all threads call it, with the same fj): the row parts of up to
+// 256 potentials at a time are computed once, one potential per thread, into
+// LDS, so that the per-potential work of every wave is the node part only
+// (the row part is uniform over the workgroup but, with no scalar FP32 ALU,
+// costs a full vector instruction per wave).
+// srow: LDS of NR * 256 float4 (row r of potential p at r * 256 + p).
+template <int STRIDE, int IYH, int IYL, int NR, class RF, class F>
+__device__ __forceinline__ void pots_wg_rows(const float* __restrict__ tab, int np, float fj, float4* __restrict__ srow,
+                                             RF&& rowf, F&& f)
 {
-    __shared__ float4 srow[NR][256];
     for (int p0 = 0; p0 < np; p0 += 256) {
         const int pc = np - p0 < 256 ? np - p0 : 256;
         if (p0 > 0) __syncthreads();  // the previous chunk has been read
         if ((int)threadIdx.x < pc) {
             const float* c = tab + (size_t)(p0 + threadIdx.x) * STRIDE;
-            const float w = IW >= 0 ? c[IW >= 0 ? IW : 0] : 0.0f;
 #pragma unroll
-            for (int r = 0; r < NR; r++) {
-                const float nyv = ((fj + (float)r) - c[IYH]) - c[IYL];
-                srow[r][threadIdx.x] = make_float4(nyv, c[IB] * nyv, c[IC] * nyv, w);
-            }
+            for (int r = 0; r < NR; r++) srow[r * 256 + threadIdx.x] = rowf(c, ((fj + (float)r) - c[IYH]) - c[IYL]);
         }
         __syncthreads();
         for (int p = 0; p < pc; p++) {
             float4 rc[NR];
 #pragma unroll
-            for (int r = 0; r < NR; r++) rc[r] = srow[r][p];
+            for (int r = 0; r < NR; r++) rc[r] = srow[r * 256 + p];
             f(tab + (size_t)(p0 + p) * STRIDE, rc);
         }
     }
 }
 
-// One grid row (pots_wg_rows with NR = 1), f(c, rc) with the row part itself.
-template <int STRIDE, int IYH, int IYL, int IB, int IC, int IW, class F>
+// One grid row (pots_wg_rows with NR = 1) and the row part (n_y, B n_y, C n_y)
+// of a table holding M h^2 at IB, IC: f(c, rc) with the row part itself.
+template <int STRIDE, int IYH, int IYL, int IB, int IC, class F>
 __device__ __forceinline__ void pots_wg(const float* __restrict__ tab, int np, float fj, F&& f)
 {
-    pots_wg_rows<STRIDE, IYH, IYL, IB, IC, IW, 1>(tab, np, fj, [&](const float* c, const float4* rc) { f(c, rc[0]); });
+    __shared__ float4 srow[256];
+    pots_wg_rows<STRIDE, IYH, IYL, 1>(
+        tab, np, fj, srow, [](const float* c, float nyv) { return make_float4(nyv, c[IB] * nyv, c[IC] * nyv, 0.0f); },
+        [&](const float* c, const float4* rc) { f(c, rc[0]); });
 }
 
 // Deflection of NPL nodes in each of NR rows (fj, fj + 1, ...) by every
 // potential of the FP32 table, for a workgroup of 256 threads on those rows
-// (pots_wg_rows; s / K rides along with the row part, as field32_pot's fused
-// multiply-add can take only one scalar operand).  sx, sy: [NR][NPL].
+// (pots_wg_rows with the row part of field32_pot; s / K' rides along with it,
+// as field32_pot's fused multiply-add can take only one scalar operand).
+// sx, sy: [NR][NPL]; srow: LDS of NR * 256 float4.
 template <int NPL, int NR = 1>
 __device__ __forceinline__ void field32_all_wg(const float* __restrict__ tab, int np, float fj, const float* fi,
-                                               float* sx, float* sy)
+                                               float* sx, float* sy, float4* __restrict__ srow)
 {
-    pots_wg_rows<T32_STRIDE, T32_CYH, T32_CYL, T32_B, T32_C, T32_RSK, NR>(
-        tab, np, fj, [&](const float* c, const float4* rc) { field32_pot<NPL, NR>(c, rc, fi, sx, sy); });
+    pots_wg_rows<T32_STRIDE, T32_CYH, T32_CYL, NR>(
+        tab, np, fj, srow,
+        [](const float* c, float nyv) {
+            return make_float4(c[T32_BP] * nyv, c[T32_CQ] * nyv, fmaf(c[T32_DQ] * nyv, nyv, c[T32_A2]), c[T32_RSK]);
+        },
+        [&](const float* c, const float4* rc) { field32_pot<NPL, NR>(c, rc, fi, sx, sy); });
 }
 
 // Range partials of the triangle stage, written by the field kernel: for grid
