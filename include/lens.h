@@ -46,6 +46,7 @@ extern "C" {
 #define LENS_ERR_INVALID 1   /* bad argument or parameter domain             */
 #define LENS_ERR_DEVICE 2    /* a HIP call failed                             */
 #define LENS_ERR_CAPACITY 3  /* more predicted images than the output holds  */
+#define LENS_ERR_SCRATCH 4   /* input too large for lens_image_chi2_noalloc's fixed scratch */
 
 /* Slots of the int64 statistics array written by lens_image_chi2. */
 #define LENS_STAT_HITS 0        /* predicted images (triangle hits) found          */
@@ -226,6 +227,29 @@ int lens_source_positions(lens_ctx *ctx, const lens_potentials *pot, const lens_
 int lens_image_chi2(lens_ctx *ctx, const lens_potentials *pot, const lens_grid *grid,
                     const lens_obs *obs, const lens_chi2_opts *opts, lens_chi2_out *out,
                     hipStream_t stream);
+
+/* Bytes of the fixed device scratch of lens_image_chi2_noalloc (per device). */
+#define LENS_NOALLOC_SCRATCH_BYTES (512ull << 20)
+
+/* lens_image_chi2 for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments (no context), results, status and stream semantics as
+ * lens_image_chi2; it runs on the calling thread's current HIP device with the
+ * library's default tile shape and field layout for the grid size (or those
+ * set in opts), and calls no hipMalloc, hipFree or allocating routine.  Its
+ * scratch is one fixed array of LENS_NOALLOC_SCRATCH_BYTES in device memory
+ * that the library holds on every device it runs on until the process ends
+ * (512 MiB holds a 4096^2 grid with 100 systems in either precision).
+ * An input that needs more returns LENS_ERR_SCRATCH before anything is
+ * enqueued.  The array's address on a device is looked up once, on the first
+ * call on that device or by lens_create for it; that lookup is not a stream
+ * operation, so make the first call outside graph capture or create a context
+ * on the device first.  Every call on one device shares that array and
+ * leaves its contents behind: calls whose work overlaps on one device
+ * (different streams, or threads without ordering) race and give wrong
+ * results. */
+int lens_image_chi2_noalloc(const lens_potentials *pot, const lens_grid *grid, const lens_obs *obs,
+                            const lens_chi2_opts *opts, lens_chi2_out *out, hipStream_t stream);
 
 /* Outputs of the batched chi^2 (device arrays). */
 typedef struct {

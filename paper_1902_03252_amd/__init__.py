@@ -270,6 +270,27 @@ def lens_image_chi2(params: torch.Tensor, grid, obs: Obs, prec: str = "mixed", f
     return out
 
 
+def lens_image_chi2_noalloc(params: torch.Tensor, grid, obs: Obs, prec: str = "mixed", fb_mode: int = 0,
+                            fb_tau: float = 1e-6, hit_capacity: int = 4096, out: Chi2Result | None = None,
+                            field_npl: int = 0, tile: int = 0) -> Chi2Result:
+    """lens_image_chi2 through the entry point that allocates no device memory
+    (no context; the library's fixed scratch on params' device).  Callers that
+    cannot allocate pass `out`; without it the buffers are made here, outside
+    the library call."""
+    if prec not in ("fp64", "mixed"):
+        raise ValueError("prec must be 'fp64' or 'mixed'")
+    lib = L.load()
+    p, o = _pots(params), _obs(obs)
+    out = out or chi2_buffers(obs, hit_capacity, params.device)
+    opts = L.LensChi2Opts(_PREC[prec], int(fb_mode), float(fb_tau), int(out.hits.shape[0]), int(field_npl),
+                          int(tile))
+    with torch.cuda.device(params.device):
+        L.check(lib.lens_image_chi2_noalloc(C.byref(p), C.byref(_grid(grid)), C.byref(o), C.byref(opts),
+                                            C.byref(_chi2_out(out)), L.stream_handle(params.device)),
+                "lens_image_chi2_noalloc")
+    return out
+
+
 def _chi2_out(out: Chi2Result):
     return L.LensChi2Out(out.chi2.data_ptr(), out.chi2_sys.data_ptr(), out.n_pred.data_ptr(), out.hits.data_ptr(),
                          out.img_xy.data_ptr(), out.match.data_ptr(), out.stats.data_ptr())

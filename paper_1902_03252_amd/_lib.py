@@ -14,13 +14,15 @@ import torch
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "liblens.so")
 
-LENS_OK, LENS_ERR_INVALID, LENS_ERR_DEVICE, LENS_ERR_CAPACITY = 0, 1, 2, 3
+LENS_OK, LENS_ERR_INVALID, LENS_ERR_DEVICE, LENS_ERR_CAPACITY, LENS_ERR_SCRATCH = 0, 1, 2, 3, 4
+NOALLOC_SCRATCH_BYTES = 512 << 20
 LENS_FP64, LENS_FP32, LENS_MIXED = 0, 1, 2
 STAT_HITS, STAT_FLAGGED, STAT_TILE_PASS, STAT_BBOX_PASS, STAT_STATUS, STAT_FB_HITS, STAT_TESTS = range(7)
 STAT_N = 8
 
 EXPORTS = ("lens_create", "lens_destroy", "lens_dls_dos", "lens_deflect", "lens_deflect_mixed",
-           "lens_deflect_nfw", "lens_source_positions", "lens_image_chi2", "lens_image_chi2_batched",
+           "lens_deflect_nfw", "lens_source_positions", "lens_image_chi2", "lens_image_chi2_noalloc",
+           "lens_image_chi2_batched",
            "lens_deflect_backward", "lens_src_chi2", "lens_src_chi2_backward", "lens_hmc_step",
            "lens_mh_step_batched", "lens_autotune_chi2", "lens_autotune_chi2_batched", "lens_autotune_lookup",
            "lens_autotune_save", "lens_autotune_load", "lens_set_timing", "lens_field_timing", "lens_strerror")
@@ -96,6 +98,9 @@ def load(path: str = LIB_PATH):
     lib.lens_image_chi2.argtypes = [vp, C.POINTER(LensPotentials), C.POINTER(LensGrid), C.POINTER(LensObs),
                                     C.POINTER(LensChi2Opts), C.POINTER(LensChi2Out), vp]
     lib.lens_image_chi2.restype = C.c_int
+    lib.lens_image_chi2_noalloc.argtypes = [C.POINTER(LensPotentials), C.POINTER(LensGrid), C.POINTER(LensObs),
+                                            C.POINTER(LensChi2Opts), C.POINTER(LensChi2Out), vp]
+    lib.lens_image_chi2_noalloc.restype = C.c_int
     lib.lens_image_chi2_batched.argtypes = [vp, C.POINTER(LensPotentials), i32, C.POINTER(i32), C.POINTER(LensGrid),
                                             C.POINTER(LensObs), C.POINTER(LensChi2Opts), C.POINTER(LensBatchOut), vp]
     lib.lens_image_chi2_batched.restype = C.c_int

@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <mutex>
 #include <cmath>
 #include <stdlib.h>
 #include <string.h>
@@ -69,6 +70,10 @@ struct lens_ctx {
     std::vector<PlanEntry*>* plans;  // batch plans, one per distinct shape class
     TuneTable* tune;                 // autotuned tile shape / nodes per thread per bucket
 };
+
+namespace {
+void* noalloc_scratch(int dev);  // the fixed scratch of lens_image_chi2_noalloc (below)
+}  // namespace
 
 TuneTable* lens_ctx_tune(lens_ctx* ctx) { return ctx ? ctx->tune : nullptr; }
 int lens_ctx_device(lens_ctx* ctx) { return ctx->device; }
@@ -205,7 +210,7 @@ void resolve_tuned(lens_ctx* ctx, int prec, int batched, long long side, long lo
 {
     if (shape && npl) return;
     int t = 0, n = 0;
-    if (!tune_lookup(ctx->tune, prec, batched, tune_log2(side), tune_log2(np), &t, &n)) return;
+    if (!tune_lookup(ctx ? ctx->tune : nullptr, prec, batched, tune_log2(side), tune_log2(np), &t, &n)) return;
     if (!shape) shape = t;
     if (!npl) npl = n;
 }
@@ -321,6 +326,12 @@ int lens_create(lens_ctx** ctx, int device)
     hipDeviceProp_t prop;
     if (cache && *cache && hipGetDeviceProperties(&prop, device) == hipSuccess)
         (void)tune_load(c->tune, cache, prop.gcnArchName);
+    {
+        // set-up of the no-allocation entry point's fixed scratch on this
+        // device (a failure is reported by that entry point)
+        DeviceGuard dg(device);
+        if (dg.ok) (void)noalloc_scratch(device);
+    }
     *ctx = c;
     return LENS_OK;
 }
@@ -375,6 +386,7 @@ const char* lens_strerror(int code)
     case LENS_ERR_INVALID: return "invalid argument or parameter domain";
     case LENS_ERR_DEVICE: return "HIP device error";
     case LENS_ERR_CAPACITY: return "hit capacity exceeded";
+    case LENS_ERR_SCRATCH: return "input needs more scratch than the fixed no-allocation buffer holds";
     default: return "unknown error";
     }
 }
@@ -717,6 +729,71 @@ int lens_image_chi2(lens_ctx* ctx, const lens_potentials* pot, const lens_grid* 
         b.p[k] = ctx->buf[kCtxBuf[k]];
     }
     return chi2_run(ctx, pl, b, pot, opts, out, stream);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ no-allocation chi^2
+
+// Fixed scratch of lens_image_chi2_noalloc: one copy per device, held until
+// the process ends.  In host code `scratch` names a host-side stand-in, not
+// device memory: only the address that hipGetSymbolAddress returns for the
+// current device is ever passed to a kernel or a copy.
+static __device__ __align__(256) unsigned char scratch[LENS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kNoallocDevices = 64;
+
+struct NoallocSlot {
+    std::once_flag once;
+    void* ptr = nullptr;
+};
+NoallocSlot g_noalloc[kNoallocDevices];
+
+// Device address of device `dev`'s copy of the fixed scratch, looked up once
+// per device with that device current (null if the lookup failed).
+void* noalloc_scratch(int dev)
+{
+    if (dev < 0 || dev >= kNoallocDevices) return nullptr;
+    NoallocSlot& slot = g_noalloc[dev];
+    std::call_once(slot.once, [&slot] {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess) slot.ptr = p;
+    });
+    return slot.ptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lens_image_chi2_noalloc(const lens_potentials* pot, const lens_grid* grid, const lens_obs* obs,
+                            const lens_chi2_opts* opts, lens_chi2_out* out, hipStream_t stream)
+{
+    int rc = chi2_check(pot, grid, obs, opts, out);
+    if (rc) return rc;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return LENS_ERR_DEVICE;
+    unsigned char* base = (unsigned char*)noalloc_scratch(dev);
+    if (!base) return LENS_ERR_DEVICE;
+    Chi2Plan pl;
+    if ((rc = chi2_plan(nullptr, pot, grid, obs, opts, kFlagScratch, pl))) return rc;
+    // the context path's buffers, carved in order from the fixed array
+    Chi2Bufs b;
+    size_t off = 0;
+    for (int k = 0; k < CB_N; k++) {
+        b.p[k] = base + off;
+        off += (std::max(pl.bytes[k], (size_t)1) + 255) & ~(size_t)255;
+        if (off > (size_t)LENS_NOALLOC_SCRATCH_BYTES) return LENS_ERR_SCRATCH;
+    }
+    // The evaluation state sits at the start of the array in every call; its
+    // head ticket must be zero when the head kernel starts.  The fused path's
+    // prep kernel clears it; otherwise a one-wave kernel does (no memset node
+    // in a captured graph).
+    EvalState* st = (EvalState*)b.p[CB_STATE];
+    if (!pl.fused && launch_zero_u32(&st->head_ticket, 1, stream) != hipSuccess) return LENS_ERR_DEVICE;
+    return chi2_run(nullptr, pl, b, pot, opts, out, stream);
 }
 
 }  // extern "C"

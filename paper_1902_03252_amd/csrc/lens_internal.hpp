@@ -89,6 +89,7 @@ struct HeadArgs {
 
 hipError_t launch_prep(const PotPtrs& pot, const GridDesc& g, double* tab64, float* tab32, double* bterm,
                        EvalState* st, hipStream_t s);
+hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t s);
 int fused_head_fits(const GridDesc& g, const ObsPtrs& obs, int npl, bool fp32);
 // FP32 field layout code (lens_chi2_opts.field_npl): C = 1, 2, 4 or 8
 // consecutive nodes of one row per thread, or 16 R + C for C consecutive nodes

@@ -993,6 +993,19 @@ hipError_t launch_prep(const PotPtrs& pot, const GridDesc& g, double* tab64, flo
     return hipGetLastError();
 }
 
+// Zeroes n words (a fill kernel rather than a memset, so that a captured
+// graph holds no memset node).
+__global__ __launch_bounds__(64) void k_zero_u32(unsigned* __restrict__ p, int n)
+{
+    for (int k = threadIdx.x; k < n; k += 64) p[k] = 0u;
+}
+
+hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t s)
+{
+    k_zero_u32<<<1, 64, 0, s>>>(p, n);
+    return hipGetLastError();
+}
+
 // Rows of head workgroups for a field launch `bx` workgroups wide: one wave
 // per observed image, at least one workgroup (head_finish always runs).
 static int head_rows_for(const ObsPtrs& obs, int bx)

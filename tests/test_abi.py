@@ -52,6 +52,7 @@ def test_strerror(lib):
     assert lib.lens_strerror(0) == b"ok"
     assert b"invalid" in lib.lens_strerror(1)
     assert b"capacity" in lib.lens_strerror(3)
+    assert b"no-allocation" in lib.lens_strerror(4)
 
 
 def test_host_validation_rejects_before_any_device_call(lib):
@@ -90,6 +91,12 @@ def test_host_validation_rejects_before_any_device_call(lib):
     out_null = L.LensChi2Out(None, buf, buf, buf, buf, buf, buf)
     assert lb.lens_image_chi2(ctx, C.byref(pot), C.byref(grid), C.byref(obs), C.byref(opts), C.byref(out_null),
                               None) == L.LENS_ERR_INVALID
+    # the no-allocation entry point checks the same arguments first (no device call)
+    for o in (L.LensChi2Opts(1, 0, 0.0, 16, 0, 0), L.LensChi2Opts(2, 0, 0.0, 0, 0, 0)):
+        assert lb.lens_image_chi2_noalloc(C.byref(pot), C.byref(grid), C.byref(obs), C.byref(o), C.byref(out),
+                                          None) == L.LENS_ERR_INVALID
+    assert lb.lens_image_chi2_noalloc(C.byref(pot), C.byref(grid), C.byref(obs), C.byref(opts), C.byref(out_null),
+                                      None) == L.LENS_ERR_INVALID
     # batched entry point: sample layout and per-sample limits
     bout = L.LensBatchOut(buf, buf, buf, buf, buf)
     pot2 = L.LensPotentials(4, buf, buf, buf, buf, buf, buf, buf)
