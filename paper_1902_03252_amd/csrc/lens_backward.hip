@@ -235,15 +235,32 @@ __device__ __forceinline__ double vjp_combine(const double* d, const double* sum
 
 // ============================================================== field VJP
 
-#ifndef LENS_VJP_ROWS
-#define LENS_VJP_ROWS 16
+// Rows per wave (nodes per thread, their cotangents held in registers) and
+// potentials per workgroup of the field VJP: FP32 products 16 rows and 4
+// potentials, FP64 products 8 rows and 2 potentials (twice the registers per
+// value and three times the work per term).
+#ifndef LENS_VJP32_ROWS
+#define LENS_VJP32_ROWS 8
 #endif
-#ifndef LENS_VJP_GROUP
-#define LENS_VJP_GROUP 2
+#ifndef LENS_VJP32_GROUP
+#define LENS_VJP32_GROUP 4
 #endif
-constexpr int kVjpRows = LENS_VJP_ROWS;   // grid rows per wave (nodes per thread)
-constexpr int kVjpGroup = LENS_VJP_GROUP; // potentials per workgroup
-constexpr int kVjpTileY = 4 * kVjpRows;
+#ifndef LENS_VJP64_ROWS
+#define LENS_VJP64_ROWS 4
+#endif
+#ifndef LENS_VJP64_GROUP
+#define LENS_VJP64_GROUP 2
+#endif
+template <typename T>
+struct VjpCfg {
+    static constexpr int rows = LENS_VJP32_ROWS, group = LENS_VJP32_GROUP;
+};
+template <>
+struct VjpCfg<double> {
+    static constexpr int rows = LENS_VJP64_ROWS, group = LENS_VJP64_GROUP;
+};
+// the smaller tile height (more tiles) sizes the scratch
+constexpr int kVjpMinRows = VjpCfg<double>::rows < VjpCfg<float>::rows ? VjpCfg<double>::rows : VjpCfg<float>::rows;
 
 // Derivative constants of every potential, plus (FP32 path) the node-unit
 // split of its centre as in the FP32 field: slot D_CX.. of row p.
@@ -262,78 +279,102 @@ __global__ __launch_bounds__(64) void k_vjp_prep(PotPtrs pot, GridDesc g, double
     d[D_CYL] = (float)(cyn - rint(cyn));
 }
 
-// Workgroup (tile, group): a 64 x 64 node tile of the grid, lane = column and
-// wave = a band of 16 rows, times the potentials [group*2, +2), whose
-// constants every lane reads from the same address.  Per potential every
-// thread accumulates its nodes' seven node sums in T; the workgroup reduces
-// them in FP64 in a fixed order, applies the potential's constants and writes
-// the seven products to part[(k*P + p)*n_tiles + tile].
+// The seven node sums of one potential over a thread's R rows (cotangents
+// g1, g2 in registers, rows past the grid at g = 0), for one profile kind.
+template <typename T, int R, bool CUT, bool SING>
+__device__ __forceinline__ void vjp_rows(const DConst<T>& k, T d1, const T* d2, const T* g1, const T* g2, T* acc)
+{
+#pragma unroll
+    for (int r = 0; r < R; r += 2)
+        vjp_sums2<T, CUT, SING>(k, d1, d2[r], g1[r], g2[r], d1, d2[r + 1], g1[r + 1], g2[r + 1], acc);
+}
+
+// Workgroup (tile, group): a 64-column tile of 4 R rows, lane = column and
+// wave = a band of R rows, times the potentials [group*G, +G), whose
+// constants every lane reads from the same address.  Each thread loads its
+// R nodes' cotangents once (one round of independent loads), then for every
+// potential of the group accumulates the seven node sums in T over those
+// nodes and leaves them in LDS.  The workgroup then reduces the 256 partial
+// sums of each (potential, sum) in FP64 in a fixed order (runs of 256/S
+// consecutive threads, then the S runs), applies the potential's constants
+// and writes the seven products to part[(k*P + p)*n_tiles + tile].
 template <typename T>
 __global__ __launch_bounds__(256) void k_vjp(const double* __restrict__ dtab, int np, GridDesc g,
                                              const double* __restrict__ gx, const double* __restrict__ gy,
                                              int tiles_x, int n_tiles, double* __restrict__ part)
 {
-    __shared__ double red[kVjpGroup * 7][4];
+    constexpr int R = VjpCfg<T>::rows, G = VjpCfg<T>::group;
+    constexpr int S = G * 7 * 16 <= 256 ? 16 : G * 7 * 8 <= 256 ? 8 : 4;  // runs per (potential, sum)
+    static_assert(G * 7 * S <= 256 && 256 % S == 0, "one thread per run");
+    __shared__ T red[G * 7][256];
+    __shared__ double run[G * 7][S];
+    __shared__ double tot[G * 7];
     const int tile = blockIdx.x % n_tiles, grp = blockIdx.x / n_tiles;
-    const int p0 = grp * kVjpGroup, npg = min(kVjpGroup, np - p0);
+    const int p0 = grp * G, npg = min(G, np - p0);
     const int t = threadIdx.x, lane = lane_id();
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
     const int i = (tile % tiles_x) * 64 + lane;
-    const int jb = (tile / tiles_x) * kVjpTileY + wave * kVjpRows;
-    const int nrow = min(kVjpRows, g.ny - jb);
+    const int jb = (tile / tiles_x) * (4 * R) + wave * R;
     const bool col = i < g.nx;
     const int ic = col ? i : 0;
-    T acc[kVjpGroup][7];
+    T g1[R], g2[R];
 #pragma unroll
-    for (int q = 0; q < kVjpGroup; q++)
-#pragma unroll
-        for (int c = 0; c < 7; c++) acc[q][c] = (T)0;
-    const float ihf = (float)g.h;
-    for (int u = 0; u < nrow; u += 2) {
-        // rows j and j + 1 (a row past the band or the grid has g = 0)
-        const int j = jb + u;
-        const bool two = u + 1 < nrow;
-        const size_t n0 = (size_t)j * g.nx + ic, n1 = two ? n0 + g.nx : n0;
-        T ga1 = col ? (T)gx[n0] : (T)0, ga2 = col ? (T)gy[n0] : (T)0;
-        T gb1 = col ? (T)gx[n1] : (T)0, gb2 = col ? (T)gy[n1] : (T)0;
-        gb1 = two ? gb1 : (T)0;
-        gb2 = two ? gb2 : (T)0;
-#pragma unroll
-        for (int q = 0; q < kVjpGroup; q++) {
-            if (q >= npg) break;
-            const double* d = dtab + (size_t)(p0 + q) * D_STRIDE;
-            const DConst<T> k = load_dconst<T>(d);
-            T d1, d2a, d2b;
-            if constexpr (sizeof(T) == 8) {
-                d1 = node_coord(g.x0, i, g.h) - d[D_XC];
-                d2a = node_coord(g.y0, j, g.h) - d[D_YC];
-                d2b = node_coord(g.y0, j + 1, g.h) - d[D_YC];
-            } else {
-                // offsets from the node-unit split of the centre, as in the FP32 field
-                d1 = (((float)i - (float)d[D_CXH]) - (float)d[D_CXL]) * ihf;
-                d2a = (((float)j - (float)d[D_CYH]) - (float)d[D_CYL]) * ihf;
-                d2b = (((float)(j + 1) - (float)d[D_CYH]) - (float)d[D_CYL]) * ihf;
-            }
-            vjp_pair<T>(k, d1, d2a, ga1, ga2, d1, d2b, gb1, gb2, acc[q]);
-        }
+    for (int r = 0; r < R; r++) {
+        const bool in = col && jb + r < g.ny;
+        const size_t n = in ? (size_t)(jb + r) * g.nx + ic : 0;
+        g1[r] = in ? (T)gx[n] : (T)0;
+        g2[r] = in ? (T)gy[n] : (T)0;
     }
+    const float ihf = (float)g.h;
+    for (int q = 0; q < npg; q++) {
+        const double* d = dtab + (size_t)(p0 + q) * D_STRIDE;
+        const DConst<T> k = load_dconst<T>(d);
+        T d1, d2[R];
+        if constexpr (sizeof(T) == 8) {
+            d1 = node_coord(g.x0, i, g.h) - d[D_XC];
 #pragma unroll
-    for (int q = 0; q < kVjpGroup; q++)
+            for (int r = 0; r < R; r++) d2[r] = node_coord(g.y0, jb + r, g.h) - d[D_YC];
+        } else {
+            // offsets from the node-unit split of the centre, as in the FP32 field
+            d1 = (((float)i - (float)d[D_CXH]) - (float)d[D_CXL]) * ihf;
 #pragma unroll
-        for (int c = 0; c < 7; c++) {
-            const double v = wave_sum((double)acc[q][c]);
-            if (lane == 0) red[q * 7 + c][wave] = v;
+            for (int r = 0; r < R; r++) d2[r] = (((float)(jb + r) - (float)d[D_CYH]) - (float)d[D_CYL]) * ihf;
         }
+        T acc[7];
+#pragma unroll
+        for (int c = 0; c < 7; c++) acc[c] = (T)0;
+        if (k.sinf) {
+            if (k.a == (T)0)
+                vjp_rows<T, R, false, true>(k, d1, d2, g1, g2, acc);
+            else
+                vjp_rows<T, R, false, false>(k, d1, d2, g1, g2, acc);
+        } else {
+            if (k.a == (T)0)
+                vjp_rows<T, R, true, true>(k, d1, d2, g1, g2, acc);
+            else
+                vjp_rows<T, R, true, false>(k, d1, d2, g1, g2, acc);
+        }
+#pragma unroll
+        for (int c = 0; c < 7; c++) red[q * 7 + c][t] = acc[c];
+    }
+    __syncthreads();
+    if (t < npg * 7 * S) {
+        const int qc = t / S, r0 = (t - qc * S) * (256 / S);
+        double v = 0.0;
+        for (int k = 0; k < 256 / S; k++) v += (double)red[qc][r0 + k];
+        run[qc][t - qc * S] = v;
+    }
+    __syncthreads();
+    if (t < npg * 7) {
+        double v = 0.0;
+        for (int k = 0; k < S; k++) v += run[t][k];
+        tot[t] = v;
+    }
     __syncthreads();
     if (t < 7 * npg) {
         const int q = t / 7, c = t - 7 * q;
-        double sum[7];
-#pragma unroll
-        for (int r = 0; r < 7; r++) {
-            const double* v = red[q * 7 + r];
-            sum[r] = (v[0] + v[1]) + (v[2] + v[3]);
-        }
-        part[((size_t)c * np + p0 + q) * n_tiles + tile] = vjp_combine(dtab + (size_t)(p0 + q) * D_STRIDE, sum, c);
+        part[((size_t)c * np + p0 + q) * n_tiles + tile] =
+            vjp_combine(dtab + (size_t)(p0 + q) * D_STRIDE, tot + 7 * q, c);
     }
 }
 
@@ -484,9 +525,13 @@ __global__ void k_status(int* status, int v)
 
 static int vjp_tiles_x(const GridDesc& g) { return (g.nx + 63) / 64; }
 
-int vjp_chunks(const GridDesc& g) { return vjp_tiles_x(g) * ((g.ny + kVjpTileY - 1) / kVjpTileY); }
+// Tiles of 64 columns x 4 rows-per-wave rows.
+static int vjp_chunks(const GridDesc& g, int rows) { return vjp_tiles_x(g) * ((g.ny + 4 * rows - 1) / (4 * rows)); }
 
-size_t vjp_scratch(int np, const GridDesc& g) { return ((size_t)7 * vjp_chunks(g) + D_STRIDE) * (size_t)np * 8; }
+size_t vjp_scratch(int np, const GridDesc& g)
+{
+    return ((size_t)7 * vjp_chunks(g, kVjpMinRows) + D_STRIDE) * (size_t)np * 8;
+}
 
 hipError_t launch_vjp(const PotPtrs& pot, const GridDesc& g, bool fp32, const double* gx, const double* gy,
                       double* scratch, double* grad, int* status, const KernelEvents* ev, hipStream_t s)
@@ -495,13 +540,15 @@ hipError_t launch_vjp(const PotPtrs& pot, const GridDesc& g, bool fp32, const do
         if (status) k_status<<<1, 64, 0, s>>>(status, kStatusOk);
         return hipGetLastError();
     }
-    const int nc = vjp_chunks(g), tx = vjp_tiles_x(g);
+    const int rows = fp32 ? VjpCfg<float>::rows : VjpCfg<double>::rows;
+    const int group = fp32 ? VjpCfg<float>::group : VjpCfg<double>::group;
+    const int nc = vjp_chunks(g, rows), tx = vjp_tiles_x(g);
     double* dtab = scratch;
     double* part = scratch + (size_t)D_STRIDE * pot.n;
     k_vjp_prep<<<(unsigned)((pot.n + 63) / 64), 64, 0, s>>>(pot, g, dtab, status);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const long long nb = (long long)nc * ((pot.n + kVjpGroup - 1) / kVjpGroup);
+    const long long nb = (long long)nc * ((pot.n + group - 1) / group);
     e = fp32 ? launch_ev(ev, k_vjp<float>, dim3((unsigned)nb), dim3(256), s, (const double*)dtab, pot.n, g, gx, gy,
                          tx, nc, part)
              : launch_ev(ev, k_vjp<double>, dim3((unsigned)nb), dim3(256), s, (const double*)dtab, pot.n, g, gx, gy,

@@ -163,7 +163,6 @@ struct SrcState {
     int pad;
 };
 
-int vjp_chunks(const GridDesc& g);
 size_t vjp_scratch(int np, const GridDesc& g);  // bytes of device scratch of launch_vjp
 hipError_t launch_vjp(const PotPtrs& pot, const GridDesc& g, bool fp32, const double* gx, const double* gy,
                       double* scratch, double* grad, int* status, const KernelEvents* ev, hipStream_t s);
