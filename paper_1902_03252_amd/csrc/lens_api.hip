@@ -862,7 +862,7 @@ int batch_plan(lens_ctx* c, int n_samples, const int32_t* pot_off, const lens_gr
     }
     int tx, ty;
     tile_dims(shape, tx, ty);
-    const int seg_nodes = 256 * (fp32 ? npl : 1);
+    const int seg_nodes = 256 * (fp32 ? field_cols(npl) : 1), seg_rows = fp32 ? field_rows(npl) : 1;
     const long long elem = fp32 ? 8 : 16;  // two planes
     const long long budget = batch_field_budget();
     int s0 = 0;
@@ -922,8 +922,9 @@ int batch_plan(lens_ctx* c, int n_samples, const int32_t* pot_off, const lens_gr
         for (int k = 0; k < n; k++) {
             const lens_grid& g = grids[s0 + perm[k]];
             h_perm[k] = perm[k];
-            h_fo[k + 1] = h_fo[k] + (long long)g.ny * ((g.nx + seg_nodes - 1) / seg_nodes);
-            h_to[k + 1] = h_to[k] + (long long)((g.nx - 2) / tx + 1) * ((g.ny - 2) / ty + 1);
+            h_fo[k + 1] = h_fo[k] + (long long)((g.ny + seg_rows - 1) / seg_rows) * ((g.nx + seg_nodes - 1) / seg_nodes);
+            // triangle stage: one item per (tile row, block of 64 tile columns)
+            h_to[k + 1] = h_to[k] + (long long)(((g.nx - 2) / tx + 1 + 63) / 64) * ((g.ny - 2) / ty + 1);
         }
         ch.n_nodes = node;
         ch.n_fitems = h_fo[n];
@@ -981,8 +982,7 @@ extern "C" int lens_image_chi2_batched(lens_ctx* ctx, const lens_potentials* all
     if (opts->prec == LENS_MIXED && (opts->fb_mode < 0 || opts->fb_mode > 1)) return LENS_ERR_INVALID;
     if (opts->prec == LENS_MIXED && opts->fb_mode == 1 && !(opts->fb_tau >= 0.0 && is_fin(opts->fb_tau)))
         return LENS_ERR_INVALID;
-    if (!(opts->field_npl == 0 || opts->field_npl == 1 || opts->field_npl == 2 || opts->field_npl == 4) ||
-        opts->tile < 0 || opts->tile > 4)
+    if (!(opts->field_npl == 0 || bfield_code_ok(opts->field_npl)) || opts->tile < 0 || opts->tile > 4)
         return LENS_ERR_INVALID;
     if (pot_off[0] != 0 || pot_off[n_samples] != all->n) return LENS_ERR_INVALID;
     for (int i = 0; i < n_samples; i++) {
@@ -996,7 +996,7 @@ extern "C" int lens_image_chi2_batched(lens_ctx* ctx, const lens_potentials* all
     for (int i = 0; i < n_samples; i++) side = std::max(side, std::max(grids[i].nx, grids[i].ny));
     resolve_tuned(ctx, opts->prec, 1, side, ((long long)all->n + n_samples - 1) / n_samples, shape, npl);
     if (!shape) shape = 1;
-    npl = mixed ? (npl ? npl : 2) : 1;
+    npl = mixed ? (npl ? npl : 0x41) : 1;  // FP32 field: 1 column x 4 rows per thread (measured fastest)
     PlanEntry* plan = nullptr;
     int rc = batch_plan(ctx, n_samples, pot_off, grids, npl, shape, mixed, stream, &plan);
     if (rc) return rc;

@@ -144,43 +144,49 @@ __global__ __launch_bounds__(256) void k_bmap(BatchPlan bp, int* __restrict__ fm
 
 // ============================================================== field
 
-// One workgroup per (sample, row segment of 256*NPL nodes); the map gives the
-// sample (heaviest samples first).  Same inner loop as the single-evaluation
-// FP32 field, and the same tile range partials (per sample).
-template <int NPL>
+// One workgroup per (sample, block of NR rows, row segment of 256*NPL nodes);
+// the map gives the sample (heaviest samples first).  Same inner loop as the
+// single-evaluation FP32 field (NPL nodes in each of NR rows per thread), and
+// the same tile range partials (per sample).
+template <int NPL, int NR>
 __global__ __launch_bounds__(256) void k_bfield32(BatchPlan bp, const int* __restrict__ fmap,
                                                   const float* __restrict__ tab32, float* __restrict__ fx,
                                                   float* __restrict__ fy, float* __restrict__ rr)
 {
+    __shared__ float4 srow[NR * 256];
     const long long item = blockIdx.x;
     const int k = fmap[item];
     const int s = bp.perm[k];
     const GridDesc g = bp.grid[s];
     const int segs = (g.nx + 256 * NPL - 1) / (256 * NPL);
     const long long local = item - bp.fitem_off[k];
-    const int j = (int)(local / segs), seg = (int)(local % segs);
+    const int j0 = (int)(local / segs) * NR, seg = (int)(local % segs);
     const int i0 = (seg * 256 + threadIdx.x) * NPL;
     const int p0 = bp.pot_off[0];
     const float* tab = tab32 + (size_t)(bp.pot_off[s] - p0) * T32_STRIDE;
     const int np = bp.pot_off[s + 1] - bp.pot_off[s];
-    const float fj = (float)j;
-    float fi[NPL], sx[NPL], sy[NPL];
+    float fi[NPL], sx[NR * NPL], sy[NR * NPL];
 #pragma unroll
-    for (int q = 0; q < NPL; q++) {
-        fi[q] = (float)(i0 + q);
+    for (int q = 0; q < NPL; q++) fi[q] = (float)(i0 + q);
+#pragma unroll
+    for (int q = 0; q < NR * NPL; q++) {
         sx[q] = 0.0f;
         sy[q] = 0.0f;
     }
-    __shared__ float4 srow[256];
-    field32_all_wg<NPL>(tab, np, fj, fi, sx, sy, srow);
+    field32_all_wg<NPL, NR>(tab, np, (float)j0, fi, sx, sy, srow);
     const int tiles_x = (g.nx - 2) / (1 << bp.tx_shift) + 1;
-    tile_partials<float, NPL>(sx, sy, i0, j, g.nx, bp.tx_shift, tiles_x, rr + bp.rr_off[s]);
-    const size_t row = (size_t)bp.node_off[s] + (size_t)j * g.nx;
 #pragma unroll
-    for (int q = 0; q < NPL; q++) {
-        if (i0 + q < g.nx) {
-            fx[row + i0 + q] = sx[q];
-            fy[row + i0 + q] = sy[q];
+    for (int r = 0; r < NR; r++) {
+        const int j = j0 + r;
+        if (j >= g.ny) break;  // uniform over the workgroup
+        tile_partials<float, NPL>(sx + r * NPL, sy + r * NPL, i0, j, g.nx, bp.tx_shift, tiles_x, rr + bp.rr_off[s]);
+        const size_t row = (size_t)bp.node_off[s] + (size_t)j * g.nx;
+#pragma unroll
+        for (int q = 0; q < NPL; q++) {
+            if (i0 + q < g.nx) {
+                fx[row + i0 + q] = sx[r * NPL + q];
+                fy[row + i0 + q] = sy[r * NPL + q];
+            }
         }
     }
 }
@@ -213,12 +219,44 @@ __global__ __launch_bounds__(256) void k_bfield64(BatchPlan bp, const int* __res
 
 // ============================================================== triangles
 
-// One wave per (sample, tile) work item (heaviest samples first): the tile's
-// deflection range from the sample's range partials culls the systems (one
-// per lane); a tile that a system survives is staged in the wave's own LDS
-// tile and its cells tested for each surviving system.  Hits go to the
-// sample's own list (system << 32 | triangle id), undecided tests to the batch
-// list (sample << 44 | system << 31 | triangle id).
+// Deflection range of one tile per lane (the lane's own tile T) from the
+// sample's range partials: the same minimum and maximum over the tile's node
+// rows and halo column as tile_range_wave.
+template <class S, typename V>
+__device__ __forceinline__ void tile_range_lane(const V* __restrict__ rr, int tiles_x, const Tile& T, double* rng)
+{
+    const int col = T.ci0 / S::TX;
+    V mnx = V(INFINITY), mxx = V(-INFINITY), mny = V(INFINITY), mxy = V(-INFINITY);
+    for (int r = 0; r <= T.ncy; r++) {
+        const V* q = rr + ((size_t)(T.cj0 + r) * (tiles_x + 1) + col) * kRR;
+        mnx = fmin(mnx, q[0]);
+        mxx = fmax(mxx, q[1]);
+        mny = fmin(mny, q[2]);
+        mxy = fmax(mxy, q[3]);
+        if (T.ncx == S::TX) {  // halo column: first node of the next column group
+            const V vx = q[kRR + 4], vy = q[kRR + 5];
+            mnx = fmin(mnx, vx);
+            mxx = fmax(mxx, vx);
+            mny = fmin(mny, vy);
+            mxy = fmax(mxy, vy);
+        }
+    }
+    rng[0] = mnx;
+    rng[1] = mxx;
+    rng[2] = mny;
+    rng[3] = mxy;
+}
+
+// One wave per (sample, tile row, block of 64 tile columns) work item,
+// heaviest samples first; lane = tile column.  Each lane bounds its own
+// tile's source-plane vertices from the range partials (loads of consecutive
+// tiles are consecutive) and tests every system's barycentre against that
+// box (system rows are wave-uniform), keeping a mask of the passing systems.
+// The wave then stages each tile with a passing system in its own LDS tile
+// (lane order) and tests its cells for those systems, all lanes over the
+// cells.  Hits go to the sample's own list (system << 32 | triangle id),
+// undecided tests to the batch list (sample << 44 | system << 31 | triangle
+// id).
 template <class S, typename V>
 __global__ __launch_bounds__(256) void k_btri(BatchPlan bp, const int* __restrict__ tmap, long long n_items,
                                               int nsys, const double* __restrict__ sysrow, const V* __restrict__ fx,
@@ -231,56 +269,64 @@ __global__ __launch_bounds__(256) void k_btri(BatchPlan bp, const int* __restric
     __shared__ unsigned sp[4][2];
     const int wave = threadIdx.x >> 6, lane = lane_id();
     const long long item = (long long)blockIdx.x * 4 + wave;
-    unsigned ntile = 0, nbbox = 0;
+    unsigned npair = 0, nbbox = 0;  // per lane: passing (tile, system) pairs of its tile; bbox passes
     if (item < n_items) {
         const int k = tmap[item];
         const int s = bp.perm[k];
         const GridDesc g = bp.grid[s];
         const int tiles_x = (g.nx - 2) / S::TX + 1;
-        const Tile T = tile_of<S>(g, tiles_x, (int)(item - bp.titem_off[k]));
-        double rng[4];
-        tile_range_wave<S, V>(rr + bp.rr_off[s], tiles_x, T, rng);
+        const int blocks_x = (tiles_x + 63) / 64;
+        const int local = (int)(item - bp.titem_off[k]);
+        const int band = local / blocks_x, cb = local - band * blocks_x;
+        const int col = cb * 64 + lane;
+        const bool act = col < tiles_x;
+        const Tile T = tile_of<S>(g, tiles_x, band * tiles_x + (act ? col : 0));
+        double rng[4] = {0.0, 0.0, 0.0, 0.0};
+        if (act) tile_range_lane<S, V>(rr + bp.rr_off[s], tiles_x, T, rng);
         const double* rows = sysrow + (size_t)s * nsys * SYS_STRIDE;
-        bool staged = false;
+        const V* sfx = fx + bp.node_off[s];
+        const V* sfy = fy + bp.node_off[s];
         for (int sb = 0; sb < nsys; sb += 64) {
-            const int sl = sb + lane;
-            double r = 0.0, eb = 0.0, bx = 0.0, by = 0.0;
-            if (sl < nsys) {
-                const double* row = rows + (size_t)sl * SYS_STRIDE;
-                r = row[SYS_R];
-                eb = row[SYS_EB];
-                bx = row[SYS_BX];
-                by = row[SYS_BY];
+            const int ns = min(64, nsys - sb);
+            unsigned long long mask = 0;
+            for (int c = 0; c < ns; c++) {
+                const double* row = rows + (size_t)(sb + c) * SYS_STRIDE;  // wave-uniform
+                const double eb = sizeof(V) == 4 ? row[SYS_EB] : 1e-9;
+                if (act && tile_box_contains(g, T, rng, row[SYS_R], eb, row[SYS_BX], row[SYS_BY]))
+                    mask |= 1ull << c;
             }
-            const bool pass = sl < nsys && tile_box_contains(g, T, rng, r, sizeof(V) == 4 ? eb : 1e-9, bx, by);
-            unsigned long long m = __ballot(pass);
-            ntile += (unsigned)__popcll(m);
-            if (m != 0 && !staged) {
-                stage_tile_wave<S, V>(fx + bp.node_off[s], fy + bp.node_off[s], g, T, sx[wave], sy[wave]);
-                staged = true;
-            }
-            while (m) {
-                const int c = __ffsll((long long)m) - 1;
-                m &= m - 1;
-                const unsigned sys = (unsigned)(sb + c);
-                if constexpr (sizeof(V) == 4) {
+            npair += (unsigned)__popcll(mask);
+            unsigned long long tiles = __ballot(mask != 0);
+            while (tiles) {
+                const int l = __ffsll((long long)tiles) - 1;
+                tiles &= tiles - 1;
+                unsigned long long m = __shfl(mask, l, 64);
+                const Tile Tl = tile_of<S>(g, tiles_x, band * tiles_x + cb * 64 + l);
+                stage_tile_wave<S, V>(sfx, sfy, g, Tl, sx[wave], sy[wave]);
+                while (m) {
+                    const int c = __ffsll((long long)m) - 1;
+                    m &= m - 1;
+                    const unsigned sys = (unsigned)(sb + c);
                     const double* row = rows + (size_t)sys * SYS_STRIDE;  // wave-uniform
-                    const float fr[6] = {(float)row[SYS_R],   (float)row[SYS_EB],  (float)row[SYS_BXH],
-                                         (float)row[SYS_BXL], (float)row[SYS_BYH], (float)row[SYS_BYL]};
-                    tri32_system<S, 64>(g, T, sx[wave], sy[wave], fr, ((unsigned long long)sys << 32),
-                                        ((unsigned long long)s << 44) | ((unsigned long long)sys << 31), mode,
-                                        (float)(tau * g.h * g.h),
-                                        &bs.n_hits[s], hits + (size_t)s * hcap, hcap, bs.n_flags, flags, flag_cap,
-                                        nbbox, lane);
-                } else {
-                    tri64_system<S, 64>(g, T, sx[wave], sy[wave], bcast(r, c), bcast(bx, c), bcast(by, c),
-                                        ((unsigned long long)sys << 32), &bs.n_hits[s], hits + (size_t)s * hcap,
-                                        hcap, nbbox, lane);
+                    if constexpr (sizeof(V) == 4) {
+                        const float fr[6] = {(float)row[SYS_R],   (float)row[SYS_EB],  (float)row[SYS_BXH],
+                                             (float)row[SYS_BXL], (float)row[SYS_BYH], (float)row[SYS_BYL]};
+                        tri32_system<S, 64>(g, Tl, sx[wave], sy[wave], fr, ((unsigned long long)sys << 32),
+                                            ((unsigned long long)s << 44) | ((unsigned long long)sys << 31), mode,
+                                            (float)(tau * g.h * g.h), &bs.n_hits[s], hits + (size_t)s * hcap, hcap,
+                                            bs.n_flags, flags, flag_cap, nbbox, lane);
+                    } else {
+                        tri64_system<S, 64>(g, Tl, sx[wave], sy[wave], row[SYS_R], row[SYS_BX], row[SYS_BY],
+                                            ((unsigned long long)sys << 32), &bs.n_hits[s], hits + (size_t)s * hcap,
+                                            hcap, nbbox, lane);
+                    }
                 }
             }
         }
     }
-    write_part_sum(part, blockIdx.x, ntile, nbbox, sp);
+    // the pairs as a wave-uniform count, as write_part_sum takes them
+    for (int m = 32; m >= 1; m >>= 1) npair += __shfl_xor(npair, m, 64);
+    write_part_sum(part, blockIdx.x, npair, nbbox, sp);
 }
 
 // ============================================================== positions and fallback
@@ -525,9 +571,12 @@ hipError_t launch_bfield32(const BatchPlan& bp, const int* fmap, long long n_ite
 {
     const dim3 grid((unsigned)n_items), block(256);
     switch (npl) {
-    case 1: return launch_ev(ev, k_bfield32<1>, grid, block, s, bp, fmap, tab32, fx, fy, rr);
-    case 4: return launch_ev(ev, k_bfield32<4>, grid, block, s, bp, fmap, tab32, fx, fy, rr);
-    default: return launch_ev(ev, k_bfield32<2>, grid, block, s, bp, fmap, tab32, fx, fy, rr);
+    case 0x01: return launch_ev(ev, k_bfield32<1, 1>, grid, block, s, bp, fmap, tab32, fx, fy, rr);
+    case 0x04: return launch_ev(ev, k_bfield32<4, 1>, grid, block, s, bp, fmap, tab32, fx, fy, rr);
+    case 0x21: return launch_ev(ev, k_bfield32<1, 2>, grid, block, s, bp, fmap, tab32, fx, fy, rr);
+    case 0x22: return launch_ev(ev, k_bfield32<2, 2>, grid, block, s, bp, fmap, tab32, fx, fy, rr);
+    case 0x41: return launch_ev(ev, k_bfield32<1, 4>, grid, block, s, bp, fmap, tab32, fx, fy, rr);
+    default: return launch_ev(ev, k_bfield32<2, 1>, grid, block, s, bp, fmap, tab32, fx, fy, rr);
     }
 }
 

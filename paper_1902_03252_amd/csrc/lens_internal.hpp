@@ -56,7 +56,7 @@ struct BatchPlan {
     const GridDesc* grid;         // [n]
     const int* perm;              // [n] plan position -> sample (heaviest first)
     const long long* fitem_off;   // [n+1] field work items, in plan order
-    const long long* titem_off;   // [n+1] triangle-stage tiles, in plan order
+    const long long* titem_off;   // [n+1] triangle-stage items (tile row x 64 tile columns), in plan order
     const long long* node_off;    // [n] offset of each sample's field (nodes)
     const long long* rr_off;      // [n] offset of each sample's tile range partials (values)
     int tx_shift;                 // log2 of the tile width in cells
@@ -100,6 +100,12 @@ inline bool field_code_ok(int code)
 {
     return code == 1 || code == 2 || code == 4 || code == 8 || code == 0x21 || code == 0x22 || code == 0x24 ||
            code == 0x41 || code == 0x42;
+}
+// Layouts of the batched FP32 field (one workgroup per (sample, block of rows,
+// row segment)).
+inline bool bfield_code_ok(int code)
+{
+    return code == 1 || code == 2 || code == 4 || code == 0x21 || code == 0x22 || code == 0x41;
 }
 
 hipError_t launch_field32h(const float* tab32, int np, const GridDesc& g, float* ax, float* ay, int npl, float* rr,

@@ -65,7 +65,7 @@ static void record(TuneTable* t, const TuneEntry& v)
 
 static bool valid_entry(const TuneEntry& e)
 {
-    const bool npl_ok = e.npl == 0 || (e.batched ? (e.npl == 1 || e.npl == 2 || e.npl == 4) : field_code_ok(e.npl));
+    const bool npl_ok = e.npl == 0 || (e.batched ? bfield_code_ok(e.npl) : field_code_ok(e.npl));
     return (e.prec == LENS_FP64 || e.prec == LENS_MIXED) && (e.batched == 0 || e.batched == 1) && e.n_log2 >= 0 &&
            e.n_log2 <= 62 && e.p_log2 >= 0 && e.p_log2 <= 62 && e.tile >= 1 && e.tile <= 4 && npl_ok;
 }
@@ -367,8 +367,9 @@ int tune(lens_ctx* ctx, int prec, int batched, int n_log2, int p_log2, int defau
     trial(best_tile, best_npl);
     if (mixed) {  // FP32 field layouts: nodes of one row, then blocks of rows x columns
         const int npls[9] = {1, 2, 4, 8, 0x21, 0x22, 0x24, 0x41, 0x42};
-        for (int k = 0; k < (batched ? 3 : 9); k++)
-            if (npls[k] != default_npl) trial(1, npls[k]);
+        for (int k = 0; k < 9; k++)
+            if (npls[k] != default_npl && (batched ? bfield_code_ok(npls[k]) : field_code_ok(npls[k])))
+                trial(1, npls[k]);
     }
     const int npl = best_npl;
     for (int tile = 2; tile <= 4; tile++) trial(tile, npl);
@@ -432,7 +433,7 @@ int lens_autotune_chi2_batched(lens_ctx* ctx, const lens_potentials* all, int32_
             o.field_npl = npl;
             return lens_image_chi2_batched(ctx, all, n_samples, pot_off, grids, obs, &o, out, stream);
         };
-        return tune(ctx, opts->prec, 1, tune_log2(side), tune_log2(mean_p), 2, reps, stream, run, tile, field_npl);
+        return tune(ctx, opts->prec, 1, tune_log2(side), tune_log2(mean_p), 0x41, reps, stream, run, tile, field_npl);
     } catch (...) {
         return LENS_ERR_DEVICE;
     }
