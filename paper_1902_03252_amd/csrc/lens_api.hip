@@ -583,10 +583,11 @@ int chi2_plan(lens_ctx* ctx, const lens_potentials* pot, const lens_grid* grid, 
     tile_dims(pl.shape, tile_x, tile_y);
     pl.tx_shift = tile_x == 64 ? 6 : 5;
     tri_tiles(pl.g, pl.shape, &pl.tiles_x);
-    cull_shape(pl.g, pl.shape, &pl.n_cull, &pl.tpw);
+    int sc, nch;
+    cull_shape(pl.g, pl.shape, pl.o.n_sys, &pl.n_cull, &pl.tpw, &sc, &nch);
     pl.n_parts = pl.n_cull + kPairBlocks;
-    // each culling workgroup owns room for every pair of its tiles
-    pl.region = 4ll * pl.tpw * pl.o.n_sys;
+    // each culling wave owns room for every pair of its tiles and systems
+    pl.region = 64ll * pl.tpw * sc;
     if (pl.region * pl.n_cull > (1ll << 28)) return LENS_ERR_CAPACITY;  // 2 GiB of pair keys
     pl.vbytes = pl.mixed ? 4 : 8;
     pl.flag_cap = pl.mixed ? flag_cap : 0;

@@ -219,34 +219,6 @@ __global__ __launch_bounds__(256) void k_bfield64(BatchPlan bp, const int* __res
 
 // ============================================================== triangles
 
-// Deflection range of one tile per lane (the lane's own tile T) from the
-// sample's range partials: the same minimum and maximum over the tile's node
-// rows and halo column as tile_range_wave.
-template <class S, typename V>
-__device__ __forceinline__ void tile_range_lane(const V* __restrict__ rr, int tiles_x, const Tile& T, double* rng)
-{
-    const int col = T.ci0 / S::TX;
-    V mnx = V(INFINITY), mxx = V(-INFINITY), mny = V(INFINITY), mxy = V(-INFINITY);
-    for (int r = 0; r <= T.ncy; r++) {
-        const V* q = rr + ((size_t)(T.cj0 + r) * (tiles_x + 1) + col) * kRR;
-        mnx = fmin(mnx, q[0]);
-        mxx = fmax(mxx, q[1]);
-        mny = fmin(mny, q[2]);
-        mxy = fmax(mxy, q[3]);
-        if (T.ncx == S::TX) {  // halo column: first node of the next column group
-            const V vx = q[kRR + 4], vy = q[kRR + 5];
-            mnx = fmin(mnx, vx);
-            mxx = fmax(mxx, vx);
-            mny = fmin(mny, vy);
-            mxy = fmax(mxy, vy);
-        }
-    }
-    rng[0] = mnx;
-    rng[1] = mxx;
-    rng[2] = mny;
-    rng[3] = mxy;
-}
-
 // One wave per (sample, tile row, block of 64 tile columns) work item,
 // heaviest samples first; lane = tile column.  Each lane bounds its own
 // tile's source-plane vertices from the range partials (loads of consecutive

@@ -122,10 +122,10 @@ hipError_t launch_field64(const double* tab64, int np, const GridDesc& g, double
                           hipStream_t s);
 constexpr int kRR = 8;                     // values per (row, column group) of the tile range partials
 constexpr int kPairBlocks = 512;           // persistent workgroups of the pair kernel
-constexpr int kMaxCull = 1024;             // culling workgroups (4 tiles per round)
+constexpr int kMaxCull = 1024;             // culling waves (64 tiles per round)
 void tile_dims(int shape, int& tx, int& ty);
 long long tri_tiles(const GridDesc& g, int shape, int* tiles_x);
-void cull_shape(const GridDesc& g, int shape, int* n_cull, int* tpw);
+void cull_shape(const GridDesc& g, int shape, int nsys, int* n_cull, int* tpw, int* sc, int* n_chunks);
 hipError_t launch_cull(bool fp32, const void* rr, const GridDesc& g, int nsys,
                        const double* sysrow, unsigned long long* pairs, long long region, unsigned* counts,
                        unsigned* part, int shape, hipStream_t s);

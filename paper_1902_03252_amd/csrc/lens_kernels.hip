@@ -21,6 +21,7 @@
 // 65535 rows of workgroups.
 #include "lens_path.hpp"
 
+#include <algorithm>
 #include <type_traits>
 
 namespace lens {
@@ -391,61 +392,63 @@ __global__ __launch_bounds__(256) void k_field64h(const double* __restrict__ tab
 
 // ============================================================== triangle stage
 
-// Culling, one wave per tile of S::TX x S::TY cells (workgroups of 4 waves,
-// `tpw` rounds of tiles): the tile's deflection range (the field kernel's row
-// partials plus the halo column) bounds every source-plane vertex of the tile
-// by the box [theta_min - r alpha_max, theta_max - r alpha_min], widened by
-// the FP32 bound E_B (mixed path) or 1e-9" (FP64 path); every system whose
-// barycentre lies in the box (systems over the lanes) gives a (tile, system)
-// pair.  The workgroup compacts its pairs into its own region through LDS and
-// writes its count to counts[blockIdx.x]: no atomic is shared between
-// workgroups.
+// Culling, one wave per (block of 64 consecutive tiles of S::TX x S::TY
+// cells, chunk of `sc` systems) with `tpw` blocks per wave, lane = tile: each
+// lane bounds its tile's source-plane vertices by the box [theta_min -
+// r alpha_max, theta_max - r alpha_min] from the field kernel's row partials
+// plus the halo column (consecutive tiles read consecutive partials), widened
+// by the FP32 bound E_B (mixed path) or 1e-9" (FP64 path), and tests the
+// barycentre of every system of its chunk (the chunk's rows loaded at once,
+// lane = system, then broadcast); every passing (tile, system) pair is
+// appended to the wave's own region (ballot and lane prefix) and the wave's
+// count written to counts[wave]: no atomic, no barrier.  Small grids split the
+// systems over more waves, large grids give a wave several blocks.
 template <class S, typename V>
 __global__ __launch_bounds__(256) void k_cull(const V* __restrict__ rr, GridDesc g, int tiles_x, int n_tiles,
-                                              int tpw, int nsys, const double* __restrict__ sysrow,
-                                              unsigned long long* __restrict__ pairs, long long region,
-                                              unsigned* __restrict__ counts, unsigned* __restrict__ part)
+                                              int tpw, int sc, int n_chunks, int n_cull, int nsys,
+                                              const double* __restrict__ sysrow, unsigned long long* __restrict__ pairs,
+                                              long long region, unsigned* __restrict__ counts,
+                                              unsigned* __restrict__ part)
 {
-    __shared__ unsigned swc[4];
-    const int lane = lane_id(), wave = threadIdx.x >> 6;
-    unsigned long long* out = pairs + (size_t)blockIdx.x * region;
-    unsigned cnt = 0;  // pairs of the workgroup so far (uniform)
+    const int lane = lane_id();
+    const int w = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    if (w >= n_cull) return;  // the whole wave
+    const int blk = w / n_chunks, s0 = (w - blk * n_chunks) * sc;
+    const int ns = min(sc, nsys - s0);  // <= 64
+    // the chunk's system rows, lane = system
+    double r = 0.0, eb = 0.0, bx = 0.0, by = 0.0;
+    if (lane < ns) {
+        const double* row = sysrow + (size_t)(s0 + lane) * SYS_STRIDE;
+        r = row[SYS_R];
+        eb = sizeof(V) == 4 ? row[SYS_EB] : 1e-9;
+        bx = row[SYS_BX];
+        by = row[SYS_BY];
+    }
+    unsigned long long* out = pairs + (size_t)w * region;
+    unsigned cnt = 0;  // pairs of the wave so far (uniform)
     for (int k = 0; k < tpw; k++) {
-        const int tile = (blockIdx.x * tpw + k) * 4 + wave;
+        const int tile = (blk * tpw + k) * 64 + lane;
         const bool act = tile < n_tiles;
         Tile T = {0, 0, 0, 0};
         double rng[4] = {0.0, 0.0, 0.0, 0.0};
         if (act) {
             T = tile_of<S>(g, tiles_x, tile);
-            tile_range_wave<S, V>(rr, tiles_x, T, rng);
+            tile_range_lane<S, V>(rr, tiles_x, T, rng);
         }
-        for (int sb = 0; sb < nsys; sb += 64) {
-            const int s = sb + lane;
-            bool pass = false;
-            if (act && s < nsys) {
-                const double* row = sysrow + (size_t)s * SYS_STRIDE;
-                const double eb = sizeof(V) == 4 ? row[SYS_EB] : 1e-9;
-                pass = tile_box_contains(g, T, rng, row[SYS_R], eb, row[SYS_BX], row[SYS_BY]);
-            }
+        for (int c = 0; c < ns; c++) {
+            const bool pass =
+                act && tile_box_contains(g, T, rng, bcast(r, c), bcast(eb, c), bcast(bx, c), bcast(by, c));
             const unsigned long long m = __ballot(pass);
-            if (lane == 0) swc[wave] = (unsigned)__popcll(m);
-            __syncthreads();
-            unsigned before = 0, total = 0;
-            for (int w = 0; w < 4; w++) {
-                before += w < wave ? swc[w] : 0u;
-                total += swc[w];
-            }
             const int off =
                 __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-            if (pass) out[cnt + before + off] = ((unsigned long long)(unsigned)tile << 32) | (unsigned)s;
-            cnt += total;
-            __syncthreads();
+            if (pass) out[cnt + off] = ((unsigned long long)(unsigned)tile << 32) | (unsigned)(s0 + c);
+            cnt += (unsigned)__popcll(m);
         }
     }
-    if (threadIdx.x == 0) {
-        counts[blockIdx.x] = cnt;
-        part[2 * blockIdx.x + 0] = cnt;
-        part[2 * blockIdx.x + 1] = 0;
+    if (lane == 0) {
+        counts[w] = cnt;
+        part[2 * w + 0] = cnt;
+        part[2 * w + 1] = 0;
     }
 }
 
@@ -1083,20 +1086,31 @@ long long tri_tiles(const GridDesc& g, int shape, int* tiles_x)
     return (long long)*tiles_x * cdiv(g.ny - 1, ty);
 }
 
-// Culling workgroups (4 waves, one tile per wave and round) and rounds for a
-// grid: at most kMaxCull workgroups.
-void cull_shape(const GridDesc& g, int shape, int* n_cull, int* tpw)
+// Culling waves for a grid and nsys systems, at most kMaxCull: blocks of 64
+// tiles times chunks of at most 64 systems.  Large grids give a wave several
+// blocks (tpw) until blocks x the necessary chunks fit; small grids split the
+// systems over more waves while that keeps at least 4 systems per wave.  Each
+// wave's pair region holds 64 * tpw * sc pairs.
+void cull_shape(const GridDesc& g, int shape, int nsys, int* n_cull, int* tpw, int* sc, int* n_chunks)
 {
     int tiles_x;
     const long long n_tiles = tri_tiles(g, shape, &tiles_x);
-    long long nc = cdiv(n_tiles, 4);
+    const long long ns = nsys > 0 ? nsys : 1;
+    const long long chmin = (ns + 63) / 64;
+    const long long budget = std::max(1ll, (long long)kMaxCull / chmin);
+    long long nb = cdiv(n_tiles, 64);
     int k = 1;
-    while (nc > kMaxCull) {
+    while (nb > budget) {
         k *= 2;
-        nc = cdiv(n_tiles, 4ll * k);
+        nb = cdiv(n_tiles, 64ll * k);
     }
-    *n_cull = (int)nc;
+    long long ch = std::max(chmin, std::min((long long)kMaxCull / nb, std::max(chmin, ns / 4)));
+    const long long per = (ns + ch - 1) / ch;  // <= 64
+    ch = (ns + per - 1) / per;
     *tpw = k;
+    *sc = (int)per;
+    *n_chunks = (int)ch;
+    *n_cull = (int)(nb * ch);
 }
 
 hipError_t launch_cull(bool fp32, const void* rr, const GridDesc& g, int nsys,
@@ -1105,15 +1119,16 @@ hipError_t launch_cull(bool fp32, const void* rr, const GridDesc& g, int nsys,
 {
     return with_shape(shape, [&](auto sh) {
         using S = decltype(sh);
-        int tiles_x, nb, tpw;
+        int tiles_x, nw, tpw, sc, nch;
         const int n_tiles = (int)tri_tiles(g, shape, &tiles_x);
-        cull_shape(g, shape, &nb, &tpw);
+        cull_shape(g, shape, nsys, &nw, &tpw, &sc, &nch);
+        const unsigned nb = (unsigned)cdiv(nw, 4);
         if (fp32)
-            k_cull<S, float><<<nb, 256, 0, s>>>((const float*)rr, g, tiles_x, n_tiles, tpw, nsys, sysrow, pairs,
-                                                region, counts, part);
+            k_cull<S, float><<<nb, 256, 0, s>>>((const float*)rr, g, tiles_x, n_tiles, tpw, sc, nch, nw, nsys, sysrow,
+                                                pairs, region, counts, part);
         else
-            k_cull<S, double><<<nb, 256, 0, s>>>((const double*)rr, g, tiles_x, n_tiles, tpw, nsys, sysrow, pairs,
-                                                 region, counts, part);
+            k_cull<S, double><<<nb, 256, 0, s>>>((const double*)rr, g, tiles_x, n_tiles, tpw, sc, nch, nw, nsys,
+                                                 sysrow, pairs, region, counts, part);
         return hipGetLastError();
     });
 }

@@ -494,6 +494,35 @@ __device__ __forceinline__ void tile_range_wave(const V* __restrict__ rr, int ti
     rng[3] = mxy;
 }
 
+// Deflection range of one tile per lane (the lane's own tile T) from the
+// field kernel's row partials: the same minimum and maximum over the tile's node
+// rows and halo column as tile_range_wave.
+template <class S, typename V>
+__device__ __forceinline__ void tile_range_lane(const V* __restrict__ rr, int tiles_x, const Tile& T, double* rng)
+{
+    const int col = T.ci0 / S::TX;
+    const bool halo = T.ncx == S::TX;  // halo column: first node of the next column group
+    V mnx = V(INFINITY), mxx = V(-INFINITY), mny = V(INFINITY), mxy = V(-INFINITY);
+    // every row's loads issued at once, without branches: a fixed trip count
+    // with rows past the tile's last node row clamped to it (a repeated row
+    // leaves the minimum and maximum unchanged), and the halo record always
+    // loaded (it lies inside the partials, past the grid's last column group
+    // unwritten) and selected only for a full-width tile
+#pragma unroll
+    for (int r = 0; r <= S::TY; r++) {
+        const V* q = rr + ((size_t)(T.cj0 + min(r, T.ncy)) * (tiles_x + 1) + col) * kRR;
+        const V a0 = q[0], a1 = q[1], a2 = q[2], a3 = q[3], hx = q[kRR + 4], hy = q[kRR + 5];
+        mnx = fmin(mnx, halo ? fmin(a0, hx) : a0);
+        mxx = fmax(mxx, halo ? fmax(a1, hx) : a1);
+        mny = fmin(mny, halo ? fmin(a2, hy) : a2);
+        mxy = fmax(mxy, halo ? fmax(a3, hy) : a3);
+    }
+    rng[0] = mnx;
+    rng[1] = mxx;
+    rng[2] = mny;
+    rng[3] = mxy;
+}
+
 // Loads tile T's nodes (with the halo) into a wave-private LDS tile.
 template <class S, typename V>
 __device__ __forceinline__ void stage_tile_wave(const V* __restrict__ ax, const V* __restrict__ ay, const GridDesc& g,
