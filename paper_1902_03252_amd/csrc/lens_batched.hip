@@ -260,21 +260,44 @@ __global__ __launch_bounds__(256) void k_btri(BatchPlan bp, const int* __restric
         const V* sfy = fy + bp.node_off[s];
         for (int sb = 0; sb < nsys; sb += 64) {
             const int ns = min(64, nsys - sb);
+            // the chunk's system rows in one round of loads (lane = system), then broadcast
+            double lr = 0.0, leb = 0.0, lbx = 0.0, lby = 0.0;
+            if (lane < ns) {
+                const double* row = rows + (size_t)(sb + lane) * SYS_STRIDE;
+                lr = row[SYS_R];
+                leb = sizeof(V) == 4 ? row[SYS_EB] : 1e-9;
+                lbx = row[SYS_BX];
+                lby = row[SYS_BY];
+            }
             unsigned long long mask = 0;
             for (int c = 0; c < ns; c++) {
-                const double* row = rows + (size_t)(sb + c) * SYS_STRIDE;  // wave-uniform
-                const double eb = sizeof(V) == 4 ? row[SYS_EB] : 1e-9;
-                if (act && tile_box_contains(g, T, rng, row[SYS_R], eb, row[SYS_BX], row[SYS_BY]))
+                if (act && tile_box_contains(g, T, rng, bcast(lr, c), bcast(leb, c), bcast(lbx, c), bcast(lby, c)))
                     mask |= 1ull << c;
             }
             npair += (unsigned)__popcll(mask);
             unsigned long long tiles = __ballot(mask != 0);
+            // the passing tiles in lane order; for tiles of up to 40 bytes of
+            // nodes per lane the next tile's nodes are loaded into registers
+            // while the current one is tested
+            constexpr bool kPre = TileRegs<S, V>::K * (int)sizeof(V) <= 40;
+            int l = tiles ? __ffsll((long long)tiles) - 1 : 0;
+            TileRegs<S, V> nxt;
+            if (kPre && tiles)
+                fetch_tile_regs<S, V>(sfx, sfy, g, tile_of<S>(g, tiles_x, band * tiles_x + cb * 64 + l), nxt);
             while (tiles) {
-                const int l = __ffsll((long long)tiles) - 1;
                 tiles &= tiles - 1;
                 unsigned long long m = __shfl(mask, l, 64);
                 const Tile Tl = tile_of<S>(g, tiles_x, band * tiles_x + cb * 64 + l);
-                stage_tile_wave<S, V>(sfx, sfy, g, Tl, sx[wave], sy[wave]);
+                if constexpr (kPre) {
+                    store_tile_regs<S, V>(nxt, Tl, sx[wave], sy[wave]);
+                    if (tiles) {
+                        l = __ffsll((long long)tiles) - 1;
+                        fetch_tile_regs<S, V>(sfx, sfy, g, tile_of<S>(g, tiles_x, band * tiles_x + cb * 64 + l), nxt);
+                    }
+                } else {
+                    stage_tile_wave<S, V>(sfx, sfy, g, Tl, sx[wave], sy[wave]);
+                    if (tiles) l = __ffsll((long long)tiles) - 1;
+                }
                 while (m) {
                     const int c = __ffsll((long long)m) - 1;
                     m &= m - 1;
@@ -303,10 +326,15 @@ __global__ __launch_bounds__(256) void k_btri(BatchPlan bp, const int* __restric
 
 // ============================================================== positions and fallback
 
-// Workgroups [0, n): the FP64 position of every certain hit of sample
-// `blockIdx.x`, one wave per hit.  Workgroups beyond: persistent waves over
-// the batch's undecided tests, each decided exactly on FP64 vertices and, if a
-// hit, appended with its position to its sample's fallback list.
+// Workgroups [0, kBfbSub n): the FP64 position of every certain hit, one wave
+// per hit, kBfbSub workgroups per sample.  The kBfbFlagBlocks workgroups
+// beyond: persistent waves over the batch's undecided tests, each decided
+// exactly on FP64 vertices and, if a hit, appended with its position to its
+// sample's fallback list.  Each item is a chain of dependent steps (the three
+// vertices over the potentials, the wave reductions, the position), so the
+// launch spreads the items over many waves.
+constexpr int kBfbSub = 4;
+constexpr int kBfbFlagBlocks = 2048;
 __global__ __launch_bounds__(256) void k_bfbpos(BatchPlan bp, int nsys, const double* __restrict__ tab64,
                                                 const double* __restrict__ sysrow, BatchState bs, int hcap,
                                                 const unsigned long long* __restrict__ hits,
@@ -316,14 +344,14 @@ __global__ __launch_bounds__(256) void k_bfbpos(BatchPlan bp, int nsys, const do
 {
     const int p0 = bp.pot_off[0];
     const int wave = threadIdx.x >> 6;
-    if ((int)blockIdx.x < bp.n) {
-        const int s = blockIdx.x;
+    if ((int)blockIdx.x < bp.n * kBfbSub) {
+        const int s = blockIdx.x / kBfbSub, sub = blockIdx.x - s * kBfbSub;
         if (bs.status[s] != kStatusOk) return;
         const int nh = (int)min((unsigned long long)hcap, bs.n_hits[s]);
         const GridDesc g = bp.grid[s];
         const double* tab = tab64 + (size_t)(bp.pot_off[s] - p0) * T64_STRIDE;
         const int np = bp.pot_off[s + 1] - bp.pot_off[s];
-        for (int q = wave; q < nh; q += 4) {
+        for (int q = sub * 4 + wave; q < nh; q += 4 * kBfbSub) {
             const unsigned long long key = hits[(size_t)s * hcap + q];
             const int sys = (int)(key >> 32), tid = (int)(key & 0xffffffffu);
             const double* row = sysrow + ((size_t)s * nsys + sys) * SYS_STRIDE;
@@ -335,8 +363,8 @@ __global__ __launch_bounds__(256) void k_bfbpos(BatchPlan bp, int nsys, const do
         }
         return;
     }
-    const long long nwaves = (long long)(gridDim.x - bp.n) * 4;
-    const long long w0 = (long long)(blockIdx.x - bp.n) * 4 + wave;
+    const long long nwaves = (long long)(gridDim.x - bp.n * kBfbSub) * 4;
+    const long long w0 = (long long)(blockIdx.x - bp.n * kBfbSub) * 4 + wave;
     const long long nf = (long long)min((unsigned long long)flag_cap, *bs.n_flags);
     for (long long it = w0; it < nf; it += nwaves) {
         const unsigned long long key = flags[it];
@@ -593,7 +621,8 @@ hipError_t launch_bfbpos(const BatchPlan& bp, int nsys, const double* tab64, con
                          const unsigned long long* flags, long long flag_cap, unsigned long long* fb, double* pos,
                          double* fb_pos, hipStream_t s)
 {
-    k_bfbpos<<<bp.n + 256, 256, 0, s>>>(bp, nsys, tab64, sysrow, bs, hcap, hits, flags, flag_cap, fb, pos, fb_pos);
+    k_bfbpos<<<bp.n * kBfbSub + kBfbFlagBlocks, 256, 0, s>>>(bp, nsys, tab64, sysrow, bs, hcap, hits, flags,
+                                                             flag_cap, fb, pos, fb_pos);
     return hipGetLastError();
 }
 

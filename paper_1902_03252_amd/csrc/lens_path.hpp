@@ -545,6 +545,50 @@ __device__ __forceinline__ void stage_tile_wave(const V* __restrict__ ax, const 
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// A tile's nodes (with the halo) held in registers, lane-strided as
+// stage_tile_wave places them: fetched while the wave still works on the
+// previous tile, then written to the wave's LDS tile.
+template <class S, typename V>
+struct TileRegs {
+    static constexpr int N = S::TNX * S::TNY, K = (N + 63) / 64;
+    V x[K], y[K];
+};
+
+template <class S, typename V>
+__device__ __forceinline__ void fetch_tile_regs(const V* __restrict__ ax, const V* __restrict__ ay,
+                                                const GridDesc& g, const Tile& T, TileRegs<S, V>& t)
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int k = 0; k < TileRegs<S, V>::K; k++) {
+        const int q = lane + 64 * k;
+        const int li = q % S::TNX, lj = q / S::TNX;
+        const bool in = q < TileRegs<S, V>::N && li <= T.ncx && lj <= T.ncy;
+        const size_t n = in ? (size_t)(T.cj0 + lj) * g.nx + (T.ci0 + li) : 0;
+        t.x[k] = ax[n];
+        t.y[k] = ay[n];
+    }
+}
+
+template <class S, typename V>
+__device__ __forceinline__ void store_tile_regs(const TileRegs<S, V>& t, const Tile& T, V (*sx)[S::TNX],
+                                                V (*sy)[S::TNX])
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int k = 0; k < TileRegs<S, V>::K; k++) {
+        const int q = lane + 64 * k;
+        const int li = q % S::TNX, lj = q / S::TNX;
+        if (q < TileRegs<S, V>::N && li <= T.ncx && lj <= T.ncy) {
+            sx[lj][li] = t.x[k];
+            sy[lj][li] = t.y[k];
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Sums a wave-uniform count a and a per-lane count b over the workgroup and
 // writes them to the workgroup's statistics slot.  All threads must call it.
 __device__ __forceinline__ void write_part_sum(unsigned* part, size_t slot, unsigned a, unsigned b,
@@ -583,6 +627,9 @@ __device__ __forceinline__ bool tile_box_contains(const GridDesc& g, const Tile&
 // certified FP32 decision for each, hits and undecided tests appended with
 // one atomic per wave.  fr = {r, E_B, bx_hi, bx_lo, by_hi, by_lo} as float;
 // an appended key is (hit_base | triangle id) or (flag_base | triangle id).
+// NT threads share the tile, a multiple of its width, so a thread keeps its
+// column in every pass; the passes' results are kept as bits and the appends
+// run only when some thread of the wave has a hit or an undecided test.
 template <class S, int NT = 256>
 __device__ __forceinline__ void tri32_system(const GridDesc& g, const Tile& T, const float (*sx)[S::TNX],
                                              const float (*sy)[S::TNX], const float* fr,
@@ -592,40 +639,50 @@ __device__ __forceinline__ void tri32_system(const GridDesc& g, const Tile& T, c
                                              unsigned long long* flag_counter, unsigned long long* flag_keys,
                                              long long flag_cap, unsigned& nbbox, int tix = threadIdx.x)
 {
+    constexpr int IT = S::TX * S::TY / NT;  // cells per thread
+    static_assert(NT % S::TX == 0 && IT * 4 <= 64, "column per thread; 4 result bits per cell");
     const float r = fr[0], E = fr[1], bxh = fr[2], bxl = fr[3], byh = fr[4], byl = fr[5];
     const float h32 = (float)g.h;
+    const int li = tix % S::TX, lj0 = tix / S::TX;
+    const int gi = T.ci0 + li;
+    // offsets theta - barycentre in node units (exact hi part), then arcsec
+    const float ex0 = (((float)gi - bxh) - bxl) * h32;
+    const float ex1 = (((float)(gi + 1) - bxh) - bxl) * h32;
+    unsigned long long bits = 0;
 #pragma unroll 1
-    for (int it = 0; it < S::TX * S::TY / NT; it++) {
-        const int cidx = tix + NT * it;
-        const int li = cidx % S::TX, lj = cidx / S::TX;
-        const bool valid = li < T.ncx && lj < T.ncy;
-        const int gi = T.ci0 + li, gj = T.cj0 + lj;
-        // offsets theta - barycentre in node units (exact hi part), then arcsec
-        const float ex0 = (((float)gi - bxh) - bxl) * h32;
-        const float ex1 = (((float)(gi + 1) - bxh) - bxl) * h32;
+    for (int it = 0; it < IT; it++) {
+        const int lj = lj0 + (NT / S::TX) * it;
+        const int gj = T.cj0 + lj;
         const float ey0 = (((float)gj - byh) - byl) * h32;
         const float ey1 = (((float)(gj + 1) - byh) - byl) * h32;
         const float d00x = fmaf(-r, sx[lj][li], ex0), d00y = fmaf(-r, sy[lj][li], ey0);
         const float d10x = fmaf(-r, sx[lj][li + 1], ex1), d10y = fmaf(-r, sy[lj][li + 1], ey0);
         const float d01x = fmaf(-r, sx[lj + 1][li], ex0), d01y = fmaf(-r, sy[lj + 1][li], ey1);
         const float d11x = fmaf(-r, sx[lj + 1][li + 1], ex1), d11y = fmaf(-r, sy[lj + 1][li + 1], ey1);
-        int res0 = kMiss, res1 = kMiss;
-        if (valid) {
+        if (li < T.ncx && lj < T.ncy) {
             const float tx[3] = {d00x, d10x, d01x}, ty[3] = {d00y, d10y, d01y};
             const float ux[3] = {d11x, d01x, d10x}, uy[3] = {d11y, d01y, d10y};
-            res0 = decide32(tx, ty, E, mode, tau, nbbox);
-            res1 = decide32(ux, uy, E, mode, tau, nbbox);
+            const int res0 = decide32(tx, ty, E, mode, tau, nbbox);
+            const int res1 = decide32(ux, uy, E, mode, tau, nbbox);
+            bits |= (unsigned long long)(res0 | (res1 << 2)) << (4 * it);
         }
+    }
+    if (__ballot(bits != 0) == 0) return;  // the common case: no hit, nothing undecided
+#pragma unroll 1
+    for (int it = 0; it < IT; it++) {
+        const unsigned rb = (unsigned)(bits >> (4 * it)) & 15u;
+        const int gj = T.cj0 + lj0 + (NT / S::TX) * it;
         const unsigned tid0 = (unsigned)(2 * (gj * (g.nx - 1) + gi));
-        wave_append(res0 == kHit, hit_base | tid0, hit_counter, hit_keys, hit_cap);
-        wave_append(res1 == kHit, hit_base | (tid0 + 1), hit_counter, hit_keys, hit_cap);
-        wave_append(res0 == kFlag, flag_base | tid0, flag_counter, flag_keys, flag_cap);
-        wave_append(res1 == kFlag, flag_base | (tid0 + 1), flag_counter, flag_keys, flag_cap);
+        wave_append((rb & 3u) == kHit, hit_base | tid0, hit_counter, hit_keys, hit_cap);
+        wave_append((rb >> 2) == kHit, hit_base | (tid0 + 1), hit_counter, hit_keys, hit_cap);
+        wave_append((rb & 3u) == kFlag, flag_base | tid0, flag_counter, flag_keys, flag_cap);
+        wave_append((rb >> 2) == kFlag, flag_base | (tid0 + 1), flag_counter, flag_keys, flag_cap);
     }
 }
 
 // All triangles of a staged FP64 tile against one system (FP64 path): exact
-// bounding box, then exact orientation signs.
+// bounding box, then exact orientation signs; hits kept as bits and appended
+// only when some thread of the wave has one (as tri32_system).
 template <class S, int NT = 256>
 __device__ __forceinline__ void tri64_system(const GridDesc& g, const Tile& T, const double (*sx)[S::TNX],
                                              const double (*sy)[S::TNX], double r, double bx, double by,
@@ -633,15 +690,17 @@ __device__ __forceinline__ void tri64_system(const GridDesc& g, const Tile& T, c
                                              unsigned long long* hit_keys, long long hit_cap, unsigned& nbbox,
                                              int tix = threadIdx.x)
 {
+    constexpr int IT = S::TX * S::TY / NT;
+    static_assert(NT % S::TX == 0 && IT * 2 <= 64, "column per thread; 2 result bits per cell");
+    const int li = tix % S::TX, lj0 = tix / S::TX;
+    const int gi = T.ci0 + li;
+    const double t0x = node_coord(g.x0, gi, g.h), t1x = node_coord(g.x0, gi + 1, g.h);
+    unsigned long long bits = 0;
 #pragma unroll 1
-    for (int it = 0; it < S::TX * S::TY / NT; it++) {
-        const int cidx = tix + NT * it;
-        const int li = cidx % S::TX, lj = cidx / S::TX;
-        const bool valid = li < T.ncx && lj < T.ncy;
-        const int gi = T.ci0 + li, gj = T.cj0 + lj;
-        bool h0 = false, h1 = false;
-        if (valid) {
-            const double t0x = node_coord(g.x0, gi, g.h), t1x = node_coord(g.x0, gi + 1, g.h);
+    for (int it = 0; it < IT; it++) {
+        const int lj = lj0 + (NT / S::TX) * it;
+        const int gj = T.cj0 + lj;
+        if (li < T.ncx && lj < T.ncy) {
             const double t0y = node_coord(g.y0, gj, g.h), t1y = node_coord(g.y0, gj + 1, g.h);
             const double b00x = src_map(t0x, r, sx[lj][li]), b00y = src_map(t0y, r, sy[lj][li]);
             const double b10x = src_map(t1x, r, sx[lj][li + 1]), b10y = src_map(t0y, r, sy[lj][li + 1]);
@@ -653,18 +712,23 @@ __device__ __forceinline__ void tri64_system(const GridDesc& g, const Tile& T, c
             const double lo1 = fmin(vy0[0], fmin(vy0[1], vy0[2])), hi1 = fmax(vy0[0], fmax(vy0[1], vy0[2]));
             if (!(bx < lo0 || bx > hi0 || by < lo1 || by > hi1)) {
                 nbbox++;
-                h0 = contains_exact(vx0, vy0, bx, by);
+                if (contains_exact(vx0, vy0, bx, by)) bits |= 1ull << (2 * it);
             }
             const double lo2 = fmin(vx1[0], fmin(vx1[1], vx1[2])), hi2 = fmax(vx1[0], fmax(vx1[1], vx1[2]));
             const double lo3 = fmin(vy1[0], fmin(vy1[1], vy1[2])), hi3 = fmax(vy1[0], fmax(vy1[1], vy1[2]));
             if (!(bx < lo2 || bx > hi2 || by < lo3 || by > hi3)) {
                 nbbox++;
-                h1 = contains_exact(vx1, vy1, bx, by);
+                if (contains_exact(vx1, vy1, bx, by)) bits |= 2ull << (2 * it);
             }
         }
+    }
+    if (__ballot(bits != 0) == 0) return;
+#pragma unroll 1
+    for (int it = 0; it < IT; it++) {
+        const int gj = T.cj0 + lj0 + (NT / S::TX) * it;
         const unsigned tid0 = (unsigned)(2 * (gj * (g.nx - 1) + gi));
-        wave_append(h0, hit_base | tid0, hit_counter, hit_keys, hit_cap);
-        wave_append(h1, hit_base | (tid0 + 1), hit_counter, hit_keys, hit_cap);
+        wave_append(((bits >> (2 * it)) & 1ull) != 0, hit_base | tid0, hit_counter, hit_keys, hit_cap);
+        wave_append(((bits >> (2 * it)) & 2ull) != 0, hit_base | (tid0 + 1), hit_counter, hit_keys, hit_cap);
     }
 }
 
