@@ -458,6 +458,41 @@ def cpu_baseline(prm, grid, obs_np, budget_s: float, band_rows: int):
     return base, want
 
 
+def cpu_extras(obs2_np, batch: int, batch_samples: int):
+    """The FP64 oracle on the batched and backward legs' workloads, as context
+    beside the GPU figures: chi^2 of batch_samples evenly spaced samples of the
+    batch on cpu_threads() threads, extrapolated to the whole batch in
+    proportion to sum N^2 P, and one deflection VJP of the differentiation
+    workload (512^2 grid, 50 potentials) on the same threads."""
+    import oracle
+    import synthlens as S
+    threads = cpu_threads()
+    out = {}
+    if batch > 0 and batch_samples > 0:
+        params, pot_off, grids = S.batch_samples(batch)
+        cost = np.array([g.nx * g.ny for g in grids], dtype=np.float64) * np.diff(pot_off)
+        step = max(1, batch // batch_samples)
+        idx = list(range(0, batch, step))[:batch_samples]
+        t0 = time.perf_counter()
+        for s in idx:
+            oracle.image_chi2(params[:, pot_off[s]:pot_off[s + 1]], grids[s], obs2_np, nthreads=threads)
+        dt = time.perf_counter() - t0
+        t_batch = dt * cost.sum() / cost[idx].sum()
+        out["batched"] = dict(value=batch / t_batch, unit="chi2 evals/s", cores=threads, kind="oracle",
+                              sample=(f"{len(idx)} of the {batch} samples (every {step}th, {dt:.1f} s), "
+                                      f"extrapolated to the batch in proportion to sum N^2 P"))
+    w = S.WORKLOADS[5]
+    cot = S.cotangent(w.grid.nx * w.grid.ny)
+    prm5 = S.potentials(5)
+    t0 = time.perf_counter()
+    oracle.alpha_vjp(prm5, w.grid, cot[0].reshape(w.grid.ny, w.grid.nx), cot[1].reshape(w.grid.ny, w.grid.nx),
+                     nthreads=threads)
+    dt = time.perf_counter() - t0
+    out["backward"] = dict(value=1.0 / dt, unit="deflection VJPs/s", cores=threads, kind="oracle",
+                           sample=f"one VJP of the 512^2 / 50-potential workload ({dt:.2f} s)")
+    return out
+
+
 def hit_set(r):
     return set(zip(np.asarray(r["hit_sys"]).tolist(), np.asarray(r["hit_tid"]).tolist()))
 
@@ -471,6 +506,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=10.0,
                     help="seconds of full oracle evaluations for the baseline (at least one)")
     ap.add_argument("--cpu-band", type=int, default=48, help="grid rows of the one-thread oracle sample")
+    ap.add_argument("--cpu-batch-samples", type=int, default=8,
+                    help="batch samples the oracle evaluates for its batched figure (0 skips it)")
     ap.add_argument("--batch", type=int, default=1024, help="samples of the batched leg (0 skips it)")
     ap.add_argument("--batch-steps", type=int, default=5, help="timed replays of the batched leg")
     ap.add_argument("--no-backward", dest="backward", action="store_false", help="skip the backward leg")
@@ -512,6 +549,8 @@ def main():
     traffic = traffic_per_launch(HEADLINE_FIELD)
 
     cpu, want = (None, None) if args.no_cpu else cpu_baseline(prm, grid, obs_np, args.cpu_budget, args.cpu_band)
+    if cpu is not None:
+        cpu.update(cpu_extras(obs2_np, args.batch, args.cpu_batch_samples))
     parity = None
     lit = res["literal"]
     literal = {"rule": "FP64 fallback when |c_k| < 1e-6 h^2 (FP32 sign taken otherwise)",
