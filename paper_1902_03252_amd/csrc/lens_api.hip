@@ -538,7 +538,7 @@ struct Chi2Plan {
     ObsPtrs o;
     int np;
     bool mixed, fused;
-    int shape, npl, tiles_x, tx_shift, n_cull, tpw, n_parts;
+    int shape, npl, tiles_x, tx_shift, n_cull, tpw, n_parts, fb_blocks;
     long long region, flag_cap;
     size_t nn, vbytes;
     size_t bytes[CB_N];
@@ -582,9 +582,10 @@ int chi2_plan(lens_ctx* ctx, const lens_potentials* pot, const lens_grid* grid, 
     int tile_x, tile_y;
     tile_dims(pl.shape, tile_x, tile_y);
     pl.tx_shift = tile_x == 64 ? 6 : 5;
-    tri_tiles(pl.g, pl.shape, &pl.tiles_x);
+    const long long n_tiles = tri_tiles(pl.g, pl.shape, &pl.tiles_x);
     int sc, nch;
     cull_shape(pl.g, pl.shape, pl.o.n_sys, &pl.n_cull, &pl.tpw, &sc, &nch);
+    pl.fb_blocks = fbpos_blocks(n_tiles);
     pl.n_parts = pl.n_cull + kPairBlocks;
     // each culling wave owns room for every pair of its tiles and systems
     pl.region = 64ll * pl.tpw * sc;
@@ -683,7 +684,7 @@ int chi2_run(lens_ctx* ctx, const Chi2Plan& pl, const Chi2Bufs& b, const lens_po
                          kHitScratch, flags, pl.flag_cap, part, pl.n_cull, pl.shape, stream);
     if (e == hipSuccess)
         e = launch_fbpos(tab64, np, g, sysrow, st, hits, kHitScratch, flags, pl.flag_cap, fb_hits, kHitScratch, pos,
-                         fb_pos, stream);
+                         fb_pos, pl.fb_blocks, stream);
     if (e != hipSuccess) return LENS_ERR_DEVICE;
     TailLaunch tl;
     tl.obs = o;

@@ -122,7 +122,8 @@ hipError_t launch_field64(const double* tab64, int np, const GridDesc& g, double
                           hipStream_t s);
 constexpr int kRR = 8;                     // values per (row, column group) of the tile range partials
 constexpr int kPairBlocks = 512;           // persistent workgroups of the pair kernel
-constexpr int kMaxCull = 1024;             // culling waves (64 tiles per round)
+constexpr int kMaxCull = 4096;             // culling waves (64 tiles per round)
+int fbpos_blocks(long long n_tiles);       // persistent workgroups of the positions / fallback kernel
 void tile_dims(int shape, int& tx, int& ty);
 long long tri_tiles(const GridDesc& g, int shape, int* tiles_x);
 void cull_shape(const GridDesc& g, int shape, int nsys, int* n_cull, int* tpw, int* sc, int* n_chunks);
@@ -137,7 +138,7 @@ hipError_t launch_pairs(bool fp32, const void* ax, const void* ay, const GridDes
 hipError_t launch_fbpos(const double* tab64, int np, const GridDesc& g, const double* sysrow, EvalState* st,
                         const unsigned long long* hit_keys, long long hit_cap, const unsigned long long* flag_keys,
                         long long flag_cap, unsigned long long* fb_keys, long long fb_cap, double* pos,
-                        double* fb_pos, hipStream_t s);
+                        double* fb_pos, int blocks, hipStream_t s);
 
 // Arguments of the tail kernel.
 struct TailLaunch {

@@ -564,14 +564,15 @@ __global__ __launch_bounds__(256) void k_pairs(const V* __restrict__ ax, const V
     __shared__ unsigned sp[4][2];
     const int lane = lane_id(), t = threadIdx.x;
     // exclusive prefix of the culling counts in LDS: thread t owns counts
-    // [4t, 4t+4) (n_cull <= 1024), wave scans, then the wave totals
+    // [CT t, CT t + CT) (n_cull <= kMaxCull), wave scans, then the wave totals
+    constexpr int CT = kMaxCull / 256;
     __shared__ unsigned spre[kMaxCull + 1];
     __shared__ unsigned swt[4];
     const int wave = t >> 6;
-    unsigned cl[4], lsum = 0;
+    unsigned cl[CT], lsum = 0;
 #pragma unroll
-    for (int j = 0; j < 4; j++) {
-        const int c = 4 * t + j;
+    for (int j = 0; j < CT; j++) {
+        const int c = CT * t + j;
         cl[j] = c < n_cull ? counts[c] : 0u;
         lsum += cl[j];
     }
@@ -585,8 +586,8 @@ __global__ __launch_bounds__(256) void k_pairs(const V* __restrict__ ax, const V
     unsigned run = incl - lsum;
     for (int w = 0; w < wave; w++) run += swt[w];
 #pragma unroll
-    for (int j = 0; j < 4; j++) {
-        const int c = 4 * t + j;
+    for (int j = 0; j < CT; j++) {
+        const int c = CT * t + j;
         if (c < n_cull) spre[c] = run;
         run += cl[j];
     }
@@ -596,16 +597,21 @@ __global__ __launch_bounds__(256) void k_pairs(const V* __restrict__ ax, const V
     const long long w0 = (long long)blockIdx.x * 4 + wave;
     const long long n_pairs = st->status == kStatusOk ? (long long)total : 0;
     unsigned nbbox = 0;
-    for (long long u = w0; u < n_pairs; u += nw) {
+    // key of pair u: the last culling wave whose prefix is <= u, then its region
+    auto pair_key = [&](long long u) -> unsigned long long {
         const unsigned pidx = (unsigned)u;
-        int lo = 0, hi = n_cull - 1;  // the last culling workgroup whose prefix is <= pidx
+        int lo = 0, hi = n_cull - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
             if (spre[mid] <= pidx) lo = mid; else hi = mid - 1;
         }
-        const int cw = lo;
-        const unsigned off = pidx - spre[lo];
-        const unsigned long long pk = pairs[(size_t)cw * region + off];
+        return pairs[(size_t)lo * region + (pidx - spre[lo])];
+    };
+    // the next pair's key is looked up and loaded before the current pair's tests
+    unsigned long long nk = w0 < n_pairs ? pair_key(w0) : 0ull;
+    for (long long u = w0; u < n_pairs; u += nw) {
+        const unsigned long long pk = nk;
+        if (u + nw < n_pairs) nk = pair_key(u + nw);
         const int tile = (int)(pk >> 32), sys = (int)(pk & 0xffffffffu);
         pair_test<S, V>(ax, ay, g, tile_of<S>(g, tiles_x, tile), sys, sysrow, st, mode, tau, hit_keys, hit_cap,
                         flag_keys, flag_cap, nbbox);
@@ -1113,6 +1119,11 @@ void cull_shape(const GridDesc& g, int shape, int nsys, int* n_cull, int* tpw, i
     *n_cull = (int)(nb * ch);
 }
 
+// Persistent workgroups of the positions / fallback kernel: enough waves that
+// a large grid's hits and undecided tests (thousands) take a few items per
+// wave, at least the count that serves small grids best.
+int fbpos_blocks(long long n_tiles) { return (int)std::min(1024ll, std::max(256ll, n_tiles / 64)); }
+
 hipError_t launch_cull(bool fp32, const void* rr, const GridDesc& g, int nsys,
                        const double* sysrow, unsigned long long* pairs, long long region, unsigned* counts,
                        unsigned* part, int shape, hipStream_t s)
@@ -1158,9 +1169,9 @@ hipError_t launch_pairs(bool fp32, const void* ax, const void* ay, const GridDes
 hipError_t launch_fbpos(const double* tab64, int np, const GridDesc& g, const double* sysrow, EvalState* st,
                         const unsigned long long* hit_keys, long long hit_cap, const unsigned long long* flag_keys,
                         long long flag_cap, unsigned long long* fb_keys, long long fb_cap, double* pos,
-                        double* fb_pos, hipStream_t s)
+                        double* fb_pos, int blocks, hipStream_t s)
 {
-    k_fbpos<<<256, 256, 0, s>>>(tab64, np, g, sysrow, st, hit_keys, hit_cap, flag_keys, flag_cap, fb_keys, fb_cap,
+    k_fbpos<<<blocks, 256, 0, s>>>(tab64, np, g, sysrow, st, hit_keys, hit_cap, flag_keys, flag_cap, fb_keys, fb_cap,
                                 pos, fb_pos);
     return hipGetLastError();
 }
