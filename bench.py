@@ -89,6 +89,21 @@ def traffic_per_launch(npl: int):
         return None
 
 
+def timed_kernels(torch, ctx, fn, steps, warmup):
+    """Wall time per call of `steps` calls after `warmup` untimed ones, and the
+    library's event-timed kernel milliseconds and launch count of the timed
+    calls only."""
+    ctx.set_timing(True)
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ctx.field_timing(reset=True)
+    dt = time_steps(torch, fn, steps, 0)
+    kms, nl = ctx.field_timing(reset=True)
+    ctx.set_timing(False)
+    return dt, kms, nl
+
+
 def time_steps(torch, fn, steps, warmup):
     for _ in range(warmup):
         fn()
@@ -110,15 +125,12 @@ def autotune(args, lens, ctx, prec, batched, grid, n_pot, tune):
 
 
 def chi2_leg(torch, lens, ctx, p, grid, obs, prec, steps, warmup, **kw):
-    """K eager calls with the field kernel bracketed by HIP events on the call's
-    stream, then the same call captured once into a HIP graph and K replays."""
+    """W untimed and K timed eager calls with the field kernel bracketed by HIP
+    events on the call's stream (the kernel average covers the K timed calls),
+    then the same call captured once into a HIP graph and K replays."""
     out = lens.chi2_buffers(obs, 4096, "cuda")
     step = lambda: lens.lens_image_chi2(p, grid, obs, prec=prec, out=out, ctx=ctx, **kw)
-    ctx.set_timing(True)
-    ctx.field_timing(reset=True)
-    eager_s = time_steps(torch, step, steps, warmup)
-    kern_ms, launches = ctx.field_timing(reset=True)
-    ctx.set_timing(False)
+    eager_s, kern_ms, launches = timed_kernels(torch, ctx, step, steps, warmup)
     eager = out.host()
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
@@ -199,11 +211,7 @@ def paper_bench(torch, lens, ctx, args):
             "fp32": lambda: lens.lens_deflect(p, grid, "fp32", ctx=ctx, check=False)}
     res = {}
     for name, step in legs.items():
-        ctx.set_timing(True)
-        ctx.field_timing(reset=True)
-        dt = time_steps(torch, step, 5, 2)
-        kms, nl = ctx.field_timing(reset=True)
-        ctx.set_timing(False)
+        dt, kms, nl = timed_kernels(torch, ctx, step, 5, 2)
         res[name] = dict(ms=dt * 1e3, pixel_potential_evals_per_s=evals / dt,
                          field_kernel_ms=kms / max(nl, 1))
     st = out.stats.cpu().numpy()
@@ -252,11 +260,7 @@ def precision_bench(torch, lens, ctx, args):
         res = {}
         fields = {}
         for prec in ("fp32", "fp64"):
-            ctx.set_timing(True)
-            ctx.field_timing(reset=True)
-            dt = time_steps(torch, lambda: fn(p, grid, prec, ctx=ctx, check=False), 3, 1)
-            kms, nl = ctx.field_timing(reset=True)
-            ctx.set_timing(False)
+            dt, kms, nl = timed_kernels(torch, ctx, lambda: fn(p, grid, prec, ctx=ctx, check=False), 3, 1)
             fields[prec] = fn(p, grid, prec, ctx=ctx)
             res[f"{prec}_ms"] = dt * 1e3
             res[f"{prec}_field_kernel_ms"] = kms / max(nl, 1)
@@ -344,11 +348,7 @@ def backward_bench(torch, lens, ctx, obs, args):
     out = {"workload": f"{prm.shape[1]} potentials, {grid.nx}^2 grid, 7 parameters each, N(0,1) cotangent"}
     for prec in ("fp64", "fp32"):
         step = lambda: lens.lens_deflect_backward(p, grid, gx, gy, prec, ctx=ctx, check=False)
-        ctx.set_timing(True)
-        ctx.field_timing(reset=True)
-        dt = time_steps(torch, step, 20, 3)
-        kms, nl = ctx.field_timing(reset=True)
-        ctx.set_timing(False)
+        dt, kms, nl = timed_kernels(torch, ctx, step, 20, 3)
         kern_s = kms / 1e3 / max(nl, 1)
         peak = PEAK_FP64_TFLOPS if prec == "fp64" else PEAK_FP32_TFLOPS
         out[prec] = dict(ms_per_vjp=dt * 1e3, vjp_kernel_ms=kern_s * 1e3, tflops=flops / kern_s / 1e12,
@@ -379,13 +379,9 @@ def batched_bench(torch, lens, ctx, obs, obs_np, args, tuned):
                                             lambda: lens.autotune_chi2_batched(p, layout, obs, prec=prec, out=out,
                                                                                ctx=ctx, reps=2))
         step = lambda: lens.lens_image_chi2_batched(p, layout, obs, prec=prec, out=out, ctx=ctx)
-        ctx.set_timing(True)
         step()  # builds and caches the plan
         torch.cuda.synchronize()
-        ctx.field_timing(reset=True)
-        eager_s = time_steps(torch, step, 3, 1)
-        kms, nl = ctx.field_timing(reset=True)
-        ctx.set_timing(False)
+        eager_s, kms, nl = timed_kernels(torch, ctx, step, 3, 1)
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(s):
@@ -397,7 +393,7 @@ def batched_bench(torch, lens, ctx, obs, obs_np, args, tuned):
         dt = time_steps(torch, g.replay, args.batch_steps, 1)
         st = out.stats.cpu().numpy()
         status = out.status.cpu().numpy()
-        field_s = kms / 1e3 / 4.0  # field kernels of one batch (1 warm-up + 3 timed calls)
+        field_s = kms / 1e3 / 3.0  # field kernels of one batch (3 timed calls)
         peak = PEAK_FP32_TFLOPS if prec == "mixed" else PEAK_FP64_TFLOPS
         out_res[prec] = dict(chi2_evals_per_s=args.batch / dt, ms_per_batch=dt * 1e3,
                              eager_ms_per_batch=eager_s * 1e3, grid_triangles_per_s=tri / dt,
