@@ -78,20 +78,17 @@ __device__ __forceinline__ void dconst(const PotPtrs& pot, int p, double* d)
 }
 
 // Square root and reciprocal square root of a positive argument.  FP64: the
-// hardware estimate of 1/sqrt(x) (relative error below 2^-24 on gfx950,
-// measured) refined by one Goldschmidt iteration (error ~2^-47), then one
-// Newton correction of the root (Markstein, "IA-64 and elementary functions",
-// 2000): the root within a few ulp, the reciprocal within ~2^-46 relative.
-// FP32: the hardware instructions (1 ulp).
+// hardware estimate y of 1/sqrt(x) (relative error below 2^-24 on gfx950,
+// measured) refined by one Newton step, y (1 + (1 - x y^2) / 2), whose
+// relative error is 1.5 times the square of the estimate's (below 2^-47), and
+// the root as x times it: both within ~2^-47 relative, far inside the
+// products' 1e-11 bar.  FP32: the hardware instructions (1 ulp).
 __device__ __forceinline__ void sqrt_rsq(double x, double& s, double& is)
 {
     const double y = __builtin_amdgcn_rsq(x);
-    double g = x * y, h = 0.5 * y;
-    const double r = fma(-g, h, 0.5);
-    g = fma(g, r, g);
-    h = fma(h, r, h);
-    s = fma(fma(-g, g, x), h, g);
-    is = h + h;
+    const double e = fma(-(x * y), y, 1.0);
+    is = fma(0.5 * y, e, y);
+    s = x * is;
 }
 __device__ __forceinline__ void sqrt_rsq(float x, float& s, float& is)
 {
