@@ -78,6 +78,8 @@ struct Reader {
     const char* p;
     const char* end;
     bool ok = true;
+    int depth = 0;  // nesting of skipped objects and arrays, at most kMaxDepth
+    static constexpr int kMaxDepth = 64;
 
     void ws()
     {
@@ -141,18 +143,25 @@ struct Reader {
         if (*p == '"') {
             (void)str();
         } else if (*p == '{' || *p == '[') {
+            if (depth >= kMaxDepth) {  // a table file nests two levels; deeper input is malformed
+                ok = false;
+                return;
+            }
             const char close = *p == '{' ? '}' : ']';
             const bool obj = *p == '{';
             p++;
-            if (eat(close)) return;
-            do {
-                if (obj) {
-                    (void)str();
-                    expect(':');
-                }
-                skip();
-            } while (ok && eat(','));
-            expect(close);
+            depth++;
+            if (!eat(close)) {
+                do {
+                    if (obj) {
+                        (void)str();
+                        expect(':');
+                    }
+                    skip();
+                } while (ok && eat(','));
+                expect(close);
+            }
+            depth--;
         } else if (end - p >= 4 && (!strncmp(p, "true", 4) || !strncmp(p, "null", 4))) {
             p += 4;
         } else if (end - p >= 5 && !strncmp(p, "false", 5)) {

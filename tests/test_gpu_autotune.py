@@ -112,6 +112,8 @@ def test_autotune_table_files(lens, tmp_path):
         '"field_npl": 1, "ms": 1}]}',
         '{"entries": []}',
         '{"arch": "gfx950", "entries": []} trailing',
+        # nesting far beyond a table file's two levels is refused without recursing through it
+        '{"arch": "gfx950", "entries": [], "x": ' + "[" * 200000 + "]" * 200000 + "}",
     ]
     for k, text in enumerate(bad):
         f = tmp_path / f"bad{k}.json"
