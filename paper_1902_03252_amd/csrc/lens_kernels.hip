@@ -763,7 +763,53 @@ __global__ __launch_bounds__(1024) void k_tail(ObsPtrs obs, EvalState* __restric
         if (t == 0) chi2[0] = __builtin_nan("");
         return;
     }
-    if (n <= 1024) {
+    if (n > 256 && n <= 1024 && nsys <= kTailStage) {
+        // counting by system, then rank by (triangle id, index) inside each
+        // system's bucket: keys are unique, so the ranks give the sorted order
+        // in O(n + sum of squared bucket sizes) instead of O(n^2) (below 257
+        // keys the plain rank sort, with fewer barriers, is faster).  The
+        // upper half of the key array holds the buckets, then the bucket
+        // starts and fill counts.
+        static_assert(kSortCap >= 4096, "room for 1024 keys and the bucket arrays");
+        unsigned long long* tmp = key + kSortCap / 2;
+        int* sbeg = reinterpret_cast<int*>(tmp + 1024);
+        int* sfill = sbeg + kTailStage;
+        int* swsum = sfill + kTailStage;
+        if (t < nsys) sfill[t] = 0;
+        __syncthreads();
+        unsigned long long mine = 0;
+        int sy = 0;
+        if (t < n) {
+            mine = key[t];
+            sy = (int)(mine >> 44);
+            atomicAdd(&sfill[sy], 1);
+        }
+        __syncthreads();
+        const int cnt = t < nsys ? sfill[t] : 0;  // thread t: system t
+        int incl = cnt;
+        for (int d = 1; d < 64; d <<= 1) {
+            const int v = __shfl_up(incl, d, 64);
+            if ((t & 63) >= d) incl += v;
+        }
+        if ((t & 63) == 63) swsum[t >> 6] = incl;
+        __syncthreads();
+        int b0 = incl - cnt;
+        for (int w = 0; w < (t >> 6); w++) b0 += swsum[w];
+        if (t < nsys) {
+            sbeg[t] = b0;
+            sfill[t] = 0;
+        }
+        __syncthreads();
+        if (t < n) tmp[sbeg[sy] + atomicAdd(&sfill[sy], 1)] = mine;
+        __syncthreads();
+        if (t < n) {
+            const int q0 = sbeg[sy], q1 = q0 + sfill[sy];
+            int rank = 0;
+            for (int q = q0; q < q1; q++) rank += tmp[q] < mine;
+            key[q0 + rank] = mine;
+        }
+        __syncthreads();
+    } else if (n <= 1024) {
         // rank sort (keys are unique): one barrier instead of log^2 of them
         unsigned long long mine = 0;
         int rank = 0;
