@@ -531,3 +531,22 @@ def test_graph_replay_matches_eager(lens):
             for k in ("hit_sys", "hit_tid", "hit_x", "hit_y", "n_pred", "chi2_sys", "match"):
                 np.testing.assert_array_equal(got[k], eager[k])
         del g
+
+
+@pytest.mark.parametrize("nx,ny", [(4099, 3), (3, 4099), (1537, 10), (10, 1537), (2, 2), (65, 2)])
+@pytest.mark.parametrize("tile", [1, 2])
+def test_chi2_thin_grids(lens, nx, ny, tile):
+    """Grids of one or a few cell rows (or columns), narrower than a tile in one
+    direction, through the cluster workload's lens plane along an observed
+    image of each kind of placement: the tile ranges, halo columns, culling and
+    pair tests at the grid's edges, in both precisions, against the oracle."""
+    prm, grid0, obs = load_inputs(2)
+    h = grid0.h
+    j = int(np.argmax(np.abs(obs["x"]) + np.abs(obs["y"]) < 40.0))  # an image near the centre
+    cx, cy = float(obs["x"][j]), float(obs["y"][j])
+    grid = S.Grid(cx - h * (nx - 1) / 2 - 0.37 * h, cy - h * (ny - 1) / 2 + 0.21 * h, h, nx, ny)
+    want = oracle.image_chi2(prm, grid, obs)
+    for prec in ("fp64", "mixed"):
+        got = run_chi2(lens, prm, grid, obs, prec, tile=tile)
+        print(f"  {nx}x{ny} tile {tile} {prec}: hits {got['stats'][0]} (oracle {len(want['hit_tid'])})", flush=True)
+        compare_chi2(got, want, 1e-9 if prec == "fp64" else 1e-5, 1e-9 if prec == "fp64" else 1e-6)
