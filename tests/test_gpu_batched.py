@@ -243,3 +243,25 @@ def test_batched_full_workload_sampled_against_oracle(lens, prec):
         want = _ORACLE[key]
         print(f"  {prec} sample {s}: side {sides[s]} P {counts[s]} hits {len(want['hit_sys'])}", flush=True)
         check_sample(got, s, want, RTOL[prec], prec)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batched_thin_grids(lens, prec):
+    """One batch of thin grids (a few cell rows or columns, narrower than a tile)
+    through the cluster workload's lens plane, next to a square one: every
+    sample against the oracle, hit sets included."""
+    prm, grid0, obs = load_inputs(2)
+    h = grid0.h
+    j = int(np.argmax(np.abs(obs["x"]) + np.abs(obs["y"]) < 40.0))
+    cx, cy = float(obs["x"][j]), float(obs["y"][j])
+    shapes = [(4099, 3), (3, 4099), (1537, 10), (10, 1537), (2, 2), (65, 2), (257, 257)]
+    grids = [S.Grid(cx - h * (nx - 1) / 2 - 0.37 * h, cy - h * (ny - 1) / 2 + 0.21 * h, h, nx, ny)
+             for nx, ny in shapes]
+    params = np.concatenate([prm] * len(grids), axis=1)
+    pot_off = np.arange(len(grids) + 1, dtype=np.int32) * prm.shape[1]
+    got = run_batched(lens, params, pot_off, grids, obs, prec, hits=True)
+    assert (got["status"] == 0).all()
+    for s, g in enumerate(grids):
+        want = oracle_of(("thin", s), prm, g, obs)
+        print(f"  {g.nx}x{g.ny} {prec}: oracle hits {len(want['hit_tid'])}", flush=True)
+        check_sample(got, s, want, RTOL[prec], prec)
