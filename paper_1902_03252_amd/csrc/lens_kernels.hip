@@ -469,7 +469,12 @@ __device__ __forceinline__ void pair_test(const V* __restrict__ ax, const V* __r
     constexpr int Q = S::TX * S::TY / 64;  // cells per lane for one pair
     constexpr int QB = Q < 4 ? Q : 4;      // cells per lane per step
     const int lane = lane_id();
+    // the system's row, read once per pair (sys is wave-uniform: scalar loads)
     const double* row = sysrow + (size_t)sys * SYS_STRIDE;
+    const double rr64 = row[SYS_R], rbx = row[SYS_BX], rby = row[SYS_BY];
+    const float r32 = (float)rr64, e32 = (float)row[SYS_EB];
+    const float bxh = (float)row[SYS_BXH], bxl = (float)row[SYS_BXL];
+    const float byh = (float)row[SYS_BYH], byl = (float)row[SYS_BYL];
     for (int q0 = 0; q0 < Q; q0 += QB) {
         V va[QB][8];
 #pragma unroll
@@ -495,9 +500,7 @@ __device__ __forceinline__ void pair_test(const V* __restrict__ ax, const V* __r
             const int gi = T.ci0 + li, gj = T.cj0 + lj;
             int res0 = kMiss, res1 = kMiss;
             if constexpr (sizeof(V) == 4) {
-                const float r = (float)row[SYS_R], E = (float)row[SYS_EB];
-                const float bxh = (float)row[SYS_BXH], bxl = (float)row[SYS_BXL];
-                const float byh = (float)row[SYS_BYH], byl = (float)row[SYS_BYL];
+                const float r = r32, E = e32;
                 const float h32 = (float)g.h;
                 const float ex0 = (((float)gi - bxh) - bxl) * h32;
                 const float ex1 = (((float)(gi + 1) - bxh) - bxl) * h32;
@@ -512,7 +515,7 @@ __device__ __forceinline__ void pair_test(const V* __restrict__ ax, const V* __r
                 res0 = decide32(tx, ty, E, mode, tau, nbbox);
                 res1 = decide32(ux, uy, E, mode, tau, nbbox);
             } else {
-                const double r = row[SYS_R], bx = row[SYS_BX], by = row[SYS_BY];
+                const double r = rr64, bx = rbx, by = rby;
                 const double t0x = node_coord(g.x0, gi, g.h), t1x = node_coord(g.x0, gi + 1, g.h);
                 const double t0y = node_coord(g.y0, gj, g.h), t1y = node_coord(g.y0, gj + 1, g.h);
                 const double b00x = src_map(t0x, r, va[b][0]), b00y = src_map(t0y, r, va[b][4]);
@@ -612,7 +615,9 @@ __global__ __launch_bounds__(256) void k_pairs(const V* __restrict__ ax, const V
     for (long long u = w0; u < n_pairs; u += nw) {
         const unsigned long long pk = nk;
         if (u + nw < n_pairs) nk = pair_key(u + nw);
-        const int tile = (int)(pk >> 32), sys = (int)(pk & 0xffffffffu);
+        // the key is the wave's own (every lane loaded the same one)
+        const int tile = __builtin_amdgcn_readfirstlane((int)(pk >> 32));
+        const int sys = __builtin_amdgcn_readfirstlane((int)(pk & 0xffffffffu));
         pair_test<S, V>(ax, ay, g, tile_of<S>(g, tiles_x, tile), sys, sysrow, st, mode, tau, hit_keys, hit_cap,
                         flag_keys, flag_cap, nbbox);
     }
